@@ -1,0 +1,174 @@
+"""Seeded synthetic inputs for the radiative-transfer workloads.
+
+This module only generates input fields (opacity, thermal coupling, Planck
+function, boundary intensities).  It holds none of the method's arithmetic,
+and both the GPU library's tests/benchmark and the oracle draw their inputs
+from here.
+
+Recipes (stand-ins for the paper's PHOENIX model structures, which are not
+available; the shapes follow the paper's test setups, Sec. 3.1 and 3.2):
+
+* stratified opacity: layer k = 0 (top) .. N-1 has geometric-mean vertical
+  optical depth tau_k = tau_min * r**k with r = (tau_max/tau_min)**(1/(N-1)),
+  and the layer's optical thickness tau_k (sqrt(r) - 1/sqrt(r)) is its
+  opacity per unit voxel edge, so the vertical optical depth is log-uniform
+  over [tau_min, tau_max];
+* log-normal 3D perturbation: chi *= 10**(sigma * g) with g a Gaussian random
+  field of correlation exp(-d^2 / (2 l^2)), made by FFT-convolving N(0,1) noise
+  with a Gaussian of standard deviation l/sqrt(2) (periodic in x,y, generated
+  on twice the depth and cropped), rescaled to zero mean and unit variance;
+* eps log-uniform per voxel or per wavelength; B = 1; no incoming intensity at
+  the top, I = B entering at the bottom.
+
+All fields are generated in float64 and, for single-precision workloads,
+rounded once to float32; those rounded values are the inputs of every solver.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+
+
+def stratified_chi(Nz: int, tau_min: float = 1e-4, tau_max: float = 1e4) -> np.ndarray:
+    """Per-layer opacity (unit voxel edge), k = 0 the top layer."""
+    if Nz == 1:
+        return np.array([tau_max - tau_min], dtype=np.float64)
+    lr = np.log10(tau_max / tau_min) / (Nz - 1)
+    r = 10.0 ** lr
+    k = np.arange(Nz, dtype=np.float64)
+    tau_k = tau_min * 10.0 ** (lr * k)
+    return tau_k * (np.sqrt(r) - 1.0 / np.sqrt(r))
+
+
+def gaussian_random_field(Nz: int, Ny: int, Nx: int, ell: float, seed: int) -> np.ndarray:
+    """Zero-mean, unit-variance field with correlation exp(-d^2/(2 ell^2))."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Nz2 = 2 * Nz
+    noise = rng.standard_normal((Nz2, Ny, Nx))
+    sig = ell / np.sqrt(2.0)
+
+    def kern1d(n):
+        d = np.arange(n, dtype=np.float64)
+        d = np.minimum(d, n - d)
+        return np.exp(-0.5 * (d / sig) ** 2)
+
+    kz = np.fft.fft(kern1d(Nz2))[:, None, None]
+    ky = np.fft.fft(kern1d(Ny))[None, :, None]
+    kx = np.fft.rfft(kern1d(Nx))[None, None, :]
+    F = np.fft.rfftn(noise) * kz * ky * kx
+    g = np.fft.irfftn(F, s=noise.shape)[:Nz]
+    g = g - g.mean()
+    g = g / g.std()
+    return g
+
+
+@dataclasses.dataclass
+class BoxCase:
+    """One workload on the periodic box.  Arrays are [lambda][k][y][x]."""
+    name: str
+    Nx: int
+    Ny: int
+    Nz: int
+    n_mu: int
+    n_phi: int
+    chi: np.ndarray          # (n_lambda, Nz, Ny, Nx)
+    eps: np.ndarray          # (n_lambda, Nz, Ny, Nx)
+    B: np.ndarray            # (n_lambda, Nz, Ny, Nx)
+    I_bc: np.ndarray         # (n_lambda, 2): intensity entering at top, at bottom
+    dtype: str               # "f64" or "f32": precision of the formal solution
+    tol: float = 1e-8
+
+    @property
+    def n_lambda(self) -> int:
+        return self.chi.shape[0]
+
+    @property
+    def n_dir(self) -> int:
+        return self.n_mu * self.n_phi
+
+    @property
+    def n_vox(self) -> int:
+        return self.Nx * self.Ny * self.Nz
+
+    def vdu_per_fs(self) -> int:
+        """voxel-direction updates of one formal solution over all wavelengths."""
+        return self.n_vox * self.n_dir * self.n_lambda
+
+
+def _round(a: np.ndarray, dtype: str) -> np.ndarray:
+    if dtype == "f32":
+        return a.astype(np.float32).astype(np.float64)
+    return a.astype(np.float64)
+
+
+def box_stratified(N: int = 33, Nz: Optional[int] = None, n_mu: int = 8, n_phi: int = 16,
+                   eps: float = 1e-2, dtype: str = "f64", tau_min: float = 1e-4,
+                   tau_max: float = 1e4, name: str = "box-stratified") -> BoxCase:
+    """x,y-uniform stratified slab: the 33^3, 8x16-direction FP64 workload at its defaults."""
+    Nz = N if Nz is None else Nz
+    chi = np.broadcast_to(stratified_chi(Nz, tau_min, tau_max)[:, None, None], (Nz, N, N))
+    chi = _round(np.array(chi), dtype)[None]
+    e = np.full_like(chi, eps)
+    e = _round(e, dtype)
+    B = np.ones_like(chi)
+    I_bc = np.array([[0.0, 1.0]])
+    return BoxCase(name, N, N, Nz, n_mu, n_phi, chi, e, B, I_bc, dtype, tol=1e-8)
+
+
+def box_lognormal(N: int = 129, Nz: Optional[int] = None, n_mu: int = 32, n_phi: int = 64,
+                  sigma_dex: float = 1.0, ell: float = 8.0, field_seed: int = 1, eps_seed: int = 101,
+                  eps_range=(-6.0, 0.0), dtype: str = "f32", name: str = "box-lognormal",
+                  Ny: Optional[int] = None) -> BoxCase:
+    """Stratified opacity times a log-normal 3D perturbation, eps log-uniform per voxel.
+
+    Defaults: the 129^3, 32x64-direction single-precision workload."""
+    Nz = N if Nz is None else Nz
+    Ny = N if Ny is None else Ny
+    g = gaussian_random_field(Nz, Ny, N, ell, field_seed)
+    chi = stratified_chi(Nz)[:, None, None] * 10.0 ** (sigma_dex * g)
+    rng = np.random.Generator(np.random.PCG64(eps_seed))
+    e = 10.0 ** rng.uniform(eps_range[0], eps_range[1], size=chi.shape)
+    chi = _round(chi, dtype)[None]
+    e = _round(e, dtype)[None]
+    B = np.ones_like(chi)
+    I_bc = np.array([[0.0, 1.0]])
+    return BoxCase(name, N, Ny, Nz, n_mu, n_phi, chi, e, B, I_bc, dtype, tol=1e-8)
+
+
+def box_batched(N: int = 129, Nz: Optional[int] = None, n_lambda: int = 64, n_mu: int = 32,
+                n_phi: int = 32, scale_seed: int = 2, eps_seed: int = 102, field_seed: int = 1,
+                dtype: str = "f32", name: str = "box-batched") -> BoxCase:
+    """Wavelength batch on one structure: chi_l = f_l chi_1, f_l log-uniform in [1e-3, 1e3],
+    eps_l log-uniform in [1e-5, 1e-1], uniform in space per wavelength."""
+    Nz = N if Nz is None else Nz
+    g = gaussian_random_field(Nz, N, N, 8.0, field_seed)
+    chi1 = stratified_chi(Nz)[:, None, None] * 10.0 ** g
+    rs = np.random.Generator(np.random.PCG64(scale_seed))
+    f = 10.0 ** rs.uniform(-3.0, 3.0, size=n_lambda)
+    re = np.random.Generator(np.random.PCG64(eps_seed))
+    el = 10.0 ** re.uniform(-5.0, -1.0, size=n_lambda)
+    chi = _round(f[:, None, None, None] * chi1[None], dtype)
+    e = _round(np.broadcast_to(el[:, None, None, None], chi.shape).copy(), dtype)
+    B = np.ones_like(chi)
+    I_bc = np.tile(np.array([[0.0, 1.0]]), (n_lambda, 1))
+    return BoxCase(name, N, N, Nz, n_mu, n_phi, chi, e, B, I_bc, dtype, tol=1e-8)
+
+
+def random_box(Nx: int, Ny: int, Nz: int, n_mu: int, n_phi: int, seed: int, dtype: str = "f64",
+               n_lambda: int = 1, chi_dex=(-2.0, 2.0), eps_dex=(-3.0, 0.0),
+               name: str = "box-random") -> BoxCase:
+    """Small heterogeneous box with iid log-uniform fields: parity-test input."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shape = (n_lambda, Nz, Ny, Nx)
+    chi = _round(10.0 ** rng.uniform(chi_dex[0], chi_dex[1], size=shape), dtype)
+    e = _round(10.0 ** rng.uniform(eps_dex[0], eps_dex[1], size=shape), dtype)
+    B = _round(rng.uniform(0.5, 1.5, size=shape), dtype)
+    I_bc = np.stack([rng.uniform(0.0, 0.5, size=n_lambda), rng.uniform(0.5, 1.5, size=n_lambda)], axis=1)
+    return BoxCase(name, Nx, Ny, Nz, n_mu, n_phi, chi, e, B, I_bc, dtype)
+
+
+def random_source(shape, seed: int, lo: float = 0.0, hi: float = 1.0, dtype: str = "f64") -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return _round(rng.uniform(lo, hi, size=shape), dtype)
