@@ -1,0 +1,201 @@
+/*
+ * rt3d.h -- C ABI of the MI355X (gfx950) library for the 3D radiative
+ * transfer formal solution and its operator-splitting (ALI) iteration.
+ *
+ * Method: P. H. Hauschildt & E. Baron, "A 3D radiative transfer framework.
+ * XII. Many-core, vector and GPU methods" (arXiv 2102.01734):
+ *   - static transfer equation n.grad I = eta - chi I, S = eta/chi      (Sec. 2.1, eq. 1)
+ *   - formal solution J = Lambda S along characteristics for all solid
+ *     angles, with the approximate operator Lambda*                      (Sec. 2.2 eq. frmsol; Sec. 4)
+ *   - per-point steps: gather previous/next S and chi, optical steps,
+ *     interpolation weights, boundary/vacuum fix-up, Lambda* data,
+ *     Delta I and exp(-dtau)                                            (Listing 1, steps 0-5)
+ *   - operator splitting [1 - Lambda*(1-eps)] J_new = J_fs - Lambda*(1-eps) J_old,
+ *     S = (1-eps) J + eps B                                             (Sec. 2.2, eq. alo)
+ *   - geometry (tracker) computed once and reused for every wavelength  (Sec. 4.1)
+ *
+ * Conventions shared by every entry point:
+ *   - Box grid: cubic voxels of unit edge, Nx x Ny x Nz voxels, periodic in
+ *     x and y.  Layer k = 0 is the top (outer boundary, z max), k = Nz-1 the
+ *     bottom (inner boundary).  Field arrays are structure-of-arrays,
+ *     [lambda][k][y][x], x fastest, contiguous, one value per voxel.
+ *   - Directions: n_mu x n_phi, mu_i = -1 + (2i+1)/n_mu, phi_j = 2 pi (j+1/2)/n_phi,
+ *     equal weights 1/(n_mu n_phi) (Sec. 3.1: equally spaced in mu and phi).
+ *   - Precision: RT_FP64 grids take double fields and compute the formal
+ *     solution in double.  RT_FP32 grids take float fields, run the formal
+ *     solution recurrence and J accumulation in float, and keep the optical
+ *     steps, interpolation weights and all ALI state (J, S, Ng, norms) in
+ *     double.
+ *   - Pointers marked "device" are HIP device pointers (e.g. from
+ *     torch.Tensor.data_ptr()); the caller allocates and owns them and the
+ *     library never frees them.  The grid handle owns its geometry tables,
+ *     partial-sum buffers and scratch; rt_destroy_grid frees all of them.
+ *   - stream: a hipStream_t cast to void* (NULL = the default stream).  Work is
+ *     enqueued asynchronously on it unless stated otherwise.
+ *   - Errors: every call returns an rt_status; arguments are validated before
+ *     anything is launched.  rt_last_error() returns a message for the most
+ *     recent failure on the calling thread.  A handle must not be used from two
+ *     threads at once; different handles are independent.
+ */
+#ifndef RT3D_H
+#define RT3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RT_OK = 0,
+    RT_E_INVALID = 1,       /* bad argument or descriptor                      */
+    RT_E_NOMEM = 2,         /* device allocation failed                        */
+    RT_E_HIP = 3,           /* a HIP runtime call failed                       */
+    RT_E_NOT_CONVERGED = 4, /* rt_solve reached max_iter; state stays valid    */
+    RT_E_NUMERIC = 5,       /* NaN or Inf met in the iteration                 */
+    RT_E_UNSUPPORTED = 6    /* valid request this build cannot serve           */
+} rt_status;
+
+typedef enum { RT_GEOM_BOX_PERIODIC_XY = 0, RT_GEOM_SPHERICAL = 1 } rt_geom;
+typedef enum { RT_FP64 = 0, RT_FP32 = 1 } rt_prec;
+
+/* rt_grid_desc.flags */
+#define RT_F_LSTAR_PARABOLIC 0x1u /* Lambda* = exact diagonal of the parabolic
+                                     formal solution; default: diagonal of the
+                                     linear-interpolation operator            */
+
+typedef struct rt_grid *rt_grid_t;
+
+typedef struct {
+    uint32_t struct_size;  /* sizeof(rt_grid_desc)                              */
+    int32_t geom;          /* rt_geom                                           */
+    int32_t n[3];          /* box: Nx, Ny, Nz (each >= 1)                       */
+    double h[3];           /* box: ignored (unit voxels)                        */
+    int32_t n_mu, n_phi;   /* direction quadrature; n_mu even, n_phi >= 1       */
+    int32_t n_lambda_max;  /* largest wavelength batch any call will pass       */
+    int32_t prec;          /* rt_prec                                           */
+    uint32_t flags;        /* RT_F_*                                            */
+} rt_grid_desc;
+
+/*
+ * Builds the tracker output (one characteristic template per direction; every
+ * other characteristic of that direction is an integer translate of it) on the
+ * host in double precision, uploads it once, and sizes the work schedule and
+ * partial-sum buffers for up to n_lambda_max wavelengths (Sec. 4.1: the
+ * geometry cache is built once and reused for all wavelengths).
+ * Blocks until the upload is complete.  Errors: RT_E_INVALID (descriptor),
+ * RT_E_UNSUPPORTED (grid larger than the on-chip layer tile allows),
+ * RT_E_NOMEM, RT_E_HIP.  *out is NULL on error.
+ */
+rt_status rt_create_grid(const rt_grid_desc *desc, rt_grid_t *out);
+
+/* Frees every device buffer of the handle (after synchronising its device). */
+rt_status rt_destroy_grid(rt_grid_t grid);
+
+/* Read-only facts about a grid.  Any out pointer may be NULL. */
+rt_status rt_grid_info(rt_grid_t grid, int64_t *n_vox, int32_t *n_dir,
+                       int64_t *n_visits_total, int32_t *n_workgroups);
+
+/*
+ * Formal solution J = Lambda S + Lambda_bc (Sec. 2.2 eq. frmsol) and,
+ * optionally, the diagonal Lambda* (Sec. 4; Listing 1 step 4b), for n_lambda
+ * independent wavelengths on the same grid.
+ *   chi, S     device, [n_lambda][Nz][Ny][Nx], grid precision (float/double);
+ *              chi >= 0 (chi = 0 marks vacuum: Listing 1 step 4a)
+ *   I_bc       device, [n_lambda][2] grid precision: intensity entering at the
+ *              top (mu < 0 rays) and at the bottom (mu > 0 rays); NULL = 0
+ *   J_out      device, [n_lambda][Nz][Ny][Nx], grid precision
+ *   lstar_out  device, same shape, or NULL to skip Lambda*
+ * n_lambda = 0 is a no-op.  Deterministic: the same inputs give bitwise the
+ * same outputs (fixed summation order, no floating-point atomics across
+ * workgroups).  Errors: RT_E_INVALID (NULL pointer, n_lambda out of range),
+ * RT_E_HIP.
+ */
+rt_status rt_formal_solution(rt_grid_t grid, int32_t n_lambda, const void *chi, const void *S,
+                             const void *I_bc, void *J_out, void *lstar_out, void *stream);
+
+/* State of the ALI iteration for a batch of wavelengths. */
+typedef struct {
+    uint32_t struct_size; /* sizeof(rt_state)                                   */
+    int32_t n_lambda;     /* 1 .. n_lambda_max                                  */
+    const void *chi;      /* device [n_lambda][vox], grid precision             */
+    const void *eps;      /* device [n_lambda][vox], grid precision, 0<=eps<=1  */
+    const void *B;        /* device [n_lambda][vox], grid precision             */
+    const void *I_bc;     /* device [n_lambda][2], grid precision; NULL = 0     */
+    double *J;            /* device [n_lambda][vox] double: current iterate;
+                             on entry the start value (e.g. B), on exit the
+                             result.  Resuming from any J is allowed.           */
+    double *S;            /* device [n_lambda][vox] double: S = (1-eps)J + eps B
+                             of the returned J (written by the library)         */
+    void *lstar;          /* device [n_lambda][vox] grid precision: Lambda*     */
+    int32_t lstar_valid;  /* in/out: 0 = compute Lambda* on the next step       */
+    int32_t iter;         /* in/out: ALI steps taken since the last restart     */
+    double *rel_change;   /* device [n_lambda] double, out: max_v |dJ/J| of the
+                             last step (0 for wavelengths already converged)   */
+} rt_state;
+
+typedef struct {
+    uint32_t struct_size; /* sizeof(rt_solve_opts)                              */
+    double tol;           /* stop when max_v |J_new - J_old|/|J_new| < tol      */
+    int32_t max_iter;     /* ALI steps per rt_solve call                        */
+    int32_t ng_every;     /* Ng acceleration every k plain steps (0 = off)      */
+    int32_t ng_start;     /* first step at which Ng may be applied              */
+    int32_t reanchor;     /* FP32 grids: new FP64 anchor once max |dJ/J| has
+                             fallen by this factor since the last anchor
+                             (0 = library default 100)                          */
+} rt_solve_opts;
+
+typedef struct {
+    int32_t iters;          /* ALI steps taken by this call                     */
+    int32_t n_fs;           /* formal solutions (all precisions)                */
+    int32_t n_fs64;         /* of which double-precision anchors                */
+    int32_t n_ng;           /* Ng extrapolations applied                        */
+    int32_t n_converged;    /* wavelengths below tol at return                  */
+    double max_rel_change;  /* max over wavelengths of the last step's change   */
+    double seconds;         /* wall time of the call                            */
+} rt_solve_report;
+
+/*
+ * One ALI step (Sec. 2.2 eq. alo with the diagonal Lambda*): formal solution
+ * of the current S (building Lambda* first when lstar_valid == 0), the
+ * pointwise operator-splitting update of J, S = (1-eps)J + eps B, the
+ * per-wavelength norm max_v |dJ/J| into state->rel_change, and -- when the
+ * schedule in opts says so -- the Ng extrapolation of the last four iterates.
+ * Asynchronous on `stream`.  For RT_FP32 grids the formal solution of the
+ * step is single precision on S - S_anchor; the anchor (a double-precision
+ * formal solution) is taken on the first step and refreshed by rt_solve.
+ * Errors: RT_E_INVALID, RT_E_HIP.
+ */
+rt_status rt_ali_step(rt_grid_t grid, rt_state *state, const rt_solve_opts *opts, void *stream);
+
+/*
+ * Runs ALI steps until every wavelength has max_v |dJ/J| < tol or max_iter
+ * steps were taken.  Wavelengths that converge drop out of later steps.
+ * Blocks (reads a few bytes per step back to the host).  Returns
+ * RT_E_NOT_CONVERGED (state valid and resumable) or RT_E_NUMERIC (NaN/Inf).
+ */
+rt_status rt_solve(rt_grid_t grid, rt_state *state, const rt_solve_opts *opts,
+                   rt_solve_report *report, void *stream);
+
+/*
+ * Host-only tracker output for one direction of the box (no GPU needed): the
+ * characteristic entering the centre of the inflow face of column (0,0),
+ * segment by segment -- unwrapped voxel offsets di, dj from the entry column,
+ * layer kk (0 = top) and path length s.  dir = i_mu * n_phi + j_phi.
+ * *M receives the segment count; the arrays (host memory, cap entries each)
+ * are filled when cap >= *M.  For inspection and tests of the geometry cache.
+ */
+rt_status rt_box_template(int32_t Nz, int32_t n_mu, int32_t n_phi, int32_t dir, int32_t cap, int32_t *di,
+                          int32_t *dj, int32_t *kk, double *s, int32_t *M);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *rt_last_error(void);
+
+/* Library version string. */
+const char *rt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RT3D_H */

@@ -1,0 +1,62 @@
+// ali.hpp -- launch interface of the padding, reduction, ALI and Ng kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace rt3d {
+
+template <typename TS, typename TD>
+hipError_t pad_field(const TS *src, const double *anchor, TD *dst, int Nx, int Ny, int Nz, int n_lambda,
+                     hipStream_t st);
+
+template <typename TP, typename TO>
+hipError_t reduce_partials(const TP *part, const int32_t *slot_begin, const int32_t *slot_ids,
+                           const int32_t *lambda_of, int n_batch, TO *out, int64_t n_vox, hipStream_t st);
+
+template <typename G, typename TN>
+hipError_t source_update(const double *J, const G *eps, const G *B, double *S, const double *S_anchor, TN *next_pad,
+                         int Nx, int Ny, int64_t n_vox, const int32_t *lambda_of, int n_batch, hipStream_t st);
+
+template <typename TS, typename TD>
+hipError_t cast_array(const TS *src, TD *dst, int64_t n, hipStream_t st);
+
+hipError_t fill_u64(unsigned long long *p, unsigned long long v, int n, hipStream_t st);
+
+struct AliUpdateArgs {
+    int Nx, Ny;
+    int64_t n_vox;
+    const int32_t *lambda_of;   // batch entry -> wavelength index
+    const void *part;           // partial slots of the formal solution, or null
+    const int32_t *slot_begin;  // per batch entry
+    const int32_t *slot_ids;
+    const double *J_anchor;     // double-precision anchor J_fs(S_anchor), or null
+    const double *S_anchor;     // anchor source, or null
+    const void *eps, *B, *lstar;  // grid precision
+    double *J;                  // in/out
+    double *S;                  // out
+    double *hist;               // out: copy of the new J into the Ng ring, or null
+    void *next_pad;             // out: padded formal-solution input (S - S_anchor)
+    double *rel_change;         // out: per wavelength max |dJ/J| (atomic max)
+};
+
+hipError_t ali_update(const AliUpdateArgs &a, bool part_double, bool grid_double, bool next_double, int n_batch,
+                      hipStream_t st);
+
+struct NgApplyArgs {
+    int Nx, Ny;
+    int64_t n_vox;
+    const int32_t *lambda_of;
+    const double *x0, *x1, *x2, *x3;  // newest .. oldest iterate
+    double *coef;                     // [batch][3]: a, b, applied
+    const void *eps, *B;
+    const double *S_anchor;
+    double *J, *S;
+    void *next_pad;
+};
+
+hipError_t ng_accelerate(const NgApplyArgs &a, double *blk, int nblk, int n_batch, bool grid_double,
+                         hipStream_t st);
+
+}  // namespace rt3d

@@ -1,0 +1,45 @@
+// fs_box.hpp -- launch interface of the box formal-solution kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "rt_internal.hpp"
+
+namespace rt3d {
+
+struct FsBoxArgs {
+    int Nx, Ny, Nz;
+    int64_t n_vox;
+    // visit table (directions back to back) and per-direction data
+    const int32_t *goff;
+    const uint32_t *dxy;
+    const double *s;
+    const int64_t *dir_vbegin;
+    const int32_t *dir_M;
+    const double *dir_wmu;  // w_d |mu_d|
+    const double *dir_mu;
+    // schedule
+    const int32_t *wg_begin;
+    const WorkItem *items;
+    // fields: padded [lambda][Nz][2Ny][2Nx], element type = kernel type
+    const void *chi_pad;
+    const void *S_pad;
+    int64_t pad_stride;
+    const void *I_bc;  // [lambda][2] or null
+    // partial sums [slot][n_vox]
+    void *partJ;
+    void *partL;
+};
+
+// Rays per thread R and threads per workgroup for a direction of n_rays rays.
+int fs_box_pick_r(int n_rays, int max_threads, int *nthr);
+
+hipError_t fs_box_launch(const FsBoxArgs &a, bool is_double, bool want_j, bool want_l, bool parabolic_lstar,
+                         int R, int n_wg, int nthr, size_t lds_bytes, hipStream_t stream);
+
+int fs_box_occupancy(bool is_double, bool want_j, bool want_l, bool parabolic_lstar, int R, int nthr,
+                     size_t lds_bytes);
+
+}  // namespace rt3d

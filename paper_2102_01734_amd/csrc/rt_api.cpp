@@ -1,0 +1,646 @@
+// rt_api.cpp -- the C ABI declared in include/rt3d.h.
+//
+// Host side of the library: argument validation, the geometry cache upload,
+// workgroup schedules, lazily sized device buffers, and the order of kernel
+// launches for one formal solution, one ALI step and a full solve.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "ali.hpp"
+#include "fs_box.hpp"
+#include "rt_internal.hpp"
+
+using namespace rt3d;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static rt_status fail(rt_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(...)                                                                         \
+    do {                                                                                    \
+        hipError_t e_ = (__VA_ARGS__);                                                      \
+        if (e_ != hipSuccess)                                                               \
+            return fail(RT_E_HIP, "HIP error %s at %s:%d", hipGetErrorString(e_), __FILE__, \
+                        __LINE__);                                                          \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// device buffer helper
+// ---------------------------------------------------------------------------
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    ~DevBuf() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    // grows (never shrinks); contents are not preserved
+    hipError_t ensure(size_t n)
+    {
+        if (n <= bytes) return hipSuccess;
+        release();
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) { p = nullptr; return e; }
+        bytes = n;
+        return hipSuccess;
+    }
+    template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+// One kernel variant: element type, outputs, launch shape and resident count.
+struct Variant {
+    bool dbl = false, wj = false, wl = false;
+    int R = 0, nthr = 0, n_wg = 0;
+    size_t lds = 0;
+    bool ok = false;
+};
+
+struct DevSchedule {
+    int n_wg = 0, n_slots = 0, n_batch = 0;
+    DevBuf wg_begin, items, slot_begin, slot_ids, lambda_of;
+};
+
+struct rt_grid {
+    rt_grid_desc desc{};
+    BoxGeometry geo;
+    int device = 0;
+    int n_cu = 0;
+    size_t max_lds = 0;
+    bool dbl = false;
+    bool para = false;
+    int64_t n_vox = 0;
+    int n_dir = 0;
+    int64_t n_visits = 0;
+
+    DevBuf goff, dxy, s, vbegin, M, wmu, mu;
+    Variant var[2][2][2];  // [dbl][wj][wl]
+
+    std::map<std::string, std::unique_ptr<DevSchedule>> schedules;
+
+    // rt_formal_solution scratch
+    DevBuf fs_chi_pad, fs_S_pad;
+    // ALI scratch (sized for n_lambda_max)
+    DevBuf chi_pad, chi_pad64, S_pad, S_pad64, ibc64;
+    DevBuf partJ, partL, partJ64, partL64;
+    // ALI state owned by the library
+    DevBuf J_anchor, S_anchor, hist, ng_blk, ng_coef;
+    int hist_count = 0;
+    const void *chi_src = nullptr;
+    int anchor_due = 1;
+};
+
+static Variant &variant(rt_grid *g, bool dbl, bool wj, bool wl) { return g->var[dbl][wj][wl]; }
+
+static void setup_variant(rt_grid *g, bool dbl, bool wj, bool wl)
+{
+    Variant &v = variant(g, dbl, wj, wl);
+    v = Variant();
+    v.dbl = dbl; v.wj = wj; v.wl = wl;
+    const int rays = g->geo.Nx * g->geo.Ny;
+    v.R = fs_box_pick_r(rays, 1024, &v.nthr);
+    if (v.R == 0) return;
+    v.lds = (size_t)rays * (dbl ? 8 : 4) * ((wj ? 1 : 0) + (wl ? 1 : 0));
+    if (v.lds > g->max_lds) return;
+    int occ = fs_box_occupancy(dbl, wj, wl, g->para, v.R, v.nthr, v.lds);
+    if (occ <= 0) return;
+    v.n_wg = occ * g->n_cu;
+    v.ok = true;
+}
+
+// ---------------------------------------------------------------------------
+// schedules
+// ---------------------------------------------------------------------------
+static rt_status get_schedule(rt_grid *g, int n_wg, const std::vector<int32_t> &lambdas, DevSchedule **out)
+{
+    std::string key = std::to_string(n_wg) + ":";
+    for (int l : lambdas) key += std::to_string(l) + ",";
+    auto it = g->schedules.find(key);
+    if (it != g->schedules.end()) {
+        *out = it->second.get();
+        return RT_OK;
+    }
+    Schedule sc;
+    build_schedule(g->geo, lambdas, n_wg, sc);
+    auto ds = std::make_unique<DevSchedule>();
+    ds->n_wg = sc.n_wg;
+    ds->n_slots = sc.n_slots;
+    ds->n_batch = (int)lambdas.size();
+    auto up = [](DevBuf &b, const void *src, size_t n) -> hipError_t {
+        hipError_t e = b.ensure(n > 0 ? n : 16);
+        if (e != hipSuccess) return e;
+        if (n > 0) return hipMemcpy(b.p, src, n, hipMemcpyHostToDevice);
+        return hipSuccess;
+    };
+    HIPCHK(up(ds->wg_begin, sc.wg_begin.data(), sc.wg_begin.size() * sizeof(int32_t)));
+    HIPCHK(up(ds->items, sc.items.data(), sc.items.size() * sizeof(WorkItem)));
+    HIPCHK(up(ds->slot_begin, sc.slot_begin.data(), sc.slot_begin.size() * sizeof(int32_t)));
+    HIPCHK(up(ds->slot_ids, sc.slot_ids.data(), sc.slot_ids.size() * sizeof(int32_t)));
+    HIPCHK(up(ds->lambda_of, lambdas.data(), lambdas.size() * sizeof(int32_t)));
+    if (g->schedules.size() > 64) g->schedules.clear();
+    *out = ds.get();
+    g->schedules[key] = std::move(ds);
+    return RT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// formal solution on padded inputs already in place
+// ---------------------------------------------------------------------------
+static rt_status run_fs(rt_grid *g, bool dbl, bool wj, bool wl, const std::vector<int32_t> &lambdas,
+                        const void *chi_pad, const void *S_pad, const void *I_bc, DevBuf &partJ, DevBuf &partL,
+                        DevSchedule **sched_out, hipStream_t st)
+{
+    Variant &v = variant(g, dbl, wj, wl);
+    if (!v.ok) return fail(RT_E_UNSUPPORTED, "no kernel configuration fits this grid (layer tile of %d voxels)",
+                           g->geo.Nx * g->geo.Ny);
+    DevSchedule *sc = nullptr;
+    rt_status rs = get_schedule(g, v.n_wg, lambdas, &sc);
+    if (rs != RT_OK) return rs;
+    const size_t esz = dbl ? 8 : 4;
+    if (wj) HIPCHK(partJ.ensure((size_t)sc->n_slots * g->n_vox * esz));
+    if (wl) HIPCHK(partL.ensure((size_t)sc->n_slots * g->n_vox * esz));
+    FsBoxArgs a{};
+    a.Nx = g->geo.Nx; a.Ny = g->geo.Ny; a.Nz = g->geo.Nz;
+    a.n_vox = g->n_vox;
+    a.goff = g->goff.as<int32_t>();
+    a.dxy = g->dxy.as<uint32_t>();
+    a.s = g->s.as<double>();
+    a.dir_vbegin = g->vbegin.as<int64_t>();
+    a.dir_M = g->M.as<int32_t>();
+    a.dir_wmu = g->wmu.as<double>();
+    a.dir_mu = g->mu.as<double>();
+    a.wg_begin = sc->wg_begin.as<int32_t>();
+    a.items = sc->items.as<WorkItem>();
+    a.chi_pad = chi_pad;
+    a.S_pad = S_pad;
+    a.pad_stride = 4 * g->n_vox;
+    a.I_bc = I_bc;
+    a.partJ = wj ? partJ.p : nullptr;
+    a.partL = wl ? partL.p : nullptr;
+    HIPCHK(fs_box_launch(a, dbl, wj, wl, g->para, v.R, sc->n_wg, v.nthr, v.lds, st));
+    *sched_out = sc;
+    return RT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// API
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *rt_last_error(void) { return g_err.c_str(); }
+
+const char *rt_version(void) { return "rt3d 0.1 (gfx950)"; }
+
+rt_status rt_box_template(int32_t Nz, int32_t n_mu, int32_t n_phi, int32_t dir, int32_t cap, int32_t *di,
+                          int32_t *dj, int32_t *kk, double *s, int32_t *M)
+{
+    if (Nz < 1 || n_mu < 2 || (n_mu % 2) || n_phi < 1 || dir < 0 || dir >= n_mu * n_phi || !M)
+        return fail(RT_E_INVALID, "bad template request");
+    const int i = dir / n_phi, j = dir % n_phi;
+    double n[3];
+    const double mu = -1.0 + (2.0 * i + 1.0) / n_mu;
+    const double phi = 2.0 * M_PI * (j + 0.5) / n_phi;
+    const double st = std::sqrt(1.0 - mu * mu);
+    n[0] = st * std::cos(phi);
+    n[1] = st * std::sin(phi);
+    n[2] = mu;
+    std::vector<int32_t> a, b, c;
+    std::vector<double> l;
+    const int m = trace_box_ray(Nz, n, a, b, c, l);
+    if (m < 0) return fail(RT_E_INVALID, "tracker failed");
+    *M = m;
+    if (!di || !dj || !kk || !s) return RT_OK;  // size query
+    if (m > cap) return fail(RT_E_INVALID, "cap %d < %d segments", cap, m);
+    for (int q = 0; q < m; ++q) { di[q] = a[q]; dj[q] = b[q]; kk[q] = c[q]; s[q] = l[q]; }
+    return RT_OK;
+}
+
+rt_status rt_create_grid(const rt_grid_desc *desc, rt_grid_t *out)
+{
+    if (!out) return fail(RT_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!desc) return fail(RT_E_INVALID, "desc is NULL");
+    if (desc->struct_size != sizeof(rt_grid_desc)) return fail(RT_E_INVALID, "desc->struct_size mismatch");
+    if (desc->geom == RT_GEOM_SPHERICAL)
+        return fail(RT_E_UNSUPPORTED, "spherical grids are not available in this build");
+    if (desc->geom != RT_GEOM_BOX_PERIODIC_XY) return fail(RT_E_INVALID, "unknown geometry %d", desc->geom);
+    if (desc->prec != RT_FP32 && desc->prec != RT_FP64) return fail(RT_E_INVALID, "unknown precision %d", desc->prec);
+    if (desc->n_lambda_max < 1) return fail(RT_E_INVALID, "n_lambda_max must be >= 1");
+    if (desc->flags & ~RT_F_LSTAR_PARABOLIC) return fail(RT_E_INVALID, "unknown flags 0x%x", desc->flags);
+    const int64_t nv = (int64_t)desc->n[0] * desc->n[1] * desc->n[2];
+    if (desc->n[0] < 1 || desc->n[1] < 1 || desc->n[2] < 1) return fail(RT_E_INVALID, "grid sizes must be >= 1");
+    if (desc->n[0] > 4096 || desc->n[1] > 4096 || desc->n[2] > 1000000)
+        return fail(RT_E_INVALID, "grid sizes out of range");
+    if (nv * 4 * desc->n_lambda_max > (int64_t)1 << 40) return fail(RT_E_INVALID, "grid x batch too large");
+    if (desc->n_mu > 4096 || desc->n_phi > 4096) return fail(RT_E_INVALID, "direction counts out of range");
+
+    auto g = std::make_unique<rt_grid>();
+    g->desc = *desc;
+    g->dbl = desc->prec == RT_FP64;
+    g->para = (desc->flags & RT_F_LSTAR_PARABOLIC) != 0;
+    std::string err = build_box_geometry(desc->n[0], desc->n[1], desc->n[2], desc->n_mu, desc->n_phi, g->geo);
+    if (!err.empty()) return fail(RT_E_INVALID, "%s", err.c_str());
+    g->n_vox = nv;
+    g->n_dir = (int)g->geo.dirs.size();
+    g->n_visits = (int64_t)g->geo.s.size();
+
+    HIPCHK(hipGetDevice(&g->device));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, g->device));
+    g->n_cu = prop.multiProcessorCount;
+    g->max_lds = prop.sharedMemPerBlock;
+    if (prop.maxSharedMemoryPerMultiProcessor > 0 && (size_t)prop.maxSharedMemoryPerMultiProcessor < g->max_lds)
+        g->max_lds = prop.maxSharedMemoryPerMultiProcessor;
+
+    const size_t nvis = (size_t)g->n_visits;
+    HIPCHK(g->goff.ensure(nvis * 4));
+    HIPCHK(g->dxy.ensure(nvis * 4));
+    HIPCHK(g->s.ensure(nvis * 8));
+    HIPCHK(hipMemcpy(g->goff.p, g->geo.goff.data(), nvis * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(g->dxy.p, g->geo.dxy.data(), nvis * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(g->s.p, g->geo.s.data(), nvis * 8, hipMemcpyHostToDevice));
+    std::vector<int64_t> vb(g->n_dir);
+    std::vector<int32_t> Ms(g->n_dir);
+    std::vector<double> wmu(g->n_dir), mu(g->n_dir);
+    for (int d = 0; d < g->n_dir; ++d) {
+        vb[d] = g->geo.dirs[d].vbegin;
+        Ms[d] = g->geo.dirs[d].M;
+        wmu[d] = g->geo.dirs[d].w * std::fabs(g->geo.dirs[d].mu);
+        mu[d] = g->geo.dirs[d].mu;
+    }
+    HIPCHK(g->vbegin.ensure(g->n_dir * 8));
+    HIPCHK(g->M.ensure(g->n_dir * 4));
+    HIPCHK(g->wmu.ensure(g->n_dir * 8));
+    HIPCHK(g->mu.ensure(g->n_dir * 8));
+    HIPCHK(hipMemcpy(g->vbegin.p, vb.data(), g->n_dir * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(g->M.p, Ms.data(), g->n_dir * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(g->wmu.p, wmu.data(), g->n_dir * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(g->mu.p, mu.data(), g->n_dir * 8, hipMemcpyHostToDevice));
+
+    for (int d = 0; d < 2; ++d)
+        for (int j = 0; j < 2; ++j)
+            for (int l = 0; l < 2; ++l)
+                if (j || l) setup_variant(g.get(), d, j, l);
+    const bool self_ok = variant(g.get(), g->dbl, true, false).ok && variant(g.get(), g->dbl, false, true).ok;
+    const bool anchor_ok = g->dbl || variant(g.get(), true, true, false).ok;
+    if (!self_ok || !anchor_ok)
+        return fail(RT_E_UNSUPPORTED, "layer of %d x %d voxels does not fit the on-chip tile (%zu bytes of LDS)",
+                    g->geo.Nx, g->geo.Ny, g->max_lds);
+    *out = g.release();
+    g_err.clear();
+    return RT_OK;
+}
+
+rt_status rt_destroy_grid(rt_grid_t grid)
+{
+    if (!grid) return fail(RT_E_INVALID, "grid is NULL");
+    (void)hipDeviceSynchronize();
+    delete grid;
+    return RT_OK;
+}
+
+rt_status rt_grid_info(rt_grid_t g, int64_t *n_vox, int32_t *n_dir, int64_t *n_visits_total, int32_t *n_wg)
+{
+    if (!g) return fail(RT_E_INVALID, "grid is NULL");
+    if (n_vox) *n_vox = g->n_vox;
+    if (n_dir) *n_dir = g->n_dir;
+    if (n_visits_total) *n_visits_total = g->n_visits;
+    if (n_wg) *n_wg = variant(g, g->dbl, true, false).n_wg;
+    return RT_OK;
+}
+
+rt_status rt_formal_solution(rt_grid_t g, int32_t n_lambda, const void *chi, const void *S, const void *I_bc,
+                             void *J_out, void *lstar_out, void *stream)
+{
+    if (!g) return fail(RT_E_INVALID, "grid is NULL");
+    if (n_lambda < 0 || n_lambda > g->desc.n_lambda_max)
+        return fail(RT_E_INVALID, "n_lambda %d outside [0, %d]", n_lambda, g->desc.n_lambda_max);
+    if (n_lambda == 0) return RT_OK;
+    if (!chi || !S || !J_out) return fail(RT_E_INVALID, "chi, S and J_out must not be NULL");
+    hipStream_t st = (hipStream_t)stream;
+    const bool dbl = g->dbl;
+    const size_t esz = dbl ? 8 : 4;
+    const size_t padn = (size_t)n_lambda * 4 * g->n_vox;
+    const int Nx = g->geo.Nx, Ny = g->geo.Ny, Nz = g->geo.Nz;
+    HIPCHK(g->fs_chi_pad.ensure(padn * esz));
+    HIPCHK(g->fs_S_pad.ensure(padn * esz));
+    if (dbl) {
+        HIPCHK(pad_field<double, double>((const double *)chi, nullptr, g->fs_chi_pad.as<double>(), Nx, Ny, Nz, n_lambda, st));
+        HIPCHK(pad_field<double, double>((const double *)S, nullptr, g->fs_S_pad.as<double>(), Nx, Ny, Nz, n_lambda, st));
+    } else {
+        HIPCHK(pad_field<float, float>((const float *)chi, nullptr, g->fs_chi_pad.as<float>(), Nx, Ny, Nz, n_lambda, st));
+        HIPCHK(pad_field<float, float>((const float *)S, nullptr, g->fs_S_pad.as<float>(), Nx, Ny, Nz, n_lambda, st));
+    }
+    std::vector<int32_t> lams(n_lambda);
+    for (int i = 0; i < n_lambda; ++i) lams[i] = i;
+    const bool wl = lstar_out != nullptr;
+    DevBuf &pJ = dbl ? g->partJ64 : g->partJ;
+    DevBuf &pL = dbl ? g->partL64 : g->partL;
+    const bool joint = wl && variant(g, dbl, true, true).ok;
+    DevSchedule *sc = nullptr;
+    rt_status rs;
+    if (joint) {
+        rs = run_fs(g, dbl, true, true, lams, g->fs_chi_pad.p, g->fs_S_pad.p, I_bc, pJ, pL, &sc, st);
+        if (rs != RT_OK) return rs;
+    } else {
+        if (wl) {
+            rs = run_fs(g, dbl, false, true, lams, g->fs_chi_pad.p, g->fs_S_pad.p, I_bc, pJ, pL, &sc, st);
+            if (rs != RT_OK) return rs;
+            if (dbl)
+                HIPCHK(reduce_partials<double, double>(pL.as<double>(), sc->slot_begin.as<int32_t>(), sc->slot_ids.as<int32_t>(),
+                                                       sc->lambda_of.as<int32_t>(), n_lambda, (double *)lstar_out, g->n_vox, st));
+            else
+                HIPCHK(reduce_partials<float, float>(pL.as<float>(), sc->slot_begin.as<int32_t>(), sc->slot_ids.as<int32_t>(),
+                                                     sc->lambda_of.as<int32_t>(), n_lambda, (float *)lstar_out, g->n_vox, st));
+        }
+        rs = run_fs(g, dbl, true, false, lams, g->fs_chi_pad.p, g->fs_S_pad.p, I_bc, pJ, pL, &sc, st);
+        if (rs != RT_OK) return rs;
+    }
+    if (dbl) {
+        HIPCHK(reduce_partials<double, double>(pJ.as<double>(), sc->slot_begin.as<int32_t>(), sc->slot_ids.as<int32_t>(),
+                                               sc->lambda_of.as<int32_t>(), n_lambda, (double *)J_out, g->n_vox, st));
+        if (joint)
+            HIPCHK(reduce_partials<double, double>(pL.as<double>(), sc->slot_begin.as<int32_t>(), sc->slot_ids.as<int32_t>(),
+                                                   sc->lambda_of.as<int32_t>(), n_lambda, (double *)lstar_out, g->n_vox, st));
+    } else {
+        HIPCHK(reduce_partials<float, float>(pJ.as<float>(), sc->slot_begin.as<int32_t>(), sc->slot_ids.as<int32_t>(),
+                                             sc->lambda_of.as<int32_t>(), n_lambda, (float *)J_out, g->n_vox, st));
+        if (joint)
+            HIPCHK(reduce_partials<float, float>(pL.as<float>(), sc->slot_begin.as<int32_t>(), sc->slot_ids.as<int32_t>(),
+                                                 sc->lambda_of.as<int32_t>(), n_lambda, (float *)lstar_out, g->n_vox, st));
+    }
+    return RT_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// ALI
+// ---------------------------------------------------------------------------
+static rt_status check_state(rt_grid *g, const rt_state *s)
+{
+    if (!s) return fail(RT_E_INVALID, "state is NULL");
+    if (s->struct_size != sizeof(rt_state)) return fail(RT_E_INVALID, "state->struct_size mismatch");
+    if (s->n_lambda < 1 || s->n_lambda > g->desc.n_lambda_max)
+        return fail(RT_E_INVALID, "state->n_lambda %d outside [1, %d]", s->n_lambda, g->desc.n_lambda_max);
+    if (!s->chi || !s->eps || !s->B || !s->J || !s->S || !s->lstar || !s->rel_change)
+        return fail(RT_E_INVALID, "state arrays chi, eps, B, J, S, lstar, rel_change must not be NULL");
+    if (s->iter < 0) return fail(RT_E_INVALID, "state->iter < 0");
+    return RT_OK;
+}
+
+static rt_status check_opts(const rt_solve_opts *o)
+{
+    if (!o) return fail(RT_E_INVALID, "opts is NULL");
+    if (o->struct_size != sizeof(rt_solve_opts)) return fail(RT_E_INVALID, "opts->struct_size mismatch");
+    if (!(o->tol > 0.0)) return fail(RT_E_INVALID, "opts->tol must be > 0");
+    if (o->max_iter < 1) return fail(RT_E_INVALID, "opts->max_iter must be >= 1");
+    if (o->ng_every < 0 || o->ng_start < 0 || o->reanchor < 0) return fail(RT_E_INVALID, "negative Ng/anchor option");
+    return RT_OK;
+}
+
+// Allocates the per-state buffers (sized for n_lambda_max) once.
+static rt_status ensure_state_buffers(rt_grid *g)
+{
+    const size_t nl = (size_t)g->desc.n_lambda_max;
+    const size_t nv = (size_t)g->n_vox;
+    const size_t esz = g->dbl ? 8 : 4;
+    HIPCHK(g->chi_pad.ensure(nl * 4 * nv * esz));
+    HIPCHK(g->S_pad.ensure(nl * 4 * nv * esz));
+    if (!g->dbl) {
+        HIPCHK(g->chi_pad64.ensure(nl * 4 * nv * 8));
+        HIPCHK(g->S_pad64.ensure(nl * 4 * nv * 8));
+        HIPCHK(g->J_anchor.ensure(nl * nv * 8));
+        HIPCHK(g->S_anchor.ensure(nl * nv * 8));
+        HIPCHK(g->ibc64.ensure(nl * 2 * 8));
+    }
+    HIPCHK(g->hist.ensure(4 * nl * nv * 8));
+    HIPCHK(g->ng_blk.ensure(nl * 256 * 5 * 8));
+    HIPCHK(g->ng_coef.ensure(nl * 3 * 8));
+    return RT_OK;
+}
+
+// One ALI step over the wavelengths in `lams` (all of them must be indices < n_lambda).
+static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o, const std::vector<int32_t> &lams,
+                                bool anchor, hipStream_t st, int *fs_count, int *fs64_count, int *ng_count)
+{
+    const int Nx = g->geo.Nx, Ny = g->geo.Ny, Nz = g->geo.Nz;
+    const int nl = s->n_lambda;
+    const int64_t nv = g->n_vox;
+    const int nb = (int)lams.size();
+    rt_status rs = ensure_state_buffers(g);
+    if (rs != RT_OK) return rs;
+    DevSchedule *lam_sc = nullptr;  // for lambda_of of the batch
+    rs = get_schedule(g, variant(g, g->dbl, true, false).n_wg, lams, &lam_sc);
+    if (rs != RT_OK) return rs;
+    const int32_t *lambda_of = lam_sc->lambda_of.as<int32_t>();
+
+    // (re)initialisation: padded opacity, S from J, fresh Ng history
+    if (s->iter == 0 || s->chi != g->chi_src) {
+        if (g->dbl) {
+            HIPCHK(pad_field<double, double>((const double *)s->chi, nullptr, g->chi_pad.as<double>(), Nx, Ny, Nz, nl, st));
+        } else {
+            HIPCHK(pad_field<float, float>((const float *)s->chi, nullptr, g->chi_pad.as<float>(), Nx, Ny, Nz, nl, st));
+            HIPCHK(pad_field<float, double>((const float *)s->chi, nullptr, g->chi_pad64.as<double>(), Nx, Ny, Nz, nl, st));
+        }
+        g->chi_src = s->chi;
+    }
+    if (s->iter == 0) {
+        g->hist_count = 0;
+        if (g->dbl)
+            HIPCHK(source_update<double, double>(s->J, (const double *)s->eps, (const double *)s->B, s->S, nullptr,
+                                                 g->S_pad.as<double>(), Nx, Ny, nv, lambda_of, nb, st));
+        anchor = true;
+    }
+
+    // Ng extrapolation of the last four iterates, due before this step's formal solution
+    if (o->ng_every > 0 && g->hist_count >= 4 && s->iter >= o->ng_start) {
+        NgApplyArgs na{};
+        na.Nx = Nx; na.Ny = Ny; na.n_vox = nv;
+        na.lambda_of = lambda_of;
+        const size_t hs = (size_t)nl * nv;
+        double *h = g->hist.as<double>();
+        const int c = g->hist_count;  // newest iterate sits in ring slot (c-1) mod 4
+        na.x0 = h + (size_t)((c - 1) % 4) * hs;
+        na.x1 = h + (size_t)((c - 2) % 4) * hs;
+        na.x2 = h + (size_t)((c - 3) % 4) * hs;
+        na.x3 = h + (size_t)((c - 4) % 4) * hs;
+        na.coef = g->ng_coef.as<double>();
+        na.eps = s->eps; na.B = s->B;
+        na.S_anchor = g->dbl ? nullptr : g->S_anchor.as<double>();
+        na.J = s->J; na.S = s->S;
+        na.next_pad = g->S_pad.p;
+        HIPCHK(ng_accelerate(na, g->ng_blk.as<double>(), 256, nb, g->dbl, st));
+        g->hist_count = 0;
+        ++*ng_count;
+    }
+
+    HIPCHK(fill_u64(reinterpret_cast<unsigned long long *>(s->rel_change), 0ull, nl, st));
+    const bool want_l = s->lstar_valid == 0;
+    AliUpdateArgs ua{};
+    ua.Nx = Nx; ua.Ny = Ny; ua.n_vox = nv;
+    ua.lambda_of = lambda_of;
+    ua.eps = s->eps; ua.B = s->B; ua.lstar = s->lstar;
+    ua.J = s->J; ua.S = s->S;
+    ua.hist = g->hist.as<double>() + (size_t)(g->hist_count % 4) * nl * nv;
+    ua.rel_change = s->rel_change;
+    ua.next_pad = g->S_pad.p;
+    DevSchedule *sc = nullptr;
+
+    if (g->dbl) {
+        const bool joint = want_l && variant(g, true, true, true).ok;
+        if (want_l && !joint) {
+            rs = run_fs(g, true, false, true, lams, g->chi_pad.p, g->S_pad.p, s->I_bc, g->partJ64, g->partL64, &sc, st);
+            if (rs != RT_OK) return rs;
+            HIPCHK(reduce_partials<double, double>(g->partL64.as<double>(), sc->slot_begin.as<int32_t>(), sc->slot_ids.as<int32_t>(),
+                                                   sc->lambda_of.as<int32_t>(), nb, (double *)s->lstar, nv, st));
+            ++*fs_count; ++*fs64_count;
+        }
+        rs = run_fs(g, true, true, joint, lams, g->chi_pad.p, g->S_pad.p, s->I_bc, g->partJ64, g->partL64, &sc, st);
+        if (rs != RT_OK) return rs;
+        ++*fs_count; ++*fs64_count;
+        if (joint)
+            HIPCHK(reduce_partials<double, double>(g->partL64.as<double>(), sc->slot_begin.as<int32_t>(), sc->slot_ids.as<int32_t>(),
+                                                   sc->lambda_of.as<int32_t>(), nb, (double *)s->lstar, nv, st));
+        ua.part = g->partJ64.p;
+        ua.slot_begin = sc->slot_begin.as<int32_t>();
+        ua.slot_ids = sc->slot_ids.as<int32_t>();
+        HIPCHK(ali_update(ua, true, true, true, nb, st));
+    } else {
+        if (want_l) {
+            rs = run_fs(g, false, false, true, lams, g->chi_pad.p, g->S_pad.p, nullptr, g->partJ, g->partL, &sc, st);
+            if (rs != RT_OK) return rs;
+            HIPCHK(reduce_partials<float, float>(g->partL.as<float>(), sc->slot_begin.as<int32_t>(), sc->slot_ids.as<int32_t>(),
+                                                 sc->lambda_of.as<int32_t>(), nb, (float *)s->lstar, nv, st));
+            ++*fs_count;
+        }
+        ua.S_anchor = g->S_anchor.as<double>();
+        ua.J_anchor = g->J_anchor.as<double>();
+        if (anchor) {
+            // double-precision anchor: S_a = S, J_a = Lambda S_a + Lambda_bc
+            if (s->iter == 0)
+                HIPCHK(source_update<float, double>(s->J, (const float *)s->eps, (const float *)s->B, s->S, nullptr,
+                                                    g->S_pad64.as<double>(), Nx, Ny, nv, lambda_of, nb, st));
+            else
+                HIPCHK(pad_field<double, double>(s->S, nullptr, g->S_pad64.as<double>(), Nx, Ny, Nz, nl, st));
+            HIPCHK(hipMemcpyAsync(g->S_anchor.p, s->S, (size_t)nl * nv * 8, hipMemcpyDeviceToDevice, st));
+            const void *ibc = nullptr;
+            if (s->I_bc) {
+                HIPCHK(cast_array<float, double>((const float *)s->I_bc, g->ibc64.as<double>(), 2 * (int64_t)nl, st));
+                ibc = g->ibc64.p;
+            }
+            rs = run_fs(g, true, true, false, lams, g->chi_pad64.p, g->S_pad64.p, ibc, g->partJ64, g->partL64, &sc, st);
+            if (rs != RT_OK) return rs;
+            HIPCHK(reduce_partials<double, double>(g->partJ64.as<double>(), sc->slot_begin.as<int32_t>(), sc->slot_ids.as<int32_t>(),
+                                                   sc->lambda_of.as<int32_t>(), nb, g->J_anchor.as<double>(), nv, st));
+            ++*fs_count; ++*fs64_count;
+            ua.part = nullptr;
+            ua.slot_begin = sc->slot_begin.as<int32_t>();
+            ua.slot_ids = sc->slot_ids.as<int32_t>();
+            HIPCHK(ali_update(ua, false, false, false, nb, st));
+        } else {
+            rs = run_fs(g, false, true, false, lams, g->chi_pad.p, g->S_pad.p, nullptr, g->partJ, g->partL, &sc, st);
+            if (rs != RT_OK) return rs;
+            ++*fs_count;
+            ua.part = g->partJ.p;
+            ua.slot_begin = sc->slot_begin.as<int32_t>();
+            ua.slot_ids = sc->slot_ids.as<int32_t>();
+            HIPCHK(ali_update(ua, false, false, false, nb, st));
+        }
+    }
+    s->lstar_valid = 1;
+    g->hist_count++;
+    s->iter++;
+    return RT_OK;
+}
+
+extern "C" {
+
+rt_status rt_ali_step(rt_grid_t g, rt_state *s, const rt_solve_opts *o, void *stream)
+{
+    if (!g) return fail(RT_E_INVALID, "grid is NULL");
+    rt_status rs = check_state(g, s);
+    if (rs != RT_OK) return rs;
+    rs = check_opts(o);
+    if (rs != RT_OK) return rs;
+    std::vector<int32_t> lams(s->n_lambda);
+    for (int i = 0; i < s->n_lambda; ++i) lams[i] = i;
+    int nfs = 0, nfs64 = 0, nng = 0;
+    return ali_step_batch(g, s, o, lams, false, (hipStream_t)stream, &nfs, &nfs64, &nng);
+}
+
+rt_status rt_solve(rt_grid_t g, rt_state *s, const rt_solve_opts *o, rt_solve_report *rep, void *stream)
+{
+    if (!g) return fail(RT_E_INVALID, "grid is NULL");
+    rt_status rs = check_state(g, s);
+    if (rs != RT_OK) return rs;
+    rs = check_opts(o);
+    if (rs != RT_OK) return rs;
+    hipStream_t st = (hipStream_t)stream;
+    const auto t0 = std::chrono::steady_clock::now();
+    rt_solve_report r{};
+    const int nl = s->n_lambda;
+    std::vector<int32_t> active(nl);
+    for (int i = 0; i < nl; ++i) active[i] = i;
+    std::vector<double> rel(nl, 0.0);
+    const double refac = o->reanchor > 0 ? (double)o->reanchor : 100.0;
+    double rel_at_anchor = 1e300;
+    bool anchor_next = true;
+    rt_status out = RT_E_NOT_CONVERGED;
+    for (int it = 0; it < o->max_iter; ++it) {
+        const bool anchor = !g->dbl && (anchor_next || s->iter == 0);
+        rs = ali_step_batch(g, s, o, active, anchor, st, &r.n_fs, &r.n_fs64, &r.n_ng);
+        if (rs != RT_OK) return rs;
+        HIPCHK(hipMemcpyAsync(rel.data(), s->rel_change, nl * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        r.iters++;
+        double mx = 0.0;
+        std::vector<int32_t> still;
+        for (int l : active) {
+            if (!(rel[l] <= 1e308)) {
+                r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+                if (rep) *rep = r;
+                return fail(RT_E_NUMERIC, "non-finite J in wavelength %d at step %d", l, s->iter);
+            }
+            if (rel[l] >= o->tol) still.push_back(l);
+            mx = rel[l] > mx ? rel[l] : mx;
+        }
+        r.max_rel_change = mx;
+        if (anchor) rel_at_anchor = mx;
+        anchor_next = !g->dbl && mx < rel_at_anchor / refac;
+        active.swap(still);
+        if (active.empty()) { out = RT_OK; break; }
+    }
+    r.n_converged = nl - (int)active.size();
+    r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (rep) *rep = r;
+    if (out != RT_OK) return fail(RT_E_NOT_CONVERGED, "%d of %d wavelengths not converged after %d steps",
+                                  (int)active.size(), nl, o->max_iter);
+    g_err.clear();
+    return RT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+// schedule.cpp -- static distribution of formal-solution work over the
+// persistent workgroups of one launch.
+//
+// A work item is (wavelength, direction): all characteristics of that
+// direction for that wavelength, swept through the grid by one workgroup.
+// Its cost is the template length M_d (visits per characteristic), which
+// varies by ~10x between steep and shallow directions (the load imbalance the
+// paper reports for the periodic box, Sec. 4.1).  Each workgroup writes its
+// J / Lambda* contributions into partial-sum slots that only it owns; the
+// reduction adds the slots of a wavelength in a fixed order, so results do
+// not depend on timing.
+//
+// * batch <= workgroups: every wavelength gets its own group of workgroups
+//   (sizes differ by at most one) and its directions are spread over them by
+//   longest-processing-time-first; one slot per workgroup.
+// * batch >  workgroups: items are laid out wavelength-major and cut into
+//   n_wg contiguous runs of equal cost; a workgroup opens a new slot whenever
+//   its run enters a new wavelength.
+#include <algorithm>
+#include <numeric>
+#include <queue>
+
+#include "rt_internal.hpp"
+
+namespace rt3d {
+
+void build_schedule(const BoxGeometry &g, const std::vector<int32_t> &lambdas, int n_wg, Schedule &out)
+{
+    out = Schedule();
+    const int nl = (int)lambdas.size();
+    const int nd = (int)g.dirs.size();
+    out.slot_begin.assign(nl + 1, 0);
+    if (nl == 0 || nd == 0 || n_wg <= 0) {
+        out.n_wg = 0;
+        out.wg_begin.assign(1, 0);
+        return;
+    }
+    std::vector<int> order(nd);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return g.dirs[a].M > g.dirs[b].M; });
+
+    std::vector<std::vector<WorkItem>> per_wg;
+    std::vector<std::vector<int32_t>> slots_of_lambda(nl);
+
+    if (nl <= n_wg) {
+        // workgroups per wavelength: as even as possible, but never more than directions
+        std::vector<int> cnt(nl, n_wg / nl);
+        for (int i = 0; i < n_wg % nl; ++i) cnt[i]++;
+        for (int i = 0; i < nl; ++i) cnt[i] = std::max(1, std::min(cnt[i], nd));
+        int slot = 0;
+        for (int li = 0; li < nl; ++li) {
+            const int k = cnt[li];
+            // LPT: longest direction to the least loaded workgroup of this wavelength
+            using P = std::pair<int64_t, int>;  // (load, local wg), min-heap
+            std::priority_queue<P, std::vector<P>, std::greater<P>> heap;
+            std::vector<std::vector<WorkItem>> local(k);
+            for (int w = 0; w < k; ++w) heap.push({0, w});
+            for (int di : order) {
+                P top = heap.top();
+                heap.pop();
+                local[top.second].push_back({lambdas[li], di, 0, 0});
+                heap.push({top.first + g.dirs[di].M, top.second});
+            }
+            for (int w = 0; w < k; ++w) {
+                if (local[w].empty()) continue;
+                for (auto &it : local[w]) it.slot = slot;
+                local[w][0].first = 1;
+                slots_of_lambda[li].push_back(slot);
+                ++slot;
+                per_wg.push_back(std::move(local[w]));
+            }
+        }
+        out.n_slots = slot;
+    } else {
+        // contiguous equal-cost runs over the wavelength-major item list
+        const int64_t per_lambda = std::accumulate(g.dirs.begin(), g.dirs.end(), (int64_t)0,
+                                                   [](int64_t a, const Direction &d) { return a + d.M; });
+        const int64_t total = per_lambda * nl;
+        int slot = 0;
+        int64_t acc = 0;
+        int wg = 0;
+        per_wg.emplace_back();
+        int cur_lambda = -1;
+        for (int li = 0; li < nl; ++li) {
+            for (int di : order) {
+                // move to the next workgroup once this one has its share
+                const int64_t target = (total * (wg + 1)) / n_wg;
+                if (acc >= target && wg + 1 < n_wg && !per_wg.back().empty()) {
+                    per_wg.emplace_back();
+                    ++wg;
+                    cur_lambda = -1;
+                }
+                if (cur_lambda != li) {
+                    slots_of_lambda[li].push_back(slot);
+                    per_wg.back().push_back({lambdas[li], di, slot, 1});
+                    ++slot;
+                    cur_lambda = li;
+                } else {
+                    per_wg.back().push_back({lambdas[li], di, slot - 1, 0});
+                }
+                acc += g.dirs[di].M;
+            }
+        }
+        out.n_slots = slot;
+    }
+    out.n_wg = (int)per_wg.size();
+    out.wg_begin.assign(out.n_wg + 1, 0);
+    for (int w = 0; w < out.n_wg; ++w) {
+        out.wg_begin[w + 1] = out.wg_begin[w] + (int32_t)per_wg[w].size();
+        out.items.insert(out.items.end(), per_wg[w].begin(), per_wg[w].end());
+    }
+    for (int li = 0; li < nl; ++li) {
+        out.slot_begin[li + 1] = out.slot_begin[li] + (int32_t)slots_of_lambda[li].size();
+        out.slot_ids.insert(out.slot_ids.end(), slots_of_lambda[li].begin(), slots_of_lambda[li].end());
+    }
+}
+
+}  // namespace rt3d

@@ -1,0 +1,268 @@
+"""ctypes binding of the rt3d C ABI (include/rt3d.h).
+
+Argument marshalling only: every computation runs in the HIP library.  The
+functions carry the C names; ``Grid`` is a small convenience wrapper that
+takes torch tensors (device memory) and the current torch stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librt3d.so")
+
+RT_OK, RT_E_INVALID, RT_E_NOMEM, RT_E_HIP, RT_E_NOT_CONVERGED, RT_E_NUMERIC, RT_E_UNSUPPORTED = range(7)
+RT_GEOM_BOX_PERIODIC_XY, RT_GEOM_SPHERICAL = 0, 1
+RT_FP64, RT_FP32 = 0, 1
+RT_F_LSTAR_PARABOLIC = 0x1
+
+STATUS_NAMES = {0: "RT_OK", 1: "RT_E_INVALID", 2: "RT_E_NOMEM", 3: "RT_E_HIP", 4: "RT_E_NOT_CONVERGED",
+                5: "RT_E_NUMERIC", 6: "RT_E_UNSUPPORTED"}
+
+
+class RtGridDesc(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("geom", ctypes.c_int32), ("n", ctypes.c_int32 * 3),
+                ("h", ctypes.c_double * 3), ("n_mu", ctypes.c_int32), ("n_phi", ctypes.c_int32),
+                ("n_lambda_max", ctypes.c_int32), ("prec", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class RtState(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("n_lambda", ctypes.c_int32), ("chi", ctypes.c_void_p),
+                ("eps", ctypes.c_void_p), ("B", ctypes.c_void_p), ("I_bc", ctypes.c_void_p),
+                ("J", ctypes.c_void_p), ("S", ctypes.c_void_p), ("lstar", ctypes.c_void_p),
+                ("lstar_valid", ctypes.c_int32), ("iter", ctypes.c_int32), ("rel_change", ctypes.c_void_p)]
+
+
+class RtSolveOpts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("ng_every", ctypes.c_int32), ("ng_start", ctypes.c_int32), ("reanchor", ctypes.c_int32)]
+
+
+class RtSolveReport(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("n_fs", ctypes.c_int32), ("n_fs64", ctypes.c_int32),
+                ("n_ng", ctypes.c_int32), ("n_converged", ctypes.c_int32), ("max_rel_change", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+
+class RtError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Loads librt3d.so from the package directory; raises if it was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"rt3d HIP library not built: {LIB_PATH} is missing "
+                          "(run __graft_entry__.build() or python paper_2102_01734_amd/build.py)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64p = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)
+    L.rt_create_grid.argtypes = [ctypes.POINTER(RtGridDesc), ctypes.POINTER(vp)]
+    L.rt_destroy_grid.argtypes = [vp]
+    L.rt_grid_info.argtypes = [vp, i64p, ctypes.POINTER(i32), i64p, ctypes.POINTER(i32)]
+    L.rt_formal_solution.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+    L.rt_ali_step.argtypes = [vp, ctypes.POINTER(RtState), ctypes.POINTER(RtSolveOpts), vp]
+    L.rt_solve.argtypes = [vp, ctypes.POINTER(RtState), ctypes.POINTER(RtSolveOpts),
+                           ctypes.POINTER(RtSolveReport), vp]
+    for f in ("rt_create_grid", "rt_destroy_grid", "rt_grid_info", "rt_formal_solution", "rt_ali_step", "rt_solve"):
+        getattr(L, f).restype = ctypes.c_int
+    ip, dp = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)
+    L.rt_box_template.argtypes = [i32, i32, i32, i32, i32, ip, ip, ip, dp, ip]
+    L.rt_box_template.restype = ctypes.c_int
+    L.rt_last_error.restype = ctypes.c_char_p
+    L.rt_last_error.argtypes = []
+    L.rt_version.restype = ctypes.c_char_p
+    L.rt_version.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(status: int, where: str, allow=()):
+    if status != RT_OK and status not in allow:
+        raise RtError(status, where, rt_last_error())
+    return status
+
+
+# ---------------------------------------------------------------------------
+# the C entry points, same names
+# ---------------------------------------------------------------------------
+def rt_last_error() -> str:
+    return lib().rt_last_error().decode()
+
+
+def rt_version() -> str:
+    return lib().rt_version().decode()
+
+
+def rt_create_grid(desc: RtGridDesc) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().rt_create_grid(ctypes.byref(desc), ctypes.byref(h)), "rt_create_grid")
+    return h.value
+
+
+def rt_destroy_grid(grid: int) -> None:
+    _check(lib().rt_destroy_grid(ctypes.c_void_p(grid)), "rt_destroy_grid")
+
+
+def rt_grid_info(grid: int):
+    nv, nvis = ctypes.c_int64(), ctypes.c_int64()
+    nd, nwg = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().rt_grid_info(ctypes.c_void_p(grid), ctypes.byref(nv), ctypes.byref(nd), ctypes.byref(nvis),
+                              ctypes.byref(nwg)), "rt_grid_info")
+    return dict(n_vox=nv.value, n_dir=nd.value, n_visits=nvis.value, n_workgroups=nwg.value)
+
+
+def rt_formal_solution(grid: int, n_lambda: int, chi: int, S: int, I_bc: Optional[int], J_out: int,
+                       lstar_out: Optional[int], stream: Optional[int]) -> None:
+    _check(lib().rt_formal_solution(ctypes.c_void_p(grid), int(n_lambda), ctypes.c_void_p(chi), ctypes.c_void_p(S),
+                                    ctypes.c_void_p(I_bc or None), ctypes.c_void_p(J_out),
+                                    ctypes.c_void_p(lstar_out or None), ctypes.c_void_p(stream or None)),
+           "rt_formal_solution")
+
+
+def rt_ali_step(grid: int, state: RtState, opts: RtSolveOpts, stream: Optional[int]) -> None:
+    _check(lib().rt_ali_step(ctypes.c_void_p(grid), ctypes.byref(state), ctypes.byref(opts),
+                             ctypes.c_void_p(stream or None)), "rt_ali_step")
+
+
+def rt_solve(grid: int, state: RtState, opts: RtSolveOpts, stream: Optional[int]) -> tuple[int, RtSolveReport]:
+    rep = RtSolveReport()
+    st = _check(lib().rt_solve(ctypes.c_void_p(grid), ctypes.byref(state), ctypes.byref(opts), ctypes.byref(rep),
+                               ctypes.c_void_p(stream or None)), "rt_solve", allow=(RT_E_NOT_CONVERGED,))
+    return st, rep
+
+
+def rt_box_template(Nz: int, n_mu: int, n_phi: int, d: int):
+    """Host tracker output of direction d: dict of numpy arrays di, dj, kk, s."""
+    import numpy as np
+    M = ctypes.c_int32()
+    _check(lib().rt_box_template(Nz, n_mu, n_phi, d, 0, None, None, None, None, ctypes.byref(M)), "rt_box_template")
+    n = M.value
+    di = np.zeros(n, np.int32); dj = np.zeros(n, np.int32); kk = np.zeros(n, np.int32); s = np.zeros(n)
+    ip, dp = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)
+    _check(lib().rt_box_template(Nz, n_mu, n_phi, d, n, di.ctypes.data_as(ip), dj.ctypes.data_as(ip),
+                                 kk.ctypes.data_as(ip), s.ctypes.data_as(dp), ctypes.byref(M)), "rt_box_template")
+    return dict(di=di, dj=dj, kk=kk, s=s)
+
+
+# ---------------------------------------------------------------------------
+# torch-facing convenience wrapper
+# ---------------------------------------------------------------------------
+def _stream_ptr(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream or None
+
+
+class Grid:
+    """A library grid handle.  Fields are torch tensors on the GPU, shaped
+    (n_lambda, Nz, Ny, Nx), of dtype float32 (prec "f32") or float64 ("f64")."""
+
+    def __init__(self, Nx: int, Ny: int, Nz: int, n_mu: int, n_phi: int, prec: str = "f32",
+                 n_lambda_max: int = 1, lstar: str = "linear"):
+        d = RtGridDesc()
+        d.struct_size = ctypes.sizeof(RtGridDesc)
+        d.geom = RT_GEOM_BOX_PERIODIC_XY
+        d.n[0], d.n[1], d.n[2] = Nx, Ny, Nz
+        d.n_mu, d.n_phi = n_mu, n_phi
+        d.n_lambda_max = n_lambda_max
+        d.prec = RT_FP32 if prec == "f32" else RT_FP64
+        d.flags = RT_F_LSTAR_PARABOLIC if lstar == "parabolic" else 0
+        self.desc = d
+        self.shape = (Nz, Ny, Nx)
+        self.prec = prec
+        self.n_lambda_max = n_lambda_max
+        self.handle = rt_create_grid(d)
+
+    @property
+    def dtype(self):
+        import torch
+        return torch.float32 if self.prec == "f32" else torch.float64
+
+    def info(self):
+        return rt_grid_info(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            rt_destroy_grid(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check_field(self, t, n_lambda, name, dtype=None):
+        import torch
+        dtype = dtype or self.dtype
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise ValueError(f"{name} must be a CUDA tensor")
+        if t.dtype != dtype or not t.is_contiguous() or tuple(t.shape) != (n_lambda, *self.shape):
+            raise ValueError(f"{name} must be contiguous {dtype} of shape {(n_lambda, *self.shape)}")
+        return t.data_ptr()
+
+    def formal_solution(self, chi, S, I_bc=None, want_lstar=False, stream=None, out=None):
+        import torch
+        n = chi.shape[0]
+        pc = self._check_field(chi, n, "chi")
+        ps = self._check_field(S, n, "S")
+        pb = None
+        if I_bc is not None:
+            if I_bc.dtype != self.dtype or tuple(I_bc.shape) != (n, 2) or not I_bc.is_contiguous():
+                raise ValueError("I_bc must be contiguous (n_lambda, 2) of the grid dtype")
+            pb = I_bc.data_ptr()
+        J = out if out is not None else torch.empty_like(chi)
+        L = torch.empty_like(chi) if want_lstar else None
+        rt_formal_solution(self.handle, n, pc, ps, pb, J.data_ptr(), L.data_ptr() if L is not None else None,
+                           _stream_ptr(stream))
+        return J, L
+
+    def new_state(self, chi, eps, B, I_bc=None, J0=None):
+        """Allocates the ALI state (J, S, Lambda*, norms) for a batch; J starts at B."""
+        import torch
+        n = chi.shape[0]
+        st = RtState()
+        st.struct_size = ctypes.sizeof(RtState)
+        st.n_lambda = n
+        st.chi = self._check_field(chi, n, "chi")
+        st.eps = self._check_field(eps, n, "eps")
+        st.B = self._check_field(B, n, "B")
+        st.I_bc = I_bc.data_ptr() if I_bc is not None else None
+        J = (B.double() if J0 is None else J0.double()).contiguous().clone()
+        S = torch.empty_like(J)
+        L = torch.empty_like(chi)
+        rel = torch.zeros(n, dtype=torch.float64, device=chi.device)
+        st.J, st.S, st.lstar, st.rel_change = J.data_ptr(), S.data_ptr(), L.data_ptr(), rel.data_ptr()
+        st.lstar_valid = 0
+        st.iter = 0
+        # keep the tensors alive with the state
+        st._keep = (chi, eps, B, I_bc, J, S, L, rel)
+        return st
+
+    @staticmethod
+    def opts(tol=1e-8, max_iter=1000, ng_every=4, ng_start=4, reanchor=0):
+        o = RtSolveOpts()
+        o.struct_size = ctypes.sizeof(RtSolveOpts)
+        o.tol, o.max_iter, o.ng_every, o.ng_start, o.reanchor = tol, max_iter, ng_every, ng_start, reanchor
+        return o
+
+    def ali_step(self, state: RtState, opts: RtSolveOpts, stream=None):
+        rt_ali_step(self.handle, state, opts, _stream_ptr(stream))
+
+    def solve(self, state: RtState, opts: RtSolveOpts, stream=None):
+        return rt_solve(self.handle, state, opts, _stream_ptr(stream))
+
+    @staticmethod
+    def state_tensors(state: RtState):
+        chi, eps, B, I_bc, J, S, L, rel = state._keep
+        return dict(J=J, S=S, lstar=L, rel_change=rel)

@@ -58,7 +58,7 @@ def gaussian_random_field(Nz: int, Ny: int, Nx: int, ell: float, seed: int) -> n
     ky = np.fft.fft(kern1d(Ny))[None, :, None]
     kx = np.fft.rfft(kern1d(Nx))[None, None, :]
     F = np.fft.rfftn(noise) * kz * ky * kx
-    g = np.fft.irfftn(F, s=noise.shape)[:Nz]
+    g = np.fft.irfftn(F, s=noise.shape, axes=(0, 1, 2))[:Nz]
     g = g - g.mean()
     g = g / g.std()
     return g

@@ -1,0 +1,149 @@
+"""Parity of the HIP formal solution (rt_formal_solution) with the oracle.
+
+Tolerances:
+* double-precision grids: the kernel and the oracle take identical optical
+  steps and identical fallback decisions; they differ only in how exp and the
+  weights are rounded (a few ulp per point), so J and Lambda* agree to 1e-12.
+* single-precision grids: the recurrence and the J accumulation are float;
+  per point the intensity picks up a relative error of a few 2^-24 and the
+  attenuation damps older errors, so J stays within ~1e-6 of the double
+  result; the tests allow 2e-5 relative (plus 1e-6 of max|J| absolute).
+"""
+import numpy as np
+import pytest
+
+import synthetic as sy
+from tests.gpu_helpers import gpu_fs, make_grid, to_dev, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_fs(orc, case, S, kind):
+    Js, Ls = [], []
+    for l in range(case.n_lambda):
+        J, L = orc.fs_box(case.chi[l], S[l], case.I_bc[l, 0], case.I_bc[l, 1], case.n_mu, case.n_phi, kind=kind)
+        Js.append(J); Ls.append(L)
+    return np.array(Js), np.array(Ls)
+
+
+SHAPES = [  # (Nx, Ny, Nz, n_mu, n_phi): ragged sizes, several workgroups, one voxel column
+    (7, 5, 6, 4, 8),
+    (17, 13, 9, 4, 8),
+    (33, 33, 12, 8, 16),
+    (9, 9, 1, 2, 4),
+    (1, 1, 7, 4, 4),
+    (70, 3, 5, 4, 8),
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("kind", ["linear", "parabolic"])
+def test_fs_fp64_matches_oracle(orc, shape, kind):
+    Nx, Ny, Nz, n_mu, n_phi = shape
+    print(f"fs fp64 {shape} {kind}", flush=True)
+    case = sy.random_box(Nx, Ny, Nz, n_mu, n_phi, seed=Nx * 7 + Nz, dtype="f64")
+    S = sy.random_source(case.chi.shape, seed=3)
+    J, L = gpu_fs(case, S, lstar=kind)
+    Jo, Lo = _oracle_fs(orc, case, S, kind)
+    np.testing.assert_allclose(J, Jo, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(L, Lo, rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("shape", SHAPES[:4])
+def test_fs_fp32_matches_oracle(orc, shape):
+    Nx, Ny, Nz, n_mu, n_phi = shape
+    print(f"fs fp32 {shape}", flush=True)
+    case = sy.random_box(Nx, Ny, Nz, n_mu, n_phi, seed=Nx + 100 * Nz, dtype="f32")
+    S = sy.random_source(case.chi.shape, seed=4, dtype="f32")
+    J, L = gpu_fs(case, S)
+    Jo, Lo = _oracle_fs(orc, case, S, "linear")
+    np.testing.assert_allclose(J, Jo, rtol=2e-5, atol=1e-6 * np.abs(Jo).max())
+    np.testing.assert_allclose(L, Lo, rtol=2e-5, atol=1e-7)
+
+
+def test_fs_vacuum_and_opaque_voxels(orc):
+    """chi = 0 (vacuum: no change of I) and very opaque voxels side by side."""
+    case = sy.random_box(11, 9, 8, 4, 8, seed=5, dtype="f64")
+    rng = np.random.default_rng(0)
+    mask = rng.random(case.chi.shape) < 0.2
+    case.chi[mask] = 0.0
+    case.chi[rng.random(case.chi.shape) < 0.1] = 1e6
+    S = sy.random_source(case.chi.shape, seed=6)
+    J, L = gpu_fs(case, S, lstar="parabolic")
+    Jo, Lo = _oracle_fs(orc, case, S, "parabolic")
+    np.testing.assert_allclose(J, Jo, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(L, Lo, rtol=1e-12, atol=1e-14)
+
+
+def test_fs_stratified_slab_fp64(orc):
+    """The 33^3 stratified slab (tau 1e-4..1e4, 8x16 directions): J equals the
+    oracle's layer reduction in every column."""
+    case = sy.box_stratified()
+    S = np.broadcast_to(np.linspace(0.1, 1.0, case.Nz)[None, :, None, None], case.chi.shape).copy()
+    J, L = gpu_fs(case, S)
+    J1, L1 = orc.fs_1d(case.chi[0, :, 0, 0], S[0, :, 0, 0], 0.0, 1.0, case.n_mu, case.n_phi)
+    np.testing.assert_allclose(J[0], np.broadcast_to(J1[:, None, None], J[0].shape), rtol=1e-12)
+    np.testing.assert_allclose(L[0], np.broadcast_to(L1[:, None, None], L[0].shape), rtol=1e-12)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_fs_batch_equals_single_wavelengths_bitwise(prec):
+    case = sy.random_box(13, 11, 7, 4, 8, seed=9, dtype=prec, n_lambda=3)
+    S = sy.random_source(case.chi.shape, seed=10, dtype=prec)
+    Jb, Lb = gpu_fs(case, S)
+    for l in range(3):
+        one = sy.random_box(13, 11, 7, 4, 8, seed=9, dtype=prec, n_lambda=3)
+        one.chi, one.I_bc = case.chi[l:l + 1], case.I_bc[l:l + 1]
+        one.eps, one.B = case.eps[l:l + 1], case.B[l:l + 1]
+        J1, L1 = gpu_fs(one, S[l:l + 1])
+        assert np.array_equal(J1[0], Jb[l])
+        assert np.array_equal(L1[0], Lb[l])
+
+
+def test_fs_deterministic():
+    case = sy.random_box(33, 33, 16, 8, 16, seed=11, dtype="f32")
+    S = sy.random_source(case.chi.shape, seed=12, dtype="f32")
+    g = make_grid(case)
+    a = gpu_fs(case, S, grid=g)
+    b = gpu_fs(case, S, grid=g)
+    g.close()
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_fs_zero_wavelengths_and_invalid_arguments():
+    import paper_2102_01734_amd as rt
+    torch = torch_cuda()
+    case = sy.random_box(5, 5, 5, 4, 8, seed=1, dtype="f32")
+    g = make_grid(case)
+    chi = to_dev(case.chi, "f32")
+    J = torch.zeros_like(chi)
+    rt.rt_formal_solution(g.handle, 0, chi.data_ptr(), chi.data_ptr(), None, J.data_ptr(), None, None)
+    assert float(J.abs().max()) == 0.0
+    with pytest.raises(rt.RtError) as e:
+        rt.rt_formal_solution(g.handle, 2, chi.data_ptr(), chi.data_ptr(), None, J.data_ptr(), None, None)
+    assert e.value.status == rt.rt3d.RT_E_INVALID
+    with pytest.raises(rt.RtError):
+        rt.rt_formal_solution(g.handle, 1, None, chi.data_ptr(), None, J.data_ptr(), None, None)
+    g.close()
+    with pytest.raises(rt.RtError):
+        rt.Grid(5, 5, 5, 3, 8)          # odd n_mu
+    with pytest.raises(rt.RtError):
+        rt.Grid(0, 5, 5, 4, 8)
+
+
+def test_fs_full_size_lognormal_sampled(orc):
+    """129^3 box, 32x64 directions, log-normal opacity, single precision: the
+    launch the benchmark times, checked at sampled voxels computed one by one
+    by the oracle."""
+    case = sy.box_lognormal()
+    S = sy.random_source(case.chi.shape, seed=77, lo=0.2, hi=1.0, dtype="f32")
+    print("fs full-size 129^3 x 2048 f32", flush=True)
+    J, L = gpu_fs(case, S)
+    rng = np.random.default_rng(5)
+    n = case.n_vox
+    vox = np.unique(np.concatenate([[0, n - 1, case.Nx * case.Ny - 1, n - case.Nx * case.Ny],
+                                    rng.integers(0, n, 20)]))
+    Jo, Lo = orc.fs_box_sampled(case.chi[0], S[0], case.I_bc[0, 0], case.I_bc[0, 1], case.n_mu, case.n_phi, vox)
+    np.testing.assert_allclose(J[0].ravel()[vox], Jo, rtol=2e-5, atol=1e-6 * np.abs(Jo).max())
+    np.testing.assert_allclose(L[0].ravel()[vox], Lo, rtol=2e-5, atol=1e-7)
+    assert np.all(np.isfinite(J)) and np.all((L > 0) & (L < 1))
