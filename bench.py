@@ -1,0 +1,182 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the radiative-transfer hot path on one MI355X.
+
+One step = one operator-splitting (ALI) iteration through the C ABI
+(rt_ali_step): single-precision formal solution of all 2048 directions on the
+129^3 periodic box with log-normal opacity, the fixed-order reduction of the
+workgroup partial sums, the operator-splitting update of J and S, the
+per-wavelength convergence norm, and Ng extrapolation every fourth step.
+The metric is voxel-direction updates per second (VDU/s): voxels x directions
+x wavelengths of one formal solution, divided by the time of one step.
+
+Prints one JSON line (see the design doc for the roofline and baseline definitions).
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic floating-point operations of one characteristic point (one
+# voxel visit of one ray): optical step 3, exp 1, moments 5, reciprocal of
+# D D'(D+D') 4, alpha 7, beta 4, gamma 4, intensity update 8 (4 FMA), J 2.
+FLOPS_PER_POINT = 38
+# Non-packed vector issue rate of MI355X: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
+# = 39.3e12 lane-ops/s, i.e. 78.6 TFLOP/s counting an FMA as 2 (the FP64
+# vector peak; non-packed FP32 issues at the same rate).
+PEAK_TFLOPS = 78.6
+
+WORKLOADS = {
+    "lognormal129": dict(N=129, n_mu=32, n_phi=64),
+    "lognormal65": dict(N=65, n_mu=16, n_phi=32),
+}
+
+
+def fs_source_hash() -> str:
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2102_01734_amd", "csrc", "fs_box.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(workload: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"fs_box_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_hash = re.search(r"fs_box\.hip sha256\[:16\]:\s*([0-9a-f]+)", txt)
+    m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m_hash or not m_bytes or m_hash.group(1) != fs_source_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
+def cpu_baseline(case, n_sub: int):
+    """The oracle, as it stands, on a bounded sample: all voxels, n_sub of the
+    directions spread over the sphere, all host threads."""
+    import numpy as np
+
+    import oracle
+    import synthetic as sy
+    nd = case.n_dir
+    dirs = np.unique(np.linspace(0, nd - 1, n_sub).round().astype(np.int32))
+    S = sy.random_source(case.chi.shape, seed=7, lo=0.2, hi=1.0, dtype="f32")[0]
+    threads = oracle.default_threads()
+    oracle.fs_box_dirs(case.chi[0][:2], S[:2], 0.0, 1.0, case.n_mu, case.n_phi, dirs[:1], threads=threads)
+    t0 = time.perf_counter()
+    oracle.fs_box_dirs(case.chi[0], S, case.I_bc[0, 0], case.I_bc[0, 1], case.n_mu, case.n_phi, dirs,
+                       threads=threads)
+    wall = time.perf_counter() - t0
+    vdu = case.n_vox * dirs.size
+    return {"value": vdu / wall, "unit": "VDU/s", "cores": threads, "kind": "oracle",
+            "sample": f"one FP64 formal solution of {dirs.size} of the {nd} directions over all "
+                      f"{case.n_vox} voxels ({wall:.1f} s wall)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="lognormal129", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-dirs", type=int, default=24, help="directions in the CPU-baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU; --gpus must be 1 "
+              "(multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2102_01734_amd as rt
+    import synthetic as sy
+
+    w = WORKLOADS[args.workload]
+    case = sy.box_lognormal(N=w["N"], n_mu=w["n_mu"], n_phi=w["n_phi"])
+    dev = dict(dtype=torch.float32, device="cuda")
+    chi = torch.tensor(case.chi, **dev)
+    eps = torch.tensor(case.eps, **dev)
+    B = torch.tensor(case.B, **dev)
+    Ibc = torch.tensor(case.I_bc, **dev)
+    g = rt.Grid(case.Nx, case.Ny, case.Nz, case.n_mu, case.n_phi, "f32", 1)
+    info = g.info()
+    st = g.new_state(chi, eps, B, Ibc)
+    opts = g.opts(tol=1e-30, max_iter=1, ng_every=4, ng_start=4)
+
+    for _ in range(args.warmup):
+        g.ali_step(st, opts)
+    torch.cuda.synchronize()
+    rt.rt_profile_read(g.handle)
+    rt.rt_profile_enable(g.handle, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.ali_step(st, opts)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fs_ms, fs_launches, fs_points = rt.rt_profile_read(g.handle)
+    rt.rt_profile_enable(g.handle, False)
+    rel = g.state_tensors(st)["rel_change"].cpu().numpy()
+
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    vdu_per_step = case.vdu_per_fs()
+    value = vdu_per_step / (ms_per_step * 1e-3)
+    fs_ms_launch = fs_ms / max(fs_launches, 1)
+    points_launch = fs_points / max(fs_launches, 1)
+    achieved = FLOPS_PER_POINT * points_launch / (fs_ms_launch * 1e-3) / 1e12
+    traffic = read_traffic(args.workload)
+
+    out = {
+        "metric": "voxel-direction updates/s (formal solution)",
+        "value": value,
+        "unit": "VDU/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"box {case.Nx}^3 periodic x,y, {case.n_mu}x{case.n_phi} directions, stratified "
+                        "opacity (tau 1e-4..1e4) x log-normal perturbation (1 dex, l=8), eps 1e-6..1 per voxel; "
+                        "step = one ALI iteration (FP32 formal solution + reduction + update + norm, Ng every 4)",
+            "voxels": case.n_vox, "directions": case.n_dir, "wavelengths": case.n_lambda,
+            "vdu_per_step": vdu_per_step, "visits_per_vdu": fs_points / max(fs_launches, 1) / vdu_per_step,
+            "workgroups": info["n_workgroups"],
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_TFLOPS,
+            "traffic": traffic,
+            "kernel": "fs_box_kernel<float,17,J>",
+            "kernel_ms_per_launch": fs_ms_launch,
+            "launches": fs_launches,
+            "flops_per_point": FLOPS_PER_POINT,
+            "points_per_launch": points_launch,
+        },
+        "last_rel_change": float(rel.max()),
+    }
+    g.close()
+    del st
+    torch.cuda.synchronize()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_dirs)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -189,6 +189,17 @@ rt_status rt_solve(rt_grid_t grid, rt_state *state, const rt_solve_opts *opts,
 rt_status rt_box_template(int32_t Nz, int32_t n_mu, int32_t n_phi, int32_t dir, int32_t cap, int32_t *di,
                           int32_t *dj, int32_t *kk, double *s, int32_t *M);
 
+/*
+ * Measurement hooks.  While enabled, every formal-solution kernel launch of
+ * this grid is bracketed by HIP events recorded on the launch stream.
+ * rt_profile_read waits for those events and returns the summed kernel time
+ * (ms), the number of launches and the number of characteristic points they
+ * evaluated (visits x rays, summed over work items) since the previous read,
+ * then starts a new interval.  Out pointers may be NULL.
+ */
+rt_status rt_profile_enable(rt_grid_t grid, int32_t enable);
+rt_status rt_profile_read(rt_grid_t grid, double *fs_ms, int32_t *fs_launches, int64_t *fs_points);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *rt_last_error(void);
 

@@ -62,6 +62,9 @@ def lib():
         L.orc_fs_box.argtypes = [ctypes.c_int] * 5 + [_dp, _dp, ctypes.c_double, ctypes.c_double,
                                                       ctypes.c_int, _dp, _dp, ctypes.c_int]
         L.orc_fs_box.restype = ctypes.c_int
+        L.orc_fs_box_dirs.argtypes = [ctypes.c_int] * 5 + [_dp, _dp, ctypes.c_double, ctypes.c_double,
+                                                           ctypes.c_int, ctypes.c_int, _ip, _dp, _dp, ctypes.c_int]
+        L.orc_fs_box_dirs.restype = ctypes.c_int
         L.orc_fs_box_sampled.argtypes = [ctypes.c_int] * 5 + [_dp, _dp, ctypes.c_double, ctypes.c_double,
                                                               ctypes.c_int, ctypes.c_int, _lp, _dp, _dp,
                                                               ctypes.c_int]
@@ -180,6 +183,22 @@ def fs_box(chi, S, I_top: float, I_bot: float, n_mu: int, n_phi: int, kind: str 
                           threads or default_threads())
     if rc != 0:
         raise RuntimeError(f"orc_fs_box failed ({rc})")
+    return J, L
+
+
+def fs_box_dirs(chi, S, I_top: float, I_bot: float, n_mu: int, n_phi: int, dirs, kind: str = "linear",
+                threads: int | None = None, want_lstar: bool = False):
+    """Partial angle sum of J (and Lambda*) over the listed directions only."""
+    chi = _f64(chi); S = _f64(S)
+    Nz, Ny, Nx = chi.shape
+    dirs = np.ascontiguousarray(dirs, dtype=np.int32)
+    J = np.zeros_like(chi)
+    L = np.zeros_like(chi) if want_lstar else None
+    rc = lib().orc_fs_box_dirs(Nx, Ny, Nz, n_mu, n_phi, _d(chi), _d(S), float(I_top), float(I_bot),
+                               _KINDS[kind], int(dirs.size), dirs.ctypes.data_as(_ip), _d(J),
+                               _d(L) if L is not None else None, threads or default_threads())
+    if rc != 0:
+        raise RuntimeError(f"orc_fs_box_dirs failed ({rc})")
     return J, L
 
 

@@ -288,11 +288,14 @@ static inline int wrap(int a, int n)
     return r < 0 ? r + n : r;
 }
 
-int orc_fs_box(int Nx, int Ny, int Nz, int n_mu, int n_phi,
-               const double *chi, const double *S, double I_top, double I_bot,
-               int lstar_kind, double *J, double *lstar, int nthreads)
+/* Formal solution restricted to the listed directions (dirs = NULL: all of
+   them); J and lstar then hold the partial angle sums over those directions. */
+int orc_fs_box_dirs(int Nx, int Ny, int Nz, int n_mu, int n_phi,
+                    const double *chi, const double *S, double I_top, double I_bot,
+                    int lstar_kind, int n_sub, const int *dirs, double *J, double *lstar, int nthreads)
 {
     int ndir = n_mu * n_phi;
+    int nloop = dirs ? n_sub : ndir;
     long nvox = (long)Nx * Ny * Nz;
     double *mu = (double *)malloc(sizeof(double) * ndir);
     double *ph = (double *)malloc(sizeof(double) * ndir);
@@ -318,7 +321,8 @@ int orc_fs_box(int Nx, int Ny, int Nz, int n_mu, int n_phi,
         double *Jmy = Jt + (size_t)tid * nvox;
         double *Lmy = lstar ? Lt + (size_t)tid * nvox : NULL;
 #pragma omp for schedule(static, 1)
-        for (int d = 0; d < ndir; d++) {
+        for (int q = 0; q < nloop; q++) {
+            int d = dirs ? dirs[q] : q;
             double n3[3];
             orc_direction_vector(mu[d], ph[d], n3);
             orc_path p;
@@ -374,6 +378,14 @@ int orc_fs_box(int Nx, int Ny, int Nz, int n_mu, int n_phi,
     free(Jt); free(Lt);
     free(mu); free(ph); free(w);
     return err;
+}
+
+int orc_fs_box(int Nx, int Ny, int Nz, int n_mu, int n_phi,
+               const double *chi, const double *S, double I_top, double I_bot,
+               int lstar_kind, double *J, double *lstar, int nthreads)
+{
+    return orc_fs_box_dirs(Nx, Ny, Nz, n_mu, n_phi, chi, S, I_top, I_bot, lstar_kind, 0, NULL, J, lstar,
+                           nthreads);
 }
 
 /*

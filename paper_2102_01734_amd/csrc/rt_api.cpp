@@ -81,6 +81,7 @@ struct Variant {
 
 struct DevSchedule {
     int n_wg = 0, n_slots = 0, n_batch = 0;
+    int64_t points = 0;  // characteristic points evaluated by one launch
     DevBuf wg_begin, items, slot_begin, slot_ids, lambda_of;
 };
 
@@ -110,7 +111,15 @@ struct rt_grid {
     DevBuf J_anchor, S_anchor, hist, ng_blk, ng_coef;
     int hist_count = 0;
     const void *chi_src = nullptr;
-    int anchor_due = 1;
+    // measurement hooks
+    bool prof = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
+    int64_t prof_points = 0;
+    std::vector<int64_t> dir_points;  // rays x visits of one direction
+    ~rt_grid()
+    {
+        for (auto &e : prof_events) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    }
 };
 
 static Variant &variant(rt_grid *g, bool dbl, bool wj, bool wl) { return g->var[dbl][wj][wl]; }
@@ -149,6 +158,7 @@ static rt_status get_schedule(rt_grid *g, int n_wg, const std::vector<int32_t> &
     ds->n_wg = sc.n_wg;
     ds->n_slots = sc.n_slots;
     ds->n_batch = (int)lambdas.size();
+    for (const WorkItem &w : sc.items) ds->points += (int64_t)g->geo.dirs[w.dir].M * g->geo.Nx * g->geo.Ny;
     auto up = [](DevBuf &b, const void *src, size_t n) -> hipError_t {
         hipError_t e = b.ensure(n > 0 ? n : 16);
         if (e != hipSuccess) return e;
@@ -200,7 +210,18 @@ static rt_status run_fs(rt_grid *g, bool dbl, bool wj, bool wl, const std::vecto
     a.I_bc = I_bc;
     a.partJ = wj ? partJ.p : nullptr;
     a.partL = wl ? partL.p : nullptr;
-    HIPCHK(fs_box_launch(a, dbl, wj, wl, g->para, v.R, sc->n_wg, v.nthr, v.lds, st));
+    if (g->prof) {
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        HIPCHK(hipEventRecord(e0, st));
+        HIPCHK(fs_box_launch(a, dbl, wj, wl, g->para, v.R, sc->n_wg, v.nthr, v.lds, st));
+        HIPCHK(hipEventRecord(e1, st));
+        g->prof_events.push_back({e0, e1});
+        g->prof_points += sc->points;
+    } else {
+        HIPCHK(fs_box_launch(a, dbl, wj, wl, g->para, v.R, sc->n_wg, v.nthr, v.lds, st));
+    }
     *sched_out = sc;
     return RT_OK;
 }
@@ -319,6 +340,33 @@ rt_status rt_destroy_grid(rt_grid_t grid)
     if (!grid) return fail(RT_E_INVALID, "grid is NULL");
     (void)hipDeviceSynchronize();
     delete grid;
+    return RT_OK;
+}
+
+rt_status rt_profile_enable(rt_grid_t g, int32_t enable)
+{
+    if (!g) return fail(RT_E_INVALID, "grid is NULL");
+    g->prof = enable != 0;
+    return RT_OK;
+}
+
+rt_status rt_profile_read(rt_grid_t g, double *fs_ms, int32_t *fs_launches, int64_t *fs_points)
+{
+    if (!g) return fail(RT_E_INVALID, "grid is NULL");
+    double ms = 0.0;
+    for (auto &e : g->prof_events) {
+        HIPCHK(hipEventSynchronize(e.second));
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, e.first, e.second));
+        ms += t;
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    if (fs_ms) *fs_ms = ms;
+    if (fs_launches) *fs_launches = (int32_t)g->prof_events.size();
+    if (fs_points) *fs_points = g->prof_points;
+    g->prof_events.clear();
+    g->prof_points = 0;
     return RT_OK;
 }
 

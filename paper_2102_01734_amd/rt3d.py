@@ -74,6 +74,10 @@ def lib() -> ctypes.CDLL:
                            ctypes.POINTER(RtSolveReport), vp]
     for f in ("rt_create_grid", "rt_destroy_grid", "rt_grid_info", "rt_formal_solution", "rt_ali_step", "rt_solve"):
         getattr(L, f).restype = ctypes.c_int
+    L.rt_profile_enable.argtypes = [vp, i32]
+    L.rt_profile_enable.restype = ctypes.c_int
+    L.rt_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32), i64p]
+    L.rt_profile_read.restype = ctypes.c_int
     ip, dp = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)
     L.rt_box_template.argtypes = [i32, i32, i32, i32, i32, ip, ip, ip, dp, ip]
     L.rt_box_template.restype = ctypes.c_int
@@ -138,6 +142,18 @@ def rt_solve(grid: int, state: RtState, opts: RtSolveOpts, stream: Optional[int]
     st = _check(lib().rt_solve(ctypes.c_void_p(grid), ctypes.byref(state), ctypes.byref(opts), ctypes.byref(rep),
                                ctypes.c_void_p(stream or None)), "rt_solve", allow=(RT_E_NOT_CONVERGED,))
     return st, rep
+
+
+def rt_profile_enable(grid: int, enable: bool) -> None:
+    _check(lib().rt_profile_enable(ctypes.c_void_p(grid), int(bool(enable))), "rt_profile_enable")
+
+
+def rt_profile_read(grid: int):
+    """(summed formal-solution kernel ms, launches, characteristic points) since the last read."""
+    ms, n, pts = ctypes.c_double(), ctypes.c_int32(), ctypes.c_int64()
+    _check(lib().rt_profile_read(ctypes.c_void_p(grid), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(pts)),
+           "rt_profile_read")
+    return ms.value, n.value, pts.value
 
 
 def rt_box_template(Nz: int, n_mu: int, n_phi: int, d: int):
