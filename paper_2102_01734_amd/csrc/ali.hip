@@ -23,12 +23,31 @@
 namespace rt3d {
 
 // ---------------------------------------------------------------------------
-// padded copies: dst[l][k][y2][x2] = src[l][k][y2 mod Ny][x2 mod Nx], with an
-// optional anchor subtracted (dst = src - anchor) in the destination type.
+// Formal-solution input layout: for every wavelength a doubly periodic padded
+// copy [k][y2][x2] (y2 < 2Ny, x2 < 2Nx) of the pair (chi, S), interleaved so a
+// point's opacity and source are one 8- (16-) byte load:
+//   dst[((l*Nz + k)*2Ny + y2)*2Nx + x2][comp] = src[l][k][y2 mod Ny][x2 mod Nx],
+// comp 0 = chi, comp 1 = S (optionally minus an anchor), in the kernel type.
 // ---------------------------------------------------------------------------
+template <typename TD>
+__device__ __forceinline__ void store_padded(TD *dst, int64_t l, int64_t n_vox, int64_t v, int Nx, int Ny, int comp,
+                                             TD val)
+{
+    const int x = (int)(v % Nx);
+    const int64_t r = v / Nx;
+    const int y = (int)(r % Ny);
+    const int64_t k = r / Ny;
+    TD *base = dst + 2 * (l * 4 * n_vox + k * (4LL * Nx * Ny)) + comp;
+    const int64_t W = 2 * Nx;
+    base[2 * ((int64_t)y * W + x)] = val;
+    base[2 * ((int64_t)y * W + x + Nx)] = val;
+    base[2 * ((int64_t)(y + Ny) * W + x)] = val;
+    base[2 * ((int64_t)(y + Ny) * W + x + Nx)] = val;
+}
+
 template <typename TS, typename TD>
 __global__ void pad_kernel(const TS *__restrict__ src, const double *__restrict__ anchor, TD *__restrict__ dst,
-                           int Nx, int Ny, int64_t per_lambda, int64_t total)
+                           int Nx, int Ny, int64_t per_lambda, int64_t total, int comp)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
@@ -38,19 +57,14 @@ __global__ void pad_kernel(const TS *__restrict__ src, const double *__restrict_
     const int64_t r = v / Nx;
     const int y = (int)(r % Ny);
     const int64_t k = r / Ny;
+    (void)x; (void)y; (void)k;
     double val = (double)src[i];
     if (anchor) val -= anchor[i];
-    const TD out = (TD)val;
-    TD *base = dst + l * (4 * per_lambda) + k * (4LL * Nx * Ny);
-    const int W = 2 * Nx;
-    base[(int64_t)y * W + x] = out;
-    base[(int64_t)y * W + x + Nx] = out;
-    base[(int64_t)(y + Ny) * W + x] = out;
-    base[(int64_t)(y + Ny) * W + x + Nx] = out;
+    store_padded<TD>(dst, l, per_lambda, v, Nx, Ny, comp, (TD)val);
 }
 
 template <typename TS, typename TD>
-hipError_t pad_field(const TS *src, const double *anchor, TD *dst, int Nx, int Ny, int Nz, int n_lambda,
+hipError_t pad_field(const TS *src, const double *anchor, TD *dst, int Nx, int Ny, int Nz, int n_lambda, int comp,
                      hipStream_t st)
 {
     const int64_t per = (int64_t)Nx * Ny * Nz;
@@ -58,16 +72,17 @@ hipError_t pad_field(const TS *src, const double *anchor, TD *dst, int Nx, int N
     if (total == 0) return hipSuccess;
     const int bs = 256;
     hipLaunchKernelGGL((pad_kernel<TS, TD>), dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, st, src, anchor,
-                       dst, Nx, Ny, per, total);
+                       dst, Nx, Ny, per, total, comp);
     return hipGetLastError();
 }
 
-template hipError_t pad_field<float, float>(const float *, const double *, float *, int, int, int, int, hipStream_t);
-template hipError_t pad_field<float, double>(const float *, const double *, double *, int, int, int, int,
+template hipError_t pad_field<float, float>(const float *, const double *, float *, int, int, int, int, int,
                                              hipStream_t);
-template hipError_t pad_field<double, double>(const double *, const double *, double *, int, int, int, int,
-                                              hipStream_t);
-template hipError_t pad_field<double, float>(const double *, const double *, float *, int, int, int, int,
+template hipError_t pad_field<float, double>(const float *, const double *, double *, int, int, int, int, int,
+                                             hipStream_t);
+template hipError_t pad_field<double, double>(const double *, const double *, double *, int, int, int, int, int,
+                                             hipStream_t);
+template hipError_t pad_field<double, float>(const double *, const double *, float *, int, int, int, int, int,
                                              hipStream_t);
 
 // ---------------------------------------------------------------------------
@@ -179,16 +194,7 @@ __global__ void source_kernel(const double *__restrict__ J, const G *__restrict_
     const double s = (1.0 - e) * J[i] + e * (double)B[i];
     S[i] = s;
     const TN out = (TN)(S_anchor ? s - S_anchor[i] : s);
-    const int x = (int)(v % Nx);
-    const int64_t r = v / Nx;
-    const int y = (int)(r % Ny);
-    const int64_t k = r / Ny;
-    TN *base = next_pad + (int64_t)lambda_of[blockIdx.y] * 4 * n_vox + k * (4LL * Nx * Ny);
-    const int W = 2 * Nx;
-    base[(int64_t)y * W + x] = out;
-    base[(int64_t)y * W + x + Nx] = out;
-    base[(int64_t)(y + Ny) * W + x] = out;
-    base[(int64_t)(y + Ny) * W + x + Nx] = out;
+    store_padded<TN>(next_pad, lambda_of[blockIdx.y], n_vox, v, Nx, Ny, 1, out);
 }
 
 template <typename G, typename TN>
@@ -249,16 +255,7 @@ __global__ void __launch_bounds__(256) ali_update_kernel(AliUpdateArgs a)
         const double s = (1.0 - e) * jn + e * Bv;
         a.S[i] = s;
         const TN out = (TN)(a.S_anchor ? s - a.S_anchor[i] : s);
-        const int x = (int)(v % a.Nx);
-        const int64_t r = v / a.Nx;
-        const int y = (int)(r % a.Ny);
-        const int64_t k = r / a.Ny;
-        TN *base = reinterpret_cast<TN *>(a.next_pad) + (int64_t)lam * 4 * a.n_vox + k * (4LL * a.Nx * a.Ny);
-        const int W = 2 * a.Nx;
-        base[(int64_t)y * W + x] = out;
-        base[(int64_t)y * W + x + a.Nx] = out;
-        base[(int64_t)(y + a.Ny) * W + x] = out;
-        base[(int64_t)(y + a.Ny) * W + x + a.Nx] = out;
+        store_padded<TN>(reinterpret_cast<TN *>(a.next_pad), lam, a.n_vox, v, a.Nx, a.Ny, 1, out);
     }
     rel = block_max<256>(rel);
     if (threadIdx.x == 0) atomic_max_nonneg(&a.rel_change[lam], rel);
@@ -359,16 +356,7 @@ __global__ void ng_apply_kernel(NgApplyArgs a)
     const double s = (1.0 - e) * jn + e * (double)reinterpret_cast<const G *>(a.B)[i];
     a.S[i] = s;
     const TN out = (TN)(a.S_anchor ? s - a.S_anchor[i] : s);
-    const int x = (int)(v % a.Nx);
-    const int64_t r = v / a.Nx;
-    const int y = (int)(r % a.Ny);
-    const int64_t k = r / a.Ny;
-    TN *base = reinterpret_cast<TN *>(a.next_pad) + (int64_t)lam * 4 * a.n_vox + k * (4LL * a.Nx * a.Ny);
-    const int W = 2 * a.Nx;
-    base[(int64_t)y * W + x] = out;
-    base[(int64_t)y * W + x + a.Nx] = out;
-    base[(int64_t)(y + a.Ny) * W + x] = out;
-    base[(int64_t)(y + a.Ny) * W + x + a.Nx] = out;
+    store_padded<TN>(reinterpret_cast<TN *>(a.next_pad), lam, a.n_vox, v, a.Nx, a.Ny, 1, out);
 }
 
 hipError_t ng_accelerate(const NgApplyArgs &a, double *blk, int nblk, int n_batch, bool grid_double, hipStream_t st)

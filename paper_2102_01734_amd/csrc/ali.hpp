@@ -7,8 +7,10 @@
 
 namespace rt3d {
 
+// Writes component comp (0 = chi, 1 = S) of the interleaved doubly periodic
+// padded formal-solution input (see ali.hip).
 template <typename TS, typename TD>
-hipError_t pad_field(const TS *src, const double *anchor, TD *dst, int Nx, int Ny, int Nz, int n_lambda,
+hipError_t pad_field(const TS *src, const double *anchor, TD *dst, int Nx, int Ny, int Nz, int n_lambda, int comp,
                      hipStream_t st);
 
 template <typename TP, typename TO>
@@ -37,7 +39,7 @@ struct AliUpdateArgs {
     double *J;                  // in/out
     double *S;                  // out
     double *hist;               // out: copy of the new J into the Ng ring, or null
-    void *next_pad;             // out: padded formal-solution input (S - S_anchor)
+    void *next_pad;             // out: S - S_anchor into the interleaved padded input
     double *rel_change;         // out: per wavelength max |dJ/J| (atomic max)
 };
 

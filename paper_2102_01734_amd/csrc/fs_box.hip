@@ -5,9 +5,11 @@
 // (top to bottom for mu < 0).  Every thread carries the intensity of R rays in
 // registers; all rays of a direction share the visit template, so at visit m
 // every lane reads the same template entry (scalar loads) and ray r touches
-// voxel r + offset_m.  At a fixed m that map is one-to-one, so after a
+// voxel r + offset_m.  At a fixed m that map is one-to-one, so with a
 // workgroup barrier per visit step the layer's J (and Lambda*) tile in LDS is
-// updated without collisions and in a fixed order (bitwise reproducible).
+// updated by plain read-add-write without collisions and in a fixed order
+// (bitwise reproducible; no LDS atomics, whose queueing cost a third of the
+// kernel time).
 // When the template leaves a layer the tile is added into the workgroup's own
 // partial-sum slot in HBM.
 //
@@ -22,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "fs_box.hpp"
 
@@ -51,76 +54,168 @@ __device__ __forceinline__ double rcp_f64(double x)
     return __builtin_fma(r, e, r);
 }
 
-// Attenuation moments over an optical step D >= 0:
+// exp(-D) for 1/4 <= D: x = -D = n ln2 + r with |r| <= ln2/2, exp(r) by its
+// Taylor polynomial (degree 12 for double results, 9 when the weights feed a
+// single-precision recurrence), scaled by 2^n.  D is clamped at 745, where
+// the result is already below the smallest subnormal.
+template <bool FULL>
+__device__ __forceinline__ double exp_neg(double D)
+{
+    const double x = -(D < 745.0 ? D : 745.0);
+    const double n = __builtin_rint(x * 1.4426950408889634);
+    double r = __builtin_fma(-n, 6.93147180369123816490e-01, x);
+    r = __builtin_fma(-n, 1.90821492927058770002e-10, r);
+    double p;
+    if (FULL) {
+        p = 1.0 / 479001600.0;
+        p = __builtin_fma(p, r, 1.0 / 39916800.0);
+        p = __builtin_fma(p, r, 1.0 / 3628800.0);
+        p = __builtin_fma(p, r, 1.0 / 362880.0);
+    } else {
+        p = 1.0 / 362880.0;
+    }
+    p = __builtin_fma(p, r, 1.0 / 40320.0);
+    p = __builtin_fma(p, r, 1.0 / 5040.0);
+    p = __builtin_fma(p, r, 1.0 / 720.0);
+    p = __builtin_fma(p, r, 1.0 / 120.0);
+    p = __builtin_fma(p, r, 1.0 / 24.0);
+    p = __builtin_fma(p, r, 1.0 / 6.0);
+    p = __builtin_fma(p, r, 0.5);
+    p = __builtin_fma(p, r, 1.0);
+    p = __builtin_fma(p, r, 1.0);
+    return __builtin_ldexp(p, (int)n);
+}
+
+// Attenuation moments over an optical step D > 0:
 //   ex = exp(-D), e0 = 1 - ex, e1 = D - e0, e2 = D^2 - 2 e1.
-// Below D = 1/4 e2 comes from its Taylor series 2 D^3 sum_j (-D)^j/(j+3)!,
-// and e1, e0, ex follow from it without cancellation.
+// Below D = 1/4, e2 comes from its Taylor series 2 D^3 sum_j (-D)^j/(j+3)!
+// (12 terms for double results, 8 for single-precision ones), and e1, e0, ex
+// follow from it without cancellation; from 1/4 up the closed forms are used.
+// The series is evaluated on every lane (it is short); the exponential only
+// where some lane of the wave needs it.
+template <bool FULL>
 __device__ __forceinline__ void kernel_moments(double D, double &ex, double &e0, double &e1, double &e2)
 {
-    if (D < 0.25) {
-        double p = 1.0 / 87178291200.0;           // 1/14!
+    double p;
+    if (FULL) {
+        p = 1.0 / 87178291200.0;                       // 1/14!
         p = __builtin_fma(-D, p, 1.0 / 6227020800.0);  // 1/13!
         p = __builtin_fma(-D, p, 1.0 / 479001600.0);   // 1/12!
         p = __builtin_fma(-D, p, 1.0 / 39916800.0);    // 1/11!
-        p = __builtin_fma(-D, p, 1.0 / 3628800.0);     // 1/10!
-        p = __builtin_fma(-D, p, 1.0 / 362880.0);      // 1/9!
-        p = __builtin_fma(-D, p, 1.0 / 40320.0);       // 1/8!
-        p = __builtin_fma(-D, p, 1.0 / 5040.0);        // 1/7!
-        p = __builtin_fma(-D, p, 1.0 / 720.0);         // 1/6!
-        p = __builtin_fma(-D, p, 1.0 / 120.0);         // 1/5!
-        p = __builtin_fma(-D, p, 1.0 / 24.0);          // 1/4!
-        p = __builtin_fma(-D, p, 1.0 / 6.0);           // 1/3!
-        const double D2 = D * D;
+    } else {
+        p = 1.0 / 39916800.0;                          // 1/11!
+    }
+    p = __builtin_fma(-D, p, 1.0 / 3628800.0);     // 1/10!
+    p = __builtin_fma(-D, p, 1.0 / 362880.0);      // 1/9!
+    p = __builtin_fma(-D, p, 1.0 / 40320.0);       // 1/8!
+    p = __builtin_fma(-D, p, 1.0 / 5040.0);        // 1/7!
+    p = __builtin_fma(-D, p, 1.0 / 720.0);         // 1/6!
+    p = __builtin_fma(-D, p, 1.0 / 120.0);         // 1/5!
+    p = __builtin_fma(-D, p, 1.0 / 24.0);          // 1/4!
+    p = __builtin_fma(-D, p, 1.0 / 6.0);           // 1/3!
+    const double D2 = D * D;
+    if (D < 0.25) {
         e2 = 2.0 * D2 * D * p;
         e1 = 0.5 * (D2 - e2);
         e0 = D - e1;
         ex = 1.0 - e0;
-    } else {
-        ex = exp(-D);
-        e0 = 1.0 - ex;
-        e1 = D - e0;
-        e2 = D * D - 2.0 * e1;
+        return;
     }
+    ex = exp_neg<FULL>(D);
+    e0 = 1.0 - ex;
+    e1 = D - e0;
+    e2 = __builtin_fma(D, D, -2.0 * e1);
 }
 
-struct PointWeights {
-    double a, b, g;  // weights of S_{m-1}, S_m, S_{m+1}
-    double ex;       // exp(-D)
-    double dlin;     // e1/D: linear-interpolation diagonal
-};
+// Smallest optical step used in the arithmetic: a vacuum segment (D = 0,
+// Listing 1 step 4a) is evaluated at this step, which leaves the intensity
+// unchanged to within 1e-100 of S and keeps the shared reciprocal finite.
+constexpr double kMinStep = 1e-100;
 
 // Weights of the segment from the previous point (upwind optical step D) to
-// the current one, the downwind step being Dp (ignored when last).
-// Parabolic (Lagrange quadratic through the three points integrated against
-// exp(-(D-t))), falling back to linear on the last point of a ray, when
-// Dp < D/2, or when the parabolic beta would reach 1 (Dp e0 <= D e1 - e2).
-// D = 0 is a vacuum segment: no change of the intensity.
-__device__ __forceinline__ PointWeights point_weights(double D, double Dp, bool last)
+// the current one, the downwind step being Dp (ignored when last), in the
+// type T of the recurrence:
+//   I_m = I_{m-1} ex + a S_{m-1} + b S_m + g S_{m+1}.
+// Parabolic: the Lagrange quadratic through the three points integrated
+// against exp(-(D-t)); with r = 1/(D Dp (D+Dp)),
+//   b = ((D+Dp) e1 - e2) (D+Dp) r,  g = (e2 - D e1) D r,  a = e0 - b - g.
+// Linear (the last point of a ray, Dp < D/2, or where the parabolic b would
+// reach 1, i.e. Dp e0 <= D e1 - e2):  b = e1/D, a = e0 - b, g = 0.
+// dlin = e1/D is the diagonal of the linear-interpolation operator.
+template <typename T>
+struct PointW {
+    T a, b, g, ex, dlin;
+};
+
+template <typename T>
+__device__ __forceinline__ PointW<T> point_weights(double D, double Dp, bool last)
 {
-    PointWeights w;
-    double e0, e1, e2;
-    kernel_moments(D, w.ex, e0, e1, e2);
-    if (!(D > 0.0)) {
-        w.a = w.b = w.g = 0.0;
-        w.dlin = 0.0;
-        w.ex = 1.0;
-        return w;
-    }
-    const double rD = rcp_f64(D);
-    w.dlin = e1 * rD;
-    const bool lin = last || (Dp < 0.5 * D) || (Dp * e0 <= D * e1 - e2);
-    if (lin) {
-        w.a = e0 - w.dlin;
-        w.b = w.dlin;
-        w.g = 0.0;
+    constexpr bool FULL = sizeof(T) == 8;
+    const double Dv = D < kMinStep ? kMinStep : D;  // NaN propagates
+    double ex, e0, e1, e2;
+    kernel_moments<FULL>(Dv, ex, e0, e1, e2);
+    const double Dq = Dp < kMinStep ? Dv : Dp;   // keeps r finite on last/vacuum points; NaN propagates
+    const double Ds = Dv + Dq;
+    const double r = rcp_f64(Dv * Dq * Ds);
+    const double bl = e1 * ((Dq * Ds) * r);      // e1 / D
+    const bool lin = last || (Dp < 0.5 * D) || (Dp * e0 <= __builtin_fma(Dv, e1, -e2));
+    const double bp = __builtin_fma(Ds, e1, -e2) * (Ds * r);
+    const double gp = (e2 - Dv * e1) * (Dv * r);
+    PointW<T> w;
+    w.ex = T(ex);
+    w.dlin = T(bl);
+    if (sizeof(T) == 8) {
+        w.b = lin ? T(bl) : T(bp);
+        w.g = lin ? T(0) : T(gp);
+        w.a = lin ? T(e0 - bl) : T(e0 - bp - gp);
     } else {
-        const double Ds = D + Dp;
-        const double r = rcp_f64(D * Dp * Ds);
-        w.a = e0 + (e2 - (D + Ds) * e1) * (Dp * r);
-        w.b = (Ds * e1 - e2) * (Ds * r);
-        w.g = (e2 - D * e1) * (D * r);
+        const T bl_t = T(bl), al_t = T(e0 - bl), bp_t = T(bp), gp_t = T(gp), ap_t = T(e0 - bp - gp);
+        w.b = lin ? bl_t : bp_t;
+        w.g = lin ? T(0) : gp_t;
+        w.a = lin ? al_t : ap_t;
     }
     return w;
+}
+
+// Entry half-segment: constant S from the entry point to the first point.
+template <typename T>
+__device__ __forceinline__ void entry_weights(double D0, T &ex_t, T &e0_t)
+{
+    constexpr bool FULL = sizeof(T) == 8;
+    double ex, e0, e1, e2;
+    kernel_moments<FULL>(D0 < kMinStep ? kMinStep : D0, ex, e0, e1, e2);
+    ex_t = T(ex);
+    e0_t = T(e0);
+}
+
+// ---------------------------------------------------------------------------
+// field loads: one raw buffer load per point fetches the (chi, S) pair; the
+// per-ray byte offset sits in a VGPR, the per-visit byte offset in an SGPR,
+// so there is no per-lane address arithmetic
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t field_rsrc(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+template <typename T>
+struct Pair {
+    T chi, S;
+};
+
+template <typename T>
+__device__ __forceinline__ Pair<T> ld_pair(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+
+template <>
+__device__ __forceinline__ Pair<float> ld_pair<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    return __builtin_bit_cast(Pair<float>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+template <>
+__device__ __forceinline__ Pair<double> ld_pair<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    return __builtin_bit_cast(Pair<double>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
 
 // ---------------------------------------------------------------------------
@@ -132,41 +227,48 @@ __global__ void __launch_bounds__(1024) fs_box_kernel(FsBoxArgs a)
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int Nx = a.Nx, Ny = a.Ny;
     const int NxNy = Nx * Ny;
-    T *tJ = reinterpret_cast<T *>(smem_raw);
-    T *tL = tJ + (WJ ? NxNy : 0);
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
+    // tiles of NxNy words plus one scratch word per thread (padding slots)
+    T *tJ = reinterpret_cast<T *>(smem_raw);
+    T *tL = tJ + (WJ ? NxNy + nthr : 0);
+    constexpr int ES = 2 * (int)sizeof(T);  // bytes per (chi, S) pair
+    constexpr int kPad = 1 << 31;          // xy0 flag: slot beyond the last ray
 
-    for (int i = tid; i < NxNy; i += nthr) {
+    for (int i = tid; i < NxNy + nthr; i += nthr) {
         if (WJ) tJ[i] = T(0);
         if (WL) tL[i] = T(0);
     }
 
-    // rays of this thread: q = tid + j*nthr, origin (x0, y0)
-    int gbase[R];
-    int xy0[R];
+    // rays of this thread: q = tid + j*nthr with origin (x0, y0).  Slots past
+    // the last ray repeat the ray q - NxNy and contribute exactly zero, so the
+    // body below has no per-ray branches.
+    int xy0[R];    // x0 | y0 << 16 | kPad
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        const int q = tid + j * nthr;
-        if (q < NxNy) {
-            const int y0 = q / Nx;
-            const int x0 = q - y0 * Nx;
-            gbase[j] = y0 * (2 * Nx) + x0;
-            xy0[j] = x0 | (y0 << 16);
-        } else {
-            gbase[j] = 0;
-            xy0[j] = -1;
-        }
+        int q = tid + j * nthr;
+        int pad = 0;
+        while (q >= NxNy) { q -= NxNy; pad = kPad; }
+        const int y0 = q / Nx;
+        const int x0 = q - y0 * Nx;
+        xy0[j] = x0 | (y0 << 16) | pad;
     }
+    // byte offset of ray j's origin in the padded field (recomputed: saves R registers)
+    const uint32_t row_bytes = (uint32_t)(2 * Nx * ES);
+    auto vbase = [&](int j) {
+        const uint32_t x0 = (uint32_t)xy0[j] & 0xffffu, y0 = ((uint32_t)xy0[j] >> 16) & 0x7fffu;
+        return (int)(__umul24(y0, row_bytes) + x0 * ES);
+    };
     __syncthreads();
 
+    const uint32_t slice_bytes = (uint32_t)(a.pad_stride * ES);
     const int it_end = a.wg_begin[blockIdx.x + 1];
     for (int it = a.wg_begin[blockIdx.x]; it < it_end; ++it) {
         const WorkItem item = a.items[it];
         const int lam = item.lambda;
         const int d = item.dir;
-        const T *__restrict__ chi = reinterpret_cast<const T *>(a.chi_pad) + (int64_t)lam * a.pad_stride;
-        const T *__restrict__ S = reinterpret_cast<const T *>(a.S_pad) + (int64_t)lam * a.pad_stride;
+        const __amdgpu_buffer_rsrc_t rf =
+            field_rsrc(reinterpret_cast<const T *>(a.field) + 2 * (int64_t)lam * a.pad_stride, slice_bytes);
         T *__restrict__ pJ = WJ ? reinterpret_cast<T *>(a.partJ) + (int64_t)item.slot * a.n_vox : nullptr;
         T *__restrict__ pL = WL ? reinterpret_cast<T *>(a.partL) + (int64_t)item.slot * a.n_vox : nullptr;
         const bool first = item.first != 0;
@@ -181,94 +283,120 @@ __global__ void __launch_bounds__(1024) fs_box_kernel(FsBoxArgs a)
 
         T I[R];
         T gprev[R];
-#pragma unroll
-        for (int j = 0; j < R; ++j) { I[j] = Ibc; gprev[j] = T(0); }
-
         int layer = down ? 0 : a.Nz - 1;
         const int dlayer = down ? 1 : -1;
 
-        // sliding window of template entries: previous (p), current (c), next (n)
-        int g_p = 0, g_c = goff[0];
-        double s_p = 0.0, s_c = sv[0];
-        int g_n = M > 1 ? goff[1] : 0;
-        double s_n = M > 1 ? sv[1] : 0.0;
-        uint32_t w_c = dxy[0];
+        auto flush_layer = [&]() {
+            const int64_t lo = (int64_t)layer * NxNy;
+            for (int i = tid; i < NxNy; i += nthr) {
+                if (WJ) {
+                    const T v = tJ[i];
+                    tJ[i] = T(0);
+                    pJ[lo + i] = first ? v : pJ[lo + i] + v;
+                }
+                if (WL) {
+                    const T v = tL[i];
+                    tL[i] = T(0);
+                    pL[lo + i] = first ? v : pL[lo + i] + v;
+                }
+            }
+            layer += dlayer;
+            __syncthreads();
+        };
+        // tile index of ray j at a visit with horizontal offsets packed in w;
+        // wrap by an unsigned minimum (x - N underflows when x < N).  Padding
+        // slots go to this thread's own word past the tile, so no two lanes
+        // ever update the same word in one step.
+        auto tile_index = [&](int j, uint32_t w) {
+            const uint32_t x0 = (uint32_t)xy0[j] & 0xffffu, y0 = ((uint32_t)xy0[j] >> 16) & 0x7fffu;
+            uint32_t xl = x0 + (w & kOffMask);
+            xl = min(xl, xl - (uint32_t)Nx);
+            uint32_t yl = y0 + ((w >> kOffBits) & kOffMask);
+            yl = min(yl, yl - (uint32_t)Ny);
+            const int idx = (int)__umul24(yl, (uint32_t)Nx) + (int)xl;
+            return xy0[j] < 0 ? NxNy + tid : idx;
+        };
 
-        for (int m = 0; m < M; ++m) {
-            const bool last = (m == M - 1);
-            const int di = (int)(w_c & kOffMask);
-            const int dj = (int)((w_c >> kOffBits) & kOffMask);
+        // first point: entry half-segment with constant S
+        int g_c = goff[0] * ES;
+        double s_c = sv[0];
+        uint32_t w_c = dxy[0];
+        {
             const T cw = T(wmu * s_c);
 #pragma unroll
             for (int j = 0; j < R; ++j) {
-                if (xy0[j] < 0) continue;
-                const int gb = gbase[j];
-                const T chi_c = chi[gb + g_c];
-                const T S_c = WJ ? S[gb + g_c] : T(0);
-                T dloc = T(0);
-                if (m == 0) {
-                    // entry half-segment, constant S (Listing 1 step 4a)
-                    const double D0 = 0.5 * seg_depth((double)chi_c, s_c);
-                    double ex, e0, e1, e2;
-                    kernel_moments(D0, ex, e0, e1, e2);
-                    if (WJ) I[j] = I[j] * T(ex) + S_c * T(e0);
-                    dloc = T(e0);
-                } else {
-                    const T chi_p = chi[gb + g_p];
-                    const T S_p = WJ ? S[gb + g_p] : T(0);
-                    T chi_n = T(0), S_n = T(0);
-                    if (!last) {
-                        chi_n = chi[gb + g_n];
-                        if (WJ) S_n = S[gb + g_n];
-                    }
-                    const double tp = seg_depth((double)chi_p, s_p);
-                    const double tc = seg_depth((double)chi_c, s_c);
-                    const double D = half_sum(tp, tc);
-                    const double Dp = last ? 0.0 : half_sum(tc, seg_depth((double)chi_n, s_n));
-                    const PointWeights pw = point_weights(D, Dp, last);
-                    const T ex = T(pw.ex);
-                    if (WJ) I[j] = I[j] * ex + T(pw.a) * S_p + T(pw.b) * S_c + T(pw.g) * S_n;
-                    if (WL) {
-                        if (PARA) {
-                            dloc = T(pw.b) + gprev[j] * ex;
-                            gprev[j] = T(pw.g);
-                        } else {
-                            dloc = T(pw.dlin);
-                        }
-                    }
-                }
-                const int x0 = xy0[j] & 0xffff, y0 = xy0[j] >> 16;
-                int xl = x0 + di;
-                xl = xl >= Nx ? xl - Nx : xl;
-                int yl = y0 + dj;
-                yl = yl >= Ny ? yl - Ny : yl;
-                const int idx = yl * Nx + xl;
-                if (WJ) atomicAdd(&tJ[idx], cw * I[j]);
-                if (WL) atomicAdd(&tL[idx], cw * dloc);
+                gprev[j] = T(0);
+                const Pair<T> fc = ld_pair<T>(rf, vbase(j), g_c);
+                T ex, e0;
+                entry_weights<T>(0.5 * seg_depth((double)fc.chi, s_c), ex, e0);
+                I[j] = WJ ? Ibc * ex + fc.S * e0 : T(0);
+                const int idx = tile_index(j, w_c);
+                const T cj = xy0[j] < 0 ? T(0) : cw;
+                if (WJ) tJ[idx] += cj * I[j];
+                if (WL) tL[idx] += cj * e0;
             }
             __syncthreads();
-            if (w_c & kLayerEnd) {
-                const int64_t lo = (int64_t)layer * NxNy;
-                for (int i = tid; i < NxNy; i += nthr) {
-                    if (WJ) {
-                        const T v = tJ[i];
-                        tJ[i] = T(0);
-                        pJ[lo + i] = first ? v : pJ[lo + i] + v;
-                    }
-                    if (WL) {
-                        const T v = tL[i];
-                        tL[i] = T(0);
-                        pL[lo + i] = first ? v : pL[lo + i] + v;
-                    }
+            if (w_c & kLayerEnd) flush_layer();
+        }
+
+        // one point of every ray of this thread; LAST: the final point, which
+        // has no downwind neighbour
+        int g_p = 0, g_n = 0;
+        double s_p = 0.0, s_n = 0.0;
+        auto step = [&](auto last_tag) {
+            constexpr bool LAST = decltype(last_tag)::value;
+            const T cw = T(wmu * s_c);
+            // software pipeline over the rays of this thread: the loads of
+            // ray j+1 are in flight while ray j is computed
+            const int vo0 = vbase(0);
+            Pair<T> np = ld_pair<T>(rf, vo0, g_p);
+            Pair<T> nc = ld_pair<T>(rf, vo0, g_c);
+            Pair<T> nn = LAST ? Pair<T>{T(0), T(0)} : ld_pair<T>(rf, vo0, g_n);
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const Pair<T> fp = np, fc = nc, fn = nn;
+                if (j + 1 < R) {
+                    const int vo = vbase(j + 1);
+                    np = ld_pair<T>(rf, vo, g_p);
+                    nc = ld_pair<T>(rf, vo, g_c);
+                    nn = LAST ? Pair<T>{T(0), T(0)} : ld_pair<T>(rf, vo, g_n);
                 }
-                layer += dlayer;
-                __syncthreads();
+                const double tc = seg_depth((double)fc.chi, s_c);
+                const double D = half_sum(seg_depth((double)fp.chi, s_p), tc);
+                const double Dp = LAST ? 0.0 : half_sum(tc, seg_depth((double)fn.chi, s_n));
+                const PointW<T> pw = point_weights<T>(D, Dp, LAST);
+                if (WJ) I[j] = I[j] * pw.ex + pw.a * fp.S + pw.b * fc.S + (LAST ? T(0) : pw.g * fn.S);
+                const int idx = tile_index(j, w_c);
+                const T cj = xy0[j] < 0 ? T(0) : cw;
+                if (WJ) tJ[idx] += cj * I[j];
+                if (WL) {
+                    T dloc;
+                    if (PARA) {
+                        dloc = pw.b + gprev[j] * pw.ex;
+                        gprev[j] = pw.g;
+                    } else {
+                        dloc = pw.dlin;
+                    }
+                    tL[idx] += cj * dloc;
+                }
             }
-            // advance the window
+            __syncthreads();
+            if (w_c & kLayerEnd) flush_layer();
+        };
+
+        for (int m = 1; m < M; ++m) {
+            // window of template entries: previous (p), current (c), next (n)
             g_p = g_c; s_p = s_c;
-            g_c = g_n; s_c = s_n;
-            if (m + 1 < M) w_c = dxy[m + 1];
-            if (m + 2 < M) { g_n = goff[m + 2]; s_n = sv[m + 2]; }
+            g_c = goff[m] * ES;
+            s_c = sv[m];
+            w_c = dxy[m];
+            if (m + 1 < M) {
+                g_n = goff[m + 1] * ES;
+                s_n = sv[m + 1];
+                step(std::false_type{});
+            } else {
+                step(std::true_type{});
+            }
         }
     }
 }

@@ -23,9 +23,9 @@ struct FsBoxArgs {
     // schedule
     const int32_t *wg_begin;
     const WorkItem *items;
-    // fields: padded [lambda][Nz][2Ny][2Nx], element type = kernel type
-    const void *chi_pad;
-    const void *S_pad;
+    // (chi, S) pairs, doubly periodic padded [lambda][Nz][2Ny][2Nx][2],
+    // element type = kernel type; pad_stride = pairs per wavelength
+    const void *field;
     int64_t pad_stride;
     const void *I_bc;  // [lambda][2] or null
     // partial sums [slot][n_vox]

@@ -102,10 +102,9 @@ struct rt_grid {
 
     std::map<std::string, std::unique_ptr<DevSchedule>> schedules;
 
-    // rt_formal_solution scratch
-    DevBuf fs_chi_pad, fs_S_pad;
-    // ALI scratch (sized for n_lambda_max)
-    DevBuf chi_pad, chi_pad64, S_pad, S_pad64, ibc64;
+    // formal-solution inputs: interleaved (chi, S) doubly periodic padded copies
+    DevBuf fs_fld;           // rt_formal_solution
+    DevBuf fld, fld64, ibc64;  // ALI (sized for n_lambda_max); fld64: double anchors of FP32 grids
     DevBuf partJ, partL, partJ64, partL64;
     // ALI state owned by the library
     DevBuf J_anchor, S_anchor, hist, ng_blk, ng_coef;
@@ -132,7 +131,8 @@ static void setup_variant(rt_grid *g, bool dbl, bool wj, bool wl)
     const int rays = g->geo.Nx * g->geo.Ny;
     v.R = fs_box_pick_r(rays, 1024, &v.nthr);
     if (v.R == 0) return;
-    v.lds = (size_t)rays * (dbl ? 8 : 4) * ((wj ? 1 : 0) + (wl ? 1 : 0));
+    // per tile: one word per voxel of a layer plus one scratch word per thread
+    v.lds = (size_t)(rays + v.nthr) * (dbl ? 8 : 4) * ((wj ? 1 : 0) + (wl ? 1 : 0));
     if (v.lds > g->max_lds) return;
     int occ = fs_box_occupancy(dbl, wj, wl, g->para, v.R, v.nthr, v.lds);
     if (occ <= 0) return;
@@ -180,8 +180,8 @@ static rt_status get_schedule(rt_grid *g, int n_wg, const std::vector<int32_t> &
 // formal solution on padded inputs already in place
 // ---------------------------------------------------------------------------
 static rt_status run_fs(rt_grid *g, bool dbl, bool wj, bool wl, const std::vector<int32_t> &lambdas,
-                        const void *chi_pad, const void *S_pad, const void *I_bc, DevBuf &partJ, DevBuf &partL,
-                        DevSchedule **sched_out, hipStream_t st)
+                        const void *fld, const void *I_bc, DevBuf &partJ, DevBuf &partL, DevSchedule **sched_out,
+                        hipStream_t st)
 {
     Variant &v = variant(g, dbl, wj, wl);
     if (!v.ok) return fail(RT_E_UNSUPPORTED, "no kernel configuration fits this grid (layer tile of %d voxels)",
@@ -204,8 +204,7 @@ static rt_status run_fs(rt_grid *g, bool dbl, bool wj, bool wl, const std::vecto
     a.dir_mu = g->mu.as<double>();
     a.wg_begin = sc->wg_begin.as<int32_t>();
     a.items = sc->items.as<WorkItem>();
-    a.chi_pad = chi_pad;
-    a.S_pad = S_pad;
+    a.field = fld;
     a.pad_stride = 4 * g->n_vox;
     a.I_bc = I_bc;
     a.partJ = wj ? partJ.p : nullptr;
@@ -393,14 +392,13 @@ rt_status rt_formal_solution(rt_grid_t g, int32_t n_lambda, const void *chi, con
     const size_t esz = dbl ? 8 : 4;
     const size_t padn = (size_t)n_lambda * 4 * g->n_vox;
     const int Nx = g->geo.Nx, Ny = g->geo.Ny, Nz = g->geo.Nz;
-    HIPCHK(g->fs_chi_pad.ensure(padn * esz));
-    HIPCHK(g->fs_S_pad.ensure(padn * esz));
+    HIPCHK(g->fs_fld.ensure(2 * padn * esz));
     if (dbl) {
-        HIPCHK(pad_field<double, double>((const double *)chi, nullptr, g->fs_chi_pad.as<double>(), Nx, Ny, Nz, n_lambda, st));
-        HIPCHK(pad_field<double, double>((const double *)S, nullptr, g->fs_S_pad.as<double>(), Nx, Ny, Nz, n_lambda, st));
+        HIPCHK(pad_field<double, double>((const double *)chi, nullptr, g->fs_fld.as<double>(), Nx, Ny, Nz, n_lambda, 0, st));
+        HIPCHK(pad_field<double, double>((const double *)S, nullptr, g->fs_fld.as<double>(), Nx, Ny, Nz, n_lambda, 1, st));
     } else {
-        HIPCHK(pad_field<float, float>((const float *)chi, nullptr, g->fs_chi_pad.as<float>(), Nx, Ny, Nz, n_lambda, st));
-        HIPCHK(pad_field<float, float>((const float *)S, nullptr, g->fs_S_pad.as<float>(), Nx, Ny, Nz, n_lambda, st));
+        HIPCHK(pad_field<float, float>((const float *)chi, nullptr, g->fs_fld.as<float>(), Nx, Ny, Nz, n_lambda, 0, st));
+        HIPCHK(pad_field<float, float>((const float *)S, nullptr, g->fs_fld.as<float>(), Nx, Ny, Nz, n_lambda, 1, st));
     }
     std::vector<int32_t> lams(n_lambda);
     for (int i = 0; i < n_lambda; ++i) lams[i] = i;
@@ -411,11 +409,11 @@ rt_status rt_formal_solution(rt_grid_t g, int32_t n_lambda, const void *chi, con
     DevSchedule *sc = nullptr;
     rt_status rs;
     if (joint) {
-        rs = run_fs(g, dbl, true, true, lams, g->fs_chi_pad.p, g->fs_S_pad.p, I_bc, pJ, pL, &sc, st);
+        rs = run_fs(g, dbl, true, true, lams, g->fs_fld.p, I_bc, pJ, pL, &sc, st);
         if (rs != RT_OK) return rs;
     } else {
         if (wl) {
-            rs = run_fs(g, dbl, false, true, lams, g->fs_chi_pad.p, g->fs_S_pad.p, I_bc, pJ, pL, &sc, st);
+            rs = run_fs(g, dbl, false, true, lams, g->fs_fld.p, I_bc, pJ, pL, &sc, st);
             if (rs != RT_OK) return rs;
             if (dbl)
                 HIPCHK(reduce_partials<double, double>(pL.as<double>(), sc->slot_begin.as<int32_t>(), sc->slot_ids.as<int32_t>(),
@@ -424,7 +422,7 @@ rt_status rt_formal_solution(rt_grid_t g, int32_t n_lambda, const void *chi, con
                 HIPCHK(reduce_partials<float, float>(pL.as<float>(), sc->slot_begin.as<int32_t>(), sc->slot_ids.as<int32_t>(),
                                                      sc->lambda_of.as<int32_t>(), n_lambda, (float *)lstar_out, g->n_vox, st));
         }
-        rs = run_fs(g, dbl, true, false, lams, g->fs_chi_pad.p, g->fs_S_pad.p, I_bc, pJ, pL, &sc, st);
+        rs = run_fs(g, dbl, true, false, lams, g->fs_fld.p, I_bc, pJ, pL, &sc, st);
         if (rs != RT_OK) return rs;
     }
     if (dbl) {
@@ -476,11 +474,9 @@ static rt_status ensure_state_buffers(rt_grid *g)
     const size_t nl = (size_t)g->desc.n_lambda_max;
     const size_t nv = (size_t)g->n_vox;
     const size_t esz = g->dbl ? 8 : 4;
-    HIPCHK(g->chi_pad.ensure(nl * 4 * nv * esz));
-    HIPCHK(g->S_pad.ensure(nl * 4 * nv * esz));
+    HIPCHK(g->fld.ensure(nl * 8 * nv * esz));
     if (!g->dbl) {
-        HIPCHK(g->chi_pad64.ensure(nl * 4 * nv * 8));
-        HIPCHK(g->S_pad64.ensure(nl * 4 * nv * 8));
+        HIPCHK(g->fld64.ensure(nl * 8 * nv * 8));
         HIPCHK(g->J_anchor.ensure(nl * nv * 8));
         HIPCHK(g->S_anchor.ensure(nl * nv * 8));
         HIPCHK(g->ibc64.ensure(nl * 2 * 8));
@@ -509,10 +505,10 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
     // (re)initialisation: padded opacity, S from J, fresh Ng history
     if (s->iter == 0 || s->chi != g->chi_src) {
         if (g->dbl) {
-            HIPCHK(pad_field<double, double>((const double *)s->chi, nullptr, g->chi_pad.as<double>(), Nx, Ny, Nz, nl, st));
+            HIPCHK(pad_field<double, double>((const double *)s->chi, nullptr, g->fld.as<double>(), Nx, Ny, Nz, nl, 0, st));
         } else {
-            HIPCHK(pad_field<float, float>((const float *)s->chi, nullptr, g->chi_pad.as<float>(), Nx, Ny, Nz, nl, st));
-            HIPCHK(pad_field<float, double>((const float *)s->chi, nullptr, g->chi_pad64.as<double>(), Nx, Ny, Nz, nl, st));
+            HIPCHK(pad_field<float, float>((const float *)s->chi, nullptr, g->fld.as<float>(), Nx, Ny, Nz, nl, 0, st));
+            HIPCHK(pad_field<float, double>((const float *)s->chi, nullptr, g->fld64.as<double>(), Nx, Ny, Nz, nl, 0, st));
         }
         g->chi_src = s->chi;
     }
@@ -520,7 +516,7 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
         g->hist_count = 0;
         if (g->dbl)
             HIPCHK(source_update<double, double>(s->J, (const double *)s->eps, (const double *)s->B, s->S, nullptr,
-                                                 g->S_pad.as<double>(), Nx, Ny, nv, lambda_of, nb, st));
+                                                 g->fld.as<double>(), Nx, Ny, nv, lambda_of, nb, st));
         anchor = true;
     }
 
@@ -540,7 +536,7 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
         na.eps = s->eps; na.B = s->B;
         na.S_anchor = g->dbl ? nullptr : g->S_anchor.as<double>();
         na.J = s->J; na.S = s->S;
-        na.next_pad = g->S_pad.p;
+        na.next_pad = g->fld.p;
         HIPCHK(ng_accelerate(na, g->ng_blk.as<double>(), 256, nb, g->dbl, st));
         g->hist_count = 0;
         ++*ng_count;
@@ -555,19 +551,19 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
     ua.J = s->J; ua.S = s->S;
     ua.hist = g->hist.as<double>() + (size_t)(g->hist_count % 4) * nl * nv;
     ua.rel_change = s->rel_change;
-    ua.next_pad = g->S_pad.p;
+    ua.next_pad = g->fld.p;
     DevSchedule *sc = nullptr;
 
     if (g->dbl) {
         const bool joint = want_l && variant(g, true, true, true).ok;
         if (want_l && !joint) {
-            rs = run_fs(g, true, false, true, lams, g->chi_pad.p, g->S_pad.p, s->I_bc, g->partJ64, g->partL64, &sc, st);
+            rs = run_fs(g, true, false, true, lams, g->fld.p, s->I_bc, g->partJ64, g->partL64, &sc, st);
             if (rs != RT_OK) return rs;
             HIPCHK(reduce_partials<double, double>(g->partL64.as<double>(), sc->slot_begin.as<int32_t>(), sc->slot_ids.as<int32_t>(),
                                                    sc->lambda_of.as<int32_t>(), nb, (double *)s->lstar, nv, st));
             ++*fs_count; ++*fs64_count;
         }
-        rs = run_fs(g, true, true, joint, lams, g->chi_pad.p, g->S_pad.p, s->I_bc, g->partJ64, g->partL64, &sc, st);
+        rs = run_fs(g, true, true, joint, lams, g->fld.p, s->I_bc, g->partJ64, g->partL64, &sc, st);
         if (rs != RT_OK) return rs;
         ++*fs_count; ++*fs64_count;
         if (joint)
@@ -579,7 +575,7 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
         HIPCHK(ali_update(ua, true, true, true, nb, st));
     } else {
         if (want_l) {
-            rs = run_fs(g, false, false, true, lams, g->chi_pad.p, g->S_pad.p, nullptr, g->partJ, g->partL, &sc, st);
+            rs = run_fs(g, false, false, true, lams, g->fld.p, nullptr, g->partJ, g->partL, &sc, st);
             if (rs != RT_OK) return rs;
             HIPCHK(reduce_partials<float, float>(g->partL.as<float>(), sc->slot_begin.as<int32_t>(), sc->slot_ids.as<int32_t>(),
                                                  sc->lambda_of.as<int32_t>(), nb, (float *)s->lstar, nv, st));
@@ -591,16 +587,16 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
             // double-precision anchor: S_a = S, J_a = Lambda S_a + Lambda_bc
             if (s->iter == 0)
                 HIPCHK(source_update<float, double>(s->J, (const float *)s->eps, (const float *)s->B, s->S, nullptr,
-                                                    g->S_pad64.as<double>(), Nx, Ny, nv, lambda_of, nb, st));
+                                                    g->fld64.as<double>(), Nx, Ny, nv, lambda_of, nb, st));
             else
-                HIPCHK(pad_field<double, double>(s->S, nullptr, g->S_pad64.as<double>(), Nx, Ny, Nz, nl, st));
+                HIPCHK(pad_field<double, double>(s->S, nullptr, g->fld64.as<double>(), Nx, Ny, Nz, nl, 1, st));
             HIPCHK(hipMemcpyAsync(g->S_anchor.p, s->S, (size_t)nl * nv * 8, hipMemcpyDeviceToDevice, st));
             const void *ibc = nullptr;
             if (s->I_bc) {
                 HIPCHK(cast_array<float, double>((const float *)s->I_bc, g->ibc64.as<double>(), 2 * (int64_t)nl, st));
                 ibc = g->ibc64.p;
             }
-            rs = run_fs(g, true, true, false, lams, g->chi_pad64.p, g->S_pad64.p, ibc, g->partJ64, g->partL64, &sc, st);
+            rs = run_fs(g, true, true, false, lams, g->fld64.p, ibc, g->partJ64, g->partL64, &sc, st);
             if (rs != RT_OK) return rs;
             HIPCHK(reduce_partials<double, double>(g->partJ64.as<double>(), sc->slot_begin.as<int32_t>(), sc->slot_ids.as<int32_t>(),
                                                    sc->lambda_of.as<int32_t>(), nb, g->J_anchor.as<double>(), nv, st));
@@ -610,7 +606,7 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
             ua.slot_ids = sc->slot_ids.as<int32_t>();
             HIPCHK(ali_update(ua, false, false, false, nb, st));
         } else {
-            rs = run_fs(g, false, true, false, lams, g->chi_pad.p, g->S_pad.p, nullptr, g->partJ, g->partL, &sc, st);
+            rs = run_fs(g, false, true, false, lams, g->fld.p, nullptr, g->partJ, g->partL, &sc, st);
             if (rs != RT_OK) return rs;
             ++*fs_count;
             ua.part = g->partJ.p;

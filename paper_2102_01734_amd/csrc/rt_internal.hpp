@@ -7,7 +7,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/rt3d.h"
+#include "rt3d.h"
 
 namespace rt3d {
 

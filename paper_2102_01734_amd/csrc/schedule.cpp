@@ -10,6 +10,14 @@
 // reduction adds the slots of a wavelength in a fixed order, so results do
 // not depend on timing.
 //
+// * one wavelength, workgroup count a multiple of 8 (one resident workgroup
+//   per CU; the dispatcher places workgroup i on XCD i mod 8): directions
+//   that sweep downwards go to the workgroups of XCDs 0-3, upward ones to
+//   XCDs 4-7, and each sign's directions are dealt in rounds of equal cost
+//   (sorted by cost, one item per workgroup per round, heaviest item to the
+//   least loaded workgroup).  The 32 CUs of an XCD then sweep directions of
+//   similar length through similar layers at the same time and share the
+//   opacity/source data in their L2.
 // * batch <= workgroups: every wavelength gets its own group of workgroups
 //   (sizes differ by at most one) and its directions are spread over them by
 //   longest-processing-time-first; one slot per workgroup.
@@ -42,7 +50,33 @@ void build_schedule(const BoxGeometry &g, const std::vector<int32_t> &lambdas, i
     std::vector<std::vector<WorkItem>> per_wg;
     std::vector<std::vector<int32_t>> slots_of_lambda(nl);
 
-    if (nl <= n_wg) {
+    const bool xcd_rounds = nl == 1 && n_wg % 8 == 0 && nd >= n_wg;
+    if (xcd_rounds) {
+        per_wg.assign(n_wg, {});
+        std::vector<int64_t> load(n_wg, 0);
+        for (int sign = 0; sign < 2; ++sign) {
+            std::vector<int> dirs;
+            for (int di : order)  // already sorted by decreasing cost
+                if ((g.dirs[di].mu < 0.0) == (sign == 0)) dirs.push_back(di);
+            std::vector<int> wgs;  // XCDs 0-3 for downward sweeps, 4-7 for upward
+            for (int w = 0; w < n_wg; ++w)
+                if (((w % 8) < 4) == (sign == 0)) wgs.push_back(w);
+            const int k = (int)wgs.size();
+            for (size_t r0 = 0; r0 < dirs.size(); r0 += k) {
+                const size_t r1 = std::min(dirs.size(), r0 + (size_t)k);
+                std::vector<int> by_load(wgs);
+                std::stable_sort(by_load.begin(), by_load.end(), [&](int a, int b) { return load[a] < load[b]; });
+                for (size_t t = r0; t < r1; ++t) {
+                    const int w = by_load[t - r0];
+                    per_wg[w].push_back({lambdas[0], dirs[t], w, per_wg[w].empty() ? 1 : 0});
+                    load[w] += g.dirs[dirs[t]].M;
+                }
+            }
+        }
+        out.n_slots = n_wg;
+        for (int w = 0; w < n_wg; ++w)
+            if (!per_wg[w].empty()) slots_of_lambda[0].push_back(w);
+    } else if (nl <= n_wg) {
         // workgroups per wavelength: as even as possible, but never more than directions
         std::vector<int> cnt(nl, n_wg / nl);
         for (int i = 0; i < n_wg % nl; ++i) cnt[i]++;

@@ -63,6 +63,10 @@ def lib() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"rt3d HIP library not built: {LIB_PATH} is missing "
                           "(run __graft_entry__.build() or python paper_2102_01734_amd/build.py)")
+    # torch bundles its own HIP runtime with the same soname as the system one;
+    # loading torch first makes librt3d.so bind to that single runtime (two
+    # runtimes in one process do not share the device)
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64p = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)
     L.rt_create_grid.argtypes = [ctypes.POINTER(RtGridDesc), ctypes.POINTER(vp)]

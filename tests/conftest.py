@@ -18,3 +18,14 @@ def orc():
     import oracle
     oracle.lib()
     return oracle
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _gpu_runtime(request):
+    """Initialise the HIP runtime through torch once, before any GPU test uses the library."""
+    if request.config.getoption("-m") and "not gpu" not in request.config.getoption("-m"):
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+            torch.zeros(1, device="cuda")
+    yield
