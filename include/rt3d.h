@@ -144,6 +144,10 @@ typedef struct {
     int32_t reanchor;     /* FP32 grids: new FP64 anchor once max |dJ/J| has
                              fallen by this factor since the last anchor
                              (0 = library default 100)                          */
+    int32_t use_graph;    /* 1: plain steps (no anchor, Ng or Lambda* pass) run
+                             as a captured HIP graph, replayed per step; needs
+                             a non-NULL stream.  Results are bitwise those of
+                             eager launches.                                    */
 } rt_solve_opts;
 
 typedef struct {
@@ -188,6 +192,21 @@ rt_status rt_solve(rt_grid_t grid, rt_state *state, const rt_solve_opts *opts,
  */
 rt_status rt_box_template(int32_t Nz, int32_t n_mu, int32_t n_phi, int32_t dir, int32_t cap, int32_t *di,
                           int32_t *dj, int32_t *kk, double *s, int32_t *M);
+
+/*
+ * Launch-shape autotuner (the "run-time configuration optimisation" the paper
+ * suggests, Sec. 6): times the single-output (J) formal-solution kernel of the
+ * grid's precision for every compiled (workgroup size, rays per thread) shape
+ * that can hold one direction's rays, on the caller's fields (n_lambda
+ * wavelengths of chi and S, device, as in rt_formal_solution, zero boundary
+ * intensity), and keeps the fastest for all later formal solutions and ALI
+ * steps of this grid.  The shape changes only how directions are grouped
+ * into workgroup partial sums, i.e. the summation order of J (differences
+ * at the rounding level of the grid precision).  Blocks.
+ * threads_out / rays_out (may be NULL) receive the chosen shape.
+ */
+rt_status rt_autotune(rt_grid_t grid, int32_t n_lambda, const void *chi, const void *S, int32_t *threads_out,
+                      int32_t *rays_out, void *stream);
 
 /*
  * Measurement hooks.  While enabled, every formal-solution kernel launch of

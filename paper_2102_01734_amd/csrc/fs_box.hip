@@ -221,8 +221,8 @@ __device__ __forceinline__ Pair<double> ld_pair<double>(__amdgpu_buffer_rsrc_t r
 // ---------------------------------------------------------------------------
 // the sweep kernel
 // ---------------------------------------------------------------------------
-template <typename T, int R, bool WJ, bool WL, bool PARA>
-__global__ void __launch_bounds__(1024) fs_box_kernel(FsBoxArgs a)
+template <typename T, int LB, int R, bool WJ, bool WL, bool PARA>
+__global__ void __launch_bounds__(LB) fs_box_kernel(FsBoxArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int Nx = a.Nx, Ny = a.Ny;
@@ -403,106 +403,118 @@ __global__ void __launch_bounds__(1024) fs_box_kernel(FsBoxArgs a)
 
 // ---------------------------------------------------------------------------
 // host-side dispatch
+//
+// Launch shapes: (threads per workgroup bound LB, rays per thread R).  All
+// output combinations exist for LB = 1024; the other shapes exist for the
+// J-only kernel, which runs every ALI step and is the one the autotuner
+// (rt_autotune) times.
 // ---------------------------------------------------------------------------
-template <typename T, int R, bool WJ, bool WL, bool PARA>
-static hipError_t launch_r(const FsBoxArgs &a, int n_wg, int nthr, size_t lds, hipStream_t st)
+#define RT_FS_SHAPES_FULL(X) X(1024, 1) X(1024, 2) X(1024, 4) X(1024, 8) X(1024, 12) X(1024, 17) X(1024, 24)
+#define RT_FS_SHAPES_TUNE(X)                                                                                  \
+    X(768, 2) X(768, 6) X(768, 11) X(768, 22) X(768, 32) X(512, 3) X(512, 9) X(512, 17) X(512, 33) X(256, 5)   \
+        X(256, 17) X(256, 34)
+
+static const FsShape kShapes[] = {
+#define RT_LIST(lb, r) {lb, r, true},
+    RT_FS_SHAPES_FULL(RT_LIST)
+#undef RT_LIST
+#define RT_LIST(lb, r) {lb, r, false},
+    RT_FS_SHAPES_TUNE(RT_LIST)
+#undef RT_LIST
+};
+
+int fs_box_shapes(const FsShape **out)
 {
-    auto k = fs_box_kernel<T, R, WJ, WL, PARA>;
+    *out = kShapes;
+    return (int)(sizeof(kShapes) / sizeof(kShapes[0]));
+}
+
+template <typename T, int LB, int R, bool WJ, bool WL, bool PARA>
+static hipError_t launch_one(const FsBoxArgs &a, int n_wg, int nthr, size_t lds, hipStream_t st)
+{
+    auto k = fs_box_kernel<T, LB, R, WJ, WL, PARA>;
     hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3(n_wg), dim3(nthr), lds, st, a);
     return hipGetLastError();
 }
 
-template <typename T, bool WJ, bool WL, bool PARA>
-static hipError_t launch_flags(const FsBoxArgs &a, int R, int n_wg, int nthr, size_t lds, hipStream_t st)
-{
-    switch (R) {
-    case 1: return launch_r<T, 1, WJ, WL, PARA>(a, n_wg, nthr, lds, st);
-    case 2: return launch_r<T, 2, WJ, WL, PARA>(a, n_wg, nthr, lds, st);
-    case 4: return launch_r<T, 4, WJ, WL, PARA>(a, n_wg, nthr, lds, st);
-    case 8: return launch_r<T, 8, WJ, WL, PARA>(a, n_wg, nthr, lds, st);
-    case 12: return launch_r<T, 12, WJ, WL, PARA>(a, n_wg, nthr, lds, st);
-    case 17: return launch_r<T, 17, WJ, WL, PARA>(a, n_wg, nthr, lds, st);
-    case 24: return launch_r<T, 24, WJ, WL, PARA>(a, n_wg, nthr, lds, st);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-int fs_box_pick_r(int n_rays, int max_threads, int *nthr)
-{
-    static const int Rs[] = {1, 2, 4, 8, 12, 17, 24};
-    for (int R : Rs) {
-        const int need = (n_rays + R - 1) / R;
-        if (need <= max_threads) {
-            int t = ((need + 63) / 64) * 64;
-            if (t > max_threads) t = max_threads;
-            *nthr = t;
-            return R;
-        }
-    }
-    return 0;
-}
-
-template <typename T>
-static hipError_t launch_t(const FsBoxArgs &a, bool wj, bool wl, bool para, int R, int n_wg, int nthr, size_t lds,
-                           hipStream_t st)
-{
-    if (wj && wl && para) return launch_flags<T, true, true, true>(a, R, n_wg, nthr, lds, st);
-    if (wj && wl) return launch_flags<T, true, true, false>(a, R, n_wg, nthr, lds, st);
-    if (wj) return launch_flags<T, true, false, false>(a, R, n_wg, nthr, lds, st);
-    if (wl && para) return launch_flags<T, false, true, true>(a, R, n_wg, nthr, lds, st);
-    if (wl) return launch_flags<T, false, true, false>(a, R, n_wg, nthr, lds, st);
-    return hipSuccess;
-}
-
-hipError_t fs_box_launch(const FsBoxArgs &a, bool is_double, bool want_j, bool want_l, bool para, int R,
-                         int n_wg, int nthr, size_t lds, hipStream_t st)
-{
-    if (n_wg <= 0) return hipSuccess;
-    return is_double ? launch_t<double>(a, want_j, want_l, para, R, n_wg, nthr, lds, st)
-                     : launch_t<float>(a, want_j, want_l, para, R, n_wg, nthr, lds, st);
-}
-
-template <typename T, int R, bool WJ, bool WL, bool PARA>
-static int occ_r(int nthr, size_t lds)
+template <typename T, int LB, int R, bool WJ, bool WL, bool PARA>
+static int occ_one(int nthr, size_t lds)
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fs_box_kernel<T, R, WJ, WL, PARA>, nthr, lds) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fs_box_kernel<T, LB, R, WJ, WL, PARA>, nthr, lds) !=
+        hipSuccess)
         return 0;
     return n;
 }
 
-template <typename T, bool WJ, bool WL, bool PARA>
-static int occ_flags(int R, int nthr, size_t lds)
+template <typename T, int LB, int R>
+static hipError_t launch_flags(const FsBoxArgs &a, bool wj, bool wl, bool para, int n_wg, int nthr, size_t lds,
+                               hipStream_t st)
 {
-    switch (R) {
-    case 1: return occ_r<T, 1, WJ, WL, PARA>(nthr, lds);
-    case 2: return occ_r<T, 2, WJ, WL, PARA>(nthr, lds);
-    case 4: return occ_r<T, 4, WJ, WL, PARA>(nthr, lds);
-    case 8: return occ_r<T, 8, WJ, WL, PARA>(nthr, lds);
-    case 12: return occ_r<T, 12, WJ, WL, PARA>(nthr, lds);
-    case 17: return occ_r<T, 17, WJ, WL, PARA>(nthr, lds);
-    case 24: return occ_r<T, 24, WJ, WL, PARA>(nthr, lds);
-    default: return 0;
-    }
+    if (wj && wl && para) return launch_one<T, LB, R, true, true, true>(a, n_wg, nthr, lds, st);
+    if (wj && wl) return launch_one<T, LB, R, true, true, false>(a, n_wg, nthr, lds, st);
+    if (wj) return launch_one<T, LB, R, true, false, false>(a, n_wg, nthr, lds, st);
+    if (wl && para) return launch_one<T, LB, R, false, true, true>(a, n_wg, nthr, lds, st);
+    if (wl) return launch_one<T, LB, R, false, true, false>(a, n_wg, nthr, lds, st);
+    return hipSuccess;
 }
 
-template <typename T>
-static int occ_t(bool wj, bool wl, bool para, int R, int nthr, size_t lds)
+template <typename T, int LB, int R>
+static int occ_flags(bool wj, bool wl, bool para, int nthr, size_t lds)
 {
-    if (wj && wl && para) return occ_flags<T, true, true, true>(R, nthr, lds);
-    if (wj && wl) return occ_flags<T, true, true, false>(R, nthr, lds);
-    if (wj) return occ_flags<T, true, false, false>(R, nthr, lds);
-    if (wl && para) return occ_flags<T, false, true, true>(R, nthr, lds);
-    if (wl) return occ_flags<T, false, true, false>(R, nthr, lds);
+    if (wj && wl && para) return occ_one<T, LB, R, true, true, true>(nthr, lds);
+    if (wj && wl) return occ_one<T, LB, R, true, true, false>(nthr, lds);
+    if (wj) return occ_one<T, LB, R, true, false, false>(nthr, lds);
+    if (wl && para) return occ_one<T, LB, R, false, true, true>(nthr, lds);
+    if (wl) return occ_one<T, LB, R, false, true, false>(nthr, lds);
     return 0;
 }
 
-int fs_box_occupancy(bool is_double, bool want_j, bool want_l, bool para, int R, int nthr, size_t lds)
+template <typename T>
+static hipError_t launch_t(const FsBoxArgs &a, bool wj, bool wl, bool para, int lb, int R, int n_wg, int nthr,
+                           size_t lds, hipStream_t st)
 {
-    return is_double ? occ_t<double>(want_j, want_l, para, R, nthr, lds)
-                     : occ_t<float>(want_j, want_l, para, R, nthr, lds);
+#define RT_CASE(LBv, Rv) \
+    if (lb == LBv && R == Rv) return launch_flags<T, LBv, Rv>(a, wj, wl, para, n_wg, nthr, lds, st);
+    RT_FS_SHAPES_FULL(RT_CASE)
+#undef RT_CASE
+    if (!(wj && !wl)) return hipErrorInvalidValue;
+#define RT_CASE(LBv, Rv) \
+    if (lb == LBv && R == Rv) return launch_one<T, LBv, Rv, true, false, false>(a, n_wg, nthr, lds, st);
+    RT_FS_SHAPES_TUNE(RT_CASE)
+#undef RT_CASE
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+static int occ_t(bool wj, bool wl, bool para, int lb, int R, int nthr, size_t lds)
+{
+#define RT_CASE(LBv, Rv) \
+    if (lb == LBv && R == Rv) return occ_flags<T, LBv, Rv>(wj, wl, para, nthr, lds);
+    RT_FS_SHAPES_FULL(RT_CASE)
+#undef RT_CASE
+    if (!(wj && !wl)) return 0;
+#define RT_CASE(LBv, Rv) \
+    if (lb == LBv && R == Rv) return occ_one<T, LBv, Rv, true, false, false>(nthr, lds);
+    RT_FS_SHAPES_TUNE(RT_CASE)
+#undef RT_CASE
+    return 0;
+}
+
+hipError_t fs_box_launch(const FsBoxArgs &a, bool is_double, bool want_j, bool want_l, bool para, int lb, int R,
+                         int n_wg, int nthr, size_t lds, hipStream_t st)
+{
+    if (n_wg <= 0) return hipSuccess;
+    return is_double ? launch_t<double>(a, want_j, want_l, para, lb, R, n_wg, nthr, lds, st)
+                     : launch_t<float>(a, want_j, want_l, para, lb, R, n_wg, nthr, lds, st);
+}
+
+int fs_box_occupancy(bool is_double, bool want_j, bool want_l, bool para, int lb, int R, int nthr, size_t lds)
+{
+    return is_double ? occ_t<double>(want_j, want_l, para, lb, R, nthr, lds)
+                     : occ_t<float>(want_j, want_l, para, lb, R, nthr, lds);
 }
 
 }  // namespace rt3d

@@ -33,13 +33,18 @@ struct FsBoxArgs {
     void *partL;
 };
 
-// Rays per thread R and threads per workgroup for a direction of n_rays rays.
-int fs_box_pick_r(int n_rays, int max_threads, int *nthr);
+// A compiled launch shape: workgroup size bound `lb`, rays per thread `R`;
+// `full`: available for every output combination (else J-only).
+struct FsShape {
+    int lb, R;
+    bool full;
+};
+int fs_box_shapes(const FsShape **out);
 
 hipError_t fs_box_launch(const FsBoxArgs &a, bool is_double, bool want_j, bool want_l, bool parabolic_lstar,
-                         int R, int n_wg, int nthr, size_t lds_bytes, hipStream_t stream);
+                         int lb, int R, int n_wg, int nthr, size_t lds_bytes, hipStream_t stream);
 
-int fs_box_occupancy(bool is_double, bool want_j, bool want_l, bool parabolic_lstar, int R, int nthr,
+int fs_box_occupancy(bool is_double, bool want_j, bool want_l, bool parabolic_lstar, int lb, int R, int nthr,
                      size_t lds_bytes);
 
 }  // namespace rt3d

@@ -74,7 +74,7 @@ struct DevBuf {
 // One kernel variant: element type, outputs, launch shape and resident count.
 struct Variant {
     bool dbl = false, wj = false, wl = false;
-    int R = 0, nthr = 0, n_wg = 0;
+    int lb = 0, R = 0, nthr = 0, n_wg = 0;
     size_t lds = 0;
     bool ok = false;
 };
@@ -99,6 +99,7 @@ struct rt_grid {
 
     DevBuf goff, dxy, s, vbegin, M, wmu, mu;
     Variant var[2][2][2];  // [dbl][wj][wl]
+    bool tuned = false;
 
     std::map<std::string, std::unique_ptr<DevSchedule>> schedules;
 
@@ -110,34 +111,57 @@ struct rt_grid {
     DevBuf J_anchor, S_anchor, hist, ng_blk, ng_coef;
     int hist_count = 0;
     const void *chi_src = nullptr;
+    // captured plain ALI steps, keyed by batch, ring slot and state pointers
+    std::map<std::string, hipGraphExec_t> graphs;
     // measurement hooks
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
     int64_t prof_points = 0;
-    std::vector<int64_t> dir_points;  // rays x visits of one direction
+    void drop_graphs()
+    {
+        for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        graphs.clear();
+    }
     ~rt_grid()
     {
         for (auto &e : prof_events) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+        drop_graphs();
     }
 };
 
 static Variant &variant(rt_grid *g, bool dbl, bool wj, bool wl) { return g->var[dbl][wj][wl]; }
 
-static void setup_variant(rt_grid *g, bool dbl, bool wj, bool wl)
+// Resident-workgroup count and LDS size of one launch shape; ok = false when
+// the shape cannot hold all rays of a direction or its tiles do not fit.
+static Variant make_variant(rt_grid *g, bool dbl, bool wj, bool wl, int lb, int R)
 {
-    Variant &v = variant(g, dbl, wj, wl);
-    v = Variant();
-    v.dbl = dbl; v.wj = wj; v.wl = wl;
+    Variant v;
+    v.dbl = dbl; v.wj = wj; v.wl = wl; v.lb = lb; v.R = R;
     const int rays = g->geo.Nx * g->geo.Ny;
-    v.R = fs_box_pick_r(rays, 1024, &v.nthr);
-    if (v.R == 0) return;
+    const int need = (rays + R - 1) / R;
+    if (need > lb) return v;
+    v.nthr = std::min(lb, ((need + 63) / 64) * 64);
     // per tile: one word per voxel of a layer plus one scratch word per thread
     v.lds = (size_t)(rays + v.nthr) * (dbl ? 8 : 4) * ((wj ? 1 : 0) + (wl ? 1 : 0));
-    if (v.lds > g->max_lds) return;
-    int occ = fs_box_occupancy(dbl, wj, wl, g->para, v.R, v.nthr, v.lds);
-    if (occ <= 0) return;
+    if (v.lds > g->max_lds) return v;
+    const int occ = fs_box_occupancy(dbl, wj, wl, g->para, lb, R, v.nthr, v.lds);
+    if (occ <= 0) return v;
     v.n_wg = occ * g->n_cu;
     v.ok = true;
+    return v;
+}
+
+// Default shape: 1024-thread workgroups with the fewest rays per thread.
+static void setup_variant(rt_grid *g, bool dbl, bool wj, bool wl)
+{
+    const FsShape *sh = nullptr;
+    const int n = fs_box_shapes(&sh);
+    variant(g, dbl, wj, wl) = Variant();
+    for (int i = 0; i < n; ++i) {
+        if (!sh[i].full || sh[i].lb != 1024) continue;
+        Variant v = make_variant(g, dbl, wj, wl, sh[i].lb, sh[i].R);
+        if (v.ok) { variant(g, dbl, wj, wl) = v; return; }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -170,7 +194,10 @@ static rt_status get_schedule(rt_grid *g, int n_wg, const std::vector<int32_t> &
     HIPCHK(up(ds->slot_begin, sc.slot_begin.data(), sc.slot_begin.size() * sizeof(int32_t)));
     HIPCHK(up(ds->slot_ids, sc.slot_ids.data(), sc.slot_ids.size() * sizeof(int32_t)));
     HIPCHK(up(ds->lambda_of, lambdas.data(), lambdas.size() * sizeof(int32_t)));
-    if (g->schedules.size() > 64) g->schedules.clear();
+    if (g->schedules.size() > 64) {
+        g->drop_graphs();  // captured graphs reference schedule buffers
+        g->schedules.clear();
+    }
     *out = ds.get();
     g->schedules[key] = std::move(ds);
     return RT_OK;
@@ -179,11 +206,11 @@ static rt_status get_schedule(rt_grid *g, int n_wg, const std::vector<int32_t> &
 // ---------------------------------------------------------------------------
 // formal solution on padded inputs already in place
 // ---------------------------------------------------------------------------
-static rt_status run_fs(rt_grid *g, bool dbl, bool wj, bool wl, const std::vector<int32_t> &lambdas,
-                        const void *fld, const void *I_bc, DevBuf &partJ, DevBuf &partL, DevSchedule **sched_out,
-                        hipStream_t st)
+static rt_status run_fs_with(rt_grid *g, const Variant &v, const std::vector<int32_t> &lambdas, const void *fld,
+                             const void *I_bc, DevBuf &partJ, DevBuf &partL, DevSchedule **sched_out,
+                             hipStream_t st)
 {
-    Variant &v = variant(g, dbl, wj, wl);
+    const bool dbl = v.dbl, wj = v.wj, wl = v.wl;
     if (!v.ok) return fail(RT_E_UNSUPPORTED, "no kernel configuration fits this grid (layer tile of %d voxels)",
                            g->geo.Nx * g->geo.Ny);
     DevSchedule *sc = nullptr;
@@ -214,15 +241,22 @@ static rt_status run_fs(rt_grid *g, bool dbl, bool wj, bool wl, const std::vecto
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
         HIPCHK(hipEventRecord(e0, st));
-        HIPCHK(fs_box_launch(a, dbl, wj, wl, g->para, v.R, sc->n_wg, v.nthr, v.lds, st));
+        HIPCHK(fs_box_launch(a, dbl, wj, wl, g->para, v.lb, v.R, sc->n_wg, v.nthr, v.lds, st));
         HIPCHK(hipEventRecord(e1, st));
         g->prof_events.push_back({e0, e1});
         g->prof_points += sc->points;
     } else {
-        HIPCHK(fs_box_launch(a, dbl, wj, wl, g->para, v.R, sc->n_wg, v.nthr, v.lds, st));
+        HIPCHK(fs_box_launch(a, dbl, wj, wl, g->para, v.lb, v.R, sc->n_wg, v.nthr, v.lds, st));
     }
     *sched_out = sc;
     return RT_OK;
+}
+
+static rt_status run_fs(rt_grid *g, bool dbl, bool wj, bool wl, const std::vector<int32_t> &lambdas,
+                        const void *fld, const void *I_bc, DevBuf &partJ, DevBuf &partL, DevSchedule **sched_out,
+                        hipStream_t st)
+{
+    return run_fs_with(g, variant(g, dbl, wj, wl), lambdas, fld, I_bc, partJ, partL, sched_out, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -339,6 +373,66 @@ rt_status rt_destroy_grid(rt_grid_t grid)
     if (!grid) return fail(RT_E_INVALID, "grid is NULL");
     (void)hipDeviceSynchronize();
     delete grid;
+    return RT_OK;
+}
+
+rt_status rt_autotune(rt_grid_t g, int32_t n_lambda, const void *chi, const void *S, int32_t *threads_out,
+                      int32_t *rays_out, void *stream)
+{
+    if (!g) return fail(RT_E_INVALID, "grid is NULL");
+    if (n_lambda < 1 || n_lambda > g->desc.n_lambda_max)
+        return fail(RT_E_INVALID, "n_lambda %d outside [1, %d]", n_lambda, g->desc.n_lambda_max);
+    if (!chi || !S) return fail(RT_E_INVALID, "chi and S must not be NULL");
+    hipStream_t st = (hipStream_t)stream;
+    const bool dbl = g->dbl;
+    const int Nx = g->geo.Nx, Ny = g->geo.Ny, Nz = g->geo.Nz;
+    HIPCHK(g->fs_fld.ensure(8 * (size_t)n_lambda * g->n_vox * (dbl ? 8 : 4)));
+    if (dbl) {
+        HIPCHK(pad_field<double, double>((const double *)chi, nullptr, g->fs_fld.as<double>(), Nx, Ny, Nz, n_lambda, 0, st));
+        HIPCHK(pad_field<double, double>((const double *)S, nullptr, g->fs_fld.as<double>(), Nx, Ny, Nz, n_lambda, 1, st));
+    } else {
+        HIPCHK(pad_field<float, float>((const float *)chi, nullptr, g->fs_fld.as<float>(), Nx, Ny, Nz, n_lambda, 0, st));
+        HIPCHK(pad_field<float, float>((const float *)S, nullptr, g->fs_fld.as<float>(), Nx, Ny, Nz, n_lambda, 1, st));
+    }
+    std::vector<int32_t> lams(n_lambda);
+    for (int i = 0; i < n_lambda; ++i) lams[i] = i;
+    const FsShape *sh = nullptr;
+    const int n = fs_box_shapes(&sh);
+    Variant best = variant(g, dbl, true, false);
+    float best_ms = 1e30f;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const bool prof = g->prof;
+    g->prof = false;
+    rt_status rs = RT_OK;
+    for (int i = 0; i < n && rs == RT_OK; ++i) {
+        const Variant v = make_variant(g, dbl, true, false, sh[i].lb, sh[i].R);
+        if (!v.ok) continue;
+        DevSchedule *sc = nullptr;
+        DevBuf &pJ = dbl ? g->partJ64 : g->partJ;
+        DevBuf &pL = dbl ? g->partL64 : g->partL;
+        rs = run_fs_with(g, v, lams, g->fs_fld.p, nullptr, pJ, pL, &sc, st);  // warm-up
+        if (rs != RT_OK) break;
+        if (hipEventRecord(e0, st) != hipSuccess) { rs = fail(RT_E_HIP, "event record failed"); break; }
+        rs = run_fs_with(g, v, lams, g->fs_fld.p, nullptr, pJ, pL, &sc, st);
+        if (rs != RT_OK) break;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            rs = fail(RT_E_HIP, "event timing failed");
+            break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) { best_ms = ms; best = v; }
+    }
+    g->prof = prof;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rs != RT_OK) return rs;
+    variant(g, dbl, true, false) = best;
+    g->tuned = true;
+    if (threads_out) *threads_out = best.nthr;
+    if (rays_out) *rays_out = best.R;
     return RT_OK;
 }
 
@@ -465,6 +559,7 @@ static rt_status check_opts(const rt_solve_opts *o)
     if (!(o->tol > 0.0)) return fail(RT_E_INVALID, "opts->tol must be > 0");
     if (o->max_iter < 1) return fail(RT_E_INVALID, "opts->max_iter must be >= 1");
     if (o->ng_every < 0 || o->ng_start < 0 || o->reanchor < 0) return fail(RT_E_INVALID, "negative Ng/anchor option");
+    if (o->use_graph != 0 && o->use_graph != 1) return fail(RT_E_INVALID, "opts->use_graph must be 0 or 1");
     return RT_OK;
 }
 
@@ -484,6 +579,85 @@ static rt_status ensure_state_buffers(rt_grid *g)
     HIPCHK(g->hist.ensure(4 * nl * nv * 8));
     HIPCHK(g->ng_blk.ensure(nl * 256 * 5 * 8));
     HIPCHK(g->ng_coef.ensure(nl * 3 * 8));
+    return RT_OK;
+}
+
+// The plain step (Lambda* known, no anchor, no Ng): clear the norms, formal
+// solution of the current S (FP64 grids) or of S - S_anchor (FP32 grids), and
+// the fused update.  Issues only kernel launches, so it can be captured.
+static rt_status plain_step_launches(rt_grid *g, rt_state *s, const std::vector<int32_t> &lams,
+                                     const int32_t *lambda_of, hipStream_t st)
+{
+    const int nl = s->n_lambda, nb = (int)lams.size();
+    const int64_t nv = g->n_vox;
+    HIPCHK(fill_u64(reinterpret_cast<unsigned long long *>(s->rel_change), 0ull, nl, st));
+    AliUpdateArgs ua{};
+    ua.Nx = g->geo.Nx; ua.Ny = g->geo.Ny; ua.n_vox = nv;
+    ua.lambda_of = lambda_of;
+    ua.eps = s->eps; ua.B = s->B; ua.lstar = s->lstar;
+    ua.J = s->J; ua.S = s->S;
+    ua.hist = g->hist.as<double>() + (size_t)(g->hist_count % 4) * nl * nv;
+    ua.rel_change = s->rel_change;
+    ua.next_pad = g->fld.p;
+    DevSchedule *sc = nullptr;
+    rt_status rs;
+    if (g->dbl) {
+        rs = run_fs(g, true, true, false, lams, g->fld.p, s->I_bc, g->partJ64, g->partL64, &sc, st);
+        if (rs != RT_OK) return rs;
+        ua.part = g->partJ64.p;
+    } else {
+        rs = run_fs(g, false, true, false, lams, g->fld.p, nullptr, g->partJ, g->partL, &sc, st);
+        if (rs != RT_OK) return rs;
+        ua.part = g->partJ.p;
+        ua.S_anchor = g->S_anchor.as<double>();
+        ua.J_anchor = g->J_anchor.as<double>();
+    }
+    ua.slot_begin = sc->slot_begin.as<int32_t>();
+    ua.slot_ids = sc->slot_ids.as<int32_t>();
+    HIPCHK(ali_update(ua, g->dbl, g->dbl, g->dbl, nb, st));
+    return RT_OK;
+}
+
+// The plain step through a captured HIP graph: captured on first use for this
+// batch, Ng ring slot and state, then replayed.  Schedules and partial-slot
+// buffers are prepared before capture so the capture sees launches only.
+static rt_status graph_plain_step(rt_grid *g, rt_state *s, const std::vector<int32_t> &lams,
+                                  const int32_t *lambda_of, hipStream_t st)
+{
+    const Variant &v = variant(g, g->dbl, true, false);
+    DevSchedule *sc = nullptr;
+    rt_status rs = get_schedule(g, v.n_wg, lams, &sc);
+    if (rs != RT_OK) return rs;
+    DevBuf &pJ = g->dbl ? g->partJ64 : g->partJ;
+    HIPCHK(pJ.ensure((size_t)sc->n_slots * g->n_vox * (g->dbl ? 8 : 4)));
+    char buf[512];
+    snprintf(buf, sizeof buf, "%d|%p|%p|%p|%p|%p|%p|%p|%p|%d|%d|%d:", g->hist_count % 4, (void *)s->J,
+             (void *)s->S, s->lstar, s->eps, s->B, (void *)s->rel_change, pJ.p, (void *)st, s->n_lambda,
+             v.lb, v.R);
+    std::string key(buf);
+    for (int l : lams) key += std::to_string(l) + ",";
+    auto it = g->graphs.find(key);
+    if (it == g->graphs.end()) {
+        if (g->graphs.size() > 32) g->drop_graphs();
+        const bool prof = g->prof;
+        g->prof = false;
+        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        rs = plain_step_launches(g, s, lams, lambda_of, st);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(st, &graph);
+        g->prof = prof;
+        if (rs != RT_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rs;
+        }
+        HIPCHK(e);
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPCHK(e);
+        it = g->graphs.emplace(key, exec).first;
+    }
+    HIPCHK(hipGraphLaunch(it->second, st));
     return RT_OK;
 }
 
@@ -542,8 +716,20 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
         ++*ng_count;
     }
 
-    HIPCHK(fill_u64(reinterpret_cast<unsigned long long *>(s->rel_change), 0ull, nl, st));
     const bool want_l = s->lstar_valid == 0;
+    if (!want_l && (g->dbl || !anchor)) {
+        if (o->use_graph && st != nullptr)
+            rs = graph_plain_step(g, s, lams, lambda_of, st);
+        else
+            rs = plain_step_launches(g, s, lams, lambda_of, st);
+        if (rs != RT_OK) return rs;
+        ++*fs_count;
+        if (g->dbl) ++*fs64_count;
+        g->hist_count++;
+        s->iter++;
+        return RT_OK;
+    }
+    HIPCHK(fill_u64(reinterpret_cast<unsigned long long *>(s->rel_change), 0ull, nl, st));
     AliUpdateArgs ua{};
     ua.Nx = Nx; ua.Ny = Ny; ua.n_vox = nv;
     ua.lambda_of = lambda_of;

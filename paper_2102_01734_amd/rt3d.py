@@ -37,7 +37,8 @@ class RtState(ctypes.Structure):
 
 class RtSolveOpts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
-                ("ng_every", ctypes.c_int32), ("ng_start", ctypes.c_int32), ("reanchor", ctypes.c_int32)]
+                ("ng_every", ctypes.c_int32), ("ng_start", ctypes.c_int32), ("reanchor", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32)]
 
 
 class RtSolveReport(ctypes.Structure):
@@ -78,6 +79,8 @@ def lib() -> ctypes.CDLL:
                            ctypes.POINTER(RtSolveReport), vp]
     for f in ("rt_create_grid", "rt_destroy_grid", "rt_grid_info", "rt_formal_solution", "rt_ali_step", "rt_solve"):
         getattr(L, f).restype = ctypes.c_int
+    L.rt_autotune.argtypes = [vp, i32, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32), vp]
+    L.rt_autotune.restype = ctypes.c_int
     L.rt_profile_enable.argtypes = [vp, i32]
     L.rt_profile_enable.restype = ctypes.c_int
     L.rt_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32), i64p]
@@ -146,6 +149,14 @@ def rt_solve(grid: int, state: RtState, opts: RtSolveOpts, stream: Optional[int]
     st = _check(lib().rt_solve(ctypes.c_void_p(grid), ctypes.byref(state), ctypes.byref(opts), ctypes.byref(rep),
                                ctypes.c_void_p(stream or None)), "rt_solve", allow=(RT_E_NOT_CONVERGED,))
     return st, rep
+
+
+def rt_autotune(grid: int, n_lambda: int, chi: int, S: int, stream: Optional[int]):
+    """Times the compiled launch shapes on these fields; returns (threads, rays per thread) kept."""
+    t, r = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().rt_autotune(ctypes.c_void_p(grid), int(n_lambda), ctypes.c_void_p(chi), ctypes.c_void_p(S),
+                             ctypes.byref(t), ctypes.byref(r), ctypes.c_void_p(stream or None)), "rt_autotune")
+    return t.value, r.value
 
 
 def rt_profile_enable(grid: int, enable: bool) -> None:
@@ -247,6 +258,11 @@ class Grid:
                            _stream_ptr(stream))
         return J, L
 
+    def autotune(self, chi, S, stream=None):
+        n = chi.shape[0]
+        return rt_autotune(self.handle, n, self._check_field(chi, n, "chi"), self._check_field(S, n, "S"),
+                           _stream_ptr(stream))
+
     def new_state(self, chi, eps, B, I_bc=None, J0=None):
         """Allocates the ALI state (J, S, Lambda*, norms) for a batch; J starts at B."""
         import torch
@@ -270,10 +286,11 @@ class Grid:
         return st
 
     @staticmethod
-    def opts(tol=1e-8, max_iter=1000, ng_every=4, ng_start=4, reanchor=0):
+    def opts(tol=1e-8, max_iter=1000, ng_every=4, ng_start=4, reanchor=0, use_graph=False):
         o = RtSolveOpts()
         o.struct_size = ctypes.sizeof(RtSolveOpts)
         o.tol, o.max_iter, o.ng_every, o.ng_start, o.reanchor = tol, max_iter, ng_every, ng_start, reanchor
+        o.use_graph = int(bool(use_graph))
         return o
 
     def ali_step(self, state: RtState, opts: RtSolveOpts, stream=None):

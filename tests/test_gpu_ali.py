@@ -142,3 +142,39 @@ def test_invalid_state_and_options():
     with pytest.raises(rt.RtError):
         g.ali_step(st, g.opts())
     g.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_graph_replay_equals_eager_bitwise(prec):
+    """Plain steps replayed from a captured HIP graph give bitwise the eager iterates
+    (several replays, with host synchronisation between them)."""
+    torch = torch_cuda()
+    case = sy.random_box(11, 9, 7, 4, 8, seed=71, dtype=prec, n_lambda=2, eps_dex=(-3, -1))
+    outs = []
+    for use_graph in (False, True):
+        g = make_grid(case)
+        st = g.new_state(to_dev(case.chi, prec), to_dev(case.eps, prec), to_dev(case.B, prec),
+                         to_dev(case.I_bc, prec))
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            status, rep = g.solve(st, g.opts(tol=1e-11, max_iter=400, use_graph=use_graph), stream=stream)
+        stream.synchronize()
+        outs.append((status, rep.iters, g.state_tensors(st)["J"].cpu().numpy().copy()))
+        g.close()
+    assert outs[0][0] == outs[1][0] == 0
+    assert outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][2], outs[1][2])
+
+
+def test_batched_wavelengths_converge_independently(orc):
+    """A batch with very different opacity scales and eps: every wavelength reaches
+    its own fixed point; converged ones drop out of later steps."""
+    case = sy.random_box(8, 8, 6, 4, 8, seed=73, dtype="f64", n_lambda=4)
+    scale = np.array([1e-2, 1.0, 30.0, 3e2])
+    case.chi = case.chi * scale[:, None, None, None]
+    case.eps[:] = np.array([0.5, 0.1, 0.03, 0.01])[:, None, None, None]
+    r = gpu_solve(case, tol=1e-12, max_iter=3000)
+    assert r["status"] == 0 and r["report"].n_converged == 4
+    for l in range(4):
+        ref = _lu(orc, case, l)
+        np.testing.assert_allclose(r["J"][l], ref["J"], rtol=1e-9)

@@ -147,3 +147,18 @@ def test_fs_full_size_lognormal_sampled(orc):
     np.testing.assert_allclose(J[0].ravel()[vox], Jo, rtol=2e-5, atol=1e-6 * np.abs(Jo).max())
     np.testing.assert_allclose(L[0].ravel()[vox], Lo, rtol=2e-5, atol=1e-7)
     assert np.all(np.isfinite(J)) and np.all((L > 0) & (L < 1))
+
+
+def test_autotune_keeps_results(orc):
+    """The shape the autotuner picks changes only the grouping of directions into
+    partial sums: J agrees to single-precision rounding."""
+    torch = torch_cuda()
+    case = sy.random_box(40, 37, 9, 4, 8, seed=81, dtype="f32")
+    S = sy.random_source(case.chi.shape, seed=82, dtype="f32")
+    g = make_grid(case)
+    J0, _ = gpu_fs(case, S, grid=g, want_lstar=False)
+    threads, rays = g.autotune(to_dev(case.chi, "f32"), to_dev(S, "f32"))
+    assert threads * rays >= case.Nx * case.Ny
+    J1, _ = gpu_fs(case, S, grid=g, want_lstar=False)
+    g.close()
+    np.testing.assert_allclose(J1, J0, rtol=2e-6, atol=1e-7 * np.abs(J0).max())
