@@ -88,6 +88,7 @@ def main():
     ap.add_argument("--workload", default="lognormal129", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-dirs", type=int, default=24, help="directions in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1 "
@@ -107,6 +108,10 @@ def main():
     B = torch.tensor(case.B, **dev)
     Ibc = torch.tensor(case.I_bc, **dev)
     g = rt.Grid(case.Nx, case.Ny, case.Nz, case.n_mu, case.n_phi, "f32", 1)
+    # launch-shape autotuning on this workload (part of setup, not timed)
+    S0 = torch.tensor(sy.random_source(case.chi.shape, seed=7, lo=0.2, hi=1.0, dtype="f32"), **dev)
+    shape = g.autotune(chi, S0) if not args.no_autotune else None
+    del S0
     info = g.info()
     st = g.new_state(chi, eps, B, Ibc)
     opts = g.opts(tol=1e-30, max_iter=1, ng_every=4, ng_start=4)
@@ -154,6 +159,7 @@ def main():
             "voxels": case.n_vox, "directions": case.n_dir, "wavelengths": case.n_lambda,
             "vdu_per_step": vdu_per_step, "visits_per_vdu": fs_points / max(fs_launches, 1) / vdu_per_step,
             "workgroups": info["n_workgroups"],
+            "launch_shape": {"threads": shape[0], "rays_per_thread": shape[1]} if shape else "default",
         },
         "roofline": {
             "bound": "alu",
@@ -162,7 +168,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_TFLOPS,
             "traffic": traffic,
-            "kernel": "fs_box_kernel<float,17,J>",
+            "kernel": "fs_box_kernel<float,J>",
             "kernel_ms_per_launch": fs_ms_launch,
             "launches": fs_launches,
             "flops_per_point": FLOPS_PER_POINT,

@@ -74,6 +74,18 @@ def lib():
         L.orc_fs_1d.restype = ctypes.c_int
         L.orc_fs_1d_dirs.argtypes = [ctypes.c_int] * 3 + [_dp, _dp, ctypes.c_double, ctypes.c_double, _dp]
         L.orc_fs_1d_dirs.restype = ctypes.c_int
+        L.orc_sph_spacing.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 2
+        L.orc_sph_spacing.restype = ctypes.c_double
+        L.orc_sph_rays.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + [_dp, ctypes.c_int, _dp]
+        L.orc_sph_rays.restype = ctypes.c_int
+        L.orc_sph_char.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 2 + [_dp, _dp, ctypes.c_int, _ip, _dp, _dp]
+        L.orc_sph_char.restype = ctypes.c_int
+        L.orc_sph_irradiation.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp] + [ctypes.c_double] * 3
+        L.orc_sph_irradiation.restype = ctypes.c_double
+        L.orc_fs_sphere.argtypes = ([ctypes.c_int] * 3 + [ctypes.c_double] * 2 + [ctypes.c_int] * 2
+                                    + [ctypes.c_double] * 2 + [_dp, _dp, _dp, ctypes.c_double, ctypes.c_int, _dp, _dp,
+                                                               ctypes.c_int])
+        L.orc_fs_sphere.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -237,6 +249,60 @@ def fs_1d_dirs(chi_k, S_k, I_top: float, I_bot: float, n_mu: int, n_phi: int):
     if rc != 0:
         raise RuntimeError("orc_fs_1d_dirs failed")
     return out.reshape(n_mu * n_phi, Nz)
+
+
+# --------------------------------------------------------------------------
+# spherical grid
+# --------------------------------------------------------------------------
+class SphereGrid:
+    """Voxels between r_c and r_out: Nr shells x Nt cones x Np half-planes, index (ip*Nt + it)*Nr + ir."""
+
+    def __init__(self, Nr, Nt, Np, rc=1.0, ro=2.0):
+        self.Nr, self.Nt, self.Np, self.rc, self.ro = int(Nr), int(Nt), int(Np), float(rc), float(ro)
+
+    @property
+    def n_vox(self):
+        return self.Nr * self.Nt * self.Np
+
+    def spacing(self):
+        return lib().orc_sph_spacing(self.Nr, self.Nt, self.Np, self.rc, self.ro)
+
+    def rays(self, n3):
+        """Characteristics of direction n3: array (nc, 8) = p (3), t_a, t_b, kind (1 = leaves the core)."""
+        n3 = _f64(n3)
+        h = self.spacing()
+        K = int(np.ceil(self.ro / h)) + 1
+        cap = 2 * ((2 * K + 1) ** 2 + self.n_vox) + 16
+        out = np.zeros(8 * cap)
+        nc = lib().orc_sph_rays(self.Nr, self.Nt, self.Np, self.rc, self.ro, h, _d(n3), cap, _d(out))
+        if nc < 0:
+            raise RuntimeError("too many characteristics")
+        return out[:8 * nc].reshape(nc, 8).copy()
+
+    def segments(self, ch, n3):
+        ch = _f64(ch); n3 = _f64(n3)
+        cap = 4 * (self.Nr + self.Nt + self.Np) + 20
+        vox = np.zeros(cap, np.int32); s = np.zeros(cap); t0 = np.zeros(cap)
+        M = lib().orc_sph_char(self.Nr, self.Nt, self.Np, self.rc, self.ro, _d(ch), _d(n3), cap,
+                               vox.ctypes.data_as(_ip), _d(s), _d(t0))
+        return vox[:M].copy(), s[:M].copy(), t0[:M].copy()
+
+
+def sph_irradiation(n_mu, n_phi, d, x, ro, dsrc, B_sub=1.0):
+    return lib().orc_sph_irradiation(n_mu, n_phi, d, _d(_f64(x)), float(ro), float(dsrc), float(B_sub))
+
+
+def fs_sphere(grid: SphereGrid, n_mu, n_phi, chi, S, Bv, I_out=0.0, dsrc=0.0, B_sub=1.0, kind="linear",
+              threads=None):
+    """J and Lambda* on the spherical grid; fields flat in voxel order."""
+    chi = _f64(chi).ravel(); S = _f64(S).ravel(); Bv = _f64(Bv).ravel()
+    J = np.zeros(grid.n_vox); L = np.zeros(grid.n_vox)
+    rc = lib().orc_fs_sphere(grid.Nr, grid.Nt, grid.Np, grid.rc, grid.ro, n_mu, n_phi, float(dsrc), float(B_sub),
+                             _d(chi), _d(S), _d(Bv), float(I_out), _KINDS[kind], _d(J), _d(L),
+                             threads or default_threads())
+    if rc != 0:
+        raise RuntimeError(f"orc_fs_sphere failed ({rc})")
+    return J, L
 
 
 from .solvers import *  # noqa: E402,F401,F403

@@ -578,3 +578,334 @@ int orc_fs_1d_dirs(int Nz, int n_mu, int n_phi, const double *chi_k, const doubl
     free(num); free(den); free(mu); free(ph); free(w);
     return err;
 }
+
+/* ======================================================================== */
+/* Spherical grid (Sec. 3.2: r, theta, phi voxels around a core).           */
+/* Reading: voxels are bounded by spheres r_i = rc + i (ro-rc)/Nr, cones    */
+/* theta_k = k pi/Nt and half-planes phi_j = 2 pi j/Np; index              */
+/* v = (ip*Nt + it)*Nr + ir (r fastest).  Rays of one direction: a square   */
+/* lattice of spacing h on the plane through the origin normal to n, axes   */
+/* e1 = normalise(z x n) (x if n is parallel to z), e2 = n x e1, lattice    */
+/* points with |p| < ro; then, in voxel order, one ray through the centre   */
+/* of every voxel no ray has visited yet.  A ray meeting the core (|p| <   */
+/* rc) gives two characteristics: inward to the core surface, and outward   */
+/* from it.  Crossings are collected, sorted and merged as on the box, and  */
+/* each segment is located by its midpoint.                                 */
+/* ======================================================================== */
+typedef struct {
+    int Nr, Nt, Np;
+    double rc, ro;
+} orc_sph;
+
+static void orc_sph_locate(const orc_sph *g, const double *x, int *ir, int *it, int *ip)
+{
+    double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    double th = acos(fmax(-1.0, fmin(1.0, x[2] / r)));
+    double ph = atan2(x[1], x[0]);
+    if (ph < 0.0) ph += 2.0 * M_PI;
+    int a = (int)floor((r - g->rc) / (g->ro - g->rc) * g->Nr);
+    int b = (int)floor(th / M_PI * g->Nt);
+    int c = (int)floor(ph / (2.0 * M_PI) * g->Np);
+    *ir = a < 0 ? 0 : (a >= g->Nr ? g->Nr - 1 : a);
+    *it = b < 0 ? 0 : (b >= g->Nt ? g->Nt - 1 : b);
+    *ip = c < 0 ? 0 : (c >= g->Np ? g->Np - 1 : c);
+}
+
+/* Crossings of the line p + t n (p.n = 0, |n| = 1) with every voxel
+   boundary, restricted to (t0, t1).  Returns the count written to tc. */
+static int orc_sph_crossings(const orc_sph *g, const double *p, const double *n, double t0, double t1,
+                             double *tc, int cap)
+{
+    int m = 0;
+    double pp = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+#define PUSH(t_) do { double tt_ = (t_); if (tt_ > t0 && tt_ < t1 && m < cap) tc[m++] = tt_; } while (0)
+    for (int i = 1; i < g->Nr; i++) {
+        double r = g->rc + i * (g->ro - g->rc) / g->Nr;
+        double q = r * r - pp;
+        if (q > 0.0) { double s = sqrt(q); PUSH(-s); PUSH(s); }
+    }
+    for (int k = 1; k < g->Nt; k++) {
+        double th = k * M_PI / g->Nt;
+        double c = cos(th);
+        if (2 * k == g->Nt) {                 /* equatorial plane */
+            if (n[2] != 0.0) PUSH(-p[2] / n[2]);
+            continue;
+        }
+        double c2 = c * c;
+        double A = n[2] * n[2] - c2, Bq = 2.0 * p[2] * n[2], C = p[2] * p[2] - c2 * pp;
+        double roots[2];
+        int nr = 0;
+        if (fabs(A) < 1e-300) {
+            if (Bq != 0.0) roots[nr++] = -C / Bq;
+        } else {
+            double disc = Bq * Bq - 4.0 * A * C;
+            if (disc >= 0.0) {
+                double sq = sqrt(disc);
+                roots[nr++] = (-Bq - sq) / (2.0 * A);
+                roots[nr++] = (-Bq + sq) / (2.0 * A);
+            }
+        }
+        for (int q = 0; q < nr; q++) {
+            double z = p[2] + roots[q] * n[2];
+            if ((z > 0.0) == (c > 0.0)) PUSH(roots[q]);   /* the cone's own nappe */
+        }
+    }
+    for (int j = 0; j < g->Np; j++) {
+        double ph = 2.0 * M_PI * j / g->Np;
+        double cs = cos(ph), sn = sin(ph);
+        double den = -sn * n[0] + cs * n[1];
+        if (den == 0.0) continue;
+        double t = (sn * p[0] - cs * p[1]) / den;
+        double x = p[0] + t * n[0], y = p[1] + t * n[1];
+        if (cs * x + sn * y > 0.0) PUSH(t);       /* the half-plane, not its mirror */
+    }
+#undef PUSH
+    return m;
+}
+
+/* One characteristic from ta to tb: segments (voxel, length, start) in order. */
+static int orc_sph_segments(const orc_sph *g, const double *p, const double *n, double ta, double tb,
+                            int *vox, double *s, double *t0s, int cap, double *tc, int tcap)
+{
+    int nc = orc_sph_crossings(g, p, n, ta, tb, tc, tcap);
+    qsort(tc, (size_t)nc, sizeof(double), cmp_double);
+    double prev = ta;
+    int m = 0;
+    for (int i = 0; i <= nc; i++) {
+        double t = (i < nc) ? tc[i] : tb;
+        if (t - prev > ORC_TIE * (fabs(prev) + 1.0)) {
+            if (m >= cap) return -1;
+            double tm = 0.5 * (prev + t), x[3];
+            for (int a = 0; a < 3; a++) x[a] = p[a] + tm * n[a];
+            int ir, it, ip;
+            orc_sph_locate(g, x, &ir, &it, &ip);
+            vox[m] = (ip * g->Nt + it) * g->Nr + ir;
+            s[m] = t - prev;
+            t0s[m] = prev - ta;
+            m++;
+            prev = t;
+        }
+    }
+    return m;
+}
+
+static void orc_sph_frame(const double *n, double *e1, double *e2)
+{
+    double a[3] = {-n[1], n[0], 0.0};          /* z x n */
+    double l = sqrt(a[0] * a[0] + a[1] * a[1]);
+    if (l < 1e-12) { a[0] = 1.0; a[1] = 0.0; l = 1.0; }
+    e1[0] = a[0] / l; e1[1] = a[1] / l; e1[2] = 0.0;
+    e2[0] = n[1] * e1[2] - n[2] * e1[1];
+    e2[1] = n[2] * e1[0] - n[0] * e1[2];
+    e2[2] = n[0] * e1[1] - n[1] * e1[0];
+}
+
+/* Lattice spacing: median over voxels of the cube root of the voxel volume. */
+static int cmp_dbl_asc(const void *a, const void *b) { return cmp_double(a, b); }
+double orc_sph_spacing(int Nr, int Nt, int Np, double rc, double ro)
+{
+    int nv = Nr * Nt;
+    double *v = (double *)malloc(sizeof(double) * nv);
+    for (int it = 0; it < Nt; it++)
+        for (int ir = 0; ir < Nr; ir++) {
+            double r0 = rc + ir * (ro - rc) / Nr, r1 = rc + (ir + 1) * (ro - rc) / Nr;
+            double c0 = cos(it * M_PI / Nt), c1 = cos((it + 1) * M_PI / Nt);
+            double vol = (r1 * r1 * r1 - r0 * r0 * r0) / 3.0 * (c0 - c1) * (2.0 * M_PI / Np);
+            v[it * Nr + ir] = cbrt(vol);
+        }
+    qsort(v, (size_t)nv, sizeof(double), cmp_dbl_asc);
+    double h = (nv % 2) ? v[nv / 2] : 0.5 * (v[nv / 2 - 1] + v[nv / 2]);
+    free(v);
+    return h;
+}
+
+/*
+ * Rays of one direction.  Writes, for every characteristic c: its start
+ * point offset (foot point p and [ta, tb]), kind (0 = enters from outside,
+ * 1 = leaves the core) and the entry point's position for boundary
+ * intensities.  Returns the number of characteristics, or -1 (cap).
+ *   chars: [c][8] = p0,p1,p2, ta, tb, kind, 0, 0
+ */
+int orc_sph_rays(int Nr, int Nt, int Np, double rc, double ro, double h, const double *n, int cap, double *chars)
+{
+    orc_sph g = {Nr, Nt, Np, rc, ro};
+    int nvox = Nr * Nt * Np;
+    unsigned char *seen = (unsigned char *)calloc((size_t)nvox, 1);
+    int tcap = 4 * (Nr + Nt + Np) + 16, scap = tcap + 4;
+    double *tc = (double *)malloc(sizeof(double) * tcap);
+    int *vox = (int *)malloc(sizeof(int) * scap);
+    double *s = (double *)malloc(sizeof(double) * scap), *t0s = (double *)malloc(sizeof(double) * scap);
+    double e1[3], e2[3];
+    orc_sph_frame(n, e1, e2);
+    int nc = 0, K = (int)ceil(ro / h) + 1;
+    /* p enumerates the lattice, then fill-in foot points */
+    for (int pass = 0; pass < 2; pass++) {
+        int nitems = pass == 0 ? (2 * K + 1) * (2 * K + 1) : nvox;
+        for (int q = 0; q < nitems; q++) {
+            double p[3];
+            if (pass == 0) {
+                int a = q / (2 * K + 1) - K, b = q % (2 * K + 1) - K;
+                for (int k = 0; k < 3; k++) p[k] = a * h * e1[k] + b * h * e2[k];
+            } else {
+                if (seen[q]) continue;
+                int ir = q % Nr, it = (q / Nr) % Nt, ip = q / (Nr * Nt);
+                double r = rc + (ir + 0.5) * (ro - rc) / Nr, th = (it + 0.5) * M_PI / Nt, ph = (ip + 0.5) * 2.0 * M_PI / Np;
+                double c[3] = {r * sin(th) * cos(ph), r * sin(th) * sin(ph), r * cos(th)};
+                double cn = c[0] * n[0] + c[1] * n[1] + c[2] * n[2];
+                for (int k = 0; k < 3; k++) p[k] = c[k] - cn * n[k];
+            }
+            double pp = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+            if (!(pp < ro * ro)) continue;
+            double to = sqrt(ro * ro - pp);
+            double seg[2][3];
+            int nseg = 0;
+            if (pp < rc * rc) {
+                double ti = sqrt(rc * rc - pp);
+                seg[nseg][0] = -to; seg[nseg][1] = -ti; seg[nseg][2] = 0; nseg++;
+                seg[nseg][0] = ti; seg[nseg][1] = to; seg[nseg][2] = 1; nseg++;
+            } else {
+                seg[nseg][0] = -to; seg[nseg][1] = to; seg[nseg][2] = 0; nseg++;
+            }
+            for (int k = 0; k < nseg; k++) {
+                int M = orc_sph_segments(&g, p, n, seg[k][0], seg[k][1], vox, s, t0s, scap, tc, tcap);
+                if (M <= 0) continue;
+                if (nc >= cap) { nc = -1; goto done; }
+                double *cc = chars + 8 * (size_t)nc;
+                cc[0] = p[0]; cc[1] = p[1]; cc[2] = p[2];
+                cc[3] = seg[k][0]; cc[4] = seg[k][1]; cc[5] = seg[k][2]; cc[6] = 0; cc[7] = 0;
+                nc++;
+                for (int m = 0; m < M; m++) seen[vox[m]] = 1;
+            }
+        }
+    }
+done:
+    free(seen); free(tc); free(vox); free(s); free(t0s);
+    return nc;
+}
+
+/* Segments of one characteristic (for tests and the formal solution). */
+int orc_sph_char(int Nr, int Nt, int Np, double rc, double ro, const double *ch, const double *n, int cap,
+                 int *vox, double *s, double *t0s)
+{
+    orc_sph g = {Nr, Nt, Np, rc, ro};
+    int tcap = 4 * (Nr + Nt + Np) + 16;
+    double *tc = (double *)malloc(sizeof(double) * tcap);
+    int M = orc_sph_segments(&g, ch, n, ch[3], ch[4], vox, s, t0s, cap, tc, tcap);
+    free(tc);
+    return M;
+}
+
+/* Boundary intensity of a characteristic entering from outside, from a point
+   source on the +z axis at distance dsrc*ro: the discrete inward direction
+   closest to the light's direction at the entry point receives
+   J_inc/w with J_inc = B_sub (ro (dsrc-1))^2 / |x - x_src|^2 (= B_sub at the
+   sub-source point); lit points only.  Returns the intensity for direction d. */
+double orc_sph_irradiation(int n_mu, int n_phi, int d, const double *x, double ro, double dsrc, double B_sub)
+{
+    if (dsrc <= 1.0) return 0.0;
+    double xs[3] = {0.0, 0.0, dsrc * ro};
+    double u[3] = {x[0] - xs[0], x[1] - xs[1], x[2] - xs[2]};
+    double L = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    for (int k = 0; k < 3; k++) u[k] /= L;
+    if (u[0] * x[0] + u[1] * x[1] + u[2] * x[2] >= 0.0) return 0.0;   /* not lit */
+    int ndir = n_mu * n_phi, best = -1;
+    double bestdot = -2.0;
+    for (int q = 0; q < ndir; q++) {
+        int i = q / n_phi, j = q % n_phi;
+        double mu = -1.0 + (2.0 * i + 1.0) / n_mu, ph = 2.0 * M_PI * (j + 0.5) / n_phi, v[3];
+        orc_direction_vector(mu, ph, v);
+        double dot = v[0] * u[0] + v[1] * u[1] + v[2] * u[2];
+        if (dot > bestdot) { bestdot = dot; best = q; }
+    }
+    if (best != d) return 0.0;
+    double w = 1.0 / ((double)n_mu * n_phi);
+    double Jinc = B_sub * (ro * (dsrc - 1.0)) * (ro * (dsrc - 1.0)) / (L * L);
+    return Jinc / w;
+}
+
+/*
+ * Formal solution on the spherical grid: J and Lambda* for source S and
+ * opacity chi ([ip][it][ir]).  Characteristics entering from outside start
+ * with I_out + irradiation; those leaving the core start with the core
+ * intensity B of their first voxel (Bv).
+ */
+int orc_fs_sphere(int Nr, int Nt, int Np, double rc, double ro, int n_mu, int n_phi, double dsrc, double B_sub,
+                  const double *chi, const double *S, const double *Bv, double I_out, int lstar_kind,
+                  double *J, double *lstar, int nthreads)
+{
+    int ndir = n_mu * n_phi;
+    long nvox = (long)Nr * Nt * Np;
+    double h = orc_sph_spacing(Nr, Nt, Np, rc, ro);
+    memset(J, 0, sizeof(double) * nvox);
+    if (lstar) memset(lstar, 0, sizeof(double) * nvox);
+    if (nthreads <= 0) nthreads = 1;
+    double *Jt = (double *)calloc((size_t)nthreads * nvox, sizeof(double));
+    double *Lt = (double *)calloc((size_t)nthreads * nvox, sizeof(double));
+    int err = 0;
+    int K = (int)ceil(ro / h) + 1;
+    int cap = 2 * ((2 * K + 1) * (2 * K + 1) + (int)nvox) + 16;
+#pragma omp parallel num_threads(nthreads)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *num = (double *)malloc(sizeof(double) * nvox), *den = (double *)malloc(sizeof(double) * nvox);
+        double *lnum = (double *)malloc(sizeof(double) * nvox);
+        double *chars = (double *)malloc(sizeof(double) * 8 * (size_t)cap);
+        int scap = 4 * (Nr + Nt + Np) + 20;
+        int *vox = (int *)malloc(sizeof(int) * scap);
+        double *s = (double *)malloc(sizeof(double) * scap), *t0s = (double *)malloc(sizeof(double) * scap);
+        double *tau = (double *)malloc(sizeof(double) * scap), *Sv = (double *)malloc(sizeof(double) * scap);
+        double *I = (double *)malloc(sizeof(double) * scap), *dd = (double *)malloc(sizeof(double) * scap);
+#pragma omp for schedule(static, 1)
+        for (int d = 0; d < ndir; d++) {
+            int i = d / n_phi, j = d % n_phi;
+            double mu = -1.0 + (2.0 * i + 1.0) / n_mu, ph = 2.0 * M_PI * (j + 0.5) / n_phi, n[3];
+            orc_direction_vector(mu, ph, n);
+            double w = 1.0 / ((double)n_mu * n_phi);
+            int nc = orc_sph_rays(Nr, Nt, Np, rc, ro, h, n, cap, chars);
+            if (nc < 0) {
+#pragma omp atomic write
+                err = -3;
+                continue;
+            }
+            memset(num, 0, sizeof(double) * nvox);
+            memset(den, 0, sizeof(double) * nvox);
+            memset(lnum, 0, sizeof(double) * nvox);
+            for (int c = 0; c < nc; c++) {
+                const double *ch = chars + 8 * (size_t)c;
+                int M = orc_sph_char(Nr, Nt, Np, rc, ro, ch, n, scap, vox, s, t0s);
+                if (M <= 0) continue;
+                for (int m = 0; m < M; m++) { tau[m] = chi[vox[m]] * s[m]; Sv[m] = S[vox[m]]; }
+                double Ibc;
+                if (ch[5] == 1.0) {
+                    Ibc = Bv[vox[0]];
+                } else {
+                    double x[3];
+                    for (int k = 0; k < 3; k++) x[k] = ch[k] + ch[3] * n[k];
+                    Ibc = I_out + orc_sph_irradiation(n_mu, n_phi, d, x, ro, dsrc, B_sub);
+                }
+                orc_ray(M, tau, Sv, Ibc, lstar_kind, I, dd);
+                for (int m = 0; m < M; m++) {
+                    num[vox[m]] += s[m] * I[m];
+                    den[vox[m]] += s[m];
+                    lnum[vox[m]] += s[m] * dd[m];
+                }
+            }
+            double *Jm = Jt + (size_t)tid * nvox, *Lm = Lt + (size_t)tid * nvox;
+            for (long v = 0; v < nvox; v++) {
+                if (den[v] > 0.0) { Jm[v] += w * num[v] / den[v]; Lm[v] += w * lnum[v] / den[v]; }
+            }
+        }
+        free(num); free(den); free(lnum); free(chars); free(vox); free(s); free(t0s);
+        free(tau); free(Sv); free(I); free(dd);
+    }
+    for (int t = 0; t < nthreads; t++)
+        for (long v = 0; v < nvox; v++) {
+            J[v] += Jt[(size_t)t * nvox + v];
+            if (lstar) lstar[v] += Lt[(size_t)t * nvox + v];
+        }
+    free(Jt); free(Lt);
+    return err;
+}
