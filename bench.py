@@ -89,6 +89,9 @@ def main():
     ap.add_argument("--cpu-dirs", type=int, default=24, help="directions in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
+    ap.add_argument("--shape", default=None, help="fix the launch shape THREADS,RAYS instead of autotuning")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy three times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1 "
@@ -96,6 +99,18 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.calibrate_copy:
+        n = 1 << 28
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "device copy", "bytes_read": 4 * n, "bytes_written": 4 * n,
+                          "launches": 3}), flush=True)
+        return
 
     import paper_2102_01734_amd as rt
     import synthetic as sy
@@ -110,7 +125,11 @@ def main():
     g = rt.Grid(case.Nx, case.Ny, case.Nz, case.n_mu, case.n_phi, "f32", 1)
     # launch-shape autotuning on this workload (part of setup, not timed)
     S0 = torch.tensor(sy.random_source(case.chi.shape, seed=7, lo=0.2, hi=1.0, dtype="f32"), **dev)
-    shape = g.autotune(chi, S0) if not args.no_autotune else None
+    if args.shape:
+        shape = tuple(int(v) for v in args.shape.split(","))
+        g.set_launch_shape(*shape)
+    else:
+        shape = g.autotune(chi, S0) if not args.no_autotune else None
     del S0
     info = g.info()
     st = g.new_state(chi, eps, B, Ibc)

@@ -203,10 +203,22 @@ rt_status rt_box_template(int32_t Nz, int32_t n_mu, int32_t n_phi, int32_t dir, 
  * steps of this grid.  The shape changes only how directions are grouped
  * into workgroup partial sums, i.e. the summation order of J (differences
  * at the rounding level of the grid precision).  Blocks.
- * threads_out / rays_out (may be NULL) receive the chosen shape.
+ * threads_out / rays_out (may be NULL) receive the chosen shape (workgroup
+ * size bound and rays per thread, as rt_set_launch_shape takes them).
  */
 rt_status rt_autotune(rt_grid_t grid, int32_t n_lambda, const void *chi, const void *S, int32_t *threads_out,
                       int32_t *rays_out, void *stream);
+
+/*
+ * Fixes the launch shape of the grid's single-output formal-solution kernel
+ * to one of the compiled shapes (threads = workgroup size bound, rays = rays
+ * per thread), e.g. one that rt_autotune chose in an earlier process, so that
+ * runs are reproducible without re-tuning.  A launch may use fewer threads
+ * than the bound when a direction has fewer rays.  RT_E_INVALID if no
+ * compiled shape matches or the shape cannot hold one direction's rays in
+ * the device's LDS.  Does not launch anything.
+ */
+rt_status rt_set_launch_shape(rt_grid_t grid, int32_t threads, int32_t rays);
 
 /*
  * Measurement hooks.  While enabled, every formal-solution kernel launch of

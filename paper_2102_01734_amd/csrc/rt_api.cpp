@@ -431,9 +431,27 @@ rt_status rt_autotune(rt_grid_t g, int32_t n_lambda, const void *chi, const void
     if (rs != RT_OK) return rs;
     variant(g, dbl, true, false) = best;
     g->tuned = true;
-    if (threads_out) *threads_out = best.nthr;
+    if (threads_out) *threads_out = best.lb;
     if (rays_out) *rays_out = best.R;
     return RT_OK;
+}
+
+rt_status rt_set_launch_shape(rt_grid_t g, int32_t threads, int32_t rays)
+{
+    if (!g) return fail(RT_E_INVALID, "grid is NULL");
+    const FsShape *sh = nullptr;
+    const int n = fs_box_shapes(&sh);
+    for (int i = 0; i < n; ++i) {
+        if (sh[i].lb != threads || sh[i].R != rays) continue;
+        const Variant v = make_variant(g, g->dbl, true, false, threads, rays);
+        if (!v.ok)
+            return fail(RT_E_INVALID, "shape %d x %d cannot hold the %d rays of a direction on this device", threads,
+                        rays, g->geo.Nx * g->geo.Ny);
+        variant(g, g->dbl, true, false) = v;
+        g->tuned = true;
+        return RT_OK;
+    }
+    return fail(RT_E_INVALID, "no compiled launch shape %d threads x %d rays", threads, rays);
 }
 
 rt_status rt_profile_enable(rt_grid_t g, int32_t enable)

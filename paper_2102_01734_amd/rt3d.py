@@ -81,6 +81,8 @@ def lib() -> ctypes.CDLL:
         getattr(L, f).restype = ctypes.c_int
     L.rt_autotune.argtypes = [vp, i32, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32), vp]
     L.rt_autotune.restype = ctypes.c_int
+    L.rt_set_launch_shape.argtypes = [vp, i32, i32]
+    L.rt_set_launch_shape.restype = ctypes.c_int
     L.rt_profile_enable.argtypes = [vp, i32]
     L.rt_profile_enable.restype = ctypes.c_int
     L.rt_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32), i64p]
@@ -157,6 +159,10 @@ def rt_autotune(grid: int, n_lambda: int, chi: int, S: int, stream: Optional[int
     _check(lib().rt_autotune(ctypes.c_void_p(grid), int(n_lambda), ctypes.c_void_p(chi), ctypes.c_void_p(S),
                              ctypes.byref(t), ctypes.byref(r), ctypes.c_void_p(stream or None)), "rt_autotune")
     return t.value, r.value
+
+
+def rt_set_launch_shape(grid: int, threads: int, rays: int) -> None:
+    _check(lib().rt_set_launch_shape(ctypes.c_void_p(grid), int(threads), int(rays)), "rt_set_launch_shape")
 
 
 def rt_profile_enable(grid: int, enable: bool) -> None:
@@ -262,6 +268,9 @@ class Grid:
         n = chi.shape[0]
         return rt_autotune(self.handle, n, self._check_field(chi, n, "chi"), self._check_field(S, n, "S"),
                            _stream_ptr(stream))
+
+    def set_launch_shape(self, threads, rays):
+        rt_set_launch_shape(self.handle, threads, rays)
 
     def new_state(self, chi, eps, B, I_bc=None, J0=None):
         """Allocates the ALI state (J, S, Lambda*, norms) for a batch; J starts at B."""

@@ -162,3 +162,22 @@ def test_autotune_keeps_results(orc):
     J1, _ = gpu_fs(case, S, grid=g, want_lstar=False)
     g.close()
     np.testing.assert_allclose(J1, J0, rtol=2e-6, atol=1e-7 * np.abs(J0).max())
+
+
+def test_set_launch_shape(orc):
+    """A fixed compiled shape gives the same J as the default one up to the
+    summation order; shapes that are not compiled or cannot hold a direction's
+    rays are rejected."""
+    import paper_2102_01734_amd as rt
+    case = sy.random_box(40, 37, 9, 4, 8, seed=83, dtype="f32")
+    S = sy.random_source(case.chi.shape, seed=84, dtype="f32")
+    g = make_grid(case)
+    J0, _ = gpu_fs(case, S, grid=g, want_lstar=False)
+    g.set_launch_shape(768, 2)
+    J1, _ = gpu_fs(case, S, grid=g, want_lstar=False)
+    np.testing.assert_allclose(J1, J0, rtol=2e-6, atol=1e-7 * np.abs(J0).max())
+    with pytest.raises(rt.RtError):
+        g.set_launch_shape(256, 5)       # 1280 rays < 40 x 37
+    with pytest.raises(rt.RtError):
+        g.set_launch_shape(100, 3)       # not compiled
+    g.close()
