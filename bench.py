@@ -38,9 +38,11 @@ WORKLOADS = {
 
 
 def fs_source_hash() -> str:
+    """Hash of the box sweep kernel's sources (the kernel file and its point arithmetic)."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2102_01734_amd", "csrc", "fs_box.hip"), "rb") as f:
-        h.update(f.read())
+    for name in ("fs_box.hip", "fs_point.hpp"):
+        with open(os.path.join(ROOT, "paper_2102_01734_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
@@ -86,7 +88,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="lognormal129", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-dirs", type=int, default=24, help="directions in the CPU-baseline sample")
+    ap.add_argument("--cpu-dirs", type=int, default=72, help="directions in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--shape", default=None, help="fix the launch shape THREADS,RAYS instead of autotuning")

@@ -27,166 +27,9 @@
 #include <type_traits>
 
 #include "fs_box.hpp"
+#include "fs_point.hpp"
 
 namespace rt3d {
-
-// ---------------------------------------------------------------------------
-// double-precision point arithmetic
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double seg_depth(double chi, double s)
-{
-#pragma clang fp contract(off)
-    return chi * s;
-}
-
-__device__ __forceinline__ double half_sum(double a, double b)
-{
-#pragma clang fp contract(off)
-    return 0.5 * (a + b);
-}
-
-__device__ __forceinline__ double rcp_f64(double x)
-{
-    double r = __builtin_amdgcn_rcp(x);
-    double e = __builtin_fma(-x, r, 1.0);
-    r = __builtin_fma(r, e, r);
-    e = __builtin_fma(-x, r, 1.0);
-    return __builtin_fma(r, e, r);
-}
-
-// exp(-D) for 1/4 <= D: x = -D = n ln2 + r with |r| <= ln2/2, exp(r) by its
-// Taylor polynomial (degree 12 for double results, 9 when the weights feed a
-// single-precision recurrence), scaled by 2^n.  D is clamped at 745, where
-// the result is already below the smallest subnormal.
-template <bool FULL>
-__device__ __forceinline__ double exp_neg(double D)
-{
-    const double x = -(D < 745.0 ? D : 745.0);
-    const double n = __builtin_rint(x * 1.4426950408889634);
-    double r = __builtin_fma(-n, 6.93147180369123816490e-01, x);
-    r = __builtin_fma(-n, 1.90821492927058770002e-10, r);
-    double p;
-    if (FULL) {
-        p = 1.0 / 479001600.0;
-        p = __builtin_fma(p, r, 1.0 / 39916800.0);
-        p = __builtin_fma(p, r, 1.0 / 3628800.0);
-        p = __builtin_fma(p, r, 1.0 / 362880.0);
-    } else {
-        p = 1.0 / 362880.0;
-    }
-    p = __builtin_fma(p, r, 1.0 / 40320.0);
-    p = __builtin_fma(p, r, 1.0 / 5040.0);
-    p = __builtin_fma(p, r, 1.0 / 720.0);
-    p = __builtin_fma(p, r, 1.0 / 120.0);
-    p = __builtin_fma(p, r, 1.0 / 24.0);
-    p = __builtin_fma(p, r, 1.0 / 6.0);
-    p = __builtin_fma(p, r, 0.5);
-    p = __builtin_fma(p, r, 1.0);
-    p = __builtin_fma(p, r, 1.0);
-    return __builtin_ldexp(p, (int)n);
-}
-
-// Attenuation moments over an optical step D > 0:
-//   ex = exp(-D), e0 = 1 - ex, e1 = D - e0, e2 = D^2 - 2 e1.
-// Below D = 1/4, e2 comes from its Taylor series 2 D^3 sum_j (-D)^j/(j+3)!
-// (12 terms for double results, 8 for single-precision ones), and e1, e0, ex
-// follow from it without cancellation; from 1/4 up the closed forms are used.
-// The series is evaluated on every lane (it is short); the exponential only
-// where some lane of the wave needs it.
-template <bool FULL>
-__device__ __forceinline__ void kernel_moments(double D, double &ex, double &e0, double &e1, double &e2)
-{
-    double p;
-    if (FULL) {
-        p = 1.0 / 87178291200.0;                       // 1/14!
-        p = __builtin_fma(-D, p, 1.0 / 6227020800.0);  // 1/13!
-        p = __builtin_fma(-D, p, 1.0 / 479001600.0);   // 1/12!
-        p = __builtin_fma(-D, p, 1.0 / 39916800.0);    // 1/11!
-    } else {
-        p = 1.0 / 39916800.0;                          // 1/11!
-    }
-    p = __builtin_fma(-D, p, 1.0 / 3628800.0);     // 1/10!
-    p = __builtin_fma(-D, p, 1.0 / 362880.0);      // 1/9!
-    p = __builtin_fma(-D, p, 1.0 / 40320.0);       // 1/8!
-    p = __builtin_fma(-D, p, 1.0 / 5040.0);        // 1/7!
-    p = __builtin_fma(-D, p, 1.0 / 720.0);         // 1/6!
-    p = __builtin_fma(-D, p, 1.0 / 120.0);         // 1/5!
-    p = __builtin_fma(-D, p, 1.0 / 24.0);          // 1/4!
-    p = __builtin_fma(-D, p, 1.0 / 6.0);           // 1/3!
-    const double D2 = D * D;
-    if (D < 0.25) {
-        e2 = 2.0 * D2 * D * p;
-        e1 = 0.5 * (D2 - e2);
-        e0 = D - e1;
-        ex = 1.0 - e0;
-        return;
-    }
-    ex = exp_neg<FULL>(D);
-    e0 = 1.0 - ex;
-    e1 = D - e0;
-    e2 = __builtin_fma(D, D, -2.0 * e1);
-}
-
-// Smallest optical step used in the arithmetic: a vacuum segment (D = 0,
-// Listing 1 step 4a) is evaluated at this step, which leaves the intensity
-// unchanged to within 1e-100 of S and keeps the shared reciprocal finite.
-constexpr double kMinStep = 1e-100;
-
-// Weights of the segment from the previous point (upwind optical step D) to
-// the current one, the downwind step being Dp (ignored when last), in the
-// type T of the recurrence:
-//   I_m = I_{m-1} ex + a S_{m-1} + b S_m + g S_{m+1}.
-// Parabolic: the Lagrange quadratic through the three points integrated
-// against exp(-(D-t)); with r = 1/(D Dp (D+Dp)),
-//   b = ((D+Dp) e1 - e2) (D+Dp) r,  g = (e2 - D e1) D r,  a = e0 - b - g.
-// Linear (the last point of a ray, Dp < D/2, or where the parabolic b would
-// reach 1, i.e. Dp e0 <= D e1 - e2):  b = e1/D, a = e0 - b, g = 0.
-// dlin = e1/D is the diagonal of the linear-interpolation operator.
-template <typename T>
-struct PointW {
-    T a, b, g, ex, dlin;
-};
-
-template <typename T>
-__device__ __forceinline__ PointW<T> point_weights(double D, double Dp, bool last)
-{
-    constexpr bool FULL = sizeof(T) == 8;
-    const double Dv = D < kMinStep ? kMinStep : D;  // NaN propagates
-    double ex, e0, e1, e2;
-    kernel_moments<FULL>(Dv, ex, e0, e1, e2);
-    const double Dq = Dp < kMinStep ? Dv : Dp;   // keeps r finite on last/vacuum points; NaN propagates
-    const double Ds = Dv + Dq;
-    const double r = rcp_f64(Dv * Dq * Ds);
-    const double bl = e1 * ((Dq * Ds) * r);      // e1 / D
-    const bool lin = last || (Dp < 0.5 * D) || (Dp * e0 <= __builtin_fma(Dv, e1, -e2));
-    const double bp = __builtin_fma(Ds, e1, -e2) * (Ds * r);
-    const double gp = (e2 - Dv * e1) * (Dv * r);
-    PointW<T> w;
-    w.ex = T(ex);
-    w.dlin = T(bl);
-    if (sizeof(T) == 8) {
-        w.b = lin ? T(bl) : T(bp);
-        w.g = lin ? T(0) : T(gp);
-        w.a = lin ? T(e0 - bl) : T(e0 - bp - gp);
-    } else {
-        const T bl_t = T(bl), al_t = T(e0 - bl), bp_t = T(bp), gp_t = T(gp), ap_t = T(e0 - bp - gp);
-        w.b = lin ? bl_t : bp_t;
-        w.g = lin ? T(0) : gp_t;
-        w.a = lin ? al_t : ap_t;
-    }
-    return w;
-}
-
-// Entry half-segment: constant S from the entry point to the first point.
-template <typename T>
-__device__ __forceinline__ void entry_weights(double D0, T &ex_t, T &e0_t)
-{
-    constexpr bool FULL = sizeof(T) == 8;
-    double ex, e0, e1, e2;
-    kernel_moments<FULL>(D0 < kMinStep ? kMinStep : D0, ex, e0, e1, e2);
-    ex_t = T(ex);
-    e0_t = T(e0);
-}
 
 // ---------------------------------------------------------------------------
 // field loads: one raw buffer load per point fetches the (chi, S) pair; the

@@ -60,6 +60,19 @@ int trace_box_ray(int Nz, const double n[3], std::vector<int32_t> &di, std::vect
     return (int)s.size();
 }
 
+Direction quadrature_direction(int i, int j, int n_mu, int n_phi)
+{
+    Direction d;
+    d.mu = -1.0 + (2.0 * i + 1.0) / n_mu;
+    d.phi = 2.0 * M_PI * (j + 0.5) / n_phi;
+    d.w = 1.0 / ((double)n_mu * (double)n_phi);
+    const double st = std::sqrt(1.0 - d.mu * d.mu);
+    d.n[0] = st * std::cos(d.phi);
+    d.n[1] = st * std::sin(d.phi);
+    d.n[2] = d.mu;
+    return d;
+}
+
 std::string build_box_geometry(int Nx, int Ny, int Nz, int n_mu, int n_phi, BoxGeometry &g)
 {
     if (Nx < 1 || Ny < 1 || Nz < 1) return "grid sizes must be >= 1";
@@ -76,13 +89,7 @@ std::string build_box_geometry(int Nx, int Ny, int Nz, int n_mu, int n_phi, BoxG
     for (int i = 0; i < n_mu; ++i) {
         for (int j = 0; j < n_phi; ++j) {
             Direction &d = g.dirs[i * n_phi + j];
-            d.mu = -1.0 + (2.0 * i + 1.0) / n_mu;
-            d.phi = 2.0 * M_PI * (j + 0.5) / n_phi;
-            d.w = 1.0 / ((double)n_mu * (double)n_phi);
-            const double st = std::sqrt(1.0 - d.mu * d.mu);
-            d.n[0] = st * std::cos(d.phi);
-            d.n[1] = st * std::sin(d.phi);
-            d.n[2] = d.mu;
+            d = quadrature_direction(i, j, n_mu, n_phi);
             int M = trace_box_ray(Nz, d.n, di, dj, kk, s);
             if (M <= 0) return "tracker failed";
             // the sweep kernel advances its layer counter at every layer end:

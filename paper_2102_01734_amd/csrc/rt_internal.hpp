@@ -38,6 +38,10 @@ struct BoxGeometry {
     std::vector<int32_t> di, dj, kk;  // unwrapped offsets and layer (tests, tools)
 };
 
+// Direction (i, j) of the midpoint quadrature: mu_i = -1 + (2i+1)/n_mu,
+// phi_j = 2 pi (j + 1/2)/n_phi, equal weights 1/(n_mu n_phi).
+Direction quadrature_direction(int i, int j, int n_mu, int n_phi);
+
 // Builds directions and templates.  Returns an empty string on success.
 std::string build_box_geometry(int Nx, int Ny, int Nz, int n_mu, int n_phi, BoxGeometry &g);
 
@@ -64,5 +68,61 @@ struct Schedule {
 // Distributes (lambda, direction) items over n_wg persistent workgroups so
 // that their summed visit counts balance; see schedule.cpp.
 void build_schedule(const BoxGeometry &g, const std::vector<int32_t> &lambdas, int n_wg, Schedule &out);
+
+// ---------------------------------------------------------------------------
+// Spherical grid: voxels bounded by the spheres r_i = rc + i (ro - rc)/Nr,
+// the cones theta_k = k pi/Nt and the half-planes phi_j = 2 pi j/Np; voxel
+// index v = (ip Nt + it) Nr + ir.  See sphere_geometry.cpp.
+// ---------------------------------------------------------------------------
+struct SphereSpec {
+    int Nr = 0, Nt = 0, Np = 0;
+    double rc = 0, ro = 0;
+    double dsrc = 0;  // point source on +z at dsrc * ro (0: none)
+    int n_mu = 0, n_phi = 0;
+};
+
+// Characteristics of one direction in trace order.  Characteristic c covers
+// visits [begin[c], begin[c+1]) and has foot point p (p.n = 0), parameter
+// range [ta, tb] along n and kind 0 (enters from outside) or 1 (leaves the
+// core).
+struct SphereTracks {
+    std::vector<int64_t> begin;
+    std::vector<double> p, ta, tb;   // p: 3 per characteristic
+    std::vector<int8_t> kind;
+    std::vector<int32_t> vox;
+    std::vector<double> s;
+};
+
+std::string check_sphere_spec(const SphereSpec &g);
+// Lattice spacing of the ray set: median over voxels of the cube root of the voxel volume.
+double sphere_spacing(const SphereSpec &g);
+// Traces every characteristic of direction n (lattice rays, then fill-in rays).
+void trace_sphere_direction(const SphereSpec &g, double h, const double n[3], SphereTracks &out);
+// Irradiation factor of an outer characteristic of direction d entering at x:
+// (ro (dsrc - 1))^2 / |x - x_src|^2 / w_d when x is lit and d is the inward
+// quadrature direction closest to the light's direction, else 0.
+double sphere_irradiation(const SphereSpec &g, const std::vector<Direction> &dirs, int d, const double x[3]);
+
+// The spherical geometry cache: the characteristics of all directions, in
+// chunks of consecutive directions.  Per visit: voxel, path length s and
+// averaging weight w_d s / (sum of s over the visits of that voxel in that
+// direction).  Per characteristic: the boundary factor (>= 0: outer entry,
+// irradiation factor; < 0: core start).  Per chunk: a voxel -> visit index
+// (CSR) for the fixed-order gather of J.
+struct SphereChunk {
+    int dir_begin = 0, dir_end = 0;
+    int64_t char_begin = 0, char_end = 0;   // global characteristic range
+    int64_t visit_begin = 0, visit_end = 0;  // global visit range
+    int max_len = 0;
+};
+
+struct SphereCache {
+    SphereSpec spec;
+    double h = 0;
+    std::vector<Direction> dirs;
+    std::vector<SphereChunk> chunks;
+    int64_t n_chars = 0, n_visits = 0;
+    int64_t max_chunk_visits = 0;
+};
 
 }  // namespace rt3d
