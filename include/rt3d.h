@@ -19,6 +19,15 @@
  *     x and y.  Layer k = 0 is the top (outer boundary, z max), k = Nz-1 the
  *     bottom (inner boundary).  Field arrays are structure-of-arrays,
  *     [lambda][k][y][x], x fastest, contiguous, one value per voxel.
+ *   - Spherical grid (Sec. 3.2): Nr x Ntheta x Nphi voxels between the core
+ *     radius r_core and the outer radius r_out, bounded by the spheres
+ *     r_i = r_core + i (r_out - r_core)/Nr, the cones theta_k = k pi/Ntheta
+ *     and the half-planes phi_j = 2 pi j/Nphi.  Voxel index
+ *     v = (iphi Ntheta + itheta) Nr + ir (r fastest); field arrays are
+ *     [lambda][v].  The core is opaque: characteristics that hit it end
+ *     there, characteristics leaving it start with I_core.  Characteristics
+ *     entering through r_out start with I_out plus, optionally, the
+ *     irradiation of a point source on the +z axis.
  *   - Directions: n_mu x n_phi, mu_i = -1 + (2i+1)/n_mu, phi_j = 2 pi (j+1/2)/n_phi,
  *     equal weights 1/(n_mu n_phi) (Sec. 3.1: equally spaced in mu and phi).
  *   - Precision: RT_FP64 grids take double fields and compute the formal
@@ -70,8 +79,10 @@ typedef struct rt_grid *rt_grid_t;
 typedef struct {
     uint32_t struct_size;  /* sizeof(rt_grid_desc)                              */
     int32_t geom;          /* rt_geom                                           */
-    int32_t n[3];          /* box: Nx, Ny, Nz (each >= 1)                       */
-    double h[3];           /* box: ignored (unit voxels)                        */
+    int32_t n[3];          /* box: Nx, Ny, Nz; sphere: Nr, Ntheta, Nphi (>= 1)  */
+    double h[3];           /* box: ignored (unit voxels); sphere: r_core, r_out,
+                              source distance in units of r_out (> 1, or 0 for
+                              no irradiation)                                   */
     int32_t n_mu, n_phi;   /* direction quadrature; n_mu even, n_phi >= 1       */
     int32_t n_lambda_max;  /* largest wavelength batch any call will pass       */
     int32_t prec;          /* rt_prec                                           */
@@ -79,13 +90,18 @@ typedef struct {
 } rt_grid_desc;
 
 /*
- * Builds the tracker output (one characteristic template per direction; every
- * other characteristic of that direction is an integer translate of it) on the
- * host in double precision, uploads it once, and sizes the work schedule and
- * partial-sum buffers for up to n_lambda_max wavelengths (Sec. 4.1: the
- * geometry cache is built once and reused for all wavelengths).
+ * Builds the tracker output on the host in double precision, uploads it once,
+ * and sizes the work schedule and partial-sum buffers for up to n_lambda_max
+ * wavelengths (Sec. 4.1: the geometry cache is built once and reused for all
+ * wavelengths).
+ *   box: one characteristic template per direction (every other
+ *        characteristic of that direction is an integer translate of it).
+ *   sphere: every characteristic of every direction (see rt_sphere_tracks),
+ *        traced on up to 16 host threads, with per-visit voxel, path length
+ *        and averaging weight (float on RT_FP32 grids, double on RT_FP64),
+ *        uploaded in chunks of consecutive directions.
  * Blocks until the upload is complete.  Errors: RT_E_INVALID (descriptor),
- * RT_E_UNSUPPORTED (grid larger than the on-chip layer tile allows),
+ * RT_E_UNSUPPORTED (box layer larger than the on-chip tile allows),
  * RT_E_NOMEM, RT_E_HIP.  *out is NULL on error.
  */
 rt_status rt_create_grid(const rt_grid_desc *desc, rt_grid_t *out);
@@ -103,8 +119,14 @@ rt_status rt_grid_info(rt_grid_t grid, int64_t *n_vox, int32_t *n_dir,
  * independent wavelengths on the same grid.
  *   chi, S     device, [n_lambda][Nz][Ny][Nx], grid precision (float/double);
  *              chi >= 0 (chi = 0 marks vacuum: Listing 1 step 4a)
- *   I_bc       device, [n_lambda][2] grid precision: intensity entering at the
- *              top (mu < 0 rays) and at the bottom (mu > 0 rays); NULL = 0
+ *   I_bc       device, grid precision; NULL = all zero.  Box: [n_lambda][2],
+ *              intensity entering at the top (mu < 0 rays) and at the bottom
+ *              (mu > 0 rays).  Sphere: [n_lambda][3] = I_out (entering through
+ *              r_out), I_core (leaving the core), J_sub (mean intensity of the
+ *              point source at the sub-source point r_out z; each lit entry
+ *              point adds J_sub (r_out (d - 1))^2 / |x - x_src|^2 / w to the
+ *              quadrature direction closest to the light's direction, ties to
+ *              the lower index)
  *   J_out      device, [n_lambda][Nz][Ny][Nx], grid precision
  *   lstar_out  device, same shape, or NULL to skip Lambda*
  * n_lambda = 0 is a no-op.  Deterministic: the same inputs give bitwise the
@@ -122,7 +144,9 @@ typedef struct {
     const void *chi;      /* device [n_lambda][vox], grid precision             */
     const void *eps;      /* device [n_lambda][vox], grid precision, 0<=eps<=1  */
     const void *B;        /* device [n_lambda][vox], grid precision             */
-    const void *I_bc;     /* device [n_lambda][2], grid precision; NULL = 0     */
+    const void *I_bc;     /* device [n_lambda][2] (box) or [n_lambda][3]
+                             (sphere), grid precision, as in
+                             rt_formal_solution; NULL = 0                       */
     double *J;            /* device [n_lambda][vox] double: current iterate;
                              on entry the start value (e.g. B), on exit the
                              result.  Resuming from any J is allowed.           */
@@ -194,6 +218,27 @@ rt_status rt_box_template(int32_t Nz, int32_t n_mu, int32_t n_phi, int32_t dir, 
                           int32_t *dj, int32_t *kk, double *s, int32_t *M);
 
 /*
+ * The characteristics of direction `dir` of a spherical grid, as the library
+ * traces them (host only, no device needed).  Per direction: a square lattice
+ * of foot points p (spacing h = median cube root of the voxel volumes, axes
+ * e1 = normalise(z x n), or x when n is along z, and e2 = n x e1) with
+ * |p| < r_out, then, in voxel-index order, one line through the centre of
+ * every voxel not visited yet.  A line meeting the core gives an inward
+ * characteristic ending on it and an outward one starting on it.  Crossings
+ * with spheres, cones and half-planes are sorted; crossings within
+ * 1e-12 (|t| + 1) of the previous segment end are merged; each segment
+ * belongs to the voxel containing its midpoint.
+ *   h_out        spacing h (may be NULL)
+ *   n_chars, n_visits  in: capacity of the arrays; out: counts
+ *   chars        [n_chars][6] = p (3), t_a, t_b, kind (0 outer, 1 core):
+ *                the characteristic is p + t n for t in [t_a, t_b]
+ *   visit_begin  [n_chars + 1]; vox, s: [n_visits] voxel and path length
+ * With any of chars, visit_begin, vox, s NULL only the counts are returned.
+ */
+rt_status rt_sphere_tracks(const rt_grid_desc *desc, int32_t dir, double *h_out, int64_t *n_chars,
+                           int64_t *n_visits, double *chars, int64_t *visit_begin, int32_t *vox, double *s);
+
+/*
  * Launch-shape autotuner (the "run-time configuration optimisation" the paper
  * suggests, Sec. 6): times the single-output (J) formal-solution kernel of the
  * grid's precision for every compiled (workgroup size, rays per thread) shape
@@ -202,7 +247,8 @@ rt_status rt_box_template(int32_t Nz, int32_t n_mu, int32_t n_phi, int32_t dir, 
  * intensity), and keeps the fastest for all later formal solutions and ALI
  * steps of this grid.  The shape changes only how directions are grouped
  * into workgroup partial sums, i.e. the summation order of J (differences
- * at the rounding level of the grid precision).  Blocks.
+ * at the rounding level of the grid precision).  Blocks.  Box grids only
+ * (RT_E_UNSUPPORTED on spherical grids).
  * threads_out / rays_out (may be NULL) receive the chosen shape (workgroup
  * size bound and rays per thread, as rt_set_launch_shape takes them).
  */
@@ -216,7 +262,8 @@ rt_status rt_autotune(rt_grid_t grid, int32_t n_lambda, const void *chi, const v
  * runs are reproducible without re-tuning.  A launch may use fewer threads
  * than the bound when a direction has fewer rays.  RT_E_INVALID if no
  * compiled shape matches or the shape cannot hold one direction's rays in
- * the device's LDS.  Does not launch anything.
+ * the device's LDS; RT_E_UNSUPPORTED on spherical grids.  Does not launch
+ * anything.
  */
 rt_status rt_set_launch_shape(rt_grid_t grid, int32_t threads, int32_t rays);
 

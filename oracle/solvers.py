@@ -13,7 +13,7 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["BoxProblem", "Plane1DProblem", "ali", "ng_extrapolate", "bicgstab",
+__all__ = ["BoxProblem", "Plane1DProblem", "SphereProblem", "ali", "ng_extrapolate", "bicgstab",
            "lambda_matrix", "direct", "lambda_iteration_radius"]
 
 
@@ -73,6 +73,45 @@ class Plane1DProblem(BoxProblem):
         self.n_fs += 1
         J, L = self._fs_1d(self.chi, S, self.I_top if bc else 0.0, self.I_bot if bc else 0.0,
                            self.n_mu, self.n_phi, self.kind)
+        if want_lstar:
+            self._lstar = L
+        return (J, L) if want_lstar else J
+
+
+class SphereProblem(BoxProblem):
+    """One wavelength on a spherical grid: chi, eps, B of shape (Np, Nt, Nr);
+    boundary values I_out (entering through r_out), I_core (leaving the core)
+    and the point-source irradiation J_sub at distance dsrc * r_out (Sec. 3.2)."""
+
+    def __init__(self, grid, chi, eps, B, I_out, I_core, n_mu, n_phi, dsrc=0.0, J_sub=0.0, kind="linear",
+                 threads=None):
+        from . import fs_sphere
+        self._fs_sphere = fs_sphere
+        self.grid = grid
+        self.chi = np.ascontiguousarray(chi, dtype=np.float64).reshape(grid.Np, grid.Nt, grid.Nr)
+        shape = self.chi.shape
+
+        def field(x):
+            x = np.asarray(x, dtype=np.float64)
+            return (x.reshape(shape) if x.size == self.chi.size else np.broadcast_to(x, shape)).copy()
+        self.eps = field(eps)
+        self.B = field(B)
+        self.I_out, self.I_core = float(I_out), float(I_core)
+        self.dsrc, self.J_sub = float(dsrc), float(J_sub)
+        self.n_mu, self.n_phi = int(n_mu), int(n_phi)
+        self.kind = kind
+        self.threads = threads
+        self.n_fs = 0
+        self._lstar = None
+
+    def fs(self, S, bc=True, want_lstar=False):
+        self.n_fs += 1
+        core = np.full(self.chi.size, self.I_core if bc else 0.0)
+        J, L = self._fs_sphere(self.grid, self.n_mu, self.n_phi, self.chi, S, core,
+                               I_out=self.I_out if bc else 0.0, dsrc=self.dsrc, B_sub=self.J_sub if bc else 0.0,
+                               kind=self.kind, threads=self.threads)
+        J = J.reshape(self.chi.shape)
+        L = L.reshape(self.chi.shape)
         if want_lstar:
             self._lstar = L
         return (J, L) if want_lstar else J

@@ -8,7 +8,8 @@
 namespace rt3d {
 
 // Writes component comp (0 = chi, 1 = S) of the interleaved doubly periodic
-// padded formal-solution input (see ali.hip).
+// padded formal-solution input (see ali.hip).  Ny == 0 selects the unpadded
+// pair layout [lambda][voxel][2] of the spherical grid (n_vox = Nx * Nz).
 template <typename TS, typename TD>
 hipError_t pad_field(const TS *src, const double *anchor, TD *dst, int Nx, int Ny, int Nz, int n_lambda, int comp,
                      hipStream_t st);

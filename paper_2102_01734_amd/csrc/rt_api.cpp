@@ -5,18 +5,23 @@
 // launches for one formal solution, one ALI step and a full solve.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <map>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "ali.hpp"
 #include "fs_box.hpp"
+#include "fs_sphere.hpp"
 #include "rt_internal.hpp"
 
 using namespace rt3d;
@@ -85,9 +90,29 @@ struct DevSchedule {
     DevBuf wg_begin, items, slot_begin, slot_ids, lambda_of;
 };
 
+// Device copy of one chunk of the spherical geometry cache (chunk-local indices).
+struct SphereChunkDev {
+    SphereChunk info;
+    int64_t n_chars = 0, n_visits = 0;
+    DevBuf char_begin;  // int64 [n_chars + 1]
+    DevBuf char_g;      // double [n_chars]
+    DevBuf vox;         // int32 [n_visits]
+    DevBuf s, w;        // geometry type [n_visits]
+    DevBuf row, idx;    // CSR voxel -> chunk visits: int32 [n_vox + 1], int32 [n_visits]
+};
+
 struct rt_grid {
     rt_grid_desc desc{};
     BoxGeometry geo;
+    // spherical grids
+    bool sphere = false;
+    bool sph_gdouble = false;  // geometry cache in double (double grids) or float
+    SphereCache sph;
+    std::vector<std::unique_ptr<SphereChunkDev>> sph_chunks;
+    DevBuf sph_outJ, sph_outL;  // per-visit contributions of one chunk
+    // layout of the formal-solution input: box (Nx, Ny, Nz); sphere (n_vox, 0, 1)
+    int lx = 0, ly = 0, lz = 0;
+    int nbc = 2;  // boundary values per wavelength in I_bc
     int device = 0;
     int n_cu = 0;
     size_t max_lds = 0;
@@ -177,12 +202,23 @@ static rt_status get_schedule(rt_grid *g, int n_wg, const std::vector<int32_t> &
         return RT_OK;
     }
     Schedule sc;
-    build_schedule(g->geo, lambdas, n_wg, sc);
     auto ds = std::make_unique<DevSchedule>();
+    if (g->sphere) {
+        // one slot per batch entry: the gather writes each wavelength's J directly
+        const int nb = (int)lambdas.size();
+        sc.n_wg = 0;
+        sc.wg_begin.assign(1, 0);
+        sc.n_slots = nb;
+        for (int b = 0; b <= nb; ++b) sc.slot_begin.push_back(b);
+        for (int b = 0; b < nb; ++b) sc.slot_ids.push_back(b);
+        ds->points = g->n_visits * nb;
+    } else {
+        build_schedule(g->geo, lambdas, n_wg, sc);
+        for (const WorkItem &w : sc.items) ds->points += (int64_t)g->geo.dirs[w.dir].M * g->geo.Nx * g->geo.Ny;
+    }
     ds->n_wg = sc.n_wg;
     ds->n_slots = sc.n_slots;
     ds->n_batch = (int)lambdas.size();
-    for (const WorkItem &w : sc.items) ds->points += (int64_t)g->geo.dirs[w.dir].M * g->geo.Nx * g->geo.Ny;
     auto up = [](DevBuf &b, const void *src, size_t n) -> hipError_t {
         hipError_t e = b.ensure(n > 0 ? n : 16);
         if (e != hipSuccess) return e;
@@ -206,10 +242,70 @@ static rt_status get_schedule(rt_grid *g, int n_wg, const std::vector<int32_t> &
 // ---------------------------------------------------------------------------
 // formal solution on padded inputs already in place
 // ---------------------------------------------------------------------------
+// Spherical grid: per chunk, the characteristic kernel writes per-visit
+// contributions and the gather sums them into partJ / partL [batch][voxel]
+// (stored by the first chunk, accumulated by the others).
+static rt_status run_fs_sphere(rt_grid *g, const Variant &v, const std::vector<int32_t> &lambdas, const void *fld,
+                               const void *I_bc, DevBuf &partJ, DevBuf &partL, DevSchedule **sched_out,
+                               hipStream_t st)
+{
+    const bool dbl = v.dbl, wj = v.wj, wl = v.wl;
+    if (!dbl && g->sph_gdouble) return fail(RT_E_INVALID, "single-precision sweep on a double geometry cache");
+    DevSchedule *sc = nullptr;
+    rt_status rs = get_schedule(g, 0, lambdas, &sc);
+    if (rs != RT_OK) return rs;
+    const int nb = (int)lambdas.size();
+    const size_t esz = dbl ? 8 : 4;
+    const int64_t stride = g->sph.max_chunk_visits;
+    if (wj) HIPCHK(partJ.ensure((size_t)nb * g->n_vox * esz));
+    if (wl) HIPCHK(partL.ensure((size_t)nb * g->n_vox * esz));
+    if ((size_t)nb * stride * esz > g->sph_outJ.bytes) return fail(RT_E_INVALID, "batch larger than n_lambda_max");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (g->prof) {
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        HIPCHK(hipEventRecord(e0, st));
+    }
+    for (size_t c = 0; c < g->sph_chunks.size(); ++c) {
+        const SphereChunkDev &ch = *g->sph_chunks[c];
+        FsSphereArgs a{};
+        a.n_vox = g->n_vox;
+        a.char0 = 0;
+        a.n_chars = ch.n_chars;
+        a.visit0 = 0;
+        a.char_begin = ch.char_begin.as<int64_t>();
+        a.char_g = ch.char_g.as<double>();
+        a.vox = ch.vox.as<int32_t>();
+        a.s = ch.s.p;
+        a.w = ch.w.p;
+        a.lambda_of = sc->lambda_of.as<int32_t>();
+        a.field = fld;
+        a.I_bc = I_bc;
+        a.outJ = wj ? g->sph_outJ.p : nullptr;
+        a.outL = wl ? g->sph_outL.p : nullptr;
+        a.out_stride = stride;
+        HIPCHK(fs_sphere_launch(a, dbl, g->sph_gdouble, wj, wl, g->para, nb, st));
+        if (wj)
+            HIPCHK(sphere_gather(g->sph_outJ.p, dbl, stride, ch.row.as<int32_t>(), ch.idx.as<int32_t>(), g->n_vox, nb,
+                                 partJ.p, dbl, c > 0, st));
+        if (wl)
+            HIPCHK(sphere_gather(g->sph_outL.p, dbl, stride, ch.row.as<int32_t>(), ch.idx.as<int32_t>(), g->n_vox, nb,
+                                 partL.p, dbl, c > 0, st));
+    }
+    if (g->prof) {
+        HIPCHK(hipEventRecord(e1, st));
+        g->prof_events.push_back({e0, e1});
+        g->prof_points += sc->points;
+    }
+    *sched_out = sc;
+    return RT_OK;
+}
+
 static rt_status run_fs_with(rt_grid *g, const Variant &v, const std::vector<int32_t> &lambdas, const void *fld,
                              const void *I_bc, DevBuf &partJ, DevBuf &partL, DevSchedule **sched_out,
                              hipStream_t st)
 {
+    if (g->sphere) return run_fs_sphere(g, v, lambdas, fld, I_bc, partJ, partL, sched_out, st);
     const bool dbl = v.dbl, wj = v.wj, wl = v.wl;
     if (!v.ok) return fail(RT_E_UNSUPPORTED, "no kernel configuration fits this grid (layer tile of %d voxels)",
                            g->geo.Nx * g->geo.Ny);
@@ -262,6 +358,185 @@ static rt_status run_fs(rt_grid *g, bool dbl, bool wj, bool wl, const std::vecto
 // ---------------------------------------------------------------------------
 // API
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// spherical geometry cache: traced on host threads direction by direction,
+// then uploaded in chunks of consecutive directions
+// ---------------------------------------------------------------------------
+namespace {
+
+// One direction's characteristics in kernel order (longest first) with
+// averaging weights and boundary factors.
+struct SphereDirCache {
+    std::vector<int64_t> len;     // visits per characteristic
+    std::vector<double> g;        // boundary factor
+    std::vector<int32_t> vox;
+    std::vector<double> s, w;
+};
+
+void prepare_sphere_direction(const SphereSpec &spec, double h, const std::vector<Direction> &dirs, int d,
+                              std::vector<double> &den, SphereDirCache &out)
+{
+    SphereTracks tr;
+    trace_sphere_direction(spec, h, dirs[d].n, tr);
+    const int64_t nc = (int64_t)tr.kind.size();
+    // sum of path lengths per voxel in this direction, in trace order
+    for (size_t k = 0; k < tr.vox.size(); ++k) den[(size_t)tr.vox[k]] += tr.s[k];
+    std::vector<int64_t> order((size_t)nc);
+    for (int64_t c = 0; c < nc; ++c) order[(size_t)c] = c;
+    std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+        return tr.begin[x + 1] - tr.begin[x] > tr.begin[y + 1] - tr.begin[y];
+    });
+    out = SphereDirCache();
+    out.vox.reserve(tr.vox.size());
+    out.s.reserve(tr.vox.size());
+    out.w.reserve(tr.vox.size());
+    const double wd = dirs[d].w;
+    for (int64_t c : order) {
+        const int64_t b = tr.begin[c], e = tr.begin[c + 1];
+        out.len.push_back(e - b);
+        double gc = -1.0;
+        if (tr.kind[c] == 0) {
+            const double *p = &tr.p[3 * c];
+            const double x[3] = {p[0] + tr.ta[c] * dirs[d].n[0], p[1] + tr.ta[c] * dirs[d].n[1],
+                                 p[2] + tr.ta[c] * dirs[d].n[2]};
+            gc = sphere_irradiation(spec, dirs, d, x);
+        }
+        out.g.push_back(gc);
+        for (int64_t k = b; k < e; ++k) {
+            out.vox.push_back(tr.vox[k]);
+            out.s.push_back(tr.s[k]);
+            out.w.push_back(wd * tr.s[k] / den[(size_t)tr.vox[k]]);
+        }
+    }
+    for (int32_t v : tr.vox) den[(size_t)v] = 0.0;
+}
+
+template <typename TG>
+hipError_t upload_chunk(SphereChunkDev &ch, const std::vector<SphereDirCache> &dirs, int64_t n_vox)
+{
+    int64_t nc = 0, nv = 0;
+    for (const auto &d : dirs) { nc += (int64_t)d.len.size(); nv += (int64_t)d.vox.size(); }
+    ch.n_chars = nc;
+    ch.n_visits = nv;
+    std::vector<int64_t> cb;
+    std::vector<double> cg;
+    std::vector<int32_t> vx;
+    std::vector<TG> sv, wv;
+    cb.reserve(nc + 1); cg.reserve(nc); vx.reserve(nv); sv.reserve(nv); wv.reserve(nv);
+    cb.push_back(0);
+    for (const auto &d : dirs) {
+        for (size_t c = 0; c < d.len.size(); ++c) { cb.push_back(cb.back() + d.len[c]); cg.push_back(d.g[c]); }
+        vx.insert(vx.end(), d.vox.begin(), d.vox.end());
+        for (size_t k = 0; k < d.s.size(); ++k) { sv.push_back((TG)d.s[k]); wv.push_back((TG)d.w[k]); }
+    }
+    // CSR voxel -> visits, visits of a voxel in chunk order
+    std::vector<int32_t> row((size_t)n_vox + 1, 0), idx((size_t)nv);
+    for (int32_t v : vx) row[(size_t)v + 1]++;
+    for (int64_t v = 0; v < n_vox; ++v) row[(size_t)v + 1] += row[(size_t)v];
+    std::vector<int32_t> fill(row.begin(), row.end() - 1);
+    for (int64_t k = 0; k < nv; ++k) idx[(size_t)fill[(size_t)vx[(size_t)k]]++] = (int32_t)k;
+    auto up = [](DevBuf &b, const void *src, size_t n) -> hipError_t {
+        hipError_t e = b.ensure(n > 0 ? n : 16);
+        if (e != hipSuccess || n == 0) return e;
+        return hipMemcpy(b.p, src, n, hipMemcpyHostToDevice);
+    };
+    hipError_t e;
+    if ((e = up(ch.char_begin, cb.data(), cb.size() * 8)) != hipSuccess) return e;
+    if ((e = up(ch.char_g, cg.data(), cg.size() * 8)) != hipSuccess) return e;
+    if ((e = up(ch.vox, vx.data(), vx.size() * 4)) != hipSuccess) return e;
+    if ((e = up(ch.s, sv.data(), sv.size() * sizeof(TG))) != hipSuccess) return e;
+    if ((e = up(ch.w, wv.data(), wv.size() * sizeof(TG))) != hipSuccess) return e;
+    if ((e = up(ch.row, row.data(), row.size() * 4)) != hipSuccess) return e;
+    return up(ch.idx, idx.data(), idx.size() * 4);
+}
+
+}  // namespace
+
+// Visits per chunk: the per-visit outputs of a chunk take n_lambda_max x
+// visits x 16 bytes (double J and Lambda* for the anchors of single-precision
+// grids); chunks are sized so that this stays near 2 GiB.  The environment
+// variable RT3D_SPHERE_CHUNK_VISITS overrides the size (smaller chunks: less
+// memory, more launches).
+static int64_t sphere_chunk_cap(int n_lambda_max)
+{
+    int64_t cap = ((int64_t)2 << 30) / (16 * (int64_t)n_lambda_max);
+    if (const char *e = std::getenv("RT3D_SPHERE_CHUNK_VISITS")) {
+        const long long v = std::atoll(e);
+        if (v > 0) cap = v;
+    }
+    return std::min<int64_t>(cap, ((int64_t)1 << 31) - 1);
+}
+
+static rt_status build_sphere_grid(rt_grid *g, const rt_grid_desc *desc)
+{
+    SphereSpec spec;
+    spec.Nr = desc->n[0]; spec.Nt = desc->n[1]; spec.Np = desc->n[2];
+    spec.rc = desc->h[0]; spec.ro = desc->h[1]; spec.dsrc = desc->h[2];
+    spec.n_mu = desc->n_mu; spec.n_phi = desc->n_phi;
+    const std::string err = check_sphere_spec(spec);
+    if (!err.empty()) return fail(RT_E_INVALID, "%s", err.c_str());
+    SphereCache &sc = g->sph;
+    sc.spec = spec;
+    sc.h = sphere_spacing(spec);
+    for (int i = 0; i < spec.n_mu; ++i)
+        for (int j = 0; j < spec.n_phi; ++j) sc.dirs.push_back(quadrature_direction(i, j, spec.n_mu, spec.n_phi));
+    const int nd = (int)sc.dirs.size();
+    const int64_t nvox = (int64_t)spec.Nr * spec.Nt * spec.Np;
+    const int64_t cap = sphere_chunk_cap(desc->n_lambda_max);
+    unsigned hw = std::thread::hardware_concurrency();
+    const int nthr = (int)std::max(1u, std::min(hw == 0 ? 1u : hw, 16u));
+
+    std::vector<SphereDirCache> pending;  // directions of the open chunk
+    int64_t pend_visits = 0;
+    int chunk_dir0 = 0;
+    auto flush = [&](int dir_end) -> rt_status {
+        if (pending.empty()) return RT_OK;
+        auto ch = std::make_unique<SphereChunkDev>();
+        ch->info.dir_begin = chunk_dir0;
+        ch->info.dir_end = dir_end;
+        hipError_t e = g->sph_gdouble ? upload_chunk<double>(*ch, pending, nvox) : upload_chunk<float>(*ch, pending, nvox);
+        if (e != hipSuccess) return fail(RT_E_HIP, "geometry upload: %s", hipGetErrorString(e));
+        for (const auto &d : pending)
+            for (int64_t l : d.len) ch->info.max_len = std::max<int64_t>(ch->info.max_len, l);
+        sc.n_chars += ch->n_chars;
+        sc.n_visits += ch->n_visits;
+        sc.max_chunk_visits = std::max(sc.max_chunk_visits, ch->n_visits);
+        g->sph_chunks.push_back(std::move(ch));
+        pending.clear();
+        pend_visits = 0;
+        chunk_dir0 = dir_end;
+        return RT_OK;
+    };
+    // directions are traced in windows of 2 x threads and consumed in order
+    const int win = 2 * nthr;
+    for (int d0 = 0; d0 < nd; d0 += win) {
+        const int d1 = std::min(nd, d0 + win);
+        std::vector<SphereDirCache> res((size_t)(d1 - d0));
+        std::atomic<int> next(d0);
+        std::vector<std::thread> pool;
+        for (int t = 0; t < std::min(nthr, d1 - d0); ++t)
+            pool.emplace_back([&]() {
+                std::vector<double> den((size_t)nvox, 0.0);
+                for (int d = next++; d < d1; d = next++)
+                    prepare_sphere_direction(spec, sc.h, sc.dirs, d, den, res[(size_t)(d - d0)]);
+            });
+        for (auto &th : pool) th.join();
+        for (int d = d0; d < d1; ++d) {
+            SphereDirCache &dc = res[(size_t)(d - d0)];
+            const int64_t nv = (int64_t)dc.vox.size();
+            if (nv > cap) return fail(RT_E_INVALID, "direction %d has %lld visits, above the chunk size %lld", d,
+                                      (long long)nv, (long long)cap);
+            if (pend_visits + nv > cap) {
+                rt_status rs = flush(d);
+                if (rs != RT_OK) return rs;
+            }
+            pend_visits += nv;
+            pending.push_back(std::move(dc));
+        }
+    }
+    return flush(nd);
+}
+
 extern "C" {
 
 const char *rt_last_error(void) { return g_err.c_str(); }
@@ -292,18 +567,91 @@ rt_status rt_box_template(int32_t Nz, int32_t n_mu, int32_t n_phi, int32_t dir, 
     return RT_OK;
 }
 
+rt_status rt_sphere_tracks(const rt_grid_desc *desc, int32_t dir, double *h_out, int64_t *n_chars, int64_t *n_visits,
+                           double *chars, int64_t *visit_begin, int32_t *vox, double *s)
+{
+    if (!desc || !n_chars || !n_visits) return fail(RT_E_INVALID, "desc, n_chars and n_visits must not be NULL");
+    if (desc->struct_size != sizeof(rt_grid_desc)) return fail(RT_E_INVALID, "desc->struct_size mismatch");
+    if (desc->geom != RT_GEOM_SPHERICAL) return fail(RT_E_INVALID, "not a spherical grid");
+    SphereSpec spec;
+    spec.Nr = desc->n[0]; spec.Nt = desc->n[1]; spec.Np = desc->n[2];
+    spec.rc = desc->h[0]; spec.ro = desc->h[1]; spec.dsrc = desc->h[2];
+    spec.n_mu = desc->n_mu; spec.n_phi = desc->n_phi;
+    const std::string err = check_sphere_spec(spec);
+    if (!err.empty()) return fail(RT_E_INVALID, "%s", err.c_str());
+    if (dir < 0 || dir >= spec.n_mu * spec.n_phi) return fail(RT_E_INVALID, "direction %d out of range", dir);
+    const double h = sphere_spacing(spec);
+    const Direction d = quadrature_direction(dir / spec.n_phi, dir % spec.n_phi, spec.n_mu, spec.n_phi);
+    SphereTracks tr;
+    trace_sphere_direction(spec, h, d.n, tr);
+    const int64_t nc = (int64_t)tr.kind.size(), nv = (int64_t)tr.vox.size();
+    if (h_out) *h_out = h;
+    const bool fill = chars && visit_begin && vox && s;
+    if (fill) {
+        if (*n_chars < nc || *n_visits < nv) return fail(RT_E_INVALID, "output arrays too small");
+        for (int64_t c = 0; c < nc; ++c) {
+            double *o = chars + 6 * c;
+            o[0] = tr.p[3 * c]; o[1] = tr.p[3 * c + 1]; o[2] = tr.p[3 * c + 2];
+            o[3] = tr.ta[c]; o[4] = tr.tb[c]; o[5] = tr.kind[c];
+        }
+        std::memcpy(visit_begin, tr.begin.data(), (size_t)(nc + 1) * 8);
+        std::memcpy(vox, tr.vox.data(), (size_t)nv * 4);
+        std::memcpy(s, tr.s.data(), (size_t)nv * 8);
+    }
+    *n_chars = nc;
+    *n_visits = nv;
+    return RT_OK;
+}
+
 rt_status rt_create_grid(const rt_grid_desc *desc, rt_grid_t *out)
 {
     if (!out) return fail(RT_E_INVALID, "out is NULL");
     *out = nullptr;
     if (!desc) return fail(RT_E_INVALID, "desc is NULL");
     if (desc->struct_size != sizeof(rt_grid_desc)) return fail(RT_E_INVALID, "desc->struct_size mismatch");
-    if (desc->geom == RT_GEOM_SPHERICAL)
-        return fail(RT_E_UNSUPPORTED, "spherical grids are not available in this build");
-    if (desc->geom != RT_GEOM_BOX_PERIODIC_XY) return fail(RT_E_INVALID, "unknown geometry %d", desc->geom);
+    if (desc->geom != RT_GEOM_BOX_PERIODIC_XY && desc->geom != RT_GEOM_SPHERICAL)
+        return fail(RT_E_INVALID, "unknown geometry %d", desc->geom);
     if (desc->prec != RT_FP32 && desc->prec != RT_FP64) return fail(RT_E_INVALID, "unknown precision %d", desc->prec);
     if (desc->n_lambda_max < 1) return fail(RT_E_INVALID, "n_lambda_max must be >= 1");
     if (desc->flags & ~RT_F_LSTAR_PARABOLIC) return fail(RT_E_INVALID, "unknown flags 0x%x", desc->flags);
+    if (desc->geom == RT_GEOM_SPHERICAL) {
+        const int64_t nv = (int64_t)desc->n[0] * desc->n[1] * desc->n[2];
+        if (desc->n[0] < 1 || desc->n[1] < 1 || desc->n[2] < 1) return fail(RT_E_INVALID, "grid sizes must be >= 1");
+        if (nv > ((int64_t)1 << 30) || nv * 4 * desc->n_lambda_max > (int64_t)1 << 40)
+            return fail(RT_E_INVALID, "grid x batch too large");
+        if (desc->n_mu > 4096 || desc->n_phi > 4096) return fail(RT_E_INVALID, "direction counts out of range");
+        auto g = std::make_unique<rt_grid>();
+        g->desc = *desc;
+        g->sphere = true;
+        g->dbl = desc->prec == RT_FP64;
+        g->sph_gdouble = g->dbl;
+        g->para = (desc->flags & RT_F_LSTAR_PARABOLIC) != 0;
+        g->n_vox = nv;
+        g->lx = (int)nv; g->ly = 0; g->lz = 1;
+        g->nbc = 3;
+        HIPCHK(hipGetDevice(&g->device));
+        rt_status rs = build_sphere_grid(g.get(), desc);
+        if (rs != RT_OK) return rs;
+        g->n_dir = (int)g->sph.dirs.size();
+        g->n_visits = g->sph.n_visits;
+        // per-visit output buffers at their largest size (double, n_lambda_max), so
+        // that captured graphs never see them move
+        const size_t ob = (size_t)desc->n_lambda_max * (size_t)std::max<int64_t>(g->sph.max_chunk_visits, 1) * 8;
+        HIPCHK(g->sph_outJ.ensure(ob));
+        HIPCHK(g->sph_outL.ensure(ob));
+        // every output combination runs through the same characteristic kernel
+        for (int d = 0; d < 2; ++d)
+            for (int j = 0; j < 2; ++j)
+                for (int l = 0; l < 2; ++l) {
+                    Variant &v = variant(g.get(), d, j, l);
+                    v = Variant();
+                    v.dbl = d; v.wj = j; v.wl = l;
+                    v.ok = (j || l) && (d || !g->sph_gdouble);
+                }
+        *out = g.release();
+        g_err.clear();
+        return RT_OK;
+    }
     const int64_t nv = (int64_t)desc->n[0] * desc->n[1] * desc->n[2];
     if (desc->n[0] < 1 || desc->n[1] < 1 || desc->n[2] < 1) return fail(RT_E_INVALID, "grid sizes must be >= 1");
     if (desc->n[0] > 4096 || desc->n[1] > 4096 || desc->n[2] > 1000000)
@@ -320,6 +668,8 @@ rt_status rt_create_grid(const rt_grid_desc *desc, rt_grid_t *out)
     g->n_vox = nv;
     g->n_dir = (int)g->geo.dirs.size();
     g->n_visits = (int64_t)g->geo.s.size();
+    g->lx = g->geo.Nx; g->ly = g->geo.Ny; g->lz = g->geo.Nz;
+    g->nbc = 2;
 
     HIPCHK(hipGetDevice(&g->device));
     hipDeviceProp_t prop;
@@ -383,6 +733,7 @@ rt_status rt_autotune(rt_grid_t g, int32_t n_lambda, const void *chi, const void
     if (n_lambda < 1 || n_lambda > g->desc.n_lambda_max)
         return fail(RT_E_INVALID, "n_lambda %d outside [1, %d]", n_lambda, g->desc.n_lambda_max);
     if (!chi || !S) return fail(RT_E_INVALID, "chi and S must not be NULL");
+    if (g->sphere) return fail(RT_E_UNSUPPORTED, "launch shapes apply to the box sweep only");
     hipStream_t st = (hipStream_t)stream;
     const bool dbl = g->dbl;
     const int Nx = g->geo.Nx, Ny = g->geo.Ny, Nz = g->geo.Nz;
@@ -439,6 +790,7 @@ rt_status rt_autotune(rt_grid_t g, int32_t n_lambda, const void *chi, const void
 rt_status rt_set_launch_shape(rt_grid_t g, int32_t threads, int32_t rays)
 {
     if (!g) return fail(RT_E_INVALID, "grid is NULL");
+    if (g->sphere) return fail(RT_E_UNSUPPORTED, "launch shapes apply to the box sweep only");
     const FsShape *sh = nullptr;
     const int n = fs_box_shapes(&sh);
     for (int i = 0; i < n; ++i) {
@@ -487,7 +839,7 @@ rt_status rt_grid_info(rt_grid_t g, int64_t *n_vox, int32_t *n_dir, int64_t *n_v
     if (n_vox) *n_vox = g->n_vox;
     if (n_dir) *n_dir = g->n_dir;
     if (n_visits_total) *n_visits_total = g->n_visits;
-    if (n_wg) *n_wg = variant(g, g->dbl, true, false).n_wg;
+    if (n_wg) *n_wg = g->sphere ? (int32_t)g->sph_chunks.size() : variant(g, g->dbl, true, false).n_wg;
     return RT_OK;
 }
 
@@ -503,7 +855,7 @@ rt_status rt_formal_solution(rt_grid_t g, int32_t n_lambda, const void *chi, con
     const bool dbl = g->dbl;
     const size_t esz = dbl ? 8 : 4;
     const size_t padn = (size_t)n_lambda * 4 * g->n_vox;
-    const int Nx = g->geo.Nx, Ny = g->geo.Ny, Nz = g->geo.Nz;
+    const int Nx = g->lx, Ny = g->ly, Nz = g->lz;
     HIPCHK(g->fs_fld.ensure(2 * padn * esz));
     if (dbl) {
         HIPCHK(pad_field<double, double>((const double *)chi, nullptr, g->fs_fld.as<double>(), Nx, Ny, Nz, n_lambda, 0, st));
@@ -592,7 +944,7 @@ static rt_status ensure_state_buffers(rt_grid *g)
         HIPCHK(g->fld64.ensure(nl * 8 * nv * 8));
         HIPCHK(g->J_anchor.ensure(nl * nv * 8));
         HIPCHK(g->S_anchor.ensure(nl * nv * 8));
-        HIPCHK(g->ibc64.ensure(nl * 2 * 8));
+        HIPCHK(g->ibc64.ensure(nl * 3 * 8));
     }
     HIPCHK(g->hist.ensure(4 * nl * nv * 8));
     HIPCHK(g->ng_blk.ensure(nl * 256 * 5 * 8));
@@ -610,7 +962,7 @@ static rt_status plain_step_launches(rt_grid *g, rt_state *s, const std::vector<
     const int64_t nv = g->n_vox;
     HIPCHK(fill_u64(reinterpret_cast<unsigned long long *>(s->rel_change), 0ull, nl, st));
     AliUpdateArgs ua{};
-    ua.Nx = g->geo.Nx; ua.Ny = g->geo.Ny; ua.n_vox = nv;
+    ua.Nx = g->lx; ua.Ny = g->ly; ua.n_vox = nv;
     ua.lambda_of = lambda_of;
     ua.eps = s->eps; ua.B = s->B; ua.lstar = s->lstar;
     ua.J = s->J; ua.S = s->S;
@@ -683,7 +1035,7 @@ static rt_status graph_plain_step(rt_grid *g, rt_state *s, const std::vector<int
 static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o, const std::vector<int32_t> &lams,
                                 bool anchor, hipStream_t st, int *fs_count, int *fs64_count, int *ng_count)
 {
-    const int Nx = g->geo.Nx, Ny = g->geo.Ny, Nz = g->geo.Nz;
+    const int Nx = g->lx, Ny = g->ly, Nz = g->lz;
     const int nl = s->n_lambda;
     const int64_t nv = g->n_vox;
     const int nb = (int)lams.size();
@@ -797,7 +1149,7 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
             HIPCHK(hipMemcpyAsync(g->S_anchor.p, s->S, (size_t)nl * nv * 8, hipMemcpyDeviceToDevice, st));
             const void *ibc = nullptr;
             if (s->I_bc) {
-                HIPCHK(cast_array<float, double>((const float *)s->I_bc, g->ibc64.as<double>(), 2 * (int64_t)nl, st));
+                HIPCHK(cast_array<float, double>((const float *)s->I_bc, g->ibc64.as<double>(), (int64_t)g->nbc * nl, st));
                 ibc = g->ibc64.p;
             }
             rs = run_fs(g, true, true, false, lams, g->fld64.p, ibc, g->partJ64, g->partL64, &sc, st);

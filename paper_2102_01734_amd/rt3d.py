@@ -90,6 +90,9 @@ def lib() -> ctypes.CDLL:
     ip, dp = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)
     L.rt_box_template.argtypes = [i32, i32, i32, i32, i32, ip, ip, ip, dp, ip]
     L.rt_box_template.restype = ctypes.c_int
+    L.rt_sphere_tracks.argtypes = [ctypes.POINTER(RtGridDesc), i32, dp, ctypes.POINTER(ctypes.c_int64),
+                                   ctypes.POINTER(ctypes.c_int64), dp, ctypes.POINTER(ctypes.c_int64), ip, dp]
+    L.rt_sphere_tracks.restype = ctypes.c_int
     L.rt_last_error.restype = ctypes.c_char_p
     L.rt_last_error.argtypes = []
     L.rt_version.restype = ctypes.c_char_p
@@ -190,6 +193,37 @@ def rt_box_template(Nz: int, n_mu: int, n_phi: int, d: int):
     return dict(di=di, dj=dj, kk=kk, s=s)
 
 
+def sphere_desc(Nr: int, Nt: int, Np: int, r_core: float, r_out: float, n_mu: int, n_phi: int, prec: str = "f32",
+                n_lambda_max: int = 1, lstar: str = "linear", source_distance: float = 0.0) -> RtGridDesc:
+    d = RtGridDesc()
+    d.struct_size = ctypes.sizeof(RtGridDesc)
+    d.geom = RT_GEOM_SPHERICAL
+    d.n[0], d.n[1], d.n[2] = Nr, Nt, Np
+    d.h[0], d.h[1], d.h[2] = r_core, r_out, source_distance
+    d.n_mu, d.n_phi = n_mu, n_phi
+    d.n_lambda_max = n_lambda_max
+    d.prec = RT_FP32 if prec == "f32" else RT_FP64
+    d.flags = RT_F_LSTAR_PARABOLIC if lstar == "parabolic" else 0
+    return d
+
+
+def rt_sphere_tracks(desc: RtGridDesc, d: int):
+    """Host tracker output of direction d of a spherical grid: dict with h, chars (n, 6),
+    begin (n + 1), vox, s."""
+    import numpy as np
+    h = ctypes.c_double()
+    nc, nv = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().rt_sphere_tracks(ctypes.byref(desc), d, ctypes.byref(h), ctypes.byref(nc), ctypes.byref(nv),
+                                  None, None, None, None), "rt_sphere_tracks")
+    chars = np.zeros((nc.value, 6)); begin = np.zeros(nc.value + 1, np.int64)
+    vox = np.zeros(nv.value, np.int32); s = np.zeros(nv.value)
+    dp, ip, lp = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
+    _check(lib().rt_sphere_tracks(ctypes.byref(desc), d, ctypes.byref(h), ctypes.byref(nc), ctypes.byref(nv),
+                                  chars.ctypes.data_as(dp), begin.ctypes.data_as(lp), vox.ctypes.data_as(ip),
+                                  s.ctypes.data_as(dp)), "rt_sphere_tracks")
+    return dict(h=h.value, chars=chars, begin=begin, vox=vox, s=s)
+
+
 # ---------------------------------------------------------------------------
 # torch-facing convenience wrapper
 # ---------------------------------------------------------------------------
@@ -216,6 +250,7 @@ class Grid:
         d.flags = RT_F_LSTAR_PARABOLIC if lstar == "parabolic" else 0
         self.desc = d
         self.shape = (Nz, Ny, Nx)
+        self.nbc = 2
         self.prec = prec
         self.n_lambda_max = n_lambda_max
         self.handle = rt_create_grid(d)
@@ -255,8 +290,8 @@ class Grid:
         ps = self._check_field(S, n, "S")
         pb = None
         if I_bc is not None:
-            if I_bc.dtype != self.dtype or tuple(I_bc.shape) != (n, 2) or not I_bc.is_contiguous():
-                raise ValueError("I_bc must be contiguous (n_lambda, 2) of the grid dtype")
+            if I_bc.dtype != self.dtype or tuple(I_bc.shape) != (n, self.nbc) or not I_bc.is_contiguous():
+                raise ValueError(f"I_bc must be contiguous (n_lambda, {self.nbc}) of the grid dtype")
             pb = I_bc.data_ptr()
         J = out if out is not None else torch.empty_like(chi)
         L = torch.empty_like(chi) if want_lstar else None
@@ -312,3 +347,19 @@ class Grid:
     def state_tensors(state: RtState):
         chi, eps, B, I_bc, J, S, L, rel = state._keep
         return dict(J=J, S=S, lstar=L, rel_change=rel)
+
+
+class SphereGrid(Grid):
+    """A spherical grid handle.  Fields are torch tensors on the GPU shaped
+    (n_lambda, Nphi, Ntheta, Nr) (r fastest); I_bc is (n_lambda, 3) =
+    (I_out, I_core, J_sub)."""
+
+    def __init__(self, Nr: int, Nt: int, Np: int, r_core: float, r_out: float, n_mu: int, n_phi: int,
+                 prec: str = "f32", n_lambda_max: int = 1, lstar: str = "linear", source_distance: float = 0.0):
+        d = sphere_desc(Nr, Nt, Np, r_core, r_out, n_mu, n_phi, prec, n_lambda_max, lstar, source_distance)
+        self.desc = d
+        self.shape = (Np, Nt, Nr)
+        self.nbc = 3
+        self.prec = prec
+        self.n_lambda_max = n_lambda_max
+        self.handle = rt_create_grid(d)

@@ -18,7 +18,14 @@ available; the shapes follow the paper's test setups, Sec. 3.1 and 3.2):
   with a Gaussian of standard deviation l/sqrt(2) (periodic in x,y, generated
   on twice the depth and cropped), rescaled to zero mean and unit variance;
 * eps log-uniform per voxel or per wavelength; B = 1; no incoming intensity at
-  the top, I = B entering at the bottom.
+  the top, I = B entering at the bottom;
+* spherical shell (r_core = 1, r_out = 2, uniform radial cells): the radial
+  optical depth at shell centres is log-uniform from tau_min at the outer
+  shell to tau_max at the inner one (the stratified recipe along r, divided
+  by the radial cell size); a wavelength batch scales it by 10**U(-2, 2);
+  eps = 1e-3, B = 1, I_core = B, no diffuse incoming intensity, and a point
+  source at 5 r_out on the +z axis with mean intensity B at the sub-source
+  point.
 
 All fields are generated in float64 and, for single-precision workloads,
 rounded once to float32; those rounded values are the inputs of every solver.
@@ -172,3 +179,69 @@ def random_box(Nx: int, Ny: int, Nz: int, n_mu: int, n_phi: int, seed: int, dtyp
 def random_source(shape, seed: int, lo: float = 0.0, hi: float = 1.0, dtype: str = "f64") -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(seed))
     return _round(rng.uniform(lo, hi, size=shape), dtype)
+
+
+@dataclasses.dataclass
+class SphereCase:
+    """One workload on a spherical grid.  Arrays are [lambda][iphi][itheta][ir]."""
+    name: str
+    Nr: int
+    Nt: int
+    Np: int
+    r_core: float
+    r_out: float
+    n_mu: int
+    n_phi: int
+    source_distance: float    # in units of r_out; 0 = no point source
+    chi: np.ndarray           # (n_lambda, Np, Nt, Nr)
+    eps: np.ndarray
+    B: np.ndarray
+    I_bc: np.ndarray          # (n_lambda, 3): I_out, I_core, J_sub
+    dtype: str
+    tol: float = 1e-8
+
+    @property
+    def n_lambda(self) -> int:
+        return self.chi.shape[0]
+
+    @property
+    def n_dir(self) -> int:
+        return self.n_mu * self.n_phi
+
+    @property
+    def n_vox(self) -> int:
+        return self.Nr * self.Nt * self.Np
+
+    def vdu_per_fs(self) -> int:
+        return self.n_vox * self.n_dir * self.n_lambda
+
+
+def sphere_radial(Nr: int = 97, Nt: int = 65, Np: int = 129, n_mu: int = 32, n_phi: int = 32, n_lambda: int = 16,
+                  tau_min: float = 1e-6, tau_max: float = 1e6, eps: float = 1e-3, scale_seed: int = 3,
+                  source_distance: float = 5.0, dtype: str = "f32", name: str = "sphere-radial") -> SphereCase:
+    """Irradiated spherical shell; defaults: the 97x65x129, 32x32-direction, 16-wavelength FP32 workload."""
+    r_core, r_out = 1.0, 2.0
+    dr = (r_out - r_core) / Nr
+    chi_r = stratified_chi(Nr, tau_min, tau_max)[::-1] / dr      # ir = 0 is the innermost shell
+    rs = np.random.Generator(np.random.PCG64(scale_seed))
+    f = 10.0 ** rs.uniform(-2.0, 2.0, size=n_lambda)
+    chi = f[:, None, None, None] * np.broadcast_to(chi_r[None, None, None, :], (1, Np, Nt, Nr))
+    chi = _round(chi, dtype)
+    e = _round(np.full_like(chi, eps), dtype)
+    B = np.ones_like(chi)
+    I_bc = np.tile(np.array([[0.0, 1.0, 1.0]]), (n_lambda, 1))
+    return SphereCase(name, Nr, Nt, Np, r_core, r_out, n_mu, n_phi, source_distance, chi, e, B, I_bc, dtype)
+
+
+def random_sphere(Nr: int, Nt: int, Np: int, n_mu: int, n_phi: int, seed: int, dtype: str = "f64",
+                  n_lambda: int = 1, source_distance: float = 5.0, chi_dex=(-1.0, 1.5), eps_dex=(-3.0, 0.0),
+                  name: str = "sphere-random") -> SphereCase:
+    """Small heterogeneous spherical grid with iid log-uniform fields: parity-test input."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shape = (n_lambda, Np, Nt, Nr)
+    chi = _round(10.0 ** rng.uniform(chi_dex[0], chi_dex[1], size=shape), dtype)
+    e = _round(10.0 ** rng.uniform(eps_dex[0], eps_dex[1], size=shape), dtype)
+    B = _round(rng.uniform(0.5, 1.5, size=shape), dtype)
+    I_bc = _round(np.stack([rng.uniform(0.0, 0.3, size=n_lambda), rng.uniform(0.5, 1.5, size=n_lambda),
+                            rng.uniform(0.5, 2.0, size=n_lambda)], axis=1), dtype)
+    return SphereCase(name, Nr, Nt, Np, 1.0, 2.0, n_mu, n_phi, source_distance, chi, e, B, I_bc, dtype)

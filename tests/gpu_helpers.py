@@ -16,6 +16,10 @@ def to_dev(a, prec):
 
 def make_grid(case, n_lambda_max=None, lstar="linear", prec=None):
     import paper_2102_01734_amd as rt
+    if hasattr(case, "Nr"):
+        return rt.SphereGrid(case.Nr, case.Nt, case.Np, case.r_core, case.r_out, case.n_mu, case.n_phi,
+                             prec or case.dtype, n_lambda_max or case.n_lambda, lstar=lstar,
+                             source_distance=case.source_distance)
     return rt.Grid(case.Nx, case.Ny, case.Nz, case.n_mu, case.n_phi, prec or case.dtype,
                    n_lambda_max or case.n_lambda, lstar=lstar)
 
@@ -36,10 +40,11 @@ def gpu_fs(case, S, lstar="linear", want_lstar=True, prec=None, grid=None, I_bc=
     return out
 
 
-def gpu_solve(case, tol=1e-10, max_iter=2000, ng_every=4, ng_start=4, lstar="linear", prec=None, reanchor=0):
+def gpu_solve(case, tol=1e-10, max_iter=2000, ng_every=4, ng_start=4, lstar="linear", prec=None, reanchor=0,
+              grid=None):
     torch = torch_cuda()
     prec = prec or case.dtype
-    g = make_grid(case, lstar=lstar, prec=prec)
+    g = grid or make_grid(case, lstar=lstar, prec=prec)
     chi, eps, B = to_dev(case.chi, prec), to_dev(case.eps, prec), to_dev(case.B, prec)
     Ib = to_dev(case.I_bc, prec)
     st = g.new_state(chi, eps, B, Ib)
@@ -49,5 +54,6 @@ def gpu_solve(case, tol=1e-10, max_iter=2000, ng_every=4, ng_start=4, lstar="lin
     t = g.state_tensors(st)
     res = dict(J=t["J"].cpu().numpy(), S=t["S"].cpu().numpy(), lstar=t["lstar"].double().cpu().numpy(),
                status=status, report=rep)
-    g.close()
+    if grid is None:
+        g.close()
     return res

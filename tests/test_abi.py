@@ -70,6 +70,43 @@ def test_library_tracker_matches_oracle_tracker(orc, Nz, n_mu, n_phi):
         np.testing.assert_allclose(a["s"], b["s"], rtol=0, atol=1e-13 * Nz / abs(mu[d]))
 
 
+@pytest.mark.parametrize("Nr,Nt,Np,n_mu,n_phi", [(9, 8, 12, 4, 8), (6, 7, 5, 2, 4), (12, 10, 16, 8, 16)])
+def test_library_sphere_tracker_matches_oracle(orc, Nr, Nt, Np, n_mu, n_phi):
+    """The library's spherical tracker and the oracle's give the same
+    characteristics (foot points, ranges, kinds), voxel sequences and path
+    lengths; odd Nt has no equatorial plane, n_mu = 2 has no pole-near rays."""
+    import paper_2102_01734_amd as rt
+    g = orc.SphereGrid(Nr, Nt, Np, 1.0, 2.0)
+    desc = rt.sphere_desc(Nr, Nt, Np, 1.0, 2.0, n_mu, n_phi)
+    mu, phi, _ = orc.quadrature(n_mu, n_phi)
+    dirs = range(mu.size) if mu.size <= 32 else range(0, mu.size, 11)
+    for d in dirs:
+        n = orc.direction_vector(mu[d], phi[d])
+        a = rt.rt_sphere_tracks(desc, d)
+        assert a["h"] == pytest.approx(g.spacing(), rel=1e-15)
+        ch = g.rays(n)
+        assert a["chars"].shape[0] == ch.shape[0]
+        np.testing.assert_allclose(a["chars"][:, :5], ch[:, :5], rtol=0, atol=1e-14)
+        np.testing.assert_array_equal(a["chars"][:, 5], ch[:, 5])
+        for c in range(ch.shape[0]):
+            v, s, _ = g.segments(ch[c], n)
+            b0, b1 = a["begin"][c], a["begin"][c + 1]
+            np.testing.assert_array_equal(a["vox"][b0:b1], v)
+            np.testing.assert_allclose(a["s"][b0:b1], s, rtol=0, atol=1e-14)
+
+
+def test_sphere_tracker_rejects_bad_descriptors():
+    import paper_2102_01734_amd as rt
+    with pytest.raises(rt.RtError):
+        rt.rt_sphere_tracks(rt.sphere_desc(4, 4, 4, 2.0, 1.0, 4, 8), 0)      # r_core > r_out
+    with pytest.raises(rt.RtError):
+        rt.rt_sphere_tracks(rt.sphere_desc(4, 4, 4, 1.0, 2.0, 3, 8), 0)      # odd n_mu
+    with pytest.raises(rt.RtError):
+        rt.rt_sphere_tracks(rt.sphere_desc(4, 4, 4, 1.0, 2.0, 4, 8, source_distance=0.5), 0)
+    with pytest.raises(rt.RtError):
+        rt.rt_sphere_tracks(rt.sphere_desc(4, 4, 4, 1.0, 2.0, 4, 8), 32)     # direction out of range
+
+
 def test_tracker_rejects_bad_requests():
     import paper_2102_01734_amd as rt
     with pytest.raises(rt.RtError):
