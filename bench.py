@@ -34,6 +34,8 @@ PEAK_TFLOPS = 78.6
 WORKLOADS = {
     "lognormal129": dict(N=129, n_mu=32, n_phi=64),
     "lognormal65": dict(N=65, n_mu=16, n_phi=32),
+    # irradiated spherical shell, 16 wavelengths (not the default line)
+    "sphere97": dict(Nr=97, Nt=65, Np=129, n_mu=32, n_phi=32, n_lambda=16),
 }
 
 
@@ -82,6 +84,61 @@ def cpu_baseline(case, n_sub: int):
                       f"{case.n_vox} voxels ({wall:.1f} s wall)"}
 
 
+def bench_sphere(args, w):
+    """The spherical workload: one ALI step over the wavelength batch per step."""
+    import torch
+
+    import paper_2102_01734_amd as rt
+    import synthetic as sy
+    case = sy.sphere_radial(Nr=w["Nr"], Nt=w["Nt"], Np=w["Np"], n_mu=w["n_mu"], n_phi=w["n_phi"],
+                            n_lambda=w["n_lambda"])
+    dev = dict(dtype=torch.float32, device="cuda")
+    t0 = time.perf_counter()
+    g = rt.SphereGrid(case.Nr, case.Nt, case.Np, case.r_core, case.r_out, case.n_mu, case.n_phi, "f32",
+                      case.n_lambda, source_distance=case.source_distance)
+    t_build = time.perf_counter() - t0
+    info = g.info()
+    st = g.new_state(torch.tensor(case.chi, **dev), torch.tensor(case.eps, **dev), torch.tensor(case.B, **dev),
+                     torch.tensor(case.I_bc, **dev))
+    opts = g.opts(tol=1e-30, max_iter=1, ng_every=4, ng_start=4)
+    for _ in range(args.warmup):
+        g.ali_step(st, opts)
+    torch.cuda.synchronize()
+    rt.rt_profile_read(g.handle)
+    rt.rt_profile_enable(g.handle, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.ali_step(st, opts)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fs_ms, fs_launches, fs_points = rt.rt_profile_read(g.handle)
+    rt.rt_profile_enable(g.handle, False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    vdu = case.vdu_per_fs()
+    fs_ms_launch = fs_ms / max(fs_launches, 1)
+    points_launch = fs_points / max(fs_launches, 1)
+    achieved = FLOPS_PER_POINT * points_launch / (fs_ms_launch * 1e-3) / 1e12
+    out = {
+        "metric": "voxel-direction updates/s (formal solution)", "value": vdu / (ms_per_step * 1e-3),
+        "unit": "VDU/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"sphere r x theta x phi = {case.Nr}x{case.Nt}x{case.Np}, {case.n_mu}x{case.n_phi} "
+                               f"directions, {case.n_lambda} wavelengths, radial tau 1e-6..1e6, point source at 5 r_out; "
+                               "step = one ALI iteration over the batch",
+                   "voxels": case.n_vox, "directions": case.n_dir, "wavelengths": case.n_lambda,
+                   "vdu_per_step": vdu, "visits_per_vdu": info["n_visits"] / (case.n_vox * case.n_dir),
+                   "cache_chunks": info["n_workgroups"], "cache_build_s": t_build},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_TFLOPS, "traffic": None,
+                     "kernel": "fs_sphere_kernel<float,float,J> + sphere_gather (per chunk)",
+                     "kernel_ms_per_launch": fs_ms_launch, "launches": fs_launches,
+                     "flops_per_point": FLOPS_PER_POINT, "points_per_launch": points_launch},
+    }
+    g.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +175,8 @@ def main():
     import synthetic as sy
 
     w = WORKLOADS[args.workload]
+    if "Nr" in w:
+        return bench_sphere(args, w)
     case = sy.box_lognormal(N=w["N"], n_mu=w["n_mu"], n_phi=w["n_phi"])
     dev = dict(dtype=torch.float32, device="cuda")
     chi = torch.tensor(case.chi, **dev)
