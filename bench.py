@@ -84,6 +84,53 @@ def cpu_baseline(case, n_sub: int):
                       f"{case.n_vox} voxels ({wall:.1f} s wall)"}
 
 
+def time_to_solution(case, net_every: int = 12, tol: float = 1e-6):
+    """Wall seconds of rt_solve to the stopping tolerance `tol` (which lands below
+    1e-5 relative error on this workload) for plain double-precision Ng-ALI,
+    single-precision defect-corrected Ng-ALI, and the latter with the learned
+    correction; each with its max relative J error against a double-precision
+    solution iterated 80 steps past convergence to 1e-9 change."""
+    import torch
+
+    import paper_2102_01734_amd as rt
+    blob_path = os.path.join(ROOT, "paper_2102_01734_amd", "data", "precond_box.rtun")
+    blob = open(blob_path, "rb").read()
+
+    def run(prec, tol_, max_iter, net=0):
+        dt = torch.float32 if prec == "f32" else torch.float64
+        dev = dict(dtype=dt, device="cuda")
+        g = rt.Grid(case.Nx, case.Ny, case.Nz, case.n_mu, case.n_phi, prec, 1)
+        if net:
+            g.set_preconditioner(blob)
+        st = g.new_state(*(torch.tensor(a, **dev) for a in (case.chi, case.eps, case.B, case.I_bc)))
+        s = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(s):
+            status, rep = g.solve(st, g.opts(tol=tol_, max_iter=max_iter, use_graph=True, net_every=net), stream=s)
+        s.synchronize()
+        wall = time.perf_counter() - t0
+        J = g.state_tensors(st)["J"].clone()
+        g.close()
+        return J, status, rep, wall
+
+    ref, _, rref, _ = run("f64", 1e-9, 80)
+    out = {"tol": tol, "target_error": 1e-5,
+           "reference": f"double-precision Ng-ALI, {rref.iters} steps (last max |dJ/J| {rref.max_rel_change:.1e})"}
+    for name, prec, net in (("plain_f64_ng_ali", "f64", 0), ("f32_defect_corrected_ng_ali", "f32", 0),
+                            ("f32_learned", "f32", net_every)):
+        J, status, rep, wall = run(prec, tol, 300, net)
+        err = float(((J - ref).abs() / ref.abs()).max())
+        out[name] = {"seconds": wall, "steps": rep.iters, "formal_solutions": rep.n_fs, "fp64_fs": rep.n_fs64,
+                     "status": status, "max_rel_error": err}
+        if net:
+            out[name].update(net_every=net, accepted=rep.n_net_accept, rejected=rep.n_net_reject)
+    base = out["plain_f64_ng_ali"]["seconds"]
+    out["speedup_f32_vs_plain"] = base / out["f32_defect_corrected_ng_ali"]["seconds"]
+    out["speedup_learned_vs_plain"] = base / out["f32_learned"]["seconds"]
+    return out
+
+
 def bench_sphere(args, w):
     """The spherical workload: one ALI step over the wavelength batch per step."""
     import torch
@@ -147,6 +194,7 @@ def main():
     ap.add_argument("--workload", default="lognormal129", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-dirs", type=int, default=72, help="directions in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solve", action="store_true", help="skip the time-to-solution comparison")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--shape", default=None, help="fix the launch shape THREADS,RAYS instead of autotuning")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -259,6 +307,8 @@ def main():
     g.close()
     del st
     torch.cuda.synchronize()
+    if not args.no_solve:
+        out["time_to_solution"] = time_to_solution(case)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_dirs)
     print(json.dumps(out), flush=True)

@@ -172,6 +172,10 @@ typedef struct {
                              as a captured HIP graph, replayed per step; needs
                              a non-NULL stream.  Results are bitwise those of
                              eager launches.                                    */
+    int32_t net_every;    /* rt_solve with a preconditioner network set
+                             (rt_set_preconditioner): propose a learned
+                             correction after every net_every-th step
+                             (0 = never); see rt_set_preconditioner             */
 } rt_solve_opts;
 
 typedef struct {
@@ -182,6 +186,8 @@ typedef struct {
     int32_t n_converged;    /* wavelengths below tol at return                  */
     double max_rel_change;  /* max over wavelengths of the last step's change   */
     double seconds;         /* wall time of the call                            */
+    int32_t n_net_accept;   /* learned corrections kept (per wavelength)        */
+    int32_t n_net_reject;   /* learned corrections rejected (per wavelength)    */
 } rt_solve_report;
 
 /*
@@ -205,6 +211,48 @@ rt_status rt_ali_step(rt_grid_t grid, rt_state *state, const rt_solve_opts *opts
  */
 rt_status rt_solve(rt_grid_t grid, rt_state *state, const rt_solve_opts *opts,
                    rt_solve_report *report, void *stream);
+
+/*
+ * Learned ALI correction (an addition to the paper's method; box grids only).
+ * A 3D U-Net maps, per voxel, the features
+ *   f0 = r / max|r|,  r = (J_fs - J) / J   (the formal-solution residual of
+ *                                           the iterate before an ALI update)
+ *   f1 = log10(chi) / 4,  f2 = log10(eps) / 3 + 1
+ * to a relative correction c; the ALI iterate becomes
+ *   J <- J (1 + clamp(max|r| c, -1/2, 1)).
+ * Network: levels l = 0..L-1 with C_l in {16, 32, 64} channels and
+ * n_l = (n_{l-1} + 1)/2 points per axis; 3x3x3 convolutions (periodic in x, y,
+ * zero-padded in z) with ReLU, stride-2 convolutions down, linear 2x
+ * upsampling plus a convolution up, additive skips, a 1x1 head.  Inference
+ * runs in bf16 on the matrix cores with fp32 accumulation.
+ * Inside rt_solve (opts->net_every > 0) a correction is proposed after every
+ * net_every-th plain step k.  One ALI sweep smooths the corrected iterate, and
+ * the next sweep's formal solution gives the residual of the smoothed
+ * candidate; the correction is kept only where that residual is below
+ * res_k q^2, q = res_k / res_{k-1} the recent contraction of the plain
+ * iteration (per wavelength).  Otherwise J returns to the plain ALI iterate of
+ * step k, at the cost of two formal solutions, and the plain trajectory
+ * continues bitwise as without the network.  The fixed point is that of
+ * plain ALI, whatever the network.
+ *   blob   host memory: "RTUN", uint32 version = 1, uint32 L, uint32 C[L],
+ *          then for each convolution in the order input (3 -> C0), level-0
+ *          (C0 -> C0), for l = 1..L-1 down_l (C_{l-1} -> C_l, stride 2) and
+ *          conv_l (C_l -> C_l), for l = L-1..1 up_l (C_l -> C_{l-1}) and
+ *          dec_{l-1} (C_{l-1} -> C_{l-1}), head (C0 -> 1, one tap): float32
+ *          weights [tap][c_out][c_in] (tap = (dz*3 + dy)*3 + dx) and biases
+ *          [c_out].  Copied; the caller keeps ownership.  NULL removes the net.
+ * Errors: RT_E_INVALID (malformed blob), RT_E_UNSUPPORTED (spherical grid),
+ * RT_E_HIP.
+ */
+rt_status rt_set_preconditioner(rt_grid_t grid, const void *blob, size_t bytes);
+
+/*
+ * Network inference alone (for tests and tools): out = network(features) on
+ * the grid's Nz x Ny x Nx volume.  features: device float [Nz][Ny][Nx][3];
+ * out: device float [Nz][Ny][Nx].  Asynchronous on stream.  RT_E_INVALID if
+ * no network is set.
+ */
+rt_status rt_precond_forward(rt_grid_t grid, const float *features, float *out, void *stream);
 
 /*
  * Host-only tracker output for one direction of the box (no GPU needed): the

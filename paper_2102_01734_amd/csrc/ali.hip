@@ -180,6 +180,15 @@ __device__ __forceinline__ double block_max(double v)
     return v;
 }
 
+// S = (1-eps) J + eps B, evaluated the same way (no contraction) wherever S
+// is formed, so a source recomputed from a restored J is bitwise the one the
+// update produced
+__device__ __forceinline__ double source_value(double e, double j, double b)
+{
+#pragma clang fp contract(off)
+    return (1.0 - e) * j + e * b;
+}
+
 // ---------------------------------------------------------------------------
 // S = (1-eps) J + eps B and the padded formal-solution input (S - anchor)
 // ---------------------------------------------------------------------------
@@ -192,7 +201,7 @@ __global__ void source_kernel(const double *__restrict__ J, const G *__restrict_
     if (v >= n_vox) return;
     const int64_t i = (int64_t)lambda_of[blockIdx.y] * n_vox + v;
     const double e = (double)eps[i];
-    const double s = (1.0 - e) * J[i] + e * (double)B[i];
+    const double s = source_value(e, J[i], (double)B[i]);
     S[i] = s;
     const TN out = (TN)(S_anchor ? s - S_anchor[i] : s);
     store_padded<TN>(next_pad, lambda_of[blockIdx.y], n_vox, v, Nx, Ny, 1, out);
@@ -230,7 +239,7 @@ __global__ void __launch_bounds__(256) ali_update_kernel(AliUpdateArgs a)
     const int b = blockIdx.y;
     const int lam = a.lambda_of[b];
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double rel = 0.0;
+    double rel = 0.0, res = 0.0;
     if (v < a.n_vox) {
         const int64_t i = (int64_t)lam * a.n_vox + v;
         double jfs = a.J_anchor ? a.J_anchor[i] : 0.0;
@@ -245,6 +254,10 @@ __global__ void __launch_bounds__(256) ali_update_kernel(AliUpdateArgs a)
         const double L = (double)reinterpret_cast<const G *>(a.lstar)[i];
         const double Bv = (double)reinterpret_cast<const G *>(a.B)[i];
         const double jo = a.J[i];
+        const double rr = (jfs - jo) / jo;
+        res = fabs(rr);
+        if (!(res <= 1.0e308)) res = __builtin_inf();
+        if (a.net_r) a.net_r[i] = (float)rr;
         double den = 1.0 - (1.0 - e) * L;
         den = den < 1e-12 ? 1e-12 : den;
         const double jn = jo + (jfs - jo) / den;
@@ -253,13 +266,18 @@ __global__ void __launch_bounds__(256) ali_update_kernel(AliUpdateArgs a)
         const double dj = fabs(jn - jo);
         rel = dj == 0.0 ? 0.0 : dj / fabs(jn);
         if (!(rel <= 1.0e308)) rel = __builtin_inf();  // NaN or Inf: reported as non-finite
-        const double s = (1.0 - e) * jn + e * Bv;
+        const double s = source_value(e, jn, Bv);
         a.S[i] = s;
         const TN out = (TN)(a.S_anchor ? s - a.S_anchor[i] : s);
         store_padded<TN>(reinterpret_cast<TN *>(a.next_pad), lam, a.n_vox, v, a.Nx, a.Ny, 1, out);
     }
     rel = block_max<256>(rel);
     if (threadIdx.x == 0) atomic_max_nonneg(&a.rel_change[lam], rel);
+    if (a.resid) {
+        __syncthreads();  // the reduction scratch of block_max is reused
+        res = block_max<256>(res);
+        if (threadIdx.x == 0) atomic_max_nonneg(&a.resid[lam], res);
+    }
 }
 
 template <typename TP, typename G, typename TN>
@@ -354,7 +372,7 @@ __global__ void ng_apply_kernel(NgApplyArgs a)
     const double jn = (1.0 - ca - cb) * a.x0[i] + ca * a.x1[i] + cb * a.x2[i];
     a.J[i] = jn;
     const double e = (double)reinterpret_cast<const G *>(a.eps)[i];
-    const double s = (1.0 - e) * jn + e * (double)reinterpret_cast<const G *>(a.B)[i];
+    const double s = source_value(e, jn, (double)reinterpret_cast<const G *>(a.B)[i]);
     a.S[i] = s;
     const TN out = (TN)(a.S_anchor ? s - a.S_anchor[i] : s);
     store_padded<TN>(reinterpret_cast<TN *>(a.next_pad), lam, a.n_vox, v, a.Nx, a.Ny, 1, out);

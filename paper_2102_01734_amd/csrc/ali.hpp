@@ -42,6 +42,8 @@ struct AliUpdateArgs {
     double *hist;               // out: copy of the new J into the Ng ring, or null
     void *next_pad;             // out: S - S_anchor into the interleaved padded input
     double *rel_change;         // out: per wavelength max |dJ/J| (atomic max)
+    double *resid;              // out: per wavelength max |J_fs - J_old| / |J_old| (atomic max), or null
+    float *net_r;               // out: (J_fs - J_old) / J_old per voxel (network input), or null
 };
 
 hipError_t ali_update(const AliUpdateArgs &a, bool part_double, bool grid_double, bool next_double, int n_batch,

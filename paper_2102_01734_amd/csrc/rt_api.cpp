@@ -23,6 +23,7 @@
 #include "fs_box.hpp"
 #include "fs_sphere.hpp"
 #include "rt_internal.hpp"
+#include "unet.hpp"
 
 using namespace rt3d;
 
@@ -138,6 +139,9 @@ struct rt_grid {
     const void *chi_src = nullptr;
     // captured plain ALI steps, keyed by batch, ring slot and state pointers
     std::map<std::string, hipGraphExec_t> graphs;
+    // learned ALI correction
+    UNetDev *net = nullptr;
+    DevBuf net_r, net_f, net_out, J_save, resid;
     // measurement hooks
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
@@ -151,6 +155,7 @@ struct rt_grid {
     {
         for (auto &e : prof_events) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
         drop_graphs();
+        if (net) unet_destroy(net);
     }
 };
 
@@ -930,6 +935,7 @@ static rt_status check_opts(const rt_solve_opts *o)
     if (o->max_iter < 1) return fail(RT_E_INVALID, "opts->max_iter must be >= 1");
     if (o->ng_every < 0 || o->ng_start < 0 || o->reanchor < 0) return fail(RT_E_INVALID, "negative Ng/anchor option");
     if (o->use_graph != 0 && o->use_graph != 1) return fail(RT_E_INVALID, "opts->use_graph must be 0 or 1");
+    if (o->net_every < 0) return fail(RT_E_INVALID, "opts->net_every must be >= 0");
     return RT_OK;
 }
 
@@ -949,6 +955,13 @@ static rt_status ensure_state_buffers(rt_grid *g)
     HIPCHK(g->hist.ensure(4 * nl * nv * 8));
     HIPCHK(g->ng_blk.ensure(nl * 256 * 5 * 8));
     HIPCHK(g->ng_coef.ensure(nl * 3 * 8));
+    HIPCHK(g->resid.ensure(nl * 8));
+    if (g->net) {
+        HIPCHK(g->net_r.ensure(nl * nv * 4));
+        HIPCHK(g->J_save.ensure(nl * nv * 8));
+        HIPCHK(g->net_f.ensure(nv * 3 * 4));
+        HIPCHK(g->net_out.ensure(nv * 4));
+    }
     return RT_OK;
 }
 
@@ -956,17 +969,20 @@ static rt_status ensure_state_buffers(rt_grid *g)
 // solution of the current S (FP64 grids) or of S - S_anchor (FP32 grids), and
 // the fused update.  Issues only kernel launches, so it can be captured.
 static rt_status plain_step_launches(rt_grid *g, rt_state *s, const std::vector<int32_t> &lams,
-                                     const int32_t *lambda_of, hipStream_t st)
+                                     const int32_t *lambda_of, hipStream_t st, bool keep_hist = true)
 {
     const int nl = s->n_lambda, nb = (int)lams.size();
     const int64_t nv = g->n_vox;
     HIPCHK(fill_u64(reinterpret_cast<unsigned long long *>(s->rel_change), 0ull, nl, st));
+    HIPCHK(fill_u64(g->resid.as<unsigned long long>(), 0ull, nl, st));
     AliUpdateArgs ua{};
     ua.Nx = g->lx; ua.Ny = g->ly; ua.n_vox = nv;
+    ua.resid = g->resid.as<double>();
+    ua.net_r = g->net ? g->net_r.as<float>() : nullptr;
     ua.lambda_of = lambda_of;
     ua.eps = s->eps; ua.B = s->B; ua.lstar = s->lstar;
     ua.J = s->J; ua.S = s->S;
-    ua.hist = g->hist.as<double>() + (size_t)(g->hist_count % 4) * nl * nv;
+    ua.hist = keep_hist ? g->hist.as<double>() + (size_t)(g->hist_count % 4) * nl * nv : nullptr;
     ua.rel_change = s->rel_change;
     ua.next_pad = g->fld.p;
     DevSchedule *sc = nullptr;
@@ -1001,9 +1017,9 @@ static rt_status graph_plain_step(rt_grid *g, rt_state *s, const std::vector<int
     DevBuf &pJ = g->dbl ? g->partJ64 : g->partJ;
     HIPCHK(pJ.ensure((size_t)sc->n_slots * g->n_vox * (g->dbl ? 8 : 4)));
     char buf[512];
-    snprintf(buf, sizeof buf, "%d|%p|%p|%p|%p|%p|%p|%p|%p|%d|%d|%d:", g->hist_count % 4, (void *)s->J,
-             (void *)s->S, s->lstar, s->eps, s->B, (void *)s->rel_change, pJ.p, (void *)st, s->n_lambda,
-             v.lb, v.R);
+    snprintf(buf, sizeof buf, "%d|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%d|%d|%d:", g->hist_count % 4, (void *)s->J,
+             (void *)s->S, s->lstar, s->eps, s->B, (void *)s->rel_change, pJ.p, (void *)st,
+             g->net ? g->net_r.p : nullptr, g->resid.p, s->n_lambda, v.lb, v.R);
     std::string key(buf);
     for (int l : lams) key += std::to_string(l) + ",";
     auto it = g->graphs.find(key);
@@ -1032,8 +1048,12 @@ static rt_status graph_plain_step(rt_grid *g, rt_state *s, const std::vector<int
 }
 
 // One ALI step over the wavelengths in `lams` (all of them must be indices < n_lambda).
+// candidate: J holds a proposed (learned) iterate; the step neither applies Ng
+// nor enters the result into the Ng history, so that a rejected proposal
+// leaves the history of plain iterates untouched.
 static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o, const std::vector<int32_t> &lams,
-                                bool anchor, hipStream_t st, int *fs_count, int *fs64_count, int *ng_count)
+                                bool anchor, hipStream_t st, int *fs_count, int *fs64_count, int *ng_count,
+                                bool candidate = false)
 {
     const int Nx = g->lx, Ny = g->ly, Nz = g->lz;
     const int nl = s->n_lambda;
@@ -1065,7 +1085,7 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
     }
 
     // Ng extrapolation of the last four iterates, due before this step's formal solution
-    if (o->ng_every > 0 && g->hist_count >= 4 && s->iter >= o->ng_start) {
+    if (!candidate && o->ng_every > 0 && g->hist_count >= 4 && s->iter >= o->ng_start) {
         NgApplyArgs na{};
         na.Nx = Nx; na.Ny = Ny; na.n_vox = nv;
         na.lambda_of = lambda_of;
@@ -1088,24 +1108,27 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
 
     const bool want_l = s->lstar_valid == 0;
     if (!want_l && (g->dbl || !anchor)) {
-        if (o->use_graph && st != nullptr)
+        if (o->use_graph && st != nullptr && !candidate)
             rs = graph_plain_step(g, s, lams, lambda_of, st);
         else
-            rs = plain_step_launches(g, s, lams, lambda_of, st);
+            rs = plain_step_launches(g, s, lams, lambda_of, st, !candidate);
         if (rs != RT_OK) return rs;
         ++*fs_count;
         if (g->dbl) ++*fs64_count;
-        g->hist_count++;
+        if (!candidate) g->hist_count++;
         s->iter++;
         return RT_OK;
     }
     HIPCHK(fill_u64(reinterpret_cast<unsigned long long *>(s->rel_change), 0ull, nl, st));
+    HIPCHK(fill_u64(g->resid.as<unsigned long long>(), 0ull, nl, st));
     AliUpdateArgs ua{};
     ua.Nx = Nx; ua.Ny = Ny; ua.n_vox = nv;
+    ua.resid = g->resid.as<double>();
+    ua.net_r = g->net ? g->net_r.as<float>() : nullptr;
     ua.lambda_of = lambda_of;
     ua.eps = s->eps; ua.B = s->B; ua.lstar = s->lstar;
     ua.J = s->J; ua.S = s->S;
-    ua.hist = g->hist.as<double>() + (size_t)(g->hist_count % 4) * nl * nv;
+    ua.hist = candidate ? nullptr : g->hist.as<double>() + (size_t)(g->hist_count % 4) * nl * nv;
     ua.rel_change = s->rel_change;
     ua.next_pad = g->fld.p;
     DevSchedule *sc = nullptr;
@@ -1172,7 +1195,7 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
         }
     }
     s->lstar_valid = 1;
-    g->hist_count++;
+    if (!candidate) g->hist_count++;
     s->iter++;
     return RT_OK;
 }
@@ -1192,6 +1215,47 @@ rt_status rt_ali_step(rt_grid_t g, rt_state *s, const rt_solve_opts *o, void *st
     return ali_step_batch(g, s, o, lams, false, (hipStream_t)stream, &nfs, &nfs64, &nng);
 }
 
+// Learned correction of the wavelengths in `lams`: save the plain ALI
+// iterate, evaluate the network on (r / max|r|, chi, eps) and scale J.
+static rt_status net_propose(rt_grid *g, rt_state *s, const std::vector<int32_t> &lams, const std::vector<double> &res,
+                             hipStream_t st)
+{
+    const int64_t nv = g->n_vox;
+    const size_t esz = g->dbl ? 8 : 4;
+    for (int l : lams) {
+        double *J = s->J + (size_t)l * nv;
+        HIPCHK(hipMemcpyAsync(g->J_save.as<double>() + (size_t)l * nv, J, nv * 8, hipMemcpyDeviceToDevice, st));
+        const float *r = g->net_r.as<float>() + (size_t)l * nv;
+        const char *chi = (const char *)s->chi + (size_t)l * nv * esz;
+        const char *eps = (const char *)s->eps + (size_t)l * nv * esz;
+        if (g->dbl)
+            HIPCHK(unet_features<double>(r, res[l], (const double *)chi, (const double *)eps, nv, g->net_f.as<float>(), st));
+        else
+            HIPCHK(unet_features<float>(r, res[l], (const float *)chi, (const float *)eps, nv, g->net_f.as<float>(), st));
+        HIPCHK(unet_forward(g->net, g->net_f.as<float>(), g->net_out.as<float>(), st));
+        HIPCHK(unet_apply(g->net_out.as<float>(), res[l], J, nv, st));
+    }
+    return RT_OK;
+}
+
+// S and the formal-solution input from the current J of the wavelengths in `lams`.
+static rt_status refresh_source(rt_grid *g, rt_state *s, const std::vector<int32_t> &lams, hipStream_t st)
+{
+    DevSchedule *sc = nullptr;
+    rt_status rs = get_schedule(g, variant(g, g->dbl, true, false).n_wg, lams, &sc);
+    if (rs != RT_OK) return rs;
+    const int nb = (int)lams.size();
+    if (g->dbl)
+        HIPCHK(source_update<double, double>(s->J, (const double *)s->eps, (const double *)s->B, s->S, nullptr,
+                                             g->fld.as<double>(), g->lx, g->ly, g->n_vox, sc->lambda_of.as<int32_t>(),
+                                             nb, st));
+    else
+        HIPCHK(source_update<float, float>(s->J, (const float *)s->eps, (const float *)s->B, s->S,
+                                           g->S_anchor.as<double>(), g->fld.as<float>(), g->lx, g->ly, g->n_vox,
+                                           sc->lambda_of.as<int32_t>(), nb, st));
+    return RT_OK;
+}
+
 rt_status rt_solve(rt_grid_t g, rt_state *s, const rt_solve_opts *o, rt_solve_report *rep, void *stream)
 {
     if (!g) return fail(RT_E_INVALID, "grid is NULL");
@@ -1203,23 +1267,65 @@ rt_status rt_solve(rt_grid_t g, rt_state *s, const rt_solve_opts *o, rt_solve_re
     const auto t0 = std::chrono::steady_clock::now();
     rt_solve_report r{};
     const int nl = s->n_lambda;
+    const int64_t nv = g->n_vox;
     std::vector<int32_t> active(nl);
     for (int i = 0; i < nl; ++i) active[i] = i;
-    std::vector<double> rel(nl, 0.0);
+    std::vector<double> rel(nl, 0.0), res(nl, 0.0), res_before(nl, 0.0), res_prev(nl, 0.0), res_goal(nl, 0.0);
     const double refac = o->reanchor > 0 ? (double)o->reanchor : 100.0;
+    const bool use_net = g->net != nullptr && o->net_every > 0;
+    // Learned corrections: after a proposal, one ALI sweep smooths the candidate
+    // (phase 1), and the residual of the smoothed candidate, measured by the
+    // sweep after it (phase 2), decides.  The network removes smooth error that
+    // the residual hardly sees and leaves small-scale error that the residual
+    // amplifies and one sweep removes, so the raw candidate's residual would
+    // misjudge it.  The goal is the residual the plain iteration would reach
+    // in the same two steps, from its recent contraction.
+    std::vector<int32_t> pending;  // wavelengths whose J descends from a learned candidate
+    int phase = 0;
+    int since_net = 0;
     double rel_at_anchor = 1e300;
     bool anchor_next = true;
     rt_status out = RT_E_NOT_CONVERGED;
     for (int it = 0; it < o->max_iter; ++it) {
-        const bool anchor = !g->dbl && (anchor_next || s->iter == 0);
-        rs = ali_step_batch(g, s, o, active, anchor, st, &r.n_fs, &r.n_fs64, &r.n_ng);
+        const bool cand = !pending.empty();
+        const bool anchor = !g->dbl && !cand && (anchor_next || s->iter == 0);
+        rs = ali_step_batch(g, s, o, active, anchor, st, &r.n_fs, &r.n_fs64, &r.n_ng, cand);
         if (rs != RT_OK) return rs;
         HIPCHK(hipMemcpyAsync(rel.data(), s->rel_change, nl * sizeof(double), hipMemcpyDeviceToHost, st));
+        if (use_net) HIPCHK(hipMemcpyAsync(res.data(), g->resid.p, nl * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         r.iters++;
+        // verdict on pending candidates: this step's residual is that of the smoothed candidate
+        std::vector<int32_t> rejected;
+        if (!pending.empty() && phase == 1) {
+            phase = 2;
+        } else if (!pending.empty()) {
+            for (int l : pending) {
+                if (res[l] < res_goal[l]) r.n_net_accept++;
+                else rejected.push_back(l);
+            }
+            r.n_net_reject += (int)rejected.size();
+            for (int l : rejected)
+                HIPCHK(hipMemcpyAsync(s->J + (size_t)l * nv, g->J_save.as<double>() + (size_t)l * nv, nv * 8,
+                                      hipMemcpyDeviceToDevice, st));
+            if (!rejected.empty()) {
+                rs = refresh_source(g, s, rejected, st);
+                if (rs != RT_OK) return rs;
+            }
+            // an accepted correction breaks the sequence of plain iterates Ng works on;
+            // when every proposal is rejected the plain trajectory continues unchanged
+            if (rejected.size() != pending.size()) g->hist_count = 0;
+            pending.clear();
+            phase = 0;
+        }
         double mx = 0.0;
         std::vector<int32_t> still;
         for (int l : active) {
+            // a rejected candidate's step is discarded, whatever it produced
+            if (std::find(rejected.begin(), rejected.end(), l) != rejected.end()) {
+                still.push_back(l);
+                continue;
+            }
             if (!(rel[l] <= 1e308)) {
                 r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
                 if (rep) *rep = r;
@@ -1229,10 +1335,53 @@ rt_status rt_solve(rt_grid_t g, rt_state *s, const rt_solve_opts *o, rt_solve_re
             mx = rel[l] > mx ? rel[l] : mx;
         }
         r.max_rel_change = mx;
-        if (anchor) rel_at_anchor = mx;
-        anchor_next = !g->dbl && mx < rel_at_anchor / refac;
+        if (!cand) {  // candidate steps do not move the anchor schedule
+            if (anchor) rel_at_anchor = mx;
+            anchor_next = !g->dbl && mx < rel_at_anchor / refac;
+        }
         active.swap(still);
+        if (!pending.empty()) {  // candidates that converged during smoothing need no verdict
+            std::vector<int32_t> keep;
+            for (int l : pending)
+                if (std::find(active.begin(), active.end(), l) != active.end()) keep.push_back(l);
+                else r.n_net_accept++;
+            pending.swap(keep);
+            if (pending.empty()) phase = 0;
+        }
         if (active.empty()) { out = RT_OK; break; }
+        // propose a learned correction for the wavelengths still iterating
+        if (!cand) {
+            ++since_net;
+            for (int l : active) {
+                res_prev[l] = res_before[l];
+                res_before[l] = res[l];
+            }
+        }
+        if (use_net && !cand && since_net >= o->net_every && it + 2 < o->max_iter) {
+            for (int l : active)
+                if (res[l] > 0.0 && res[l] <= 1e308) pending.push_back(l);
+            if (!pending.empty()) {
+                rs = net_propose(g, s, pending, res, st);
+                if (rs != RT_OK) return rs;
+                rs = refresh_source(g, s, pending, st);
+                if (rs != RT_OK) return rs;
+                for (int l : pending) {
+                    const double q = res_prev[l] > 0.0 ? std::min(1.0, res[l] / res_prev[l]) : 1.0;
+                    res_goal[l] = res[l] * q * q;
+                }
+                phase = 1;
+            }
+            since_net = 0;
+        }
+    }
+    // a candidate still pending at max_iter has not been checked: return the plain iterate
+    if (!pending.empty()) {
+        for (int l : pending)
+            HIPCHK(hipMemcpyAsync(s->J + (size_t)l * nv, g->J_save.as<double>() + (size_t)l * nv, nv * 8,
+                                  hipMemcpyDeviceToDevice, st));
+        rs = refresh_source(g, s, pending, st);
+        if (rs != RT_OK) return rs;
+        HIPCHK(hipStreamSynchronize(st));
     }
     r.n_converged = nl - (int)active.size();
     r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1240,6 +1389,32 @@ rt_status rt_solve(rt_grid_t g, rt_state *s, const rt_solve_opts *o, rt_solve_re
     if (out != RT_OK) return fail(RT_E_NOT_CONVERGED, "%d of %d wavelengths not converged after %d steps",
                                   (int)active.size(), nl, o->max_iter);
     g_err.clear();
+    return RT_OK;
+}
+
+rt_status rt_set_preconditioner(rt_grid_t g, const void *blob, size_t bytes)
+{
+    if (!g) return fail(RT_E_INVALID, "grid is NULL");
+    if (g->sphere) return fail(RT_E_UNSUPPORTED, "the learned correction is available on box grids only");
+    HIPCHK(hipDeviceSynchronize());
+    g->drop_graphs();
+    if (g->net) { unet_destroy(g->net); g->net = nullptr; }
+    if (!blob) return RT_OK;
+    UNetSpec spec;
+    std::string err = parse_unet(blob, bytes, spec);
+    if (!err.empty()) return fail(RT_E_INVALID, "%s", err.c_str());
+    UNetDev *u = unet_create(spec, g->geo.Nx, g->geo.Ny, g->geo.Nz, err);
+    if (!u) return fail(RT_E_HIP, "%s", err.c_str());
+    g->net = u;
+    return RT_OK;
+}
+
+rt_status rt_precond_forward(rt_grid_t g, const float *features, float *out, void *stream)
+{
+    if (!g) return fail(RT_E_INVALID, "grid is NULL");
+    if (!g->net) return fail(RT_E_INVALID, "no network set (rt_set_preconditioner)");
+    if (!features || !out) return fail(RT_E_INVALID, "features and out must not be NULL");
+    HIPCHK(unet_forward(g->net, features, out, (hipStream_t)stream));
     return RT_OK;
 }
 

@@ -1,0 +1,455 @@
+// unet.hip -- inference of the learned ALI correction network (gfx950).
+//
+// The 3^3 convolutions between feature maps of 16, 32 or 64 channels are
+// implicit GEMMs on the matrix cores: one wavefront computes 16 consecutive
+// output voxels of one (z, y) row times all output channels.  For every tap
+// and every 16-channel slice of the input, the A operand is the 16 voxels x
+// 16 input channels (bf16, channels last, one 8-byte load per lane) and the B
+// operand the 16 input x 16 output channels of the tap's weights; the
+// products accumulate in fp32 (v_mfma_f32_16x16x16_bf16).  Bias, ReLU and
+// the U-Net skip addition are fused into the store.  The small layers (3
+// input features, the 1-channel head) and the upsampling are plain VALU
+// kernels.  Activations never leave HBM between layers; at 129^3 with 16
+// channels a level-0 map is 68 MB.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "unet.hpp"
+
+namespace rt3d {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    // round to nearest even (finite inputs)
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+static uint16_t f2bf_host(float f)
+{
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+struct Vol {
+    int nx, ny, nz;
+    __host__ __device__ int64_t n() const { return (int64_t)nx * ny * nz; }
+};
+
+// ---------------------------------------------------------------------------
+// 3^3 convolution on the matrix cores
+// ---------------------------------------------------------------------------
+struct ConvArgs {
+    const uint16_t *in;
+    Vol vi, vo;
+    int stride;
+    const uint16_t *w;     // [27][CO][CI] bf16
+    const float *bias;     // [CO]
+    const uint16_t *skip;  // [vo][CO] bf16 added after the ReLU, or null
+    uint16_t *out;         // [vo][CO]
+};
+
+template <int CI, int CO>
+__global__ void __launch_bounds__(256) conv_mfma_kernel(ConvArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int tiles_x = (a.vo.nx + 15) / 16;
+    const int64_t total = (int64_t)tiles_x * a.vo.ny * a.vo.nz;
+    if (wave >= total) return;  // uniform per wavefront
+    const int tx = (int)(wave % tiles_x);
+    const int64_t r = wave / tiles_x;
+    const int y = (int)(r % a.vo.ny);
+    const int z = (int)(r / a.vo.ny);
+    const int x0 = tx * 16;
+    const int i = lane & 15;         // A row (output voxel x0 + i) / B column (output channel)
+    const int kq = (lane >> 4) * 4;  // first of the 4 k values this lane holds
+    const int xo = min(x0 + i, a.vo.nx - 1);
+    const int S = a.stride;
+
+    v4f acc[CO / 16];
+#pragma unroll
+    for (int c = 0; c < CO / 16; ++c) acc[c] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    for (int dz = 0; dz < 3; ++dz) {
+        const int zi = z * S + dz - 1;
+        if (zi < 0 || zi >= a.vi.nz) continue;  // zero padding in z (uniform per wavefront)
+        for (int dy = 0; dy < 3; ++dy) {
+            const int yi = wrap(y * S + dy - 1, a.vi.ny);
+            for (int dx = 0; dx < 3; ++dx) {
+                const int xi = wrap(xo * S + dx - 1, a.vi.nx);
+                const int tap = (dz * 3 + dy) * 3 + dx;
+                const uint16_t *src = a.in + (((int64_t)zi * a.vi.ny + yi) * a.vi.nx + xi) * CI + kq;
+                const uint16_t *wt = a.w + ((int64_t)tap * CO + i) * CI + kq;
+#pragma unroll
+                for (int cc = 0; cc < CI / 16; ++cc) {
+                    const v4s A = *reinterpret_cast<const v4s *>(src + cc * 16);
+#pragma unroll
+                    for (int cb = 0; cb < CO / 16; ++cb) {
+                        const v4s B = *reinterpret_cast<const v4s *>(wt + (int64_t)cb * 16 * CI + cc * 16);
+                        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B, acc[cb], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+    // D layout: lane holds rows kq .. kq+3 (voxels) of column i (output channel)
+#pragma unroll
+    for (int cb = 0; cb < CO / 16; ++cb) {
+        const int co = cb * 16 + i;
+        const float b = a.bias[co];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int x = x0 + kq + j;
+            if (x >= a.vo.nx) continue;
+            const int64_t v = ((int64_t)z * a.vo.ny + y) * a.vo.nx + x;
+            float val = fmaxf(acc[cb][j] + b, 0.f);
+            if (a.skip) val += bf2f(a.skip[v * CO + co]);
+            a.out[v * CO + co] = f2bf(val);
+        }
+    }
+}
+
+template <int CI, int CO>
+static hipError_t conv_t(const ConvArgs &a, hipStream_t st)
+{
+    const int64_t waves = (int64_t)((a.vo.nx + 15) / 16) * a.vo.ny * a.vo.nz;
+    hipLaunchKernelGGL((conv_mfma_kernel<CI, CO>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+static hipError_t conv_mfma(const ConvArgs &a, int ci, int co, hipStream_t st)
+{
+#define RT_CONV_CASE(I, O) \
+    if (ci == I && co == O) return conv_t<I, O>(a, st);
+    RT_CONV_CASE(16, 16) RT_CONV_CASE(16, 32) RT_CONV_CASE(16, 64)
+    RT_CONV_CASE(32, 16) RT_CONV_CASE(32, 32) RT_CONV_CASE(32, 64)
+    RT_CONV_CASE(64, 16) RT_CONV_CASE(64, 32) RT_CONV_CASE(64, 64)
+#undef RT_CONV_CASE
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// input layer (3 features -> C channels) and head (C -> 1), fp32 VALU
+// ---------------------------------------------------------------------------
+template <int CO>
+__global__ void __launch_bounds__(256) conv_in_kernel(const float *__restrict__ f, Vol v, const float *__restrict__ w,
+                                                      const float *__restrict__ bias, uint16_t *__restrict__ out)
+{
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= v.n()) return;
+    const int x = (int)(id % v.nx);
+    const int64_t r = id / v.nx;
+    const int y = (int)(r % v.ny);
+    const int z = (int)(r / v.ny);
+    float acc[CO];
+#pragma unroll
+    for (int c = 0; c < CO; ++c) acc[c] = bias[c];
+    for (int dz = 0; dz < 3; ++dz) {
+        const int zi = z + dz - 1;
+        if (zi < 0 || zi >= v.nz) continue;
+        for (int dy = 0; dy < 3; ++dy) {
+            const int yi = wrap(y + dy - 1, v.ny);
+            for (int dx = 0; dx < 3; ++dx) {
+                const int xi = wrap(x + dx - 1, v.nx);
+                const float *fp = f + (((int64_t)zi * v.ny + yi) * v.nx + xi) * 3;
+                const float f0 = fp[0], f1 = fp[1], f2 = fp[2];
+                const float *wt = w + ((dz * 3 + dy) * 3 + dx) * CO * 3;
+#pragma unroll
+                for (int c = 0; c < CO; ++c) acc[c] += wt[3 * c] * f0 + wt[3 * c + 1] * f1 + wt[3 * c + 2] * f2;
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CO; ++c) out[id * CO + c] = f2bf(fmaxf(acc[c], 0.f));
+}
+
+template <int C>
+__global__ void __launch_bounds__(256) head_kernel(const uint16_t *__restrict__ h, int64_t n, const float *__restrict__ w,
+                                                   const float *__restrict__ bias, float *__restrict__ out)
+{
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n) return;
+    float acc = bias[0];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc += w[c] * bf2f(h[id * C + c]);
+    out[id] = acc;
+}
+
+// linear upsampling by 2 (align corners): fine index o takes the coarse
+// point o/2 (o even) or the mean of (o-1)/2 and (o+1)/2 (o odd); the upper
+// neighbour wraps in x, y and is clamped in z
+__global__ void __launch_bounds__(256) upsample_kernel(const uint16_t *__restrict__ in, Vol vc, uint16_t *__restrict__ out,
+                                                       Vol vf, int C)
+{
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= vf.n() * C) return;
+    const int c = (int)(id % C);
+    const int64_t v = id / C;
+    const int x = (int)(v % vf.nx);
+    const int64_t r = v / vf.nx;
+    const int y = (int)(r % vf.ny);
+    const int z = (int)(r / vf.ny);
+    int xs[2], ys[2], zs[2];
+    xs[0] = x >> 1; xs[1] = (x & 1) ? wrap((x + 1) >> 1, vc.nx) : xs[0];
+    ys[0] = y >> 1; ys[1] = (y & 1) ? wrap((y + 1) >> 1, vc.ny) : ys[0];
+    zs[0] = z >> 1; zs[1] = (z & 1) ? min((z + 1) >> 1, vc.nz - 1) : zs[0];
+    float acc = 0.f;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int d = 0; d < 2; ++d)
+                acc += bf2f(in[(((int64_t)zs[a] * vc.ny + ys[b]) * vc.nx + xs[d]) * C + c]);
+    out[id] = f2bf(0.125f * acc);
+}
+
+// ---------------------------------------------------------------------------
+// features and application of the correction
+// ---------------------------------------------------------------------------
+template <typename G>
+__global__ void __launch_bounds__(256) features_kernel(const float *__restrict__ r, float inv_scale,
+                                                       const G *__restrict__ chi, const G *__restrict__ eps, int64_t n,
+                                                       float *__restrict__ f)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const float c = fmaxf((float)chi[v], 1e-30f), e = fmaxf((float)eps[v], 1e-30f);
+    f[3 * v] = r[v] * inv_scale;
+    f[3 * v + 1] = log10f(c) * 0.25f;
+    f[3 * v + 2] = log10f(e) * (1.0f / 3.0f) + 1.0f;
+}
+
+template <typename G>
+hipError_t unet_features(const float *r, double scale, const G *chi, const G *eps, int64_t n, float *features,
+                         hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    const float inv = scale > 0.0 ? (float)(1.0 / scale) : 0.f;
+    hipLaunchKernelGGL((features_kernel<G>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, r, inv, chi, eps, n,
+                       features);
+    return hipGetLastError();
+}
+template hipError_t unet_features<float>(const float *, double, const float *, const float *, int64_t, float *,
+                                         hipStream_t);
+template hipError_t unet_features<double>(const float *, double, const double *, const double *, int64_t, float *,
+                                          hipStream_t);
+
+__global__ void __launch_bounds__(256) apply_kernel(const float *__restrict__ out, double scale, double *__restrict__ J,
+                                                    int64_t n)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    double d = scale * (double)out[v];
+    d = d < -0.5 ? -0.5 : (d > 1.0 ? 1.0 : d);
+    J[v] *= 1.0 + d;
+}
+
+hipError_t unet_apply(const float *out, double scale, double *J, int64_t n, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(apply_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, out, scale, J, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+std::string parse_unet(const void *blob, size_t bytes, UNetSpec &out)
+{
+    out = UNetSpec();
+    const unsigned char *p = static_cast<const unsigned char *>(blob);
+    size_t off = 0;
+    auto u32 = [&](uint32_t &v) {
+        if (off + 4 > bytes) return false;
+        std::memcpy(&v, p + off, 4);
+        off += 4;
+        return true;
+    };
+    if (bytes < 12 || std::memcmp(p, "RTUN", 4) != 0) return "not a network blob (magic)";
+    off = 4;
+    uint32_t ver = 0, L = 0;
+    if (!u32(ver) || ver != 1) return "unsupported network blob version";
+    if (!u32(L) || L < 1 || L > 6) return "number of levels must be 1..6";
+    out.L = (int)L;
+    for (uint32_t l = 0; l < L; ++l) {
+        uint32_t c = 0;
+        if (!u32(c) || (c != 16 && c != 32 && c != 64)) return "channel counts must be 16, 32 or 64";
+        out.C.push_back((int)c);
+    }
+    auto conv = [&](int ci, int co, int taps) {
+        UNetSpec::Conv cv;
+        cv.ci = ci; cv.co = co; cv.taps = taps;
+        const size_t nw = (size_t)taps * co * ci;
+        if (off + 4 * (nw + co) > bytes) return false;
+        cv.w.resize(nw);
+        cv.b.resize(co);
+        std::memcpy(cv.w.data(), p + off, 4 * nw);
+        off += 4 * nw;
+        std::memcpy(cv.b.data(), p + off, 4 * (size_t)co);
+        off += 4 * (size_t)co;
+        out.convs.push_back(std::move(cv));
+        return true;
+    };
+    const auto &C = out.C;
+    if (!conv(3, C[0], 27) || !conv(C[0], C[0], 27)) return "truncated blob";
+    for (int l = 1; l < out.L; ++l)
+        if (!conv(C[l - 1], C[l], 27) || !conv(C[l], C[l], 27)) return "truncated blob";
+    for (int l = out.L - 1; l >= 1; --l)
+        if (!conv(C[l], C[l - 1], 27) || !conv(C[l - 1], C[l - 1], 27)) return "truncated blob";
+    if (!conv(C[0], 1, 1)) return "truncated blob";
+    if (off != bytes) return "trailing bytes after the last layer";
+    for (const auto &cv : out.convs)
+        for (float x : cv.w)
+            if (!std::isfinite(x)) return "non-finite weight";
+    return "";
+}
+
+struct DevMem {
+    void *p = nullptr;
+    ~DevMem() { if (p) (void)hipFree(p); }
+};
+
+struct UNetDev {
+    UNetSpec spec;
+    std::vector<Vol> lv;                       // volume of each level
+    std::vector<std::unique_ptr<DevMem>> mem;  // every allocation
+    std::vector<const void *> w, b;            // per conv: weights (bf16 or fp32), biases (fp32)
+    std::vector<uint16_t *> h, t;              // per level activations
+    uint16_t *up = nullptr;                    // upsampled map (largest)
+};
+
+static hipError_t dev_alloc(UNetDev *u, size_t bytes, void **out)
+{
+    auto m = std::make_unique<DevMem>();
+    hipError_t e = hipMalloc(&m->p, bytes > 0 ? bytes : 16);
+    if (e != hipSuccess) return e;
+    *out = m->p;
+    u->mem.push_back(std::move(m));
+    return hipSuccess;
+}
+
+UNetDev *unet_create(const UNetSpec &spec, int nx, int ny, int nz, std::string &err)
+{
+    auto u = std::make_unique<UNetDev>();
+    u->spec = spec;
+    Vol v{nx, ny, nz};
+    for (int l = 0; l < spec.L; ++l) {
+        if (l > 0) v = Vol{(v.nx + 1) / 2, (v.ny + 1) / 2, (v.nz + 1) / 2};
+        u->lv.push_back(v);
+    }
+    hipError_t e = hipSuccess;
+    for (size_t k = 0; k < spec.convs.size() && e == hipSuccess; ++k) {
+        const auto &cv = spec.convs[k];
+        const bool mfma = cv.taps == 27 && cv.ci >= 16;
+        void *wp = nullptr, *bp = nullptr;
+        if (mfma) {
+            std::vector<uint16_t> wb(cv.w.size());
+            for (size_t i = 0; i < wb.size(); ++i) wb[i] = f2bf_host(cv.w[i]);
+            if ((e = dev_alloc(u.get(), wb.size() * 2, &wp)) == hipSuccess)
+                e = hipMemcpy(wp, wb.data(), wb.size() * 2, hipMemcpyHostToDevice);
+        } else {
+            if ((e = dev_alloc(u.get(), cv.w.size() * 4, &wp)) == hipSuccess)
+                e = hipMemcpy(wp, cv.w.data(), cv.w.size() * 4, hipMemcpyHostToDevice);
+        }
+        if (e == hipSuccess && (e = dev_alloc(u.get(), cv.b.size() * 4, &bp)) == hipSuccess)
+            e = hipMemcpy(bp, cv.b.data(), cv.b.size() * 4, hipMemcpyHostToDevice);
+        u->w.push_back(wp);
+        u->b.push_back(bp);
+    }
+    size_t up_bytes = 0;
+    for (int l = 0; l < spec.L && e == hipSuccess; ++l) {
+        void *hp = nullptr, *tp = nullptr;
+        const size_t bytes = (size_t)u->lv[l].n() * spec.C[l] * 2;
+        if ((e = dev_alloc(u.get(), bytes, &hp)) == hipSuccess) e = dev_alloc(u.get(), bytes, &tp);
+        u->h.push_back((uint16_t *)hp);
+        u->t.push_back((uint16_t *)tp);
+        if (l > 0) up_bytes = std::max(up_bytes, (size_t)u->lv[l - 1].n() * spec.C[l] * 2);
+    }
+    if (e == hipSuccess && spec.L > 1) {
+        void *p = nullptr;
+        e = dev_alloc(u.get(), up_bytes, &p);
+        u->up = (uint16_t *)p;
+    }
+    if (e != hipSuccess) {
+        err = std::string("network buffers: ") + hipGetErrorString(e);
+        return nullptr;
+    }
+    return u.release();
+}
+
+void unet_destroy(UNetDev *u) { delete u; }
+
+template <int C>
+static hipError_t conv_in_t(const float *f, Vol v, const float *w, const float *b, uint16_t *out, hipStream_t st)
+{
+    hipLaunchKernelGGL((conv_in_kernel<C>), dim3((unsigned)((v.n() + 255) / 256)), dim3(256), 0, st, f, v, w, b, out);
+    return hipGetLastError();
+}
+
+template <int C>
+static hipError_t head_t(const uint16_t *h, int64_t n, const float *w, const float *b, float *out, hipStream_t st)
+{
+    hipLaunchKernelGGL((head_kernel<C>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, h, n, w, b, out);
+    return hipGetLastError();
+}
+
+hipError_t unet_forward(UNetDev *u, const float *features, float *out, hipStream_t st)
+{
+    const UNetSpec &s = u->spec;
+    const auto &C = s.C;
+    size_t k = 0;  // conv index in blob order
+    hipError_t e;
+    auto conv = [&](const uint16_t *in, Vol vi, Vol vo, int stride, int ci, int co, const uint16_t *skip,
+                    uint16_t *o) {
+        ConvArgs a{in, vi, vo, stride, (const uint16_t *)u->w[k], (const float *)u->b[k], skip, o};
+        ++k;
+        return conv_mfma(a, ci, co, st);
+    };
+    // level 0 input layer
+    const Vol v0 = u->lv[0];
+    switch (C[0]) {
+    case 16: e = conv_in_t<16>(features, v0, (const float *)u->w[0], (const float *)u->b[0], u->t[0], st); break;
+    case 32: e = conv_in_t<32>(features, v0, (const float *)u->w[0], (const float *)u->b[0], u->t[0], st); break;
+    default: e = conv_in_t<64>(features, v0, (const float *)u->w[0], (const float *)u->b[0], u->t[0], st); break;
+    }
+    if (e != hipSuccess) return e;
+    k = 1;
+    if ((e = conv(u->t[0], v0, v0, 1, C[0], C[0], nullptr, u->h[0])) != hipSuccess) return e;
+    for (int l = 1; l < s.L; ++l) {
+        if ((e = conv(u->h[l - 1], u->lv[l - 1], u->lv[l], 2, C[l - 1], C[l], nullptr, u->t[l])) != hipSuccess)
+            return e;
+        if ((e = conv(u->t[l], u->lv[l], u->lv[l], 1, C[l], C[l], nullptr, u->h[l])) != hipSuccess) return e;
+    }
+    for (int l = s.L - 1; l >= 1; --l) {
+        const Vol vc = u->lv[l], vf = u->lv[l - 1];
+        const int64_t nup = vf.n() * C[l];
+        hipLaunchKernelGGL(upsample_kernel, dim3((unsigned)((nup + 255) / 256)), dim3(256), 0, st, u->h[l], vc, u->up,
+                           vf, C[l]);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = conv(u->up, vf, vf, 1, C[l], C[l - 1], u->h[l - 1], u->t[l - 1])) != hipSuccess) return e;
+        if ((e = conv(u->t[l - 1], vf, vf, 1, C[l - 1], C[l - 1], nullptr, u->h[l - 1])) != hipSuccess) return e;
+    }
+    const float *hw = (const float *)u->w[k], *hb = (const float *)u->b[k];
+    switch (C[0]) {
+    case 16: return head_t<16>(u->h[0], v0.n(), hw, hb, out, st);
+    case 32: return head_t<32>(u->h[0], v0.n(), hw, hb, out, st);
+    default: return head_t<64>(u->h[0], v0.n(), hw, hb, out, st);
+    }
+}
+
+}  // namespace rt3d

@@ -38,13 +38,13 @@ class RtState(ctypes.Structure):
 class RtSolveOpts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("ng_every", ctypes.c_int32), ("ng_start", ctypes.c_int32), ("reanchor", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("net_every", ctypes.c_int32)]
 
 
 class RtSolveReport(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("n_fs", ctypes.c_int32), ("n_fs64", ctypes.c_int32),
                 ("n_ng", ctypes.c_int32), ("n_converged", ctypes.c_int32), ("max_rel_change", ctypes.c_double),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("n_net_accept", ctypes.c_int32), ("n_net_reject", ctypes.c_int32)]
 
 
 class RtError(RuntimeError):
@@ -93,6 +93,10 @@ def lib() -> ctypes.CDLL:
     L.rt_sphere_tracks.argtypes = [ctypes.POINTER(RtGridDesc), i32, dp, ctypes.POINTER(ctypes.c_int64),
                                    ctypes.POINTER(ctypes.c_int64), dp, ctypes.POINTER(ctypes.c_int64), ip, dp]
     L.rt_sphere_tracks.restype = ctypes.c_int
+    L.rt_set_preconditioner.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
+    L.rt_set_preconditioner.restype = ctypes.c_int
+    L.rt_precond_forward.argtypes = [vp, vp, vp, vp]
+    L.rt_precond_forward.restype = ctypes.c_int
     L.rt_last_error.restype = ctypes.c_char_p
     L.rt_last_error.argtypes = []
     L.rt_version.restype = ctypes.c_char_p
@@ -191,6 +195,17 @@ def rt_box_template(Nz: int, n_mu: int, n_phi: int, d: int):
     _check(lib().rt_box_template(Nz, n_mu, n_phi, d, n, di.ctypes.data_as(ip), dj.ctypes.data_as(ip),
                                  kk.ctypes.data_as(ip), s.ctypes.data_as(dp), ctypes.byref(M)), "rt_box_template")
     return dict(di=di, dj=dj, kk=kk, s=s)
+
+
+def rt_set_preconditioner(grid: int, blob: Optional[bytes]) -> None:
+    """Sets (bytes) or removes (None) the learned-correction network of a box grid."""
+    _check(lib().rt_set_preconditioner(ctypes.c_void_p(grid), blob, len(blob) if blob else 0),
+           "rt_set_preconditioner")
+
+
+def rt_precond_forward(grid: int, features: int, out: int, stream: Optional[int]) -> None:
+    _check(lib().rt_precond_forward(ctypes.c_void_p(grid), ctypes.c_void_p(features), ctypes.c_void_p(out),
+                                    ctypes.c_void_p(stream or None)), "rt_precond_forward")
 
 
 def sphere_desc(Nr: int, Nt: int, Np: int, r_core: float, r_out: float, n_mu: int, n_phi: int, prec: str = "f32",
@@ -330,12 +345,27 @@ class Grid:
         return st
 
     @staticmethod
-    def opts(tol=1e-8, max_iter=1000, ng_every=4, ng_start=4, reanchor=0, use_graph=False):
+    def opts(tol=1e-8, max_iter=1000, ng_every=4, ng_start=4, reanchor=0, use_graph=False, net_every=0):
         o = RtSolveOpts()
         o.struct_size = ctypes.sizeof(RtSolveOpts)
         o.tol, o.max_iter, o.ng_every, o.ng_start, o.reanchor = tol, max_iter, ng_every, ng_start, reanchor
         o.use_graph = int(bool(use_graph))
+        o.net_every = int(net_every)
         return o
+
+    def set_preconditioner(self, blob):
+        """blob: the network weights (bytes, see include/rt3d.h) or None."""
+        rt_set_preconditioner(self.handle, blob)
+
+    def precond_forward(self, features, out=None, stream=None):
+        """Network output for a feature volume (Nz, Ny, Nx, 3) float32 on the GPU."""
+        import torch
+        if features.dtype != torch.float32 or not features.is_contiguous() or \
+                tuple(features.shape) != (*self.shape, 3):
+            raise ValueError(f"features must be contiguous float32 of shape {(*self.shape, 3)}")
+        out = out if out is not None else torch.empty(self.shape, dtype=torch.float32, device=features.device)
+        rt_precond_forward(self.handle, features.data_ptr(), out.data_ptr(), _stream_ptr(stream))
+        return out
 
     def ali_step(self, state: RtState, opts: RtSolveOpts, stream=None):
         rt_ali_step(self.handle, state, opts, _stream_ptr(stream))
