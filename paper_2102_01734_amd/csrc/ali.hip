@@ -28,15 +28,16 @@ namespace rt3d {
 // point's opacity and source are one 8- (16-) byte load:
 //   dst[((l*Nz + k)*2Ny + y2)*2Nx + x2][comp] = src[l][k][y2 mod Ny][x2 mod Nx],
 // comp 0 = chi, comp 1 = S (optionally minus an anchor), in the kernel type.
-// Ny == 0 selects the unpadded layout of the spherical grid, pairs
-// [lambda][voxel][2] (no periodic directions).
+// Ny == 0 selects the voxel-major layout of the spherical grid, pairs
+// [voxel][Nx][2] with Nx the wavelength stride (no periodic directions), so
+// the wavelengths of one voxel are contiguous.
 // ---------------------------------------------------------------------------
 template <typename TD>
 __device__ __forceinline__ void store_padded(TD *dst, int64_t l, int64_t n_vox, int64_t v, int Nx, int Ny, int comp,
                                              TD val)
 {
     if (Ny == 0) {
-        dst[2 * (l * n_vox + v) + comp] = val;
+        dst[2 * (v * Nx + l) + comp] = val;
         return;
     }
     const int x = (int)(v % Nx);
@@ -68,7 +69,7 @@ template <typename TS, typename TD>
 hipError_t pad_field(const TS *src, const double *anchor, TD *dst, int Nx, int Ny, int Nz, int n_lambda, int comp,
                      hipStream_t st)
 {
-    const int64_t per = (int64_t)Nx * (Ny > 0 ? Ny : 1) * Nz;
+    const int64_t per = Ny > 0 ? (int64_t)Nx * Ny * Nz : (int64_t)Nz;
     const int64_t total = per * n_lambda;
     if (total == 0) return hipSuccess;
     const int bs = 256;

@@ -8,8 +8,9 @@
 namespace rt3d {
 
 // Writes component comp (0 = chi, 1 = S) of the interleaved doubly periodic
-// padded formal-solution input (see ali.hip).  Ny == 0 selects the unpadded
-// pair layout [lambda][voxel][2] of the spherical grid (n_vox = Nx * Nz).
+// padded formal-solution input (see ali.hip).  Ny == 0 selects the
+// voxel-major pair layout [voxel][Nx][2] of the spherical grid, Nx the
+// wavelength stride and Nz the number of voxels.
 template <typename TS, typename TD>
 hipError_t pad_field(const TS *src, const double *anchor, TD *dst, int Nx, int Ny, int Nz, int n_lambda, int comp,
                      hipStream_t st);

@@ -7,29 +7,33 @@
 
 namespace rt3d {
 
+// One chunk of the spherical geometry cache in bundle-major form: the
+// chunk's characteristics, longest first, in bundles of 64; entry
+// e = bundle_begin[b] + m * 64 + c holds visit m of characteristic c of
+// bundle b (padding past a characteristic's length is never read).
 struct FsSphereArgs {
-    int64_t n_vox;
-    // characteristics [char0, char0 + n_chars) of one chunk; visit offsets are global
-    int64_t char0, n_chars;
-    int64_t visit0;              // first visit of the chunk
-    const int64_t *char_begin;   // visit range of characteristic c: [char_begin[c], char_begin[c+1])
-    const double *char_g;        // boundary factor: >= 0 outer entry (irradiation factor), < 0 core start
-    const int32_t *vox;          // per visit: voxel
-    const void *s, *w;           // per visit: path length, averaging weight (geometry type)
-    const int32_t *lambda_of;    // batch entry -> wavelength
-    const void *field;           // (chi, S) pairs [lambda][voxel][2], kernel type
-    const void *I_bc;            // [lambda][3]: I_out, I_core, J_sub (kernel type), or null (all zero)
-    void *outJ, *outL;           // per batch entry and chunk visit: w I, w Lambda*_point (kernel type)
-    int64_t out_stride;          // elements per batch entry in outJ / outL
+    int64_t n_bundles;
+    const int64_t *bundle_begin;  // [n_bundles]
+    const int32_t *char_len;      // [n_bundles * 64]: visits (0 for padding lanes)
+    const double *char_g;         // [n_bundles * 64]: >= 0 outer entry (irradiation factor), < 0 core start
+    const int32_t *vox;           // per entry: voxel
+    const void *s, *w;            // per entry: path length, averaging weight (geometry type)
+    const int32_t *lambda_of;     // batch entry -> wavelength
+    int n_batch;                  // batch entries (stride of the outputs)
+    int lam_stride;               // wavelengths per voxel in the field
+    int L;                        // lanes (batch entries) per characteristic: 1, 2, 4, 8 or 16
+    const void *field;            // (chi, S) pairs [voxel][lam_stride][2], kernel type
+    const void *I_bc;             // [lambda][3]: I_out, I_core, J_sub (kernel type), or null (all zero)
+    void *outJ, *outL;            // [entry][n_batch]: w I, w Lambda*-term (kernel type)
 };
 
 // T: arithmetic and field type; geometry in float (gdouble = false) or double.
 hipError_t fs_sphere_launch(const FsSphereArgs &a, bool is_double, bool gdouble, bool want_j, bool want_l,
-                            bool parabolic_lstar, int n_batch, hipStream_t st);
+                            bool parabolic_lstar, hipStream_t st);
 
-// dst[b][v] (=, or += when accumulate) sum over the chunk's visits k of voxel v,
-// in CSR order, of src[b][k] (double accumulation).
-hipError_t sphere_gather(const void *src, bool src_double, int64_t src_stride, const int32_t *row, const int32_t *idx,
-                         int64_t n_vox, int n_batch, void *dst, bool dst_double, bool accumulate, hipStream_t st);
+// dst[b][v] (=, or += when accumulate) sum over the chunk's entries k of voxel
+// v, in CSR order, of src[k][b] (double accumulation).
+hipError_t sphere_gather(const void *src, bool src_double, const int32_t *row, const int32_t *idx, int64_t n_vox,
+                         int n_batch, void *dst, bool dst_double, bool accumulate, hipStream_t st);
 
 }  // namespace rt3d

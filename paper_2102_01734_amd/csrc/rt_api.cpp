@@ -91,15 +91,17 @@ struct DevSchedule {
     DevBuf wg_begin, items, slot_begin, slot_ids, lambda_of;
 };
 
-// Device copy of one chunk of the spherical geometry cache (chunk-local indices).
+// Device copy of one chunk of the spherical geometry cache, bundle-major
+// (chunk-local indices; see fs_sphere.hpp).
 struct SphereChunkDev {
     SphereChunk info;
-    int64_t n_chars = 0, n_visits = 0;
-    DevBuf char_begin;  // int64 [n_chars + 1]
-    DevBuf char_g;      // double [n_chars]
-    DevBuf vox;         // int32 [n_visits]
-    DevBuf s, w;        // geometry type [n_visits]
-    DevBuf row, idx;    // CSR voxel -> chunk visits: int32 [n_vox + 1], int32 [n_visits]
+    int64_t n_chars = 0, n_visits = 0, n_bundles = 0, n_entries = 0;
+    DevBuf bundle_begin;  // int64 [n_bundles]
+    DevBuf char_len;      // int32 [n_bundles * 64]
+    DevBuf char_g;        // double [n_bundles * 64]
+    DevBuf vox;           // int32 [n_entries]
+    DevBuf s, w;          // geometry type [n_entries]
+    DevBuf row, idx;      // CSR voxel -> entries: int32 [n_vox + 1], int32 [n_visits]
 };
 
 struct rt_grid {
@@ -261,10 +263,13 @@ static rt_status run_fs_sphere(rt_grid *g, const Variant &v, const std::vector<i
     if (rs != RT_OK) return rs;
     const int nb = (int)lambdas.size();
     const size_t esz = dbl ? 8 : 4;
-    const int64_t stride = g->sph.max_chunk_visits;
     if (wj) HIPCHK(partJ.ensure((size_t)nb * g->n_vox * esz));
     if (wl) HIPCHK(partL.ensure((size_t)nb * g->n_vox * esz));
-    if ((size_t)nb * stride * esz > g->sph_outJ.bytes) return fail(RT_E_INVALID, "batch larger than n_lambda_max");
+    if ((size_t)nb * g->sph.max_chunk_visits * esz > g->sph_outJ.bytes)
+        return fail(RT_E_INVALID, "batch larger than n_lambda_max");
+    // lanes per characteristic: the batch entries, up to 16
+    int L = 1;
+    while (L < nb && L < 16) L *= 2;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (g->prof) {
         HIPCHK(hipEventCreate(&e0));
@@ -274,28 +279,28 @@ static rt_status run_fs_sphere(rt_grid *g, const Variant &v, const std::vector<i
     for (size_t c = 0; c < g->sph_chunks.size(); ++c) {
         const SphereChunkDev &ch = *g->sph_chunks[c];
         FsSphereArgs a{};
-        a.n_vox = g->n_vox;
-        a.char0 = 0;
-        a.n_chars = ch.n_chars;
-        a.visit0 = 0;
-        a.char_begin = ch.char_begin.as<int64_t>();
+        a.n_bundles = ch.n_bundles;
+        a.bundle_begin = ch.bundle_begin.as<int64_t>();
+        a.char_len = ch.char_len.as<int32_t>();
         a.char_g = ch.char_g.as<double>();
         a.vox = ch.vox.as<int32_t>();
         a.s = ch.s.p;
         a.w = ch.w.p;
         a.lambda_of = sc->lambda_of.as<int32_t>();
+        a.n_batch = nb;
+        a.lam_stride = g->lx;
+        a.L = L;
         a.field = fld;
         a.I_bc = I_bc;
         a.outJ = wj ? g->sph_outJ.p : nullptr;
         a.outL = wl ? g->sph_outL.p : nullptr;
-        a.out_stride = stride;
-        HIPCHK(fs_sphere_launch(a, dbl, g->sph_gdouble, wj, wl, g->para, nb, st));
+        HIPCHK(fs_sphere_launch(a, dbl, g->sph_gdouble, wj, wl, g->para, st));
         if (wj)
-            HIPCHK(sphere_gather(g->sph_outJ.p, dbl, stride, ch.row.as<int32_t>(), ch.idx.as<int32_t>(), g->n_vox, nb,
-                                 partJ.p, dbl, c > 0, st));
+            HIPCHK(sphere_gather(g->sph_outJ.p, dbl, ch.row.as<int32_t>(), ch.idx.as<int32_t>(), g->n_vox, nb, partJ.p,
+                                 dbl, c > 0, st));
         if (wl)
-            HIPCHK(sphere_gather(g->sph_outL.p, dbl, stride, ch.row.as<int32_t>(), ch.idx.as<int32_t>(), g->n_vox, nb,
-                                 partL.p, dbl, c > 0, st));
+            HIPCHK(sphere_gather(g->sph_outL.p, dbl, ch.row.as<int32_t>(), ch.idx.as<int32_t>(), g->n_vox, nb, partL.p,
+                                 dbl, c > 0, st));
     }
     if (g->prof) {
         HIPCHK(hipEventRecord(e1, st));
@@ -419,34 +424,69 @@ void prepare_sphere_direction(const SphereSpec &spec, double h, const std::vecto
 template <typename TG>
 hipError_t upload_chunk(SphereChunkDev &ch, const std::vector<SphereDirCache> &dirs, int64_t n_vox)
 {
-    int64_t nc = 0, nv = 0;
-    for (const auto &d : dirs) { nc += (int64_t)d.len.size(); nv += (int64_t)d.vox.size(); }
+    // every characteristic of the chunk, longest first (ties in direction and trace order)
+    struct Ref { int d; int64_t c, off, len; };
+    std::vector<Ref> refs;
+    int64_t nv = 0;
+    for (int d = 0; d < (int)dirs.size(); ++d) {
+        int64_t off = 0;
+        for (size_t c = 0; c < dirs[d].len.size(); ++c) {
+            refs.push_back(Ref{d, (int64_t)c, off, dirs[d].len[c]});
+            off += dirs[d].len[c];
+        }
+        nv += off;
+    }
+    std::stable_sort(refs.begin(), refs.end(), [](const Ref &a, const Ref &b) { return a.len > b.len; });
+    const int64_t nc = (int64_t)refs.size();
+    const int64_t nbun = (nc + 63) / 64;
+    std::vector<int64_t> bb((size_t)nbun);
+    std::vector<int32_t> clen((size_t)nbun * 64, 0);
+    std::vector<double> cg((size_t)nbun * 64, 0.0);
+    int64_t ne = 0;
+    for (int64_t b = 0; b < nbun; ++b) {
+        bb[(size_t)b] = ne;
+        ne += 64 * refs[(size_t)(b * 64)].len;  // the bundle's first characteristic is its longest
+    }
+    std::vector<int32_t> vx((size_t)ne, 0);
+    std::vector<TG> sv((size_t)ne, TG(0)), wv((size_t)ne, TG(0));
+    for (int64_t k = 0; k < nc; ++k) {
+        const Ref &r = refs[(size_t)k];
+        const int64_t b = k / 64, c = k % 64;
+        clen[(size_t)k] = (int32_t)r.len;
+        cg[(size_t)k] = dirs[r.d].g[(size_t)r.c];
+        for (int64_t m = 0; m < r.len; ++m) {
+            const size_t e = (size_t)(bb[(size_t)b] + 64 * m + c);
+            const size_t src = (size_t)(r.off + m);
+            vx[e] = dirs[r.d].vox[src];
+            sv[e] = (TG)dirs[r.d].s[src];
+            wv[e] = (TG)dirs[r.d].w[src];
+        }
+    }
     ch.n_chars = nc;
     ch.n_visits = nv;
-    std::vector<int64_t> cb;
-    std::vector<double> cg;
-    std::vector<int32_t> vx;
-    std::vector<TG> sv, wv;
-    cb.reserve(nc + 1); cg.reserve(nc); vx.reserve(nv); sv.reserve(nv); wv.reserve(nv);
-    cb.push_back(0);
-    for (const auto &d : dirs) {
-        for (size_t c = 0; c < d.len.size(); ++c) { cb.push_back(cb.back() + d.len[c]); cg.push_back(d.g[c]); }
-        vx.insert(vx.end(), d.vox.begin(), d.vox.end());
-        for (size_t k = 0; k < d.s.size(); ++k) { sv.push_back((TG)d.s[k]); wv.push_back((TG)d.w[k]); }
-    }
-    // CSR voxel -> visits, visits of a voxel in chunk order
+    ch.n_bundles = nbun;
+    ch.n_entries = ne;
+    // CSR voxel -> entries, in entry order
     std::vector<int32_t> row((size_t)n_vox + 1, 0), idx((size_t)nv);
-    for (int32_t v : vx) row[(size_t)v + 1]++;
+    for (int64_t k = 0; k < nc; ++k) {
+        const Ref &r = refs[(size_t)k];
+        for (int64_t m = 0; m < r.len; ++m) row[(size_t)dirs[r.d].vox[(size_t)(r.off + m)] + 1]++;
+    }
     for (int64_t v = 0; v < n_vox; ++v) row[(size_t)v + 1] += row[(size_t)v];
     std::vector<int32_t> fill(row.begin(), row.end() - 1);
-    for (int64_t k = 0; k < nv; ++k) idx[(size_t)fill[(size_t)vx[(size_t)k]]++] = (int32_t)k;
-    auto up = [](DevBuf &b, const void *src, size_t n) -> hipError_t {
-        hipError_t e = b.ensure(n > 0 ? n : 16);
+    for (int64_t b = 0; b < nbun; ++b)
+        for (int64_t e = bb[(size_t)b]; e < (b + 1 < nbun ? bb[(size_t)b + 1] : ne); ++e) {
+            const int64_t m = (e - bb[(size_t)b]) / 64, c = (e - bb[(size_t)b]) % 64;
+            if (m < clen[(size_t)(b * 64 + c)]) idx[(size_t)fill[(size_t)vx[(size_t)e]]++] = (int32_t)e;
+        }
+    auto up = [](DevBuf &d, const void *src, size_t n) -> hipError_t {
+        hipError_t e = d.ensure(n > 0 ? n : 16);
         if (e != hipSuccess || n == 0) return e;
-        return hipMemcpy(b.p, src, n, hipMemcpyHostToDevice);
+        return hipMemcpy(d.p, src, n, hipMemcpyHostToDevice);
     };
     hipError_t e;
-    if ((e = up(ch.char_begin, cb.data(), cb.size() * 8)) != hipSuccess) return e;
+    if ((e = up(ch.bundle_begin, bb.data(), bb.size() * 8)) != hipSuccess) return e;
+    if ((e = up(ch.char_len, clen.data(), clen.size() * 4)) != hipSuccess) return e;
     if ((e = up(ch.char_g, cg.data(), cg.size() * 8)) != hipSuccess) return e;
     if ((e = up(ch.vox, vx.data(), vx.size() * 4)) != hipSuccess) return e;
     if ((e = up(ch.s, sv.data(), sv.size() * sizeof(TG))) != hipSuccess) return e;
@@ -458,18 +498,19 @@ hipError_t upload_chunk(SphereChunkDev &ch, const std::vector<SphereDirCache> &d
 }  // namespace
 
 // Visits per chunk: the per-visit outputs of a chunk take n_lambda_max x
-// visits x 16 bytes (double J and Lambda* for the anchors of single-precision
-// grids); chunks are sized so that this stays near 2 GiB.  The environment
-// variable RT3D_SPHERE_CHUNK_VISITS overrides the size (smaller chunks: less
-// memory, more launches).
+// entries x 16 bytes (double J and Lambda* for the anchors of single-precision
+// grids); chunks are sized so that this stays near 8 GiB (of the 288 GB of an
+// MI355X; fewer chunks mean fewer gather passes over the voxels).  The
+// environment variable RT3D_SPHERE_CHUNK_VISITS overrides the size (smaller
+// chunks: less memory, more launches).
 static int64_t sphere_chunk_cap(int n_lambda_max)
 {
-    int64_t cap = ((int64_t)2 << 30) / (16 * (int64_t)n_lambda_max);
+    int64_t cap = ((int64_t)8 << 30) / (16 * (int64_t)n_lambda_max);
     if (const char *e = std::getenv("RT3D_SPHERE_CHUNK_VISITS")) {
         const long long v = std::atoll(e);
         if (v > 0) cap = v;
     }
-    return std::min<int64_t>(cap, ((int64_t)1 << 31) - 1);
+    return std::min<int64_t>(cap, ((int64_t)1 << 30));  // entries (with bundle padding) stay below 2^31
 }
 
 static rt_status build_sphere_grid(rt_grid *g, const rt_grid_desc *desc)
@@ -505,7 +546,7 @@ static rt_status build_sphere_grid(rt_grid *g, const rt_grid_desc *desc)
             for (int64_t l : d.len) ch->info.max_len = std::max<int64_t>(ch->info.max_len, l);
         sc.n_chars += ch->n_chars;
         sc.n_visits += ch->n_visits;
-        sc.max_chunk_visits = std::max(sc.max_chunk_visits, ch->n_visits);
+        sc.max_chunk_visits = std::max(sc.max_chunk_visits, ch->n_entries);
         g->sph_chunks.push_back(std::move(ch));
         pending.clear();
         pend_visits = 0;
@@ -632,7 +673,7 @@ rt_status rt_create_grid(const rt_grid_desc *desc, rt_grid_t *out)
         g->sph_gdouble = g->dbl;
         g->para = (desc->flags & RT_F_LSTAR_PARABOLIC) != 0;
         g->n_vox = nv;
-        g->lx = (int)nv; g->ly = 0; g->lz = 1;
+        g->lx = desc->n_lambda_max; g->ly = 0; g->lz = (int)nv;  // voxel-major pairs [v][n_lambda_max]
         g->nbc = 3;
         HIPCHK(hipGetDevice(&g->device));
         rt_status rs = build_sphere_grid(g.get(), desc);
@@ -859,7 +900,7 @@ rt_status rt_formal_solution(rt_grid_t g, int32_t n_lambda, const void *chi, con
     hipStream_t st = (hipStream_t)stream;
     const bool dbl = g->dbl;
     const size_t esz = dbl ? 8 : 4;
-    const size_t padn = (size_t)n_lambda * 4 * g->n_vox;
+    const size_t padn = g->sphere ? (size_t)g->desc.n_lambda_max * g->n_vox : (size_t)n_lambda * 4 * g->n_vox;
     const int Nx = g->lx, Ny = g->ly, Nz = g->lz;
     HIPCHK(g->fs_fld.ensure(2 * padn * esz));
     if (dbl) {
