@@ -86,6 +86,41 @@ def cpu_baseline(case, n_sub: int):
                       f"{case.n_vox} voxels ({wall:.1f} s wall)"}
 
 
+def one_gpu_share(case, shape, n_gpus: int = 8, reps: int = 3):
+    """One GPU's part of an n_gpus solid-angle decomposition: the single-precision
+    formal solution over shard 0 of the visit-balanced direction shards (no
+    all-reduce, which this one-GPU run cannot show)."""
+    import torch
+
+    import paper_2102_01734_amd as rt
+    import synthetic as sy
+    dev = dict(dtype=torch.float32, device="cuda")
+    g = rt.Grid(case.Nx, case.Ny, case.Nz, case.n_mu, case.n_phi, "f32", 1)
+    if shape:
+        g.set_launch_shape(*shape)
+    chi = torch.tensor(case.chi, **dev)
+    S = torch.tensor(sy.random_source(case.chi.shape, seed=7, lo=0.2, hi=1.0, dtype="f32"), **dev)
+    Ib = torch.tensor(case.I_bc, **dev)
+    M = [rt.rt_box_template(case.Nz, case.n_mu, case.n_phi, d)["s"].size for d in range(case.n_dir)]
+    shards = [g.shard_directions(n_gpus, k) for k in range(n_gpus)]
+    loads = [sum(M[d] for d in s) for s in shards]
+    dirs = shards[0]
+    g.formal_solution_dirs(chi, S, dirs, I_bc=Ib)
+    torch.cuda.synchronize()
+    rt.rt_profile_read(g.handle)
+    rt.rt_profile_enable(g.handle, True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.formal_solution_dirs(chi, S, dirs, I_bc=Ib)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    fs_ms, n, _ = rt.rt_profile_read(g.handle)
+    g.close()
+    return {"gpus": n_gpus, "directions": int(len(dirs)), "visit_imbalance": max(loads) / (sum(loads) / n_gpus),
+            "ms_per_fs": wall * 1e3, "kernel_ms": fs_ms / max(n, 1),
+            "vdu_per_s": case.n_vox * len(dirs) / wall}
+
+
 def time_to_solution(case, net_every: int = 12, tol: float = 1e-6):
     """Wall seconds of rt_solve to the stopping tolerance `tol` (which lands below
     1e-5 relative error on this workload) for plain double-precision Ng-ALI,
@@ -316,6 +351,8 @@ def main():
     g.close()
     del st
     torch.cuda.synchronize()
+    if case.n_lambda == 1:
+        out["one_gpu_share"] = one_gpu_share(case, shape)
     if not args.no_solve and case.n_lambda == 1:
         out["time_to_solution"] = time_to_solution(case)
     if not args.no_cpu_baseline and case.n_lambda == 1:

@@ -137,6 +137,31 @@ rt_status rt_grid_info(rt_grid_t grid, int64_t *n_vox, int32_t *n_dir,
 rt_status rt_formal_solution(rt_grid_t grid, int32_t n_lambda, const void *chi, const void *S,
                              const void *I_bc, void *J_out, void *lstar_out, void *stream);
 
+/*
+ * The formal solution over a subset of the directions (box grids): J and
+ * Lambda* summed over the listed directions only, i.e. the partial sums one
+ * of several GPUs holding those directions would contribute before the
+ * all-reduce of J over solid angles (Sec. 4).  Summing the results over
+ * disjoint subsets that cover all directions gives rt_formal_solution's
+ * output up to the summation order.
+ *   dirs  host, n_dirs >= 1 direction indices (i_mu * n_phi + j_phi),
+ *         strictly increasing
+ * Other arguments and errors as rt_formal_solution; RT_E_UNSUPPORTED on
+ * spherical grids.
+ */
+rt_status rt_formal_solution_dirs(rt_grid_t grid, int32_t n_lambda, const void *chi, const void *S,
+                                  const void *I_bc, int32_t n_dirs, const int32_t *dirs, void *J_out,
+                                  void *lstar_out, void *stream);
+
+/*
+ * Host-side planning of a solid-angle decomposition: directions are dealt,
+ * longest characteristic first, to the shard with the fewest visits so far,
+ * so shards carry nearly equal work (shallow directions cost up to ~7x the
+ * mean).  Writes shard `shard` of `n_shards` (sorted) to dirs_out (host, may
+ * be NULL for a size query) and its size to *n_out.  No device work.
+ */
+rt_status rt_shard_directions(rt_grid_t grid, int32_t n_shards, int32_t shard, int32_t *dirs_out, int32_t *n_out);
+
 /* State of the ALI iteration for a batch of wavelengths. */
 typedef struct {
     uint32_t struct_size; /* sizeof(rt_state)                                   */

@@ -7,7 +7,7 @@ the library and fails if it has not been built.
 """
 from .rt3d import (Grid, RtError, RtGridDesc, RtSolveOpts, RtSolveReport, RtState, lib, rt_ali_step, rt_autotune,  # noqa: F401
                    rt_set_launch_shape, rt_sphere_tracks, sphere_desc, SphereGrid, rt_set_preconditioner,
-                   rt_precond_forward,
+                   rt_precond_forward, rt_formal_solution_dirs, rt_shard_directions,
                    rt_box_template, rt_create_grid, rt_destroy_grid, rt_formal_solution, rt_grid_info, rt_last_error, rt_profile_enable, rt_profile_read, rt_solve,
                    rt_version)
 

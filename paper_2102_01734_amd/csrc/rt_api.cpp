@@ -199,10 +199,15 @@ static void setup_variant(rt_grid *g, bool dbl, bool wj, bool wl)
 // ---------------------------------------------------------------------------
 // schedules
 // ---------------------------------------------------------------------------
-static rt_status get_schedule(rt_grid *g, int n_wg, const std::vector<int32_t> &lambdas, DevSchedule **out)
+static rt_status get_schedule(rt_grid *g, int n_wg, const std::vector<int32_t> &lambdas, DevSchedule **out,
+                              const std::vector<int32_t> *subset = nullptr)
 {
     std::string key = std::to_string(n_wg) + ":";
     for (int l : lambdas) key += std::to_string(l) + ",";
+    if (subset) {
+        key += "|d";
+        for (int d : *subset) key += std::to_string(d) + ",";
+    }
     auto it = g->schedules.find(key);
     if (it != g->schedules.end()) {
         *out = it->second.get();
@@ -220,7 +225,7 @@ static rt_status get_schedule(rt_grid *g, int n_wg, const std::vector<int32_t> &
         for (int b = 0; b < nb; ++b) sc.slot_ids.push_back(b);
         ds->points = g->n_visits * nb;
     } else {
-        build_schedule(g->geo, lambdas, n_wg, sc);
+        build_schedule(g->geo, lambdas, n_wg, sc, subset);
         for (const WorkItem &w : sc.items) ds->points += (int64_t)g->geo.dirs[w.dir].M * g->geo.Nx * g->geo.Ny;
     }
     ds->n_wg = sc.n_wg;
@@ -313,14 +318,14 @@ static rt_status run_fs_sphere(rt_grid *g, const Variant &v, const std::vector<i
 
 static rt_status run_fs_with(rt_grid *g, const Variant &v, const std::vector<int32_t> &lambdas, const void *fld,
                              const void *I_bc, DevBuf &partJ, DevBuf &partL, DevSchedule **sched_out,
-                             hipStream_t st)
+                             hipStream_t st, const std::vector<int32_t> *subset = nullptr)
 {
     if (g->sphere) return run_fs_sphere(g, v, lambdas, fld, I_bc, partJ, partL, sched_out, st);
     const bool dbl = v.dbl, wj = v.wj, wl = v.wl;
     if (!v.ok) return fail(RT_E_UNSUPPORTED, "no kernel configuration fits this grid (layer tile of %d voxels)",
                            g->geo.Nx * g->geo.Ny);
     DevSchedule *sc = nullptr;
-    rt_status rs = get_schedule(g, v.n_wg, lambdas, &sc);
+    rt_status rs = get_schedule(g, v.n_wg, lambdas, &sc, subset);
     if (rs != RT_OK) return rs;
     const size_t esz = dbl ? 8 : 4;
     if (wj) HIPCHK(partJ.ensure((size_t)sc->n_slots * g->n_vox * esz));
@@ -360,9 +365,9 @@ static rt_status run_fs_with(rt_grid *g, const Variant &v, const std::vector<int
 
 static rt_status run_fs(rt_grid *g, bool dbl, bool wj, bool wl, const std::vector<int32_t> &lambdas,
                         const void *fld, const void *I_bc, DevBuf &partJ, DevBuf &partL, DevSchedule **sched_out,
-                        hipStream_t st)
+                        hipStream_t st, const std::vector<int32_t> *subset = nullptr)
 {
-    return run_fs_with(g, variant(g, dbl, wj, wl), lambdas, fld, I_bc, partJ, partL, sched_out, st);
+    return run_fs_with(g, variant(g, dbl, wj, wl), lambdas, fld, I_bc, partJ, partL, sched_out, st, subset);
 }
 
 // ---------------------------------------------------------------------------
@@ -889,8 +894,44 @@ rt_status rt_grid_info(rt_grid_t g, int64_t *n_vox, int32_t *n_dir, int64_t *n_v
     return RT_OK;
 }
 
+static rt_status formal_solution(rt_grid *g, int32_t n_lambda, const void *chi, const void *S, const void *I_bc,
+                                 void *J_out, void *lstar_out, void *stream, const std::vector<int32_t> *subset);
+
 rt_status rt_formal_solution(rt_grid_t g, int32_t n_lambda, const void *chi, const void *S, const void *I_bc,
                              void *J_out, void *lstar_out, void *stream)
+{
+    return formal_solution(g, n_lambda, chi, S, I_bc, J_out, lstar_out, stream, nullptr);
+}
+
+rt_status rt_formal_solution_dirs(rt_grid_t g, int32_t n_lambda, const void *chi, const void *S, const void *I_bc,
+                                  int32_t n_dirs, const int32_t *dirs, void *J_out, void *lstar_out, void *stream)
+{
+    if (!g) return fail(RT_E_INVALID, "grid is NULL");
+    if (g->sphere) return fail(RT_E_UNSUPPORTED, "direction subsets apply to box grids");
+    if (n_dirs < 1 || !dirs) return fail(RT_E_INVALID, "need at least one direction");
+    std::vector<int32_t> sub(dirs, dirs + n_dirs);
+    for (int32_t i = 0; i < n_dirs; ++i) {
+        if (sub[i] < 0 || sub[i] >= g->n_dir) return fail(RT_E_INVALID, "direction %d out of range", sub[i]);
+        if (i > 0 && sub[i] <= sub[i - 1]) return fail(RT_E_INVALID, "directions must be strictly increasing");
+    }
+    return formal_solution(g, n_lambda, chi, S, I_bc, J_out, lstar_out, stream, &sub);
+}
+
+rt_status rt_shard_directions(rt_grid_t g, int32_t n_shards, int32_t shard, int32_t *dirs_out, int32_t *n_out)
+{
+    if (!g || !n_out) return fail(RT_E_INVALID, "grid and n_out must not be NULL");
+    if (g->sphere) return fail(RT_E_UNSUPPORTED, "direction shards apply to box grids");
+    if (n_shards < 1 || shard < 0 || shard >= n_shards) return fail(RT_E_INVALID, "shard %d of %d", shard, n_shards);
+    const std::vector<int32_t> d = shard_directions(g->geo, n_shards, shard);
+    if (dirs_out) std::memcpy(dirs_out, d.data(), d.size() * sizeof(int32_t));
+    *n_out = (int32_t)d.size();
+    return RT_OK;
+}
+
+}  // extern "C"
+
+static rt_status formal_solution(rt_grid *g, int32_t n_lambda, const void *chi, const void *S, const void *I_bc,
+                                 void *J_out, void *lstar_out, void *stream, const std::vector<int32_t> *subset)
 {
     if (!g) return fail(RT_E_INVALID, "grid is NULL");
     if (n_lambda < 0 || n_lambda > g->desc.n_lambda_max)
@@ -919,11 +960,11 @@ rt_status rt_formal_solution(rt_grid_t g, int32_t n_lambda, const void *chi, con
     DevSchedule *sc = nullptr;
     rt_status rs;
     if (joint) {
-        rs = run_fs(g, dbl, true, true, lams, g->fs_fld.p, I_bc, pJ, pL, &sc, st);
+        rs = run_fs(g, dbl, true, true, lams, g->fs_fld.p, I_bc, pJ, pL, &sc, st, subset);
         if (rs != RT_OK) return rs;
     } else {
         if (wl) {
-            rs = run_fs(g, dbl, false, true, lams, g->fs_fld.p, I_bc, pJ, pL, &sc, st);
+            rs = run_fs(g, dbl, false, true, lams, g->fs_fld.p, I_bc, pJ, pL, &sc, st, subset);
             if (rs != RT_OK) return rs;
             if (dbl)
                 HIPCHK(reduce_partials<double, double>(pL.as<double>(), sc->slot_begin.as<int32_t>(), sc->slot_ids.as<int32_t>(),
@@ -932,7 +973,7 @@ rt_status rt_formal_solution(rt_grid_t g, int32_t n_lambda, const void *chi, con
                 HIPCHK(reduce_partials<float, float>(pL.as<float>(), sc->slot_begin.as<int32_t>(), sc->slot_ids.as<int32_t>(),
                                                      sc->lambda_of.as<int32_t>(), n_lambda, (float *)lstar_out, g->n_vox, st));
         }
-        rs = run_fs(g, dbl, true, false, lams, g->fs_fld.p, I_bc, pJ, pL, &sc, st);
+        rs = run_fs(g, dbl, true, false, lams, g->fs_fld.p, I_bc, pJ, pL, &sc, st, subset);
         if (rs != RT_OK) return rs;
     }
     if (dbl) {
@@ -950,8 +991,6 @@ rt_status rt_formal_solution(rt_grid_t g, int32_t n_lambda, const void *chi, con
     }
     return RT_OK;
 }
-
-}  // extern "C"
 
 // ---------------------------------------------------------------------------
 // ALI

@@ -67,7 +67,13 @@ struct Schedule {
 
 // Distributes (lambda, direction) items over n_wg persistent workgroups so
 // that their summed visit counts balance; see schedule.cpp.
-void build_schedule(const BoxGeometry &g, const std::vector<int32_t> &lambdas, int n_wg, Schedule &out);
+// subset: the directions to schedule (all when null).
+void build_schedule(const BoxGeometry &g, const std::vector<int32_t> &lambdas, int n_wg, Schedule &out,
+                    const std::vector<int32_t> *subset = nullptr);
+
+// Splits the directions into n_shards sets of nearly equal visit count
+// (longest first to the lightest shard); returns shard `shard` sorted.
+std::vector<int32_t> shard_directions(const BoxGeometry &g, int n_shards, int shard);
 
 // ---------------------------------------------------------------------------
 // Spherical grid: voxels bounded by the spheres r_i = rc + i (ro - rc)/Nr,

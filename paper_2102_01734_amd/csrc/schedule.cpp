@@ -27,24 +27,31 @@
 #include <algorithm>
 #include <numeric>
 #include <queue>
+#include <vector>
 
 #include "rt_internal.hpp"
 
 namespace rt3d {
 
-void build_schedule(const BoxGeometry &g, const std::vector<int32_t> &lambdas, int n_wg, Schedule &out)
+void build_schedule(const BoxGeometry &g, const std::vector<int32_t> &lambdas, int n_wg, Schedule &out,
+                    const std::vector<int32_t> *subset)
 {
     out = Schedule();
     const int nl = (int)lambdas.size();
-    const int nd = (int)g.dirs.size();
+    std::vector<int> order;
+    if (subset) {
+        order.assign(subset->begin(), subset->end());
+    } else {
+        order.resize(g.dirs.size());
+        std::iota(order.begin(), order.end(), 0);
+    }
+    const int nd = (int)order.size();
     out.slot_begin.assign(nl + 1, 0);
     if (nl == 0 || nd == 0 || n_wg <= 0) {
         out.n_wg = 0;
         out.wg_begin.assign(1, 0);
         return;
     }
-    std::vector<int> order(nd);
-    std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return g.dirs[a].M > g.dirs[b].M; });
 
     std::vector<std::vector<WorkItem>> per_wg;
@@ -107,8 +114,8 @@ void build_schedule(const BoxGeometry &g, const std::vector<int32_t> &lambdas, i
         out.n_slots = slot;
     } else {
         // contiguous equal-cost runs over the wavelength-major item list
-        const int64_t per_lambda = std::accumulate(g.dirs.begin(), g.dirs.end(), (int64_t)0,
-                                                   [](int64_t a, const Direction &d) { return a + d.M; });
+        int64_t per_lambda = 0;
+        for (int di : order) per_lambda += g.dirs[di].M;
         const int64_t total = per_lambda * nl;
         int slot = 0;
         int64_t acc = 0;
@@ -147,6 +154,26 @@ void build_schedule(const BoxGeometry &g, const std::vector<int32_t> &lambdas, i
         out.slot_begin[li + 1] = out.slot_begin[li] + (int32_t)slots_of_lambda[li].size();
         out.slot_ids.insert(out.slot_ids.end(), slots_of_lambda[li].begin(), slots_of_lambda[li].end());
     }
+}
+
+std::vector<int32_t> shard_directions(const BoxGeometry &g, int n_shards, int shard)
+{
+    const int nd = (int)g.dirs.size();
+    std::vector<int> order(nd);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return g.dirs[a].M > g.dirs[b].M; });
+    using P = std::pair<int64_t, int>;  // (visits, shard), min-heap
+    std::priority_queue<P, std::vector<P>, std::greater<P>> heap;
+    for (int s = 0; s < n_shards; ++s) heap.push({0, s});
+    std::vector<int32_t> out;
+    for (int di : order) {
+        P top = heap.top();
+        heap.pop();
+        if (top.second == shard) out.push_back(di);
+        heap.push({top.first + g.dirs[di].M, top.second});
+    }
+    std::sort(out.begin(), out.end());
+    return out;
 }
 
 }  // namespace rt3d

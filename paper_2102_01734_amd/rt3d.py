@@ -93,6 +93,10 @@ def lib() -> ctypes.CDLL:
     L.rt_sphere_tracks.argtypes = [ctypes.POINTER(RtGridDesc), i32, dp, ctypes.POINTER(ctypes.c_int64),
                                    ctypes.POINTER(ctypes.c_int64), dp, ctypes.POINTER(ctypes.c_int64), ip, dp]
     L.rt_sphere_tracks.restype = ctypes.c_int
+    L.rt_formal_solution_dirs.argtypes = [vp, i32, vp, vp, vp, i32, ip, vp, vp, vp]
+    L.rt_formal_solution_dirs.restype = ctypes.c_int
+    L.rt_shard_directions.argtypes = [vp, i32, i32, ip, ctypes.POINTER(i32)]
+    L.rt_shard_directions.restype = ctypes.c_int
     L.rt_set_preconditioner.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
     L.rt_set_preconditioner.restype = ctypes.c_int
     L.rt_precond_forward.argtypes = [vp, vp, vp, vp]
@@ -195,6 +199,29 @@ def rt_box_template(Nz: int, n_mu: int, n_phi: int, d: int):
     _check(lib().rt_box_template(Nz, n_mu, n_phi, d, n, di.ctypes.data_as(ip), dj.ctypes.data_as(ip),
                                  kk.ctypes.data_as(ip), s.ctypes.data_as(dp), ctypes.byref(M)), "rt_box_template")
     return dict(di=di, dj=dj, kk=kk, s=s)
+
+
+def rt_formal_solution_dirs(grid: int, n_lambda: int, chi: int, S: int, I_bc: Optional[int], dirs, J_out: int,
+                            lstar_out: Optional[int], stream: Optional[int]) -> None:
+    import numpy as np
+    d = np.ascontiguousarray(dirs, dtype=np.int32)
+    _check(lib().rt_formal_solution_dirs(ctypes.c_void_p(grid), int(n_lambda), ctypes.c_void_p(chi),
+                                         ctypes.c_void_p(S), ctypes.c_void_p(I_bc or None), int(d.size),
+                                         d.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.c_void_p(J_out),
+                                         ctypes.c_void_p(lstar_out or None), ctypes.c_void_p(stream or None)),
+           "rt_formal_solution_dirs")
+
+
+def rt_shard_directions(grid: int, n_shards: int, shard: int):
+    import numpy as np
+    n = ctypes.c_int32()
+    _check(lib().rt_shard_directions(ctypes.c_void_p(grid), n_shards, shard, None, ctypes.byref(n)),
+           "rt_shard_directions")
+    out = np.zeros(n.value, np.int32)
+    _check(lib().rt_shard_directions(ctypes.c_void_p(grid), n_shards, shard,
+                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(n)),
+           "rt_shard_directions")
+    return out
 
 
 def rt_set_preconditioner(grid: int, blob: Optional[bytes]) -> None:
@@ -313,6 +340,21 @@ class Grid:
         rt_formal_solution(self.handle, n, pc, ps, pb, J.data_ptr(), L.data_ptr() if L is not None else None,
                            _stream_ptr(stream))
         return J, L
+
+    def formal_solution_dirs(self, chi, S, dirs, I_bc=None, want_lstar=False, stream=None):
+        """Partial J (and Lambda*) over the listed directions (one shard of a solid-angle decomposition)."""
+        import torch
+        n = chi.shape[0]
+        pc, ps = self._check_field(chi, n, "chi"), self._check_field(S, n, "S")
+        pb = I_bc.data_ptr() if I_bc is not None else None
+        J = torch.empty_like(chi)
+        L = torch.empty_like(chi) if want_lstar else None
+        rt_formal_solution_dirs(self.handle, n, pc, ps, pb, dirs, J.data_ptr(),
+                                L.data_ptr() if L is not None else None, _stream_ptr(stream))
+        return J, L
+
+    def shard_directions(self, n_shards, shard):
+        return rt_shard_directions(self.handle, n_shards, shard)
 
     def autotune(self, chi, S, stream=None):
         n = chi.shape[0]

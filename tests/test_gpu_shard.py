@@ -1,0 +1,71 @@
+"""Solid-angle decomposition on one GPU: the partial formal solutions of
+disjoint direction shards add up to the full one (what an all-reduce of J
+over several GPUs would assemble), and the shard planner balances visits."""
+import numpy as np
+import pytest
+
+import synthetic as sy
+from tests.gpu_helpers import gpu_fs, make_grid, to_dev, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def test_shards_partition_balance_and_sum_fp64():
+    import paper_2102_01734_amd as rt
+    torch = torch_cuda()
+    case = sy.random_box(17, 13, 9, 4, 8, seed=21, dtype="f64")
+    S = sy.random_source(case.chi.shape, seed=22)
+    J, L = gpu_fs(case, S, lstar="parabolic")
+    g = make_grid(case, lstar="parabolic")
+    chi, St, Ib = to_dev(case.chi, "f64"), to_dev(S, "f64"), to_dev(case.I_bc, "f64")
+    M = np.array([rt.rt_box_template(case.Nz, 4, 8, d)["s"].size for d in range(32)])
+    shards = [g.shard_directions(4, k) for k in range(4)]
+    assert sorted(np.concatenate(shards).tolist()) == list(range(32))
+    loads = np.array([M[s].sum() for s in shards])
+    assert loads.max() <= 1.2 * loads.mean()
+    Js = np.zeros_like(J); Ls = np.zeros_like(L)
+    for s in shards:
+        Jp, Lp = g.formal_solution_dirs(chi, St, s, I_bc=Ib, want_lstar=True)
+        torch.cuda.synchronize()
+        Js += Jp.cpu().numpy(); Ls += Lp.cpu().numpy()
+    g.close()
+    np.testing.assert_allclose(Js, J, rtol=1e-14, atol=1e-16)
+    np.testing.assert_allclose(Ls, L, rtol=1e-14, atol=1e-16)
+
+
+def test_one_gpu_share_at_full_size_fp32():
+    """129^3, 32x64 directions, single precision: 8 visit-balanced shards of
+    ~256 directions each add up to the unsharded J."""
+    torch = torch_cuda()
+    case = sy.box_lognormal()
+    S = sy.random_source(case.chi.shape, seed=23, lo=0.2, hi=1.0, dtype="f32")
+    print("shards 129^3 x 2048 f32", flush=True)
+    g = make_grid(case)
+    chi, St, Ib = to_dev(case.chi, "f32"), to_dev(S, "f32"), to_dev(case.I_bc, "f32")
+    Jf, _ = g.formal_solution(chi, St, Ib)
+    acc = torch.zeros_like(Jf, dtype=torch.float64)
+    for k in range(8):
+        d = g.shard_directions(8, k)
+        assert 250 <= d.size <= 262
+        Jp, _ = g.formal_solution_dirs(chi, St, d, I_bc=Ib)
+        acc += Jp.double()
+    torch.cuda.synchronize()
+    g.close()
+    np.testing.assert_allclose(acc.cpu().numpy(), Jf.double().cpu().numpy(), rtol=2e-6)
+
+
+def test_shard_arguments_are_checked():
+    import paper_2102_01734_amd as rt
+    case = sy.random_box(5, 5, 5, 2, 4, seed=24, dtype="f32")
+    g = make_grid(case)
+    chi = to_dev(case.chi, "f32")
+    for bad in ([3, 1], [0, 8], [], [2, 2]):
+        with pytest.raises(rt.RtError):
+            g.formal_solution_dirs(chi, chi, np.array(bad, np.int32))
+    with pytest.raises(rt.RtError):
+        g.shard_directions(2, 2)
+    g.close()
+    sph = rt.SphereGrid(3, 3, 3, 1.0, 2.0, 2, 4)
+    with pytest.raises(rt.RtError):
+        sph.shard_directions(2, 0)
+    sph.close()
