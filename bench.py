@@ -133,7 +133,7 @@ def time_to_solution(case, net_every: int = 12, tol: float = 1e-6):
     blob_path = os.path.join(ROOT, "paper_2102_01734_amd", "data", "precond_box.rtun")
     blob = open(blob_path, "rb").read()
 
-    def run(prec, tol_, max_iter, net=0):
+    def run(prec, tol_, max_iter, net=0, method="ali"):
         dt = torch.float32 if prec == "f32" else torch.float64
         dev = dict(dtype=dt, device="cuda")
         g = rt.Grid(case.Nx, case.Ny, case.Nz, case.n_mu, case.n_phi, prec, 1)
@@ -144,7 +144,8 @@ def time_to_solution(case, net_every: int = 12, tol: float = 1e-6):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         with torch.cuda.stream(s):
-            status, rep = g.solve(st, g.opts(tol=tol_, max_iter=max_iter, use_graph=True, net_every=net), stream=s)
+            status, rep = g.solve(st, g.opts(tol=tol_, max_iter=max_iter, use_graph=True, net_every=net,
+                                             method=method), stream=s)
         s.synchronize()
         wall = time.perf_counter() - t0
         J = g.state_tensors(st)["J"].clone()
@@ -154,17 +155,20 @@ def time_to_solution(case, net_every: int = 12, tol: float = 1e-6):
     ref, _, rref, _ = run("f64", 1e-9, 80)
     out = {"tol": tol, "target_error": 1e-5,
            "reference": f"double-precision Ng-ALI, {rref.iters} steps (last max |dJ/J| {rref.max_rel_change:.1e})"}
-    for name, prec, net in (("plain_f64_ng_ali", "f64", 0), ("f32_defect_corrected_ng_ali", "f32", 0),
-                            ("f32_learned", "f32", net_every)):
-        J, status, rep, wall = run(prec, tol, 300, net)
+    for name, prec, net, method, tol_m in (("plain_f64_ng_ali", "f64", 0, "ali", tol),
+                                           ("f32_defect_corrected_ng_ali", "f32", 0, "ali", tol),
+                                           ("f32_learned", "f32", net_every, "ali", tol),
+                                           ("bicgstab_f64", "f64", 0, "bicgstab", 1e-8)):
+        J, status, rep, wall = run(prec, tol_m, 300, net, method)
         err = float(((J - ref).abs() / ref.abs()).max())
         out[name] = {"seconds": wall, "steps": rep.iters, "formal_solutions": rep.n_fs, "fp64_fs": rep.n_fs64,
-                     "status": status, "max_rel_error": err}
+                     "status": status, "max_rel_error": err, "tol": tol_m}
         if net:
             out[name].update(net_every=net, accepted=rep.n_net_accept, rejected=rep.n_net_reject)
     base = out["plain_f64_ng_ali"]["seconds"]
     out["speedup_f32_vs_plain"] = base / out["f32_defect_corrected_ng_ali"]["seconds"]
     out["speedup_learned_vs_plain"] = base / out["f32_learned"]["seconds"]
+    out["speedup_bicgstab_vs_plain"] = base / out["bicgstab_f64"]["seconds"]
     return out
 
 

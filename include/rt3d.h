@@ -184,6 +184,10 @@ typedef struct {
                              last step (0 for wavelengths already converged)   */
 } rt_state;
 
+/* rt_solve_opts.method */
+#define RT_SOLVER_ALI 0
+#define RT_SOLVER_BICGSTAB 1
+
 typedef struct {
     uint32_t struct_size; /* sizeof(rt_solve_opts)                              */
     double tol;           /* stop when max_v |J_new - J_old|/|J_new| < tol      */
@@ -197,6 +201,8 @@ typedef struct {
                              as a captured HIP graph, replayed per step; needs
                              a non-NULL stream.  Results are bitwise those of
                              eager launches.                                    */
+    int32_t method;       /* rt_solve: RT_SOLVER_ALI (operator splitting with
+                             Ng) or RT_SOLVER_BICGSTAB (see rt_solve)           */
     int32_t net_every;    /* rt_solve with a preconditioner network set
                              (rt_set_preconditioner): propose a learned
                              correction after every net_every-th step
@@ -229,8 +235,18 @@ typedef struct {
 rt_status rt_ali_step(rt_grid_t grid, rt_state *state, const rt_solve_opts *opts, void *stream);
 
 /*
- * Runs ALI steps until every wavelength has max_v |dJ/J| < tol or max_iter
- * steps were taken.  Wavelengths that converge drop out of later steps.
+ * RT_SOLVER_ALI: runs ALI steps until every wavelength has max_v |dJ/J| < tol
+ * or max_iter steps were taken.  Wavelengths that converge drop out of later
+ * steps.
+ * RT_SOLVER_BICGSTAB: BiCGStab (van der Vorst 1992; the paper names it among
+ * the solvers of the operator-splitting system, Sec. 4) on
+ * [1 - diag(1-eps) Lambda] S = (1-eps) Lambda_bc + eps B, right-preconditioned
+ * by 1 - (1-eps) Lambda*, from S(J) of the state's J, until
+ * ||b - A S||_2 / ||b||_2 < tol per wavelength (at most max_iter iterations,
+ * two formal solutions each, all in double precision); then J = Lambda S +
+ * Lambda_bc and S = (1-eps) J + eps B.  rel_change receives the final
+ * relative residuals and iter is reset to 0 (a later ALI step restarts from
+ * this J).  Ng and net options are ignored.
  * Blocks (reads a few bytes per step back to the host).  Returns
  * RT_E_NOT_CONVERGED (state valid and resumable) or RT_E_NUMERIC (NaN/Inf).
  */

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "librt3d.so")
 
-SOURCES = ["geometry.cpp", "sphere_geometry.cpp", "schedule.cpp", "fs_box.hip", "fs_sphere.hip", "ali.hip", "unet.hip",
+SOURCES = ["geometry.cpp", "sphere_geometry.cpp", "schedule.cpp", "fs_box.hip", "fs_sphere.hip", "ali.hip", "unet.hip", "krylov.hip",
            "rt_api.cpp"]
 ARCH = os.environ.get("RT3D_ARCH", "gfx950")
 CFLAGS = [

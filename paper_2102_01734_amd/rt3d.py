@@ -38,7 +38,7 @@ class RtState(ctypes.Structure):
 class RtSolveOpts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("ng_every", ctypes.c_int32), ("ng_start", ctypes.c_int32), ("reanchor", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("net_every", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("method", ctypes.c_int32), ("net_every", ctypes.c_int32)]
 
 
 class RtSolveReport(ctypes.Structure):
@@ -387,12 +387,14 @@ class Grid:
         return st
 
     @staticmethod
-    def opts(tol=1e-8, max_iter=1000, ng_every=4, ng_start=4, reanchor=0, use_graph=False, net_every=0):
+    def opts(tol=1e-8, max_iter=1000, ng_every=4, ng_start=4, reanchor=0, use_graph=False, net_every=0,
+             method="ali"):
         o = RtSolveOpts()
         o.struct_size = ctypes.sizeof(RtSolveOpts)
         o.tol, o.max_iter, o.ng_every, o.ng_start, o.reanchor = tol, max_iter, ng_every, ng_start, reanchor
         o.use_graph = int(bool(use_graph))
         o.net_every = int(net_every)
+        o.method = {"ali": 0, "bicgstab": 1}[method]
         return o
 
     def set_preconditioner(self, blob):
