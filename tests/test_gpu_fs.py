@@ -181,3 +181,40 @@ def test_set_launch_shape(orc):
     with pytest.raises(rt.RtError):
         g.set_launch_shape(100, 3)       # not compiled
     g.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_largest_layer_tile(orc, prec):
+    """140 x 140 = 19600 voxels per layer is the largest square layer whose
+    double tile (plus one scratch word for each of the 832 threads that hold
+    its rays, 24 per thread) fits the 160 KiB of LDS of a CU: it runs and
+    matches the oracle; 141 x 141 is refused."""
+    import paper_2102_01734_amd as rt
+    case = sy.random_box(140, 140, 3, 2, 4, seed=61, dtype=prec)
+    S = sy.random_source(case.chi.shape, seed=62, dtype=prec)
+    print(f"largest tile {prec}", flush=True)
+    J, L = gpu_fs(case, S)
+    Jo, Lo = _oracle_fs(orc, case, S, "linear")
+    tol = 1e-12 if prec == "f64" else 2e-5
+    np.testing.assert_allclose(J, Jo, rtol=tol, atol=tol * 0.05 * np.abs(Jo).max())
+    np.testing.assert_allclose(L, Lo, rtol=tol, atol=tol * 0.005)
+    with pytest.raises(rt.RtError) as e:
+        rt.Grid(141, 141, 3, 2, 4, prec)
+    assert e.value.status == rt.rt3d.RT_E_UNSUPPORTED
+
+
+def test_batched_64_wavelengths_full_size_sampled(orc):
+    """The 64-wavelength batch on the 129^3 box (32x32 directions, single
+    precision) in one launch: three wavelengths checked against the oracle at
+    sampled voxels, computed one by one."""
+    case = sy.box_batched()
+    S = sy.random_source(case.chi.shape[1:], seed=63, lo=0.2, hi=1.0, dtype="f32")
+    S = np.broadcast_to(S, case.chi.shape)
+    print("batched 64 x 129^3 x 1024 f32", flush=True)
+    J, L = gpu_fs(case, S)
+    rng = np.random.default_rng(8)
+    vox = np.unique(rng.integers(0, case.n_vox, 12))
+    for l in (0, 37, 63):
+        Jo, Lo = orc.fs_box_sampled(case.chi[l], S[l], case.I_bc[l, 0], case.I_bc[l, 1], case.n_mu, case.n_phi, vox)
+        np.testing.assert_allclose(J[l].ravel()[vox], Jo, rtol=2e-5, atol=1e-6 * np.abs(Jo).max())
+        np.testing.assert_allclose(L[l].ravel()[vox], Lo, rtol=2e-5, atol=1e-7)
