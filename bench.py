@@ -9,7 +9,10 @@ per-wavelength convergence norm, and Ng extrapolation every fourth step.
 The metric is voxel-direction updates per second (VDU/s): voxels x directions
 x wavelengths of one formal solution, divided by the time of one step.
 
-Prints one JSON line (see the design doc for the roofline and baseline definitions).
+Prints one JSON line: the throughput, the roofline position of the timed
+kernel (algorithmic flops of a characteristic point over its measured launch
+time, against the vector ALU peak), its HBM traffic when counters taken on
+the current kernel source are on file, and the oracle's CPU rate on a sample.
 """
 import argparse
 import hashlib
@@ -242,8 +245,8 @@ def main():
                     help="only run a plain 1 GiB device-to-device copy three times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus must be 1 "
-              "(multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+        print("bench.py: the benchmark runs on one GPU; --gpus must be 1 (the solid-angle sharding across "
+              "GPUs is not implemented; one GPU's share is measured as one_gpu_share)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -63,7 +63,7 @@ typedef enum {
     RT_E_HIP = 3,           /* a HIP runtime call failed                       */
     RT_E_NOT_CONVERGED = 4, /* rt_solve reached max_iter; state stays valid    */
     RT_E_NUMERIC = 5,       /* NaN or Inf met in the iteration                 */
-    RT_E_UNSUPPORTED = 6    /* valid request this build cannot serve           */
+    RT_E_UNSUPPORTED = 6    /* valid request the library cannot serve          */
 } rt_status;
 
 typedef enum { RT_GEOM_BOX_PERIODIC_XY = 0, RT_GEOM_SPHERICAL = 1 } rt_geom;

@@ -63,7 +63,7 @@ def lib() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"rt3d HIP library not built: {LIB_PATH} is missing "
-                          "(run __graft_entry__.build() or python paper_2102_01734_amd/build.py)")
+                          "(run python paper_2102_01734_amd/build.py)")
     # torch bundles its own HIP runtime with the same soname as the system one;
     # loading torch first makes librt3d.so bind to that single runtime (two
     # runtimes in one process do not share the device)
