@@ -84,8 +84,10 @@ __global__ void __launch_bounds__(LB) fs_box_kernel(FsBoxArgs a)
     }
 
     // rays of this thread: q = tid + j*nthr with origin (x0, y0).  Slots past
-    // the last ray repeat the ray q - NxNy and contribute exactly zero, so the
-    // body below has no per-ray branches.
+    // the last ray repeat the ray q - NxNy and contribute exactly zero.  The
+    // host admits a launch shape only if nthr * (R - 1) < NxNy, so only the
+    // last slot (j = R - 1) of a thread can be such a padding slot and the
+    // other R - 1 copies of the point body carry no padding logic.
     int xy0[R];    // x0 | y0 << 16 | kPad
 #pragma unroll
     for (int j = 0; j < R; ++j) {
@@ -157,8 +159,10 @@ __global__ void __launch_bounds__(LB) fs_box_kernel(FsBoxArgs a)
             uint32_t yl = y0 + ((w >> kOffBits) & kOffMask);
             yl = min(yl, yl - (uint32_t)Ny);
             const int idx = (int)__umul24(yl, (uint32_t)Nx) + (int)xl;
-            return xy0[j] < 0 ? NxNy + tid : idx;
+            return (j == R - 1 && xy0[j] < 0) ? NxNy + tid : idx;
         };
+        // the visit weight, zero for a padding slot
+        auto ray_weight = [&](int j, T cw) { return (j == R - 1 && xy0[j] < 0) ? T(0) : cw; };
 
         // first point: entry half-segment with constant S
         int g_c = goff[0] * ES;
@@ -174,7 +178,7 @@ __global__ void __launch_bounds__(LB) fs_box_kernel(FsBoxArgs a)
                 entry_weights<T>(0.5 * seg_depth((double)fc.chi, s_c), ex, e0);
                 I[j] = WJ ? Ibc * ex + fc.S * e0 : T(0);
                 const int idx = tile_index(j, w_c);
-                const T cj = xy0[j] < 0 ? T(0) : cw;
+                const T cj = ray_weight(j, cw);
                 if (WJ) tJ[idx] += cj * I[j];
                 if (WL) tL[idx] += cj * e0;
             }
@@ -210,7 +214,7 @@ __global__ void __launch_bounds__(LB) fs_box_kernel(FsBoxArgs a)
                 const PointW<T> pw = point_weights<T>(D, Dp, LAST);
                 if (WJ) I[j] = I[j] * pw.ex + pw.a * fp.S + pw.b * fc.S + (LAST ? T(0) : pw.g * fn.S);
                 const int idx = tile_index(j, w_c);
-                const T cj = xy0[j] < 0 ? T(0) : cw;
+                const T cj = ray_weight(j, cw);
                 if (WJ) tJ[idx] += cj * I[j];
                 if (WL) {
                     T dloc;

@@ -176,6 +176,8 @@ static Variant make_variant(rt_grid *g, bool dbl, bool wj, bool wl, int lb, int 
     const int need = (rays + R - 1) / R;
     if (need > lb) return v;
     v.nthr = std::min(lb, ((need + 63) / 64) * 64);
+    // the sweep kernel expects padding slots only in each thread's last ray slot
+    if ((int64_t)v.nthr * (R - 1) >= rays) return v;
     // per tile: one word per voxel of a layer plus one scratch word per thread
     v.lds = (size_t)(rays + v.nthr) * (dbl ? 8 : 4) * ((wj ? 1 : 0) + (wl ? 1 : 0));
     if (v.lds > g->max_lds) return v;
