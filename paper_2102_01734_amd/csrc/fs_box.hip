@@ -64,8 +64,9 @@ __device__ __forceinline__ Pair<double> ld_pair<double>(__amdgpu_buffer_rsrc_t r
 // ---------------------------------------------------------------------------
 // the sweep kernel
 // ---------------------------------------------------------------------------
-template <typename T, int LB, int R, bool WJ, bool WL, bool PARA>
-__global__ void __launch_bounds__(LB) fs_box_kernel(FsBoxArgs a)
+template <typename T, int LB, int R, bool WJ, bool WL, bool PARA, int OCC>
+__global__ void __launch_bounds__(LB) __attribute__((amdgpu_waves_per_eu(OCC * LB / 256 > 0 ? OCC * LB / 256 : 1)))
+fs_box_kernel(FsBoxArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int Nx = a.Nx, Ny = a.Ny;
@@ -83,17 +84,26 @@ __global__ void __launch_bounds__(LB) fs_box_kernel(FsBoxArgs a)
         if (WL) tL[i] = T(0);
     }
 
-    // rays of this thread: q = tid + j*nthr with origin (x0, y0).  Slots past
-    // the last ray repeat the ray q - NxNy and contribute exactly zero.  The
-    // host admits a launch shape only if nthr * (R - 1) < NxNy, so only the
-    // last slot (j = R - 1) of a thread can be such a padding slot and the
-    // other R - 1 copies of the point body carry no padding logic.
+    // The rays of a direction may be split into bundles of consecutive ray
+    // indices; workgroup w always sweeps bundle w mod n_bundles (its own layer
+    // tile and partial slot), so smaller workgroups with fewer rays per thread
+    // can share a CU.  Rays of this thread: local index l = tid + j*nthr of
+    // the bundle, origin (x0, y0) of ray q_lo + l.  Slots past the bundle's
+    // last ray repeat an earlier ray of the bundle and contribute exactly
+    // zero.  The host admits a launch shape only if nthr * (R - 1) is below
+    // the smallest bundle, so only the last slot (j = R - 1) of a thread can
+    // be such a padding slot and the other R - 1 copies of the point body
+    // carry no padding logic.
+    const int bundle = a.n_bundles > 1 ? (int)(blockIdx.x % (unsigned)a.n_bundles) : 0;
+    const int q_lo = bundle * a.bundle_rays;
+    const int q_n = min(a.bundle_rays, NxNy - q_lo);
     int xy0[R];    // x0 | y0 << 16 | kPad
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        int q = tid + j * nthr;
+        int l = tid + j * nthr;
         int pad = 0;
-        while (q >= NxNy) { q -= NxNy; pad = kPad; }
+        while (l >= q_n) { l -= q_n; pad = kPad; }
+        const int q = q_lo + l;
         const int y0 = q / Nx;
         const int x0 = q - y0 * Nx;
         xy0[j] = x0 | (y0 << 16) | pad;
@@ -256,16 +266,20 @@ __global__ void __launch_bounds__(LB) fs_box_kernel(FsBoxArgs a)
 // J-only kernel, which runs every ALI step and is the one the autotuner
 // (rt_autotune) times.
 // ---------------------------------------------------------------------------
-#define RT_FS_SHAPES_FULL(X) X(1024, 1) X(1024, 2) X(1024, 4) X(1024, 8) X(1024, 12) X(1024, 17) X(1024, 24)
-#define RT_FS_SHAPES_TUNE(X)                                                                                  \
-    X(768, 2) X(768, 6) X(768, 11) X(768, 22) X(768, 32) X(512, 3) X(512, 9) X(512, 17) X(512, 33) X(256, 5)   \
-        X(256, 17) X(256, 34)
+// Launch shapes (threads bound LB, rays per thread R, workgroups per CU OCC).
+// OCC = 2 shapes split each direction's rays into two bundles so that two
+// workgroups (two layer tiles) share a CU: twice the resident waves to hide
+// the latency of the double-precision point arithmetic.
+#define RT_FS_SHAPES_FULL(X) X(1024, 1, 1) X(1024, 2, 1) X(1024, 4, 1) X(1024, 8, 1) X(1024, 12, 1) X(1024, 17, 1) X(1024, 24, 1)
+#define RT_FS_SHAPES_TUNE(X)                                                                                     \
+    X(768, 2, 1) X(768, 6, 1) X(768, 11, 1) X(768, 22, 1) X(768, 32, 1) X(512, 33, 1) X(256, 5, 1) X(256, 17, 1) \
+        X(256, 34, 1) X(512, 3, 2) X(512, 9, 2) X(512, 17, 2)
 
 static const FsShape kShapes[] = {
-#define RT_LIST(lb, r) {lb, r, true},
+#define RT_LIST(lb, r, o) {lb, r, true, o},
     RT_FS_SHAPES_FULL(RT_LIST)
 #undef RT_LIST
-#define RT_LIST(lb, r) {lb, r, false},
+#define RT_LIST(lb, r, o) {lb, r, false, o},
     RT_FS_SHAPES_TUNE(RT_LIST)
 #undef RT_LIST
 };
@@ -276,46 +290,46 @@ int fs_box_shapes(const FsShape **out)
     return (int)(sizeof(kShapes) / sizeof(kShapes[0]));
 }
 
-template <typename T, int LB, int R, bool WJ, bool WL, bool PARA>
+template <typename T, int LB, int R, bool WJ, bool WL, bool PARA, int OCC>
 static hipError_t launch_one(const FsBoxArgs &a, int n_wg, int nthr, size_t lds, hipStream_t st)
 {
-    auto k = fs_box_kernel<T, LB, R, WJ, WL, PARA>;
+    auto k = fs_box_kernel<T, LB, R, WJ, WL, PARA, OCC>;
     hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3(n_wg), dim3(nthr), lds, st, a);
     return hipGetLastError();
 }
 
-template <typename T, int LB, int R, bool WJ, bool WL, bool PARA>
+template <typename T, int LB, int R, bool WJ, bool WL, bool PARA, int OCC>
 static int occ_one(int nthr, size_t lds)
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fs_box_kernel<T, LB, R, WJ, WL, PARA>, nthr, lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fs_box_kernel<T, LB, R, WJ, WL, PARA, OCC>, nthr, lds) !=
         hipSuccess)
         return 0;
     return n;
 }
 
-template <typename T, int LB, int R>
+template <typename T, int LB, int R, int OCC>
 static hipError_t launch_flags(const FsBoxArgs &a, bool wj, bool wl, bool para, int n_wg, int nthr, size_t lds,
                                hipStream_t st)
 {
-    if (wj && wl && para) return launch_one<T, LB, R, true, true, true>(a, n_wg, nthr, lds, st);
-    if (wj && wl) return launch_one<T, LB, R, true, true, false>(a, n_wg, nthr, lds, st);
-    if (wj) return launch_one<T, LB, R, true, false, false>(a, n_wg, nthr, lds, st);
-    if (wl && para) return launch_one<T, LB, R, false, true, true>(a, n_wg, nthr, lds, st);
-    if (wl) return launch_one<T, LB, R, false, true, false>(a, n_wg, nthr, lds, st);
+    if (wj && wl && para) return launch_one<T, LB, R, true, true, true, OCC>(a, n_wg, nthr, lds, st);
+    if (wj && wl) return launch_one<T, LB, R, true, true, false, OCC>(a, n_wg, nthr, lds, st);
+    if (wj) return launch_one<T, LB, R, true, false, false, OCC>(a, n_wg, nthr, lds, st);
+    if (wl && para) return launch_one<T, LB, R, false, true, true, OCC>(a, n_wg, nthr, lds, st);
+    if (wl) return launch_one<T, LB, R, false, true, false, OCC>(a, n_wg, nthr, lds, st);
     return hipSuccess;
 }
 
-template <typename T, int LB, int R>
+template <typename T, int LB, int R, int OCC>
 static int occ_flags(bool wj, bool wl, bool para, int nthr, size_t lds)
 {
-    if (wj && wl && para) return occ_one<T, LB, R, true, true, true>(nthr, lds);
-    if (wj && wl) return occ_one<T, LB, R, true, true, false>(nthr, lds);
-    if (wj) return occ_one<T, LB, R, true, false, false>(nthr, lds);
-    if (wl && para) return occ_one<T, LB, R, false, true, true>(nthr, lds);
-    if (wl) return occ_one<T, LB, R, false, true, false>(nthr, lds);
+    if (wj && wl && para) return occ_one<T, LB, R, true, true, true, OCC>(nthr, lds);
+    if (wj && wl) return occ_one<T, LB, R, true, true, false, OCC>(nthr, lds);
+    if (wj) return occ_one<T, LB, R, true, false, false, OCC>(nthr, lds);
+    if (wl && para) return occ_one<T, LB, R, false, true, true, OCC>(nthr, lds);
+    if (wl) return occ_one<T, LB, R, false, true, false, OCC>(nthr, lds);
     return 0;
 }
 
@@ -323,13 +337,13 @@ template <typename T>
 static hipError_t launch_t(const FsBoxArgs &a, bool wj, bool wl, bool para, int lb, int R, int n_wg, int nthr,
                            size_t lds, hipStream_t st)
 {
-#define RT_CASE(LBv, Rv) \
-    if (lb == LBv && R == Rv) return launch_flags<T, LBv, Rv>(a, wj, wl, para, n_wg, nthr, lds, st);
+#define RT_CASE(LBv, Rv, Ov) \
+    if (lb == LBv && R == Rv) return launch_flags<T, LBv, Rv, Ov>(a, wj, wl, para, n_wg, nthr, lds, st);
     RT_FS_SHAPES_FULL(RT_CASE)
 #undef RT_CASE
     if (!(wj && !wl)) return hipErrorInvalidValue;
-#define RT_CASE(LBv, Rv) \
-    if (lb == LBv && R == Rv) return launch_one<T, LBv, Rv, true, false, false>(a, n_wg, nthr, lds, st);
+#define RT_CASE(LBv, Rv, Ov) \
+    if (lb == LBv && R == Rv) return launch_one<T, LBv, Rv, true, false, false, Ov>(a, n_wg, nthr, lds, st);
     RT_FS_SHAPES_TUNE(RT_CASE)
 #undef RT_CASE
     return hipErrorInvalidValue;
@@ -338,13 +352,13 @@ static hipError_t launch_t(const FsBoxArgs &a, bool wj, bool wl, bool para, int 
 template <typename T>
 static int occ_t(bool wj, bool wl, bool para, int lb, int R, int nthr, size_t lds)
 {
-#define RT_CASE(LBv, Rv) \
-    if (lb == LBv && R == Rv) return occ_flags<T, LBv, Rv>(wj, wl, para, nthr, lds);
+#define RT_CASE(LBv, Rv, Ov) \
+    if (lb == LBv && R == Rv) return occ_flags<T, LBv, Rv, Ov>(wj, wl, para, nthr, lds);
     RT_FS_SHAPES_FULL(RT_CASE)
 #undef RT_CASE
     if (!(wj && !wl)) return 0;
-#define RT_CASE(LBv, Rv) \
-    if (lb == LBv && R == Rv) return occ_one<T, LBv, Rv, true, false, false>(nthr, lds);
+#define RT_CASE(LBv, Rv, Ov) \
+    if (lb == LBv && R == Rv) return occ_one<T, LBv, Rv, true, false, false, Ov>(nthr, lds);
     RT_FS_SHAPES_TUNE(RT_CASE)
 #undef RT_CASE
     return 0;

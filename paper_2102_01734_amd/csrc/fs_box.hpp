@@ -28,16 +28,20 @@ struct FsBoxArgs {
     const void *field;
     int64_t pad_stride;
     const void *I_bc;  // [lambda][2] or null
+    // ray bundles: workgroup w sweeps rays [b Q, min((b+1) Q, NxNy)), b = w mod n_bundles
+    int n_bundles, bundle_rays;
     // partial sums [slot][n_vox]
     void *partJ;
     void *partL;
 };
 
 // A compiled launch shape: workgroup size bound `lb`, rays per thread `R`;
-// `full`: available for every output combination (else J-only).
+// `full`: available for every output combination (else J-only); `occ`: see
+// fs_box.hip.
 struct FsShape {
     int lb, R;
     bool full;
+    int occ;  // workgroups per CU the shape is compiled for (= ray bundles per direction)
 };
 int fs_box_shapes(const FsShape **out);
 

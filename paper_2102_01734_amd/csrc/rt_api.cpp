@@ -82,6 +82,7 @@ struct DevBuf {
 struct Variant {
     bool dbl = false, wj = false, wl = false;
     int lb = 0, R = 0, nthr = 0, n_wg = 0;
+    int nb = 1, Q = 0;  // ray bundles per direction and rays per bundle
     size_t lds = 0;
     bool ok = false;
 };
@@ -168,22 +169,30 @@ static Variant &variant(rt_grid *g, bool dbl, bool wj, bool wl) { return g->var[
 
 // Resident-workgroup count and LDS size of one launch shape; ok = false when
 // the shape cannot hold all rays of a direction or its tiles do not fit.
-static Variant make_variant(rt_grid *g, bool dbl, bool wj, bool wl, int lb, int R)
+static Variant make_variant(rt_grid *g, bool dbl, bool wj, bool wl, int lb, int R, int occ = 1)
 {
     Variant v;
     v.dbl = dbl; v.wj = wj; v.wl = wl; v.lb = lb; v.R = R;
     const int rays = g->geo.Nx * g->geo.Ny;
-    const int need = (rays + R - 1) / R;
+    const int nb = occ;
+    const int Q = (rays + nb - 1) / nb;
+    const int q_last = rays - (nb - 1) * Q;  // the smallest bundle
+    if (q_last <= 0) return v;
+    v.nb = nb;
+    v.Q = Q;
+    const int need = (Q + R - 1) / R;
     if (need > lb) return v;
     v.nthr = std::min(lb, ((need + 63) / 64) * 64);
     // the sweep kernel expects padding slots only in each thread's last ray slot
-    if ((int64_t)v.nthr * (R - 1) >= rays) return v;
+    if ((int64_t)v.nthr * (R - 1) >= q_last) return v;
     // per tile: one word per voxel of a layer plus one scratch word per thread
     v.lds = (size_t)(rays + v.nthr) * (dbl ? 8 : 4) * ((wj ? 1 : 0) + (wl ? 1 : 0));
     if (v.lds > g->max_lds) return v;
-    const int occ = fs_box_occupancy(dbl, wj, wl, g->para, lb, R, v.nthr, v.lds);
-    if (occ <= 0) return v;
-    v.n_wg = occ * g->n_cu;
+    const int res = fs_box_occupancy(dbl, wj, wl, g->para, lb, R, v.nthr, v.lds);
+    if (res <= 0) return v;
+    v.n_wg = res * g->n_cu;
+    v.n_wg -= v.n_wg % nb;  // equal classes of workgroups per bundle
+    if (v.n_wg < nb) return v;
     v.ok = true;
     return v;
 }
@@ -205,9 +214,9 @@ static void setup_variant(rt_grid *g, bool dbl, bool wj, bool wl)
 // schedules
 // ---------------------------------------------------------------------------
 static rt_status get_schedule(rt_grid *g, int n_wg, const std::vector<int32_t> &lambdas, DevSchedule **out,
-                              const std::vector<int32_t> *subset = nullptr)
+                              const std::vector<int32_t> *subset = nullptr, int nb = 1, int Q = 0)
 {
-    std::string key = std::to_string(n_wg) + ":";
+    std::string key = std::to_string(n_wg) + "/" + std::to_string(nb) + ":";
     for (int l : lambdas) key += std::to_string(l) + ",";
     if (subset) {
         key += "|d";
@@ -230,8 +239,14 @@ static rt_status get_schedule(rt_grid *g, int n_wg, const std::vector<int32_t> &
         for (int b = 0; b < nb; ++b) sc.slot_ids.push_back(b);
         ds->points = g->n_visits * nb;
     } else {
-        build_schedule(g->geo, lambdas, n_wg, sc, subset);
-        for (const WorkItem &w : sc.items) ds->points += (int64_t)g->geo.dirs[w.dir].M * g->geo.Nx * g->geo.Ny;
+        build_schedule(g->geo, lambdas, n_wg, sc, subset, nb);
+        const int64_t rays = (int64_t)g->geo.Nx * g->geo.Ny;
+        for (int w = 0; w < sc.n_wg; ++w) {
+            const int64_t q_lo = nb > 1 ? (int64_t)(w % nb) * Q : 0;
+            const int64_t nr = nb > 1 ? std::min<int64_t>(Q, rays - q_lo) : rays;
+            for (int k = sc.wg_begin[w]; k < sc.wg_begin[w + 1]; ++k)
+                ds->points += (int64_t)g->geo.dirs[sc.items[k].dir].M * nr;
+        }
     }
     ds->n_wg = sc.n_wg;
     ds->n_slots = sc.n_slots;
@@ -330,7 +345,7 @@ static rt_status run_fs_with(rt_grid *g, const Variant &v, const std::vector<int
     if (!v.ok) return fail(RT_E_UNSUPPORTED, "no kernel configuration fits this grid (layer tile of %d voxels)",
                            g->geo.Nx * g->geo.Ny);
     DevSchedule *sc = nullptr;
-    rt_status rs = get_schedule(g, v.n_wg, lambdas, &sc, subset);
+    rt_status rs = get_schedule(g, v.n_wg, lambdas, &sc, subset, v.nb, v.Q);
     if (rs != RT_OK) return rs;
     const size_t esz = dbl ? 8 : 4;
     if (wj) HIPCHK(partJ.ensure((size_t)sc->n_slots * g->n_vox * esz));
@@ -352,6 +367,8 @@ static rt_status run_fs_with(rt_grid *g, const Variant &v, const std::vector<int
     a.I_bc = I_bc;
     a.partJ = wj ? partJ.p : nullptr;
     a.partL = wl ? partL.p : nullptr;
+    a.n_bundles = v.nb;
+    a.bundle_rays = v.Q;
     if (g->prof) {
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
@@ -814,7 +831,7 @@ rt_status rt_autotune(rt_grid_t g, int32_t n_lambda, const void *chi, const void
     g->prof = false;
     rt_status rs = RT_OK;
     for (int i = 0; i < n && rs == RT_OK; ++i) {
-        const Variant v = make_variant(g, dbl, true, false, sh[i].lb, sh[i].R);
+        const Variant v = make_variant(g, dbl, true, false, sh[i].lb, sh[i].R, sh[i].occ);
         if (!v.ok) continue;
         DevSchedule *sc = nullptr;
         DevBuf &pJ = dbl ? g->partJ64 : g->partJ;
@@ -851,7 +868,7 @@ rt_status rt_set_launch_shape(rt_grid_t g, int32_t threads, int32_t rays)
     const int n = fs_box_shapes(&sh);
     for (int i = 0; i < n; ++i) {
         if (sh[i].lb != threads || sh[i].R != rays) continue;
-        const Variant v = make_variant(g, g->dbl, true, false, threads, rays);
+        const Variant v = make_variant(g, g->dbl, true, false, threads, rays, sh[i].occ);
         if (!v.ok)
             return fail(RT_E_INVALID, "shape %d x %d cannot hold the %d rays of a direction on this device", threads,
                         rays, g->geo.Nx * g->geo.Ny);
@@ -1099,7 +1116,7 @@ static rt_status graph_plain_step(rt_grid *g, rt_state *s, const std::vector<int
 {
     const Variant &v = variant(g, g->dbl, true, false);
     DevSchedule *sc = nullptr;
-    rt_status rs = get_schedule(g, v.n_wg, lams, &sc);
+    rt_status rs = get_schedule(g, v.n_wg, lams, &sc, nullptr, v.nb, v.Q);
     if (rs != RT_OK) return rs;
     DevBuf &pJ = g->dbl ? g->partJ64 : g->partJ;
     HIPCHK(pJ.ensure((size_t)sc->n_slots * g->n_vox * (g->dbl ? 8 : 4)));

@@ -69,7 +69,7 @@ struct Schedule {
 // that their summed visit counts balance; see schedule.cpp.
 // subset: the directions to schedule (all when null).
 void build_schedule(const BoxGeometry &g, const std::vector<int32_t> &lambdas, int n_wg, Schedule &out,
-                    const std::vector<int32_t> *subset = nullptr);
+                    const std::vector<int32_t> *subset = nullptr, int n_bundles = 1);
 
 // Splits the directions into n_shards sets of nearly equal visit count
 // (longest first to the lightest shard); returns shard `shard` sorted.

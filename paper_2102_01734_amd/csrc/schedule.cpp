@@ -10,8 +10,11 @@
 // reduction adds the slots of a wavelength in a fixed order, so results do
 // not depend on timing.
 //
-// * one wavelength, workgroup count a multiple of 8 (one resident workgroup
-//   per CU; the dispatcher places workgroup i on XCD i mod 8): directions
+// * ray bundles: when a direction's rays are split into n_bundles bundles,
+//   workgroup w sweeps bundle w mod n_bundles, and each class of workgroups
+//   receives every item, distributed as below.
+// * one wavelength, class size a multiple of 4 (the dispatcher places
+//   workgroup i on XCD i mod 8): directions
 //   that sweep downwards go to the workgroups of XCDs 0-3, upward ones to
 //   XCDs 4-7, and each sign's directions are dealt in rounds of equal cost
 //   (sorted by cost, one item per workgroup per round, heaviest item to the
@@ -33,45 +36,31 @@
 
 namespace rt3d {
 
-void build_schedule(const BoxGeometry &g, const std::vector<int32_t> &lambdas, int n_wg, Schedule &out,
-                    const std::vector<int32_t> *subset)
+// One class of workgroups (those sweeping the same ray bundle) gets every
+// (wavelength, direction) item; `wgs` are the class's workgroup ids.
+static void schedule_class(const BoxGeometry &g, const std::vector<int32_t> &lambdas, const std::vector<int> &order,
+                           const std::vector<int> &wgs, std::vector<std::vector<WorkItem>> &per_wg,
+                           std::vector<std::vector<int32_t>> &slots_of_lambda, int &slot)
 {
-    out = Schedule();
     const int nl = (int)lambdas.size();
-    std::vector<int> order;
-    if (subset) {
-        order.assign(subset->begin(), subset->end());
-    } else {
-        order.resize(g.dirs.size());
-        std::iota(order.begin(), order.end(), 0);
-    }
     const int nd = (int)order.size();
-    out.slot_begin.assign(nl + 1, 0);
-    if (nl == 0 || nd == 0 || n_wg <= 0) {
-        out.n_wg = 0;
-        out.wg_begin.assign(1, 0);
-        return;
-    }
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return g.dirs[a].M > g.dirs[b].M; });
-
-    std::vector<std::vector<WorkItem>> per_wg;
-    std::vector<std::vector<int32_t>> slots_of_lambda(nl);
-
-    const bool xcd_rounds = nl == 1 && n_wg % 8 == 0 && nd >= n_wg;
+    const int n_wg = (int)wgs.size();
+    const bool xcd_rounds = nl == 1 && n_wg % 4 == 0 && nd >= n_wg;
     if (xcd_rounds) {
-        per_wg.assign(n_wg, {});
-        std::vector<int64_t> load(n_wg, 0);
+        std::vector<int64_t> load(per_wg.size(), 0);
+        std::vector<int> used;
         for (int sign = 0; sign < 2; ++sign) {
             std::vector<int> dirs;
             for (int di : order)  // already sorted by decreasing cost
                 if ((g.dirs[di].mu < 0.0) == (sign == 0)) dirs.push_back(di);
-            std::vector<int> wgs;  // XCDs 0-3 for downward sweeps, 4-7 for upward
-            for (int w = 0; w < n_wg; ++w)
-                if (((w % 8) < 4) == (sign == 0)) wgs.push_back(w);
-            const int k = (int)wgs.size();
+            std::vector<int> half;  // XCDs 0-3 for downward sweeps, 4-7 for upward
+            for (int w : wgs)
+                if (((w % 8) < 4) == (sign == 0)) half.push_back(w);
+            if (half.empty()) half = wgs;
+            const int k = (int)half.size();
             for (size_t r0 = 0; r0 < dirs.size(); r0 += k) {
                 const size_t r1 = std::min(dirs.size(), r0 + (size_t)k);
-                std::vector<int> by_load(wgs);
+                std::vector<int> by_load(half);
                 std::stable_sort(by_load.begin(), by_load.end(), [&](int a, int b) { return load[a] < load[b]; });
                 for (size_t t = r0; t < r1; ++t) {
                     const int w = by_load[t - r0];
@@ -80,15 +69,15 @@ void build_schedule(const BoxGeometry &g, const std::vector<int32_t> &lambdas, i
                 }
             }
         }
-        out.n_slots = n_wg;
-        for (int w = 0; w < n_wg; ++w)
+        for (int w : wgs)
             if (!per_wg[w].empty()) slots_of_lambda[0].push_back(w);
+        slot = std::max(slot, (int)per_wg.size());
     } else if (nl <= n_wg) {
         // workgroups per wavelength: as even as possible, but never more than directions
         std::vector<int> cnt(nl, n_wg / nl);
         for (int i = 0; i < n_wg % nl; ++i) cnt[i]++;
         for (int i = 0; i < nl; ++i) cnt[i] = std::max(1, std::min(cnt[i], nd));
-        int slot = 0;
+        int next = 0;  // next workgroup of the class
         for (int li = 0; li < nl; ++li) {
             const int k = cnt[li];
             // LPT: longest direction to the least loaded workgroup of this wavelength
@@ -104,47 +93,80 @@ void build_schedule(const BoxGeometry &g, const std::vector<int32_t> &lambdas, i
             }
             for (int w = 0; w < k; ++w) {
                 if (local[w].empty()) continue;
+                const int wg = wgs[(next++) % n_wg];
                 for (auto &it : local[w]) it.slot = slot;
                 local[w][0].first = 1;
                 slots_of_lambda[li].push_back(slot);
                 ++slot;
-                per_wg.push_back(std::move(local[w]));
+                for (auto &it : local[w]) per_wg[wg].push_back(it);
             }
         }
-        out.n_slots = slot;
     } else {
         // contiguous equal-cost runs over the wavelength-major item list
         int64_t per_lambda = 0;
         for (int di : order) per_lambda += g.dirs[di].M;
         const int64_t total = per_lambda * nl;
-        int slot = 0;
         int64_t acc = 0;
-        int wg = 0;
-        per_wg.emplace_back();
+        int v = 0;  // class-local workgroup
         int cur_lambda = -1;
         for (int li = 0; li < nl; ++li) {
             for (int di : order) {
                 // move to the next workgroup once this one has its share
-                const int64_t target = (total * (wg + 1)) / n_wg;
-                if (acc >= target && wg + 1 < n_wg && !per_wg.back().empty()) {
-                    per_wg.emplace_back();
-                    ++wg;
+                const int64_t target = (total * (v + 1)) / n_wg;
+                if (acc >= target && v + 1 < n_wg && !per_wg[wgs[v]].empty()) {
+                    ++v;
                     cur_lambda = -1;
                 }
+                auto &list = per_wg[wgs[v]];
                 if (cur_lambda != li) {
                     slots_of_lambda[li].push_back(slot);
-                    per_wg.back().push_back({lambdas[li], di, slot, 1});
+                    list.push_back({lambdas[li], di, slot, 1});
                     ++slot;
                     cur_lambda = li;
                 } else {
-                    per_wg.back().push_back({lambdas[li], di, slot - 1, 0});
+                    list.push_back({lambdas[li], di, slot - 1, 0});
                 }
                 acc += g.dirs[di].M;
             }
         }
-        out.n_slots = slot;
     }
-    out.n_wg = (int)per_wg.size();
+}
+
+void build_schedule(const BoxGeometry &g, const std::vector<int32_t> &lambdas, int n_wg, Schedule &out,
+                    const std::vector<int32_t> *subset, int n_bundles)
+{
+    out = Schedule();
+    const int nl = (int)lambdas.size();
+    std::vector<int> order;
+    if (subset) {
+        order.assign(subset->begin(), subset->end());
+    } else {
+        order.resize(g.dirs.size());
+        std::iota(order.begin(), order.end(), 0);
+    }
+    const int nd = (int)order.size();
+    out.slot_begin.assign(nl + 1, 0);
+    if (nl == 0 || nd == 0 || n_wg <= 0 || n_bundles < 1 || n_wg < n_bundles) {
+        out.n_wg = 0;
+        out.wg_begin.assign(1, 0);
+        return;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return g.dirs[a].M > g.dirs[b].M; });
+
+    std::vector<std::vector<WorkItem>> per_wg(n_wg);
+    std::vector<std::vector<int32_t>> slots_of_lambda(nl);
+    int slot = 0;
+    for (int b = 0; b < n_bundles; ++b) {
+        std::vector<int> wgs;
+        for (int w = b; w < n_wg; w += n_bundles) wgs.push_back(w);
+        schedule_class(g, lambdas, order, wgs, per_wg, slots_of_lambda, slot);
+    }
+    // slots are numbered by workgroup id in the XCD-rounds case and densely otherwise
+    int n_slots = 0;
+    for (int li = 0; li < nl; ++li)
+        for (int s : slots_of_lambda[li]) n_slots = std::max(n_slots, s + 1);
+    out.n_slots = n_slots;
+    out.n_wg = n_wg;
     out.wg_begin.assign(out.n_wg + 1, 0);
     for (int w = 0; w < out.n_wg; ++w) {
         out.wg_begin[w + 1] = out.wg_begin[w] + (int32_t)per_wg[w].size();

@@ -218,3 +218,22 @@ def test_batched_64_wavelengths_full_size_sampled(orc):
         Jo, Lo = orc.fs_box_sampled(case.chi[l], S[l], case.I_bc[l, 0], case.I_bc[l, 1], case.n_mu, case.n_phi, vox)
         np.testing.assert_allclose(J[l].ravel()[vox], Jo, rtol=2e-5, atol=1e-6 * np.abs(Jo).max())
         np.testing.assert_allclose(L[l].ravel()[vox], Lo, rtol=2e-5, atol=1e-7)
+
+
+@pytest.mark.parametrize("prec,shape", [("f32", (512, 3)), ("f32", (512, 17)), ("f64", (512, 3)), ("f64", (512, 17))])
+def test_ray_bundle_shapes_match_single_workgroup_sweeps(orc, prec, shape):
+    """Shapes that split each direction's rays into two bundles (two workgroups
+    and two layer tiles per direction) give the oracle's J; against the default
+    one-workgroup sweep they differ only in the summation order."""
+    Nx, Ny = (40, 37) if shape[1] < 10 else (129, 129)
+    case = sy.random_box(Nx, Ny, 6, 4, 8, seed=85, dtype=prec)
+    S = sy.random_source(case.chi.shape, seed=86, dtype=prec)
+    g = make_grid(case)
+    J0, _ = gpu_fs(case, S, grid=g, want_lstar=False)
+    g.set_launch_shape(*shape)
+    J1, _ = gpu_fs(case, S, grid=g, want_lstar=False)
+    g.close()
+    tol = 1e-14 if prec == "f64" else 2e-6
+    np.testing.assert_allclose(J1, J0, rtol=tol, atol=tol * np.abs(J0).max())
+    Jo, _ = _oracle_fs(orc, case, S, "linear")
+    np.testing.assert_allclose(J1, Jo, rtol=1e-12 if prec == "f64" else 2e-5, atol=1e-6 * np.abs(Jo).max())
