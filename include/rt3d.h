@@ -73,6 +73,13 @@ typedef enum { RT_FP64 = 0, RT_FP32 = 1 } rt_prec;
 #define RT_F_LSTAR_PARABOLIC 0x1u /* Lambda* = exact diagonal of the parabolic
                                      formal solution; default: diagonal of the
                                      linear-interpolation operator            */
+#define RT_F_BAND_TILES 0x2u      /* box: accumulate J / Lambda* of a workgroup
+                                     in a band of rows of the layer instead of
+                                     the whole layer.  Used by itself for layers
+                                     whose tile does not fit the LDS of a CU
+                                     (e.g. 257 x 257); the flag forces it for
+                                     any box grid (results differ only in the
+                                     summation order).                         */
 
 typedef struct rt_grid *rt_grid_t;
 
@@ -355,6 +362,16 @@ rt_status rt_autotune(rt_grid_t grid, int32_t n_lambda, const void *chi, const v
  * anything.
  */
 rt_status rt_set_launch_shape(rt_grid_t grid, int32_t threads, int32_t rays);
+
+/*
+ * The launch shape that the grid's single-output formal-solution kernel
+ * uses now (box grids): workgroup size bound, rays per thread, ray bundles
+ * per direction (workgroups that share one direction, each with its own tile
+ * and partial sums), and band = 1 if the tiles are row bands
+ * (RT_F_BAND_TILES, or a layer too wide for a whole-layer tile in LDS), else
+ * 0.  Any out pointer may be NULL.  RT_E_UNSUPPORTED on spherical grids.
+ */
+rt_status rt_launch_shape(rt_grid_t grid, int32_t *threads, int32_t *rays, int32_t *bundles, int32_t *band);
 
 /*
  * Measurement hooks.  While enabled, every formal-solution kernel launch of

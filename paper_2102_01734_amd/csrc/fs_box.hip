@@ -21,6 +21,17 @@
 //
 // Fields are read from doubly periodic padded copies [Nz][2Ny][2Nx], so the
 // address of ray r at visit m is base_r + offset_m with no wrap arithmetic.
+//
+// Band tiles (layers too wide for LDS): the rays of a direction are split
+// into bundles of whole ray rows, and a workgroup's tile holds only the rows
+// that its bundle reaches within the current layer.  Within one layer the
+// template's row offsets span at most `span` rows (its horizontal travel per
+// layer), so rays of origin rows [yb, yb + h) land in the h + span + 1 rows
+// that start at yb + (lowest template row of the layer); the visit table
+// carries each visit's row relative to that lowest row.  The tile index is
+// then (origin row - yb + relative row) * Nx + x, and the flush maps tile
+// word i to layer word (base * Nx + i) mod NxNy.  The workgroup clears its
+// partial slot when it opens it, because a band touches only part of it.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -64,7 +75,7 @@ __device__ __forceinline__ Pair<double> ld_pair<double>(__amdgpu_buffer_rsrc_t r
 // ---------------------------------------------------------------------------
 // the sweep kernel
 // ---------------------------------------------------------------------------
-template <typename T, int LB, int R, bool WJ, bool WL, bool PARA, int OCC>
+template <typename T, int LB, int R, bool WJ, bool WL, bool PARA, int OCC, bool BAND>
 __global__ void __launch_bounds__(LB) __attribute__((amdgpu_waves_per_eu(OCC * LB / 256 > 0 ? OCC * LB / 256 : 1)))
 fs_box_kernel(FsBoxArgs a)
 {
@@ -73,13 +84,14 @@ fs_box_kernel(FsBoxArgs a)
     const int NxNy = Nx * Ny;
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
-    // tiles of NxNy words plus one scratch word per thread (padding slots)
+    // tiles of tile_words words plus one scratch word per thread (padding slots)
+    const int TW = a.tile_words;
     T *tJ = reinterpret_cast<T *>(smem_raw);
-    T *tL = tJ + (WJ ? NxNy + nthr : 0);
+    T *tL = tJ + (WJ ? TW + nthr : 0);
     constexpr int ES = 2 * (int)sizeof(T);  // bytes per (chi, S) pair
     constexpr int kPad = 1 << 31;          // xy0 flag: slot beyond the last ray
 
-    for (int i = tid; i < NxNy + nthr; i += nthr) {
+    for (int i = tid; i < TW + nthr; i += nthr) {
         if (WJ) tJ[i] = T(0);
         if (WL) tL[i] = T(0);
     }
@@ -95,9 +107,17 @@ fs_box_kernel(FsBoxArgs a)
     // be such a padding slot and the other R - 1 copies of the point body
     // carry no padding logic.
     const int bundle = a.n_bundles > 1 ? (int)(blockIdx.x % (unsigned)a.n_bundles) : 0;
-    const int q_lo = bundle * a.bundle_rays;
-    const int q_n = min(a.bundle_rays, NxNy - q_lo);
-    int xy0[R];    // x0 | y0 << 16 | kPad
+    int q_lo, q_n, yb = 0, hb = 0;
+    if (BAND) {
+        yb = (int)(((int64_t)bundle * Ny) / a.n_bundles);
+        hb = (int)(((int64_t)(bundle + 1) * Ny) / a.n_bundles) - yb;
+        q_lo = yb * Nx;
+        q_n = hb * Nx;
+    } else {
+        q_lo = bundle * a.bundle_rays;
+        q_n = min(a.bundle_rays, NxNy - q_lo);
+    }
+    int xy0[R];    // x0 | (y0 - yb) << 16 | kPad
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         int l = tid + j * nthr;
@@ -106,10 +126,13 @@ fs_box_kernel(FsBoxArgs a)
         const int q = q_lo + l;
         const int y0 = q / Nx;
         const int x0 = q - y0 * Nx;
-        xy0[j] = x0 | (y0 << 16) | pad;
+        xy0[j] = x0 | ((y0 - yb) << 16) | pad;
     }
-    // byte offset of ray j's origin in the padded field (recomputed: saves R registers)
+    // byte offset of ray j's origin in the padded field (recomputed: saves R
+    // registers); with band tiles the bundle's first row yb goes into the
+    // scalar (per visit) part of the address
     const uint32_t row_bytes = (uint32_t)(2 * Nx * ES);
+    const int gshift = BAND ? (int)((uint32_t)yb * row_bytes) : 0;
     auto vbase = [&](int j) {
         const uint32_t x0 = (uint32_t)xy0[j] & 0xffffu, y0 = ((uint32_t)xy0[j] >> 16) & 0x7fffu;
         return (int)(__umul24(y0, row_bytes) + x0 * ES);
@@ -135,49 +158,90 @@ fs_box_kernel(FsBoxArgs a)
         const int32_t *__restrict__ goff = a.goff + vb;
         const uint32_t *__restrict__ dxy = a.dxy + vb;
         const double *__restrict__ sv = a.s + vb;
+        const int32_t *__restrict__ brow = BAND ? a.brow + vb : nullptr;
+        const int span = BAND ? a.dir_span[d] : 0;
+
+        if (BAND && first) {
+            // a band touches only part of the slot: clear all of it once
+            for (int64_t i = tid; i < a.n_vox; i += nthr) {
+                if (WJ) pJ[i] = T(0);
+                if (WL) pL[i] = T(0);
+            }
+            __syncthreads();
+        }
 
         T I[R];
         T gprev[R];
         int layer = down ? 0 : a.Nz - 1;
         const int dlayer = down ? 1 : -1;
 
-        auto flush_layer = [&]() {
+        // w, r: offsets word and relative row of the layer's last visit
+        auto flush_layer = [&](uint32_t w, int r) {
             const int64_t lo = (int64_t)layer * NxNy;
-            for (int i = tid; i < NxNy; i += nthr) {
-                if (WJ) {
-                    const T v = tJ[i];
-                    tJ[i] = T(0);
-                    pJ[lo + i] = first ? v : pJ[lo + i] + v;
+            if (BAND) {
+                // tile row 0 is layer row yb + (lowest template row of the layer)
+                int base = (yb + (int)((w >> kOffBits) & kOffMask) - r) % Ny;
+                if (base < 0) base += Ny;
+                const uint32_t g0 = (uint32_t)base * (uint32_t)Nx;
+                const int n = (hb + span + 1) * Nx;
+                for (int i = tid; i < n; i += nthr) {
+                    uint32_t gi = g0 + (uint32_t)i;
+                    gi = min(gi, gi - (uint32_t)NxNy);
+                    if (WJ) {
+                        const T v = tJ[i];
+                        tJ[i] = T(0);
+                        pJ[lo + gi] += v;
+                    }
+                    if (WL) {
+                        const T v = tL[i];
+                        tL[i] = T(0);
+                        pL[lo + gi] += v;
+                    }
                 }
-                if (WL) {
-                    const T v = tL[i];
-                    tL[i] = T(0);
-                    pL[lo + i] = first ? v : pL[lo + i] + v;
+            } else {
+                for (int i = tid; i < NxNy; i += nthr) {
+                    if (WJ) {
+                        const T v = tJ[i];
+                        tJ[i] = T(0);
+                        pJ[lo + i] = first ? v : pJ[lo + i] + v;
+                    }
+                    if (WL) {
+                        const T v = tL[i];
+                        tL[i] = T(0);
+                        pL[lo + i] = first ? v : pL[lo + i] + v;
+                    }
                 }
             }
             layer += dlayer;
             __syncthreads();
         };
-        // tile index of ray j at a visit with horizontal offsets packed in w;
-        // wrap by an unsigned minimum (x - N underflows when x < N).  Padding
-        // slots go to this thread's own word past the tile, so no two lanes
-        // ever update the same word in one step.
-        auto tile_index = [&](int j, uint32_t w) {
+        // tile index of ray j at a visit with horizontal offsets packed in w
+        // (and, for band tiles, relative row r); wrap by an unsigned minimum
+        // (x - N underflows when x < N).  Padding slots go to this thread's own
+        // word past the tile, so no two lanes ever update the same word in one
+        // step.
+        auto tile_index = [&](int j, uint32_t w, int r) {
             const uint32_t x0 = (uint32_t)xy0[j] & 0xffffu, y0 = ((uint32_t)xy0[j] >> 16) & 0x7fffu;
             uint32_t xl = x0 + (w & kOffMask);
             xl = min(xl, xl - (uint32_t)Nx);
-            uint32_t yl = y0 + ((w >> kOffBits) & kOffMask);
-            yl = min(yl, yl - (uint32_t)Ny);
+            uint32_t yl;
+            if (BAND) {
+                yl = y0 + (uint32_t)r;
+            } else {
+                yl = y0 + ((w >> kOffBits) & kOffMask);
+                yl = min(yl, yl - (uint32_t)Ny);
+            }
             const int idx = (int)__umul24(yl, (uint32_t)Nx) + (int)xl;
-            return (j == R - 1 && xy0[j] < 0) ? NxNy + tid : idx;
+            return (j == R - 1 && xy0[j] < 0) ? TW + tid : idx;
         };
         // the visit weight, zero for a padding slot
         auto ray_weight = [&](int j, T cw) { return (j == R - 1 && xy0[j] < 0) ? T(0) : cw; };
 
         // first point: entry half-segment with constant S
-        int g_c = goff[0] * ES;
+        int g_c = goff[0] * ES + gshift;
         double s_c = sv[0];
         uint32_t w_c = dxy[0];
+        int r_c = BAND ? brow[0] : 0;
         {
             const T cw = T(wmu * s_c);
 #pragma unroll
@@ -187,13 +251,13 @@ fs_box_kernel(FsBoxArgs a)
                 T ex, e0;
                 entry_weights<T>(0.5 * seg_depth((double)fc.chi, s_c), ex, e0);
                 I[j] = WJ ? Ibc * ex + fc.S * e0 : T(0);
-                const int idx = tile_index(j, w_c);
+                const int idx = tile_index(j, w_c, r_c);
                 const T cj = ray_weight(j, cw);
                 if (WJ) tJ[idx] += cj * I[j];
                 if (WL) tL[idx] += cj * e0;
             }
             __syncthreads();
-            if (w_c & kLayerEnd) flush_layer();
+            if (w_c & kLayerEnd) flush_layer(w_c, r_c);
         }
 
         // one point of every ray of this thread; LAST: the final point, which
@@ -223,7 +287,7 @@ fs_box_kernel(FsBoxArgs a)
                 const double Dp = LAST ? 0.0 : half_sum(tc, seg_depth((double)fn.chi, s_n));
                 const PointW<T> pw = point_weights<T>(D, Dp, LAST);
                 if (WJ) I[j] = I[j] * pw.ex + pw.a * fp.S + pw.b * fc.S + (LAST ? T(0) : pw.g * fn.S);
-                const int idx = tile_index(j, w_c);
+                const int idx = tile_index(j, w_c, r_c);
                 const T cj = ray_weight(j, cw);
                 if (WJ) tJ[idx] += cj * I[j];
                 if (WL) {
@@ -238,17 +302,18 @@ fs_box_kernel(FsBoxArgs a)
                 }
             }
             __syncthreads();
-            if (w_c & kLayerEnd) flush_layer();
+            if (w_c & kLayerEnd) flush_layer(w_c, r_c);
         };
 
         for (int m = 1; m < M; ++m) {
             // window of template entries: previous (p), current (c), next (n)
             g_p = g_c; s_p = s_c;
-            g_c = goff[m] * ES;
+            g_c = goff[m] * ES + gshift;
             s_c = sv[m];
             w_c = dxy[m];
+            if (BAND) r_c = brow[m];
             if (m + 1 < M) {
-                g_n = goff[m + 1] * ES;
+                g_n = goff[m + 1] * ES + gshift;
                 s_n = sv[m + 1];
                 step(std::false_type{});
             } else {
@@ -269,18 +334,28 @@ fs_box_kernel(FsBoxArgs a)
 // Launch shapes (threads bound LB, rays per thread R, workgroups per CU OCC).
 // OCC = 2 shapes split each direction's rays into two bundles so that two
 // workgroups (two layer tiles) share a CU: twice the resident waves to hide
-// the latency of the double-precision point arithmetic.
+// the latency of the double-precision point arithmetic.  Band-tile shapes
+// serve layers too wide for a whole-layer tile (and grids that ask for band
+// tiles); their bundle count follows from the LDS left per workgroup.
 #define RT_FS_SHAPES_FULL(X) X(1024, 1, 1) X(1024, 2, 1) X(1024, 4, 1) X(1024, 8, 1) X(1024, 12, 1) X(1024, 17, 1) X(1024, 24, 1)
 #define RT_FS_SHAPES_TUNE(X)                                                                                     \
     X(768, 2, 1) X(768, 6, 1) X(768, 11, 1) X(768, 22, 1) X(768, 32, 1) X(512, 33, 1) X(256, 5, 1) X(256, 17, 1) \
         X(256, 34, 1) X(512, 3, 2) X(512, 9, 2) X(512, 17, 2)
+#define RT_FS_SHAPES_BAND_FULL(X) X(1024, 1, 1) X(1024, 2, 1) X(1024, 4, 1) X(1024, 8, 1) X(1024, 12, 1) X(1024, 17, 1)
+#define RT_FS_SHAPES_BAND_TUNE(X) X(768, 11, 1) X(768, 22, 1) X(512, 9, 2) X(512, 17, 2)
 
 static const FsShape kShapes[] = {
-#define RT_LIST(lb, r, o) {lb, r, true, o},
+#define RT_LIST(lb, r, o) {lb, r, true, o, false},
     RT_FS_SHAPES_FULL(RT_LIST)
 #undef RT_LIST
-#define RT_LIST(lb, r, o) {lb, r, false, o},
+#define RT_LIST(lb, r, o) {lb, r, false, o, false},
     RT_FS_SHAPES_TUNE(RT_LIST)
+#undef RT_LIST
+#define RT_LIST(lb, r, o) {lb, r, true, o, true},
+    RT_FS_SHAPES_BAND_FULL(RT_LIST)
+#undef RT_LIST
+#define RT_LIST(lb, r, o) {lb, r, false, o, true},
+    RT_FS_SHAPES_BAND_TUNE(RT_LIST)
 #undef RT_LIST
 };
 
@@ -290,92 +365,119 @@ int fs_box_shapes(const FsShape **out)
     return (int)(sizeof(kShapes) / sizeof(kShapes[0]));
 }
 
-template <typename T, int LB, int R, bool WJ, bool WL, bool PARA, int OCC>
+template <typename T, int LB, int R, bool WJ, bool WL, bool PARA, int OCC, bool BAND>
 static hipError_t launch_one(const FsBoxArgs &a, int n_wg, int nthr, size_t lds, hipStream_t st)
 {
-    auto k = fs_box_kernel<T, LB, R, WJ, WL, PARA, OCC>;
+    auto k = fs_box_kernel<T, LB, R, WJ, WL, PARA, OCC, BAND>;
     hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3(n_wg), dim3(nthr), lds, st, a);
     return hipGetLastError();
 }
 
-template <typename T, int LB, int R, bool WJ, bool WL, bool PARA, int OCC>
+template <typename T, int LB, int R, bool WJ, bool WL, bool PARA, int OCC, bool BAND>
 static int occ_one(int nthr, size_t lds)
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fs_box_kernel<T, LB, R, WJ, WL, PARA, OCC>, nthr, lds) !=
-        hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fs_box_kernel<T, LB, R, WJ, WL, PARA, OCC, BAND>, nthr,
+                                                     lds) != hipSuccess)
         return 0;
     return n;
 }
 
-template <typename T, int LB, int R, int OCC>
+template <typename T, int LB, int R, int OCC, bool BAND>
 static hipError_t launch_flags(const FsBoxArgs &a, bool wj, bool wl, bool para, int n_wg, int nthr, size_t lds,
                                hipStream_t st)
 {
-    if (wj && wl && para) return launch_one<T, LB, R, true, true, true, OCC>(a, n_wg, nthr, lds, st);
-    if (wj && wl) return launch_one<T, LB, R, true, true, false, OCC>(a, n_wg, nthr, lds, st);
-    if (wj) return launch_one<T, LB, R, true, false, false, OCC>(a, n_wg, nthr, lds, st);
-    if (wl && para) return launch_one<T, LB, R, false, true, true, OCC>(a, n_wg, nthr, lds, st);
-    if (wl) return launch_one<T, LB, R, false, true, false, OCC>(a, n_wg, nthr, lds, st);
+    if (wj && wl && para) return launch_one<T, LB, R, true, true, true, OCC, BAND>(a, n_wg, nthr, lds, st);
+    if (wj && wl) return launch_one<T, LB, R, true, true, false, OCC, BAND>(a, n_wg, nthr, lds, st);
+    if (wj) return launch_one<T, LB, R, true, false, false, OCC, BAND>(a, n_wg, nthr, lds, st);
+    if (wl && para) return launch_one<T, LB, R, false, true, true, OCC, BAND>(a, n_wg, nthr, lds, st);
+    if (wl) return launch_one<T, LB, R, false, true, false, OCC, BAND>(a, n_wg, nthr, lds, st);
     return hipSuccess;
 }
 
-template <typename T, int LB, int R, int OCC>
+template <typename T, int LB, int R, int OCC, bool BAND>
 static int occ_flags(bool wj, bool wl, bool para, int nthr, size_t lds)
 {
-    if (wj && wl && para) return occ_one<T, LB, R, true, true, true, OCC>(nthr, lds);
-    if (wj && wl) return occ_one<T, LB, R, true, true, false, OCC>(nthr, lds);
-    if (wj) return occ_one<T, LB, R, true, false, false, OCC>(nthr, lds);
-    if (wl && para) return occ_one<T, LB, R, false, true, true, OCC>(nthr, lds);
-    if (wl) return occ_one<T, LB, R, false, true, false, OCC>(nthr, lds);
+    if (wj && wl && para) return occ_one<T, LB, R, true, true, true, OCC, BAND>(nthr, lds);
+    if (wj && wl) return occ_one<T, LB, R, true, true, false, OCC, BAND>(nthr, lds);
+    if (wj) return occ_one<T, LB, R, true, false, false, OCC, BAND>(nthr, lds);
+    if (wl && para) return occ_one<T, LB, R, false, true, true, OCC, BAND>(nthr, lds);
+    if (wl) return occ_one<T, LB, R, false, true, false, OCC, BAND>(nthr, lds);
     return 0;
 }
 
 template <typename T>
-static hipError_t launch_t(const FsBoxArgs &a, bool wj, bool wl, bool para, int lb, int R, int n_wg, int nthr,
-                           size_t lds, hipStream_t st)
+static hipError_t launch_t(const FsBoxArgs &a, bool wj, bool wl, bool para, bool band, int lb, int R, int n_wg,
+                           int nthr, size_t lds, hipStream_t st)
 {
+    const bool j_only = wj && !wl;
+    if (!band) {
 #define RT_CASE(LBv, Rv, Ov) \
-    if (lb == LBv && R == Rv) return launch_flags<T, LBv, Rv, Ov>(a, wj, wl, para, n_wg, nthr, lds, st);
-    RT_FS_SHAPES_FULL(RT_CASE)
+    if (lb == LBv && R == Rv) return launch_flags<T, LBv, Rv, Ov, false>(a, wj, wl, para, n_wg, nthr, lds, st);
+        RT_FS_SHAPES_FULL(RT_CASE)
 #undef RT_CASE
-    if (!(wj && !wl)) return hipErrorInvalidValue;
+        if (!j_only) return hipErrorInvalidValue;
 #define RT_CASE(LBv, Rv, Ov) \
-    if (lb == LBv && R == Rv) return launch_one<T, LBv, Rv, true, false, false, Ov>(a, n_wg, nthr, lds, st);
-    RT_FS_SHAPES_TUNE(RT_CASE)
+    if (lb == LBv && R == Rv) return launch_one<T, LBv, Rv, true, false, false, Ov, false>(a, n_wg, nthr, lds, st);
+        RT_FS_SHAPES_TUNE(RT_CASE)
 #undef RT_CASE
+    } else {
+#define RT_CASE(LBv, Rv, Ov) \
+    if (lb == LBv && R == Rv) return launch_flags<T, LBv, Rv, Ov, true>(a, wj, wl, para, n_wg, nthr, lds, st);
+        RT_FS_SHAPES_BAND_FULL(RT_CASE)
+#undef RT_CASE
+        if (!j_only) return hipErrorInvalidValue;
+#define RT_CASE(LBv, Rv, Ov) \
+    if (lb == LBv && R == Rv) return launch_one<T, LBv, Rv, true, false, false, Ov, true>(a, n_wg, nthr, lds, st);
+        RT_FS_SHAPES_BAND_TUNE(RT_CASE)
+#undef RT_CASE
+    }
     return hipErrorInvalidValue;
 }
 
 template <typename T>
-static int occ_t(bool wj, bool wl, bool para, int lb, int R, int nthr, size_t lds)
+static int occ_t(bool wj, bool wl, bool para, bool band, int lb, int R, int nthr, size_t lds)
 {
+    const bool j_only = wj && !wl;
+    if (!band) {
 #define RT_CASE(LBv, Rv, Ov) \
-    if (lb == LBv && R == Rv) return occ_flags<T, LBv, Rv, Ov>(wj, wl, para, nthr, lds);
-    RT_FS_SHAPES_FULL(RT_CASE)
+    if (lb == LBv && R == Rv) return occ_flags<T, LBv, Rv, Ov, false>(wj, wl, para, nthr, lds);
+        RT_FS_SHAPES_FULL(RT_CASE)
 #undef RT_CASE
-    if (!(wj && !wl)) return 0;
+        if (!j_only) return 0;
 #define RT_CASE(LBv, Rv, Ov) \
-    if (lb == LBv && R == Rv) return occ_one<T, LBv, Rv, true, false, false, Ov>(nthr, lds);
-    RT_FS_SHAPES_TUNE(RT_CASE)
+    if (lb == LBv && R == Rv) return occ_one<T, LBv, Rv, true, false, false, Ov, false>(nthr, lds);
+        RT_FS_SHAPES_TUNE(RT_CASE)
 #undef RT_CASE
+    } else {
+#define RT_CASE(LBv, Rv, Ov) \
+    if (lb == LBv && R == Rv) return occ_flags<T, LBv, Rv, Ov, true>(wj, wl, para, nthr, lds);
+        RT_FS_SHAPES_BAND_FULL(RT_CASE)
+#undef RT_CASE
+        if (!j_only) return 0;
+#define RT_CASE(LBv, Rv, Ov) \
+    if (lb == LBv && R == Rv) return occ_one<T, LBv, Rv, true, false, false, Ov, true>(nthr, lds);
+        RT_FS_SHAPES_BAND_TUNE(RT_CASE)
+#undef RT_CASE
+    }
     return 0;
 }
 
-hipError_t fs_box_launch(const FsBoxArgs &a, bool is_double, bool want_j, bool want_l, bool para, int lb, int R,
-                         int n_wg, int nthr, size_t lds, hipStream_t st)
+hipError_t fs_box_launch(const FsBoxArgs &a, bool is_double, bool want_j, bool want_l, bool para, bool band, int lb,
+                         int R, int n_wg, int nthr, size_t lds, hipStream_t st)
 {
     if (n_wg <= 0) return hipSuccess;
-    return is_double ? launch_t<double>(a, want_j, want_l, para, lb, R, n_wg, nthr, lds, st)
-                     : launch_t<float>(a, want_j, want_l, para, lb, R, n_wg, nthr, lds, st);
+    return is_double ? launch_t<double>(a, want_j, want_l, para, band, lb, R, n_wg, nthr, lds, st)
+                     : launch_t<float>(a, want_j, want_l, para, band, lb, R, n_wg, nthr, lds, st);
 }
 
-int fs_box_occupancy(bool is_double, bool want_j, bool want_l, bool para, int lb, int R, int nthr, size_t lds)
+int fs_box_occupancy(bool is_double, bool want_j, bool want_l, bool para, bool band, int lb, int R, int nthr,
+                     size_t lds)
 {
-    return is_double ? occ_t<double>(want_j, want_l, para, lb, R, nthr, lds)
-                     : occ_t<float>(want_j, want_l, para, lb, R, nthr, lds);
+    return is_double ? occ_t<double>(want_j, want_l, para, band, lb, R, nthr, lds)
+                     : occ_t<float>(want_j, want_l, para, band, lb, R, nthr, lds);
 }
 
 }  // namespace rt3d

@@ -28,8 +28,15 @@ struct FsBoxArgs {
     const void *field;
     int64_t pad_stride;
     const void *I_bc;  // [lambda][2] or null
-    // ray bundles: workgroup w sweeps rays [b Q, min((b+1) Q, NxNy)), b = w mod n_bundles
+    // ray bundles, b = w mod n_bundles for workgroup w.  Layer tiles: workgroup
+    // w sweeps rays [b Q, min((b+1) Q, NxNy)), Q = bundle_rays, into a tile of
+    // the whole layer.  Band tiles: it sweeps the ray rows
+    // [b Ny / n_bundles, (b+1) Ny / n_bundles) into a tile of the rows that
+    // those rays reach within one layer (see fs_box.hip)
     int n_bundles, bundle_rays;
+    int tile_words;           // words of one tile (NxNy for layer tiles)
+    const int32_t *brow;      // per visit: row relative to the layer's lowest template row
+    const int32_t *dir_span;  // per direction: largest such relative row
     // partial sums [slot][n_vox]
     void *partJ;
     void *partL;
@@ -37,18 +44,19 @@ struct FsBoxArgs {
 
 // A compiled launch shape: workgroup size bound `lb`, rays per thread `R`;
 // `full`: available for every output combination (else J-only); `occ`: see
-// fs_box.hip.
+// fs_box.hip; `band`: band tiles instead of layer tiles.
 struct FsShape {
     int lb, R;
     bool full;
-    int occ;  // workgroups per CU the shape is compiled for (= ray bundles per direction)
+    int occ;  // workgroups per CU the shape is compiled for (layer tiles: = ray bundles per direction)
+    bool band;
 };
 int fs_box_shapes(const FsShape **out);
 
 hipError_t fs_box_launch(const FsBoxArgs &a, bool is_double, bool want_j, bool want_l, bool parabolic_lstar,
-                         int lb, int R, int n_wg, int nthr, size_t lds_bytes, hipStream_t stream);
+                         bool band, int lb, int R, int n_wg, int nthr, size_t lds_bytes, hipStream_t stream);
 
-int fs_box_occupancy(bool is_double, bool want_j, bool want_l, bool parabolic_lstar, int lb, int R, int nthr,
-                     size_t lds_bytes);
+int fs_box_occupancy(bool is_double, bool want_j, bool want_l, bool parabolic_lstar, bool band, int lb, int R,
+                     int nthr, size_t lds_bytes);
 
 }  // namespace rt3d

@@ -13,6 +13,7 @@
 // single correctly rounded division).  A crossing that follows the previous
 // recorded one by at most 1e-12 (t + 1) closes no segment: the voxel index
 // steps but no zero-length piece is stored.  The ray ends at the far face.
+#include <algorithm>
 #include <cmath>
 #include <limits>
 
@@ -105,6 +106,22 @@ std::string build_box_geometry(int Nx, int Ny, int Nz, int n_mu, int n_phi, BoxG
                 return "tracker did not visit every layer once";
             d.vbegin = (int64_t)g.s.size();
             d.M = M;
+            // row of each visit relative to the lowest row the template reaches in
+            // the same layer (the layer-band tiles of the sweep index by it)
+            std::vector<int32_t> rel((size_t)M);
+            d.span = 0;
+            for (int m0 = 0; m0 < M;) {
+                int m1 = m0;
+                int jlo = dj[m0], jhi = dj[m0];
+                while (m1 + 1 < M && kk[m1 + 1] == kk[m0]) {
+                    ++m1;
+                    jlo = std::min(jlo, dj[m1]);
+                    jhi = std::max(jhi, dj[m1]);
+                }
+                for (int m = m0; m <= m1; ++m) rel[(size_t)m] = dj[m] - jlo;
+                d.span = std::max(d.span, jhi - jlo);
+                m0 = m1 + 1;
+            }
             for (int m = 0; m < M; ++m) {
                 int a = di[m] % Nx; if (a < 0) a += Nx;
                 int b = dj[m] % Ny; if (b < 0) b += Ny;
@@ -115,6 +132,7 @@ std::string build_box_geometry(int Nx, int Ny, int Nz, int n_mu, int n_phi, BoxG
                 g.goff.push_back((int32_t)off);
                 g.dxy.push_back(w);
                 g.s.push_back(s[m]);
+                g.brow.push_back(rel[(size_t)m]);
                 g.di.push_back(di[m]);
                 g.dj.push_back(dj[m]);
                 g.kk.push_back(kk[m]);

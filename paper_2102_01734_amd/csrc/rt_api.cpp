@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstdlib>
 #include <cstdarg>
@@ -82,7 +83,9 @@ struct DevBuf {
 struct Variant {
     bool dbl = false, wj = false, wl = false;
     int lb = 0, R = 0, nthr = 0, n_wg = 0;
-    int nb = 1, Q = 0;  // ray bundles per direction and rays per bundle
+    int nb = 1, Q = 0;  // ray bundles per direction and rays per (largest) bundle
+    bool band = false;  // band tiles (bundles of whole ray rows) instead of layer tiles
+    int tile_words = 0;
     size_t lds = 0;
     bool ok = false;
 };
@@ -127,7 +130,9 @@ struct rt_grid {
     int n_dir = 0;
     int64_t n_visits = 0;
 
-    DevBuf goff, dxy, s, vbegin, M, wmu, mu;
+    DevBuf goff, dxy, s, vbegin, M, wmu, mu, brow, span;
+    int span_max = 0;   // largest per-layer row extent of any template
+    bool band = false;  // the box sweep uses band tiles (see fs_box.hip)
     Variant var[2][2][2];  // [dbl][wj][wl]
     bool tuned = false;
 
@@ -168,55 +173,98 @@ struct rt_grid {
 static Variant &variant(rt_grid *g, bool dbl, bool wj, bool wl) { return g->var[dbl][wj][wl]; }
 
 // Resident-workgroup count and LDS size of one launch shape; ok = false when
-// the shape cannot hold all rays of a direction or its tiles do not fit.
-static Variant make_variant(rt_grid *g, bool dbl, bool wj, bool wl, int lb, int R, int occ = 1)
+// the shape cannot hold all rays of a bundle or its tiles do not fit.
+static Variant make_variant(rt_grid *g, bool dbl, bool wj, bool wl, int lb, int R, int occ = 1, bool band = false)
 {
     Variant v;
-    v.dbl = dbl; v.wj = wj; v.wl = wl; v.lb = lb; v.R = R;
-    const int rays = g->geo.Nx * g->geo.Ny;
-    const int nb = occ;
-    const int Q = (rays + nb - 1) / nb;
-    const int q_last = rays - (nb - 1) * Q;  // the smallest bundle
-    if (q_last <= 0) return v;
-    v.nb = nb;
-    v.Q = Q;
-    const int need = (Q + R - 1) / R;
-    if (need > lb) return v;
-    v.nthr = std::min(lb, ((need + 63) / 64) * 64);
-    // the sweep kernel expects padding slots only in each thread's last ray slot
-    if ((int64_t)v.nthr * (R - 1) >= q_last) return v;
-    // per tile: one word per voxel of a layer plus one scratch word per thread
-    v.lds = (size_t)(rays + v.nthr) * (dbl ? 8 : 4) * ((wj ? 1 : 0) + (wl ? 1 : 0));
+    v.dbl = dbl; v.wj = wj; v.wl = wl; v.lb = lb; v.R = R; v.band = band;
+    const int Nx = g->geo.Nx, Ny = g->geo.Ny;
+    const int rays = Nx * Ny;
+    const size_t esz = dbl ? 8 : 4;
+    const size_t nout = (wj ? 1 : 0) + (wl ? 1 : 0);
+    // the padded field of one wavelength must stay addressable by 32-bit buffer offsets
+    if ((int64_t)4 * g->n_vox * 2 * (int64_t)esz > (int64_t)INT_MAX) return v;
+    if (!band) {
+        const int nb = occ;
+        const int Q = (rays + nb - 1) / nb;
+        const int q_last = rays - (nb - 1) * Q;  // the smallest bundle
+        if (q_last <= 0) return v;
+        v.nb = nb;
+        v.Q = Q;
+        const int need = (Q + R - 1) / R;
+        if (need > lb) return v;
+        v.nthr = std::min(lb, ((need + 63) / 64) * 64);
+        // the sweep kernel expects padding slots only in each thread's last ray slot
+        if ((int64_t)v.nthr * (R - 1) >= q_last) return v;
+        // per tile: one word per voxel of a layer plus one scratch word per thread
+        v.tile_words = rays;
+    } else {
+        // fewest bundles of whole rows (sizes Ny/nb rounded down or up) whose
+        // rays fit the shape and whose band tiles leave room for `occ`
+        // workgroups per CU
+        const int span = g->span_max;
+        bool found = false;
+        for (int nb = 2; nb <= Ny && !found; ++nb) {
+            const int H = (Ny + nb - 1) / nb, Hmin = Ny / nb;
+            if (H + span + 1 > Ny) continue;
+            const int64_t Q = (int64_t)H * Nx;
+            const int64_t need = (Q + R - 1) / R;
+            if (need > lb) continue;
+            const int nthr = std::min(lb, (int)((need + 63) / 64) * 64);
+            if ((int64_t)nthr * (R - 1) >= (int64_t)Hmin * Nx) continue;
+            const int tw = (H + span + 1) * Nx;
+            if ((size_t)(tw + nthr) * esz * nout * (size_t)occ > g->max_lds) continue;
+            v.nb = nb; v.Q = (int)Q; v.nthr = nthr; v.tile_words = tw;
+            found = true;
+        }
+        if (!found) return v;
+    }
+    v.lds = (size_t)(v.tile_words + v.nthr) * esz * nout;
     if (v.lds > g->max_lds) return v;
-    const int res = fs_box_occupancy(dbl, wj, wl, g->para, lb, R, v.nthr, v.lds);
+    const int res = fs_box_occupancy(dbl, wj, wl, g->para, band, lb, R, v.nthr, v.lds);
     if (res <= 0) return v;
     v.n_wg = res * g->n_cu;
-    v.n_wg -= v.n_wg % nb;  // equal classes of workgroups per bundle
-    if (v.n_wg < nb) return v;
+    v.n_wg -= v.n_wg % v.nb;  // equal classes of workgroups per bundle
+    if (v.n_wg < v.nb) return v;
     v.ok = true;
     return v;
 }
 
-// Default shape: 1024-thread workgroups with the fewest rays per thread.
+// Default shape: 1024-thread workgroups.  Layer tiles: the fewest rays per
+// thread.  Band tiles: the fewest bundles (widest bands, least flush traffic
+// per ray), then the fewest rays per thread.
 static void setup_variant(rt_grid *g, bool dbl, bool wj, bool wl)
 {
     const FsShape *sh = nullptr;
     const int n = fs_box_shapes(&sh);
-    variant(g, dbl, wj, wl) = Variant();
+    Variant &best = variant(g, dbl, wj, wl);
+    best = Variant();
     for (int i = 0; i < n; ++i) {
-        if (!sh[i].full || sh[i].lb != 1024) continue;
-        Variant v = make_variant(g, dbl, wj, wl, sh[i].lb, sh[i].R);
-        if (v.ok) { variant(g, dbl, wj, wl) = v; return; }
+        if (!sh[i].full || sh[i].lb != 1024 || sh[i].band != g->band) continue;
+        Variant v = make_variant(g, dbl, wj, wl, sh[i].lb, sh[i].R, sh[i].occ, sh[i].band);
+        if (!v.ok) continue;
+        if (!g->band) { best = v; return; }
+        if (!best.ok || v.nb < best.nb) best = v;
     }
+}
+
+// Rays swept by the workgroups of bundle b of a launch.
+static int64_t bundle_ray_count(const rt_grid *g, const Variant *v, int b)
+{
+    const int64_t Nx = g->geo.Nx, Ny = g->geo.Ny;
+    if (!v || v->nb <= 1) return Nx * Ny;
+    if (v->band) return ((int64_t)(b + 1) * Ny / v->nb - (int64_t)b * Ny / v->nb) * Nx;
+    return std::min<int64_t>(v->Q, Nx * Ny - (int64_t)b * v->Q);
 }
 
 // ---------------------------------------------------------------------------
 // schedules
 // ---------------------------------------------------------------------------
 static rt_status get_schedule(rt_grid *g, int n_wg, const std::vector<int32_t> &lambdas, DevSchedule **out,
-                              const std::vector<int32_t> *subset = nullptr, int nb = 1, int Q = 0)
+                              const std::vector<int32_t> *subset = nullptr, const Variant *v = nullptr)
 {
-    std::string key = std::to_string(n_wg) + "/" + std::to_string(nb) + ":";
+    const int nb = v ? v->nb : 1;
+    std::string key = std::to_string(n_wg) + "/" + std::to_string(nb) + (v && v->band ? "b" : "") + ":";
     for (int l : lambdas) key += std::to_string(l) + ",";
     if (subset) {
         key += "|d";
@@ -240,10 +288,8 @@ static rt_status get_schedule(rt_grid *g, int n_wg, const std::vector<int32_t> &
         ds->points = g->n_visits * nb;
     } else {
         build_schedule(g->geo, lambdas, n_wg, sc, subset, nb);
-        const int64_t rays = (int64_t)g->geo.Nx * g->geo.Ny;
         for (int w = 0; w < sc.n_wg; ++w) {
-            const int64_t q_lo = nb > 1 ? (int64_t)(w % nb) * Q : 0;
-            const int64_t nr = nb > 1 ? std::min<int64_t>(Q, rays - q_lo) : rays;
+            const int64_t nr = bundle_ray_count(g, v, w % nb);
             for (int k = sc.wg_begin[w]; k < sc.wg_begin[w + 1]; ++k)
                 ds->points += (int64_t)g->geo.dirs[sc.items[k].dir].M * nr;
         }
@@ -345,7 +391,7 @@ static rt_status run_fs_with(rt_grid *g, const Variant &v, const std::vector<int
     if (!v.ok) return fail(RT_E_UNSUPPORTED, "no kernel configuration fits this grid (layer tile of %d voxels)",
                            g->geo.Nx * g->geo.Ny);
     DevSchedule *sc = nullptr;
-    rt_status rs = get_schedule(g, v.n_wg, lambdas, &sc, subset, v.nb, v.Q);
+    rt_status rs = get_schedule(g, v.n_wg, lambdas, &sc, subset, &v);
     if (rs != RT_OK) return rs;
     const size_t esz = dbl ? 8 : 4;
     if (wj) HIPCHK(partJ.ensure((size_t)sc->n_slots * g->n_vox * esz));
@@ -369,17 +415,20 @@ static rt_status run_fs_with(rt_grid *g, const Variant &v, const std::vector<int
     a.partL = wl ? partL.p : nullptr;
     a.n_bundles = v.nb;
     a.bundle_rays = v.Q;
+    a.tile_words = v.tile_words;
+    a.brow = g->brow.as<int32_t>();
+    a.dir_span = g->span.as<int32_t>();
     if (g->prof) {
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
         HIPCHK(hipEventRecord(e0, st));
-        HIPCHK(fs_box_launch(a, dbl, wj, wl, g->para, v.lb, v.R, sc->n_wg, v.nthr, v.lds, st));
+        HIPCHK(fs_box_launch(a, dbl, wj, wl, g->para, v.band, v.lb, v.R, sc->n_wg, v.nthr, v.lds, st));
         HIPCHK(hipEventRecord(e1, st));
         g->prof_events.push_back({e0, e1});
         g->prof_points += sc->points;
     } else {
-        HIPCHK(fs_box_launch(a, dbl, wj, wl, g->para, v.lb, v.R, sc->n_wg, v.nthr, v.lds, st));
+        HIPCHK(fs_box_launch(a, dbl, wj, wl, g->para, v.band, v.lb, v.R, sc->n_wg, v.nthr, v.lds, st));
     }
     *sched_out = sc;
     return RT_OK;
@@ -686,7 +735,10 @@ rt_status rt_create_grid(const rt_grid_desc *desc, rt_grid_t *out)
         return fail(RT_E_INVALID, "unknown geometry %d", desc->geom);
     if (desc->prec != RT_FP32 && desc->prec != RT_FP64) return fail(RT_E_INVALID, "unknown precision %d", desc->prec);
     if (desc->n_lambda_max < 1) return fail(RT_E_INVALID, "n_lambda_max must be >= 1");
-    if (desc->flags & ~RT_F_LSTAR_PARABOLIC) return fail(RT_E_INVALID, "unknown flags 0x%x", desc->flags);
+    if (desc->flags & ~(RT_F_LSTAR_PARABOLIC | RT_F_BAND_TILES))
+        return fail(RT_E_INVALID, "unknown flags 0x%x", desc->flags);
+    if (desc->geom == RT_GEOM_SPHERICAL && (desc->flags & RT_F_BAND_TILES))
+        return fail(RT_E_INVALID, "RT_F_BAND_TILES applies to box grids only");
     if (desc->geom == RT_GEOM_SPHERICAL) {
         const int64_t nv = (int64_t)desc->n[0] * desc->n[1] * desc->n[2];
         if (desc->n[0] < 1 || desc->n[1] < 1 || desc->n[2] < 1) return fail(RT_E_INVALID, "grid sizes must be >= 1");
@@ -759,12 +811,16 @@ rt_status rt_create_grid(const rt_grid_desc *desc, rt_grid_t *out)
     HIPCHK(hipMemcpy(g->goff.p, g->geo.goff.data(), nvis * 4, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(g->dxy.p, g->geo.dxy.data(), nvis * 4, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(g->s.p, g->geo.s.data(), nvis * 8, hipMemcpyHostToDevice));
+    HIPCHK(g->brow.ensure(nvis * 4));
+    HIPCHK(hipMemcpy(g->brow.p, g->geo.brow.data(), nvis * 4, hipMemcpyHostToDevice));
     std::vector<int64_t> vb(g->n_dir);
-    std::vector<int32_t> Ms(g->n_dir);
+    std::vector<int32_t> Ms(g->n_dir), sp(g->n_dir);
     std::vector<double> wmu(g->n_dir), mu(g->n_dir);
     for (int d = 0; d < g->n_dir; ++d) {
         vb[d] = g->geo.dirs[d].vbegin;
         Ms[d] = g->geo.dirs[d].M;
+        sp[d] = g->geo.dirs[d].span;
+        g->span_max = std::max(g->span_max, sp[d]);
         wmu[d] = g->geo.dirs[d].w * std::fabs(g->geo.dirs[d].mu);
         mu[d] = g->geo.dirs[d].mu;
     }
@@ -776,16 +832,30 @@ rt_status rt_create_grid(const rt_grid_desc *desc, rt_grid_t *out)
     HIPCHK(hipMemcpy(g->M.p, Ms.data(), g->n_dir * 4, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(g->wmu.p, wmu.data(), g->n_dir * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(g->mu.p, mu.data(), g->n_dir * 8, hipMemcpyHostToDevice));
+    HIPCHK(g->span.ensure(g->n_dir * 4));
+    HIPCHK(hipMemcpy(g->span.p, sp.data(), g->n_dir * 4, hipMemcpyHostToDevice));
 
-    for (int d = 0; d < 2; ++d)
-        for (int j = 0; j < 2; ++j)
-            for (int l = 0; l < 2; ++l)
-                if (j || l) setup_variant(g.get(), d, j, l);
-    const bool self_ok = variant(g.get(), g->dbl, true, false).ok && variant(g.get(), g->dbl, false, true).ok;
-    const bool anchor_ok = g->dbl || variant(g.get(), true, true, false).ok;
-    if (!self_ok || !anchor_ok)
-        return fail(RT_E_UNSUPPORTED, "layer of %d x %d voxels does not fit the on-chip tile (%zu bytes of LDS)",
-                    g->geo.Nx, g->geo.Ny, g->max_lds);
+    // whole-layer tiles where they fit, else (or when asked for) band tiles
+    auto setup_all = [&]() {
+        for (int d = 0; d < 2; ++d)
+            for (int j = 0; j < 2; ++j)
+                for (int l = 0; l < 2; ++l)
+                    if (j || l) setup_variant(g.get(), d, j, l);
+        const bool self_ok = variant(g.get(), g->dbl, true, false).ok && variant(g.get(), g->dbl, false, true).ok;
+        const bool anchor_ok = g->dbl || variant(g.get(), true, true, false).ok;
+        return self_ok && anchor_ok;
+    };
+    g->band = (desc->flags & RT_F_BAND_TILES) != 0;
+    bool ok = setup_all();
+    if (!ok && !g->band) {
+        g->band = true;
+        ok = setup_all();
+    }
+    if (!ok)
+        return fail(RT_E_UNSUPPORTED,
+                    "layer of %d x %d voxels (row span %d per layer) fits neither a layer tile nor a band tile in "
+                    "%zu bytes of LDS",
+                    g->geo.Nx, g->geo.Ny, g->span_max, g->max_lds);
     *out = g.release();
     g_err.clear();
     return RT_OK;
@@ -831,7 +901,8 @@ rt_status rt_autotune(rt_grid_t g, int32_t n_lambda, const void *chi, const void
     g->prof = false;
     rt_status rs = RT_OK;
     for (int i = 0; i < n && rs == RT_OK; ++i) {
-        const Variant v = make_variant(g, dbl, true, false, sh[i].lb, sh[i].R, sh[i].occ);
+        if (sh[i].band != g->band) continue;
+        const Variant v = make_variant(g, dbl, true, false, sh[i].lb, sh[i].R, sh[i].occ, sh[i].band);
         if (!v.ok) continue;
         DevSchedule *sc = nullptr;
         DevBuf &pJ = dbl ? g->partJ64 : g->partJ;
@@ -867,8 +938,8 @@ rt_status rt_set_launch_shape(rt_grid_t g, int32_t threads, int32_t rays)
     const FsShape *sh = nullptr;
     const int n = fs_box_shapes(&sh);
     for (int i = 0; i < n; ++i) {
-        if (sh[i].lb != threads || sh[i].R != rays) continue;
-        const Variant v = make_variant(g, g->dbl, true, false, threads, rays, sh[i].occ);
+        if (sh[i].lb != threads || sh[i].R != rays || sh[i].band != g->band) continue;
+        const Variant v = make_variant(g, g->dbl, true, false, threads, rays, sh[i].occ, sh[i].band);
         if (!v.ok)
             return fail(RT_E_INVALID, "shape %d x %d cannot hold the %d rays of a direction on this device", threads,
                         rays, g->geo.Nx * g->geo.Ny);
@@ -877,6 +948,18 @@ rt_status rt_set_launch_shape(rt_grid_t g, int32_t threads, int32_t rays)
         return RT_OK;
     }
     return fail(RT_E_INVALID, "no compiled launch shape %d threads x %d rays", threads, rays);
+}
+
+rt_status rt_launch_shape(rt_grid_t g, int32_t *threads, int32_t *rays, int32_t *bundles, int32_t *band)
+{
+    if (!g) return fail(RT_E_INVALID, "grid is NULL");
+    if (g->sphere) return fail(RT_E_UNSUPPORTED, "launch shapes apply to the box sweep only");
+    const Variant &v = variant(g, g->dbl, true, false);
+    if (threads) *threads = v.lb;
+    if (rays) *rays = v.R;
+    if (bundles) *bundles = v.nb;
+    if (band) *band = v.band ? 1 : 0;
+    return RT_OK;
 }
 
 rt_status rt_profile_enable(rt_grid_t g, int32_t enable)
@@ -1116,7 +1199,7 @@ static rt_status graph_plain_step(rt_grid *g, rt_state *s, const std::vector<int
 {
     const Variant &v = variant(g, g->dbl, true, false);
     DevSchedule *sc = nullptr;
-    rt_status rs = get_schedule(g, v.n_wg, lams, &sc, nullptr, v.nb, v.Q);
+    rt_status rs = get_schedule(g, v.n_wg, lams, &sc, nullptr, &v);
     if (rs != RT_OK) return rs;
     DevBuf &pJ = g->dbl ? g->partJ64 : g->partJ;
     HIPCHK(pJ.ensure((size_t)sc->n_slots * g->n_vox * (g->dbl ? 8 : 4)));

@@ -23,6 +23,7 @@ struct Direction {
     double n[3] = {0, 0, 0};
     int64_t vbegin = 0;  // first visit of the template in the visit table
     int32_t M = 0;       // number of visits (segments) of every ray
+    int32_t span = 0;    // largest row extent (max dj - min dj) of the template within one layer
 };
 
 // Characteristic templates of all directions (the geometry cache).  All rays
@@ -35,6 +36,7 @@ struct BoxGeometry {
     std::vector<int32_t> goff;   // offset in the doubly periodic padded field
     std::vector<uint32_t> dxy;   // di mod Nx | (dj mod Ny) << 15 | layer-end flag
     std::vector<double> s;       // path length inside the voxel
+    std::vector<int32_t> brow;   // dj - (smallest dj of the visits in the same layer)
     std::vector<int32_t> di, dj, kk;  // unwrapped offsets and layer (tests, tools)
 };
 

@@ -17,6 +17,7 @@ RT_OK, RT_E_INVALID, RT_E_NOMEM, RT_E_HIP, RT_E_NOT_CONVERGED, RT_E_NUMERIC, RT_
 RT_GEOM_BOX_PERIODIC_XY, RT_GEOM_SPHERICAL = 0, 1
 RT_FP64, RT_FP32 = 0, 1
 RT_F_LSTAR_PARABOLIC = 0x1
+RT_F_BAND_TILES = 0x2
 
 STATUS_NAMES = {0: "RT_OK", 1: "RT_E_INVALID", 2: "RT_E_NOMEM", 3: "RT_E_HIP", 4: "RT_E_NOT_CONVERGED",
                 5: "RT_E_NUMERIC", 6: "RT_E_UNSUPPORTED"}
@@ -83,6 +84,8 @@ def lib() -> ctypes.CDLL:
     L.rt_autotune.restype = ctypes.c_int
     L.rt_set_launch_shape.argtypes = [vp, i32, i32]
     L.rt_set_launch_shape.restype = ctypes.c_int
+    L.rt_launch_shape.argtypes = [vp] + [ctypes.POINTER(i32)] * 4
+    L.rt_launch_shape.restype = ctypes.c_int
     L.rt_profile_enable.argtypes = [vp, i32]
     L.rt_profile_enable.restype = ctypes.c_int
     L.rt_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32), i64p]
@@ -174,6 +177,13 @@ def rt_autotune(grid: int, n_lambda: int, chi: int, S: int, stream: Optional[int
 
 def rt_set_launch_shape(grid: int, threads: int, rays: int) -> None:
     _check(lib().rt_set_launch_shape(ctypes.c_void_p(grid), int(threads), int(rays)), "rt_set_launch_shape")
+
+
+def rt_launch_shape(grid: int) -> dict:
+    """Launch shape of the single-output sweep: threads, rays, bundles, band (bool)."""
+    v = [ctypes.c_int32() for _ in range(4)]
+    _check(lib().rt_launch_shape(ctypes.c_void_p(grid), *[ctypes.byref(x) for x in v]), "rt_launch_shape")
+    return dict(threads=v[0].value, rays=v[1].value, bundles=v[2].value, band=bool(v[3].value))
 
 
 def rt_profile_enable(grid: int, enable: bool) -> None:
@@ -281,7 +291,7 @@ class Grid:
     (n_lambda, Nz, Ny, Nx), of dtype float32 (prec "f32") or float64 ("f64")."""
 
     def __init__(self, Nx: int, Ny: int, Nz: int, n_mu: int, n_phi: int, prec: str = "f32",
-                 n_lambda_max: int = 1, lstar: str = "linear"):
+                 n_lambda_max: int = 1, lstar: str = "linear", band_tiles: bool = False):
         d = RtGridDesc()
         d.struct_size = ctypes.sizeof(RtGridDesc)
         d.geom = RT_GEOM_BOX_PERIODIC_XY
@@ -289,7 +299,7 @@ class Grid:
         d.n_mu, d.n_phi = n_mu, n_phi
         d.n_lambda_max = n_lambda_max
         d.prec = RT_FP32 if prec == "f32" else RT_FP64
-        d.flags = RT_F_LSTAR_PARABOLIC if lstar == "parabolic" else 0
+        d.flags = (RT_F_LSTAR_PARABOLIC if lstar == "parabolic" else 0) | (RT_F_BAND_TILES if band_tiles else 0)
         self.desc = d
         self.shape = (Nz, Ny, Nx)
         self.nbc = 2
@@ -363,6 +373,10 @@ class Grid:
 
     def set_launch_shape(self, threads, rays):
         rt_set_launch_shape(self.handle, threads, rays)
+
+    def launch_shape(self):
+        """dict(threads, rays, bundles, band) of the single-output sweep."""
+        return rt_launch_shape(self.handle)
 
     def new_state(self, chi, eps, B, I_bc=None, J0=None):
         """Allocates the ALI state (J, S, Lambda*, norms) for a batch; J starts at B."""

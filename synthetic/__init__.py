@@ -144,6 +144,13 @@ def box_lognormal(N: int = 129, Nz: Optional[int] = None, n_mu: int = 32, n_phi:
     return BoxCase(name, N, Ny, Nz, n_mu, n_phi, chi, e, B, I_bc, dtype, tol=1e-8)
 
 
+def box_lognormal257(dtype: str = "f32") -> BoxCase:
+    """The 257^3 box with 32x16 directions: the log-normal recipe of box_lognormal
+    with its own seeds (field 4, eps 104)."""
+    return box_lognormal(N=257, n_mu=32, n_phi=16, field_seed=4, eps_seed=104, dtype=dtype,
+                         name="box-lognormal-257")
+
+
 def box_batched(N: int = 129, Nz: Optional[int] = None, n_lambda: int = 64, n_mu: int = 32,
                 n_phi: int = 32, scale_seed: int = 2, eps_seed: int = 102, field_seed: int = 1,
                 dtype: str = "f32", name: str = "box-batched") -> BoxCase:

@@ -14,14 +14,14 @@ def to_dev(a, prec):
     return torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
 
 
-def make_grid(case, n_lambda_max=None, lstar="linear", prec=None):
+def make_grid(case, n_lambda_max=None, lstar="linear", prec=None, band_tiles=False):
     import paper_2102_01734_amd as rt
     if hasattr(case, "Nr"):
         return rt.SphereGrid(case.Nr, case.Nt, case.Np, case.r_core, case.r_out, case.n_mu, case.n_phi,
                              prec or case.dtype, n_lambda_max or case.n_lambda, lstar=lstar,
                              source_distance=case.source_distance)
     return rt.Grid(case.Nx, case.Ny, case.Nz, case.n_mu, case.n_phi, prec or case.dtype,
-                   n_lambda_max or case.n_lambda, lstar=lstar)
+                   n_lambda_max or case.n_lambda, lstar=lstar, band_tiles=band_tiles)
 
 
 def gpu_fs(case, S, lstar="linear", want_lstar=True, prec=None, grid=None, I_bc=None):

@@ -187,20 +187,21 @@ def test_set_launch_shape(orc):
 def test_largest_layer_tile(orc, prec):
     """140 x 140 = 19600 voxels per layer is the largest square layer whose
     double tile (plus one scratch word for each of the 832 threads that hold
-    its rays, 24 per thread) fits the 160 KiB of LDS of a CU: it runs and
-    matches the oracle; 141 x 141 is refused."""
-    import paper_2102_01734_amd as rt
-    case = sy.random_box(140, 140, 3, 2, 4, seed=61, dtype=prec)
-    S = sy.random_source(case.chi.shape, seed=62, dtype=prec)
-    print(f"largest tile {prec}", flush=True)
-    J, L = gpu_fs(case, S)
-    Jo, Lo = _oracle_fs(orc, case, S, "linear")
-    tol = 1e-12 if prec == "f64" else 2e-5
-    np.testing.assert_allclose(J, Jo, rtol=tol, atol=tol * 0.05 * np.abs(Jo).max())
-    np.testing.assert_allclose(L, Lo, rtol=tol, atol=tol * 0.005)
-    with pytest.raises(rt.RtError) as e:
-        rt.Grid(141, 141, 3, 2, 4, prec)
-    assert e.value.status == rt.rt3d.RT_E_UNSUPPORTED
+    its rays, 24 per thread) fits the 160 KiB of LDS of a CU: it runs on
+    layer tiles and matches the oracle; 141 x 141 switches to band tiles and
+    matches the oracle as well."""
+    for N, band in ((140, False), (141, True)):
+        case = sy.random_box(N, N, 3, 2, 4, seed=61, dtype=prec)
+        S = sy.random_source(case.chi.shape, seed=62, dtype=prec)
+        print(f"largest tile {prec} {N}", flush=True)
+        g = make_grid(case)
+        assert g.launch_shape()["band"] == band
+        J, L = gpu_fs(case, S, grid=g)
+        g.close()
+        Jo, Lo = _oracle_fs(orc, case, S, "linear")
+        tol = 1e-12 if prec == "f64" else 2e-5
+        np.testing.assert_allclose(J, Jo, rtol=tol, atol=tol * 0.05 * np.abs(Jo).max())
+        np.testing.assert_allclose(L, Lo, rtol=tol, atol=tol * 0.005)
 
 
 def test_batched_64_wavelengths_full_size_sampled(orc):
