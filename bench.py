@@ -37,6 +37,8 @@ PEAK_TFLOPS = 78.6
 WORKLOADS = {
     "lognormal129": dict(N=129, n_mu=32, n_phi=64),
     "lognormal65": dict(N=65, n_mu=16, n_phi=32),
+    # the 257^3 box (band tiles: a 257 x 257 layer does not fit one LDS tile; not the default line)
+    "lognormal257": dict(N=257, n_mu=32, n_phi=16, field_seed=4, eps_seed=104),
     # 64 wavelengths of uneven optical depth in one launch per step (not the default line)
     "batched129": dict(N=129, n_mu=32, n_phi=32, n_lambda=64),
     # irradiated spherical shell, 16 wavelengths (not the default line)
@@ -236,7 +238,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="lognormal129", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-dirs", type=int, default=192, help="directions in the CPU-baseline sample")
+    ap.add_argument("--cpu-dirs", type=int, default=None,
+                    help="directions in the CPU-baseline sample (default: about 4e8 voxel-directions)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-solution comparison")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
@@ -272,7 +275,8 @@ def main():
     if "n_lambda" in w:
         case = sy.box_batched(N=w["N"], n_lambda=w["n_lambda"], n_mu=w["n_mu"], n_phi=w["n_phi"])
     else:
-        case = sy.box_lognormal(N=w["N"], n_mu=w["n_mu"], n_phi=w["n_phi"])
+        case = sy.box_lognormal(N=w["N"], n_mu=w["n_mu"], n_phi=w["n_phi"], field_seed=w.get("field_seed", 1),
+                                eps_seed=w.get("eps_seed", 101))
     dev = dict(dtype=torch.float32, device="cuda")
     chi = torch.tensor(case.chi, **dev)
     eps = torch.tensor(case.eps, **dev)
@@ -288,6 +292,7 @@ def main():
         shape = g.autotune(chi[:1].contiguous(), S0[:1].contiguous()) if not args.no_autotune else None
     del S0
     info = g.info()
+    ls = g.launch_shape()
     st = g.new_state(chi, eps, B, Ibc)
     opts = g.opts(tol=1e-30, max_iter=1, ng_every=4, ng_start=4)
 
@@ -338,7 +343,8 @@ def main():
             "voxels": case.n_vox, "directions": case.n_dir, "wavelengths": case.n_lambda,
             "vdu_per_step": vdu_per_step, "visits_per_vdu": fs_points / max(fs_launches, 1) / vdu_per_step,
             "workgroups": info["n_workgroups"],
-            "launch_shape": {"threads": shape[0], "rays_per_thread": shape[1]} if shape else "default",
+            "launch_shape": {"threads": ls["threads"], "rays_per_thread": ls["rays"], "bundles": ls["bundles"],
+                             "tiles": "band" if ls["band"] else "layer"},
         },
         "roofline": {
             "bound": "alu",
@@ -363,7 +369,8 @@ def main():
     if not args.no_solve and case.n_lambda == 1:
         out["time_to_solution"] = time_to_solution(case)
     if not args.no_cpu_baseline and case.n_lambda == 1:
-        out["cpu_baseline"] = cpu_baseline(case, args.cpu_dirs)
+        n_sub = args.cpu_dirs or max(8, min(case.n_dir, round(4.1e8 / case.n_vox)))
+        out["cpu_baseline"] = cpu_baseline(case, n_sub)
     print(json.dumps(out), flush=True)
 
 
