@@ -11,6 +11,9 @@ What it follows (Hauschildt & Baron, arXiv 2102.01734):
   * operator splitting [1 - Lambda*(1-eps)] J_new = J_fs - Lambda*(1-eps) J_old
                                                                   -- Sec. 2.2, eq. (alo)
   * Lambda* = Lambda is a direct solution by matrix inversion    -- Sec. 2.2
+  * the non-local (nearest-neighbour) Lambda*: Lambda restricted to the 27
+    neighbours of each voxel, the OS system then solved as a sparse system
+                                                                  -- Sec. 2.2, Sec. 3
   * BiCGStab as the linear solver                                 -- Sec. 4 ("Method")
   * the per-point steps of the formal solution                    -- Listing 1, steps 1-5
 Ng acceleration (Ng 1974, Auer 1987) is not in the paper; it is written here
@@ -65,6 +68,12 @@ def lib():
         L.orc_fs_box_dirs.argtypes = [ctypes.c_int] * 5 + [_dp, _dp, ctypes.c_double, ctypes.c_double,
                                                            ctypes.c_int, ctypes.c_int, _ip, _dp, _dp, ctypes.c_int]
         L.orc_fs_box_dirs.restype = ctypes.c_int
+        L.orc_ray_op.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_double, _dp]
+        L.orc_fs_box_op.argtypes = [ctypes.c_int] * 5 + [_dp, _dp, ctypes.c_double, ctypes.c_double,
+                                                         ctypes.c_int, _dp]
+        L.orc_fs_box_op.restype = ctypes.c_int
+        L.orc_lstar_stencil_box.argtypes = [ctypes.c_int] * 5 + [_dp, ctypes.c_int, _dp, ctypes.c_int]
+        L.orc_lstar_stencil_box.restype = ctypes.c_int
         L.orc_fs_box_sampled.argtypes = [ctypes.c_int] * 5 + [_dp, _dp, ctypes.c_double, ctypes.c_double,
                                                               ctypes.c_int, ctypes.c_int, _lp, _dp, _dp,
                                                               ctypes.c_int]
@@ -196,6 +205,59 @@ def fs_box(chi, S, I_top: float, I_bot: float, n_mu: int, n_phi: int, kind: str 
     if rc != 0:
         raise RuntimeError(f"orc_fs_box failed ({rc})")
     return J, L
+
+
+def fs_box_op(chi, S, I_top: float, I_bot: float, n_mu: int, n_phi: int, op: str = "parabolic"):
+    """J = Lambda_op S (+ boundary term): op "parabolic" is the formal solution
+    itself, op "linear" the linear-interpolation operator (single thread)."""
+    chi = _f64(chi); S = _f64(S)
+    Nz, Ny, Nx = chi.shape
+    J = np.zeros_like(chi)
+    rc = lib().orc_fs_box_op(Nx, Ny, Nz, n_mu, n_phi, _d(chi), _d(S), float(I_top), float(I_bot),
+                             _KINDS[op], _d(J))
+    if rc != 0:
+        raise RuntimeError(f"orc_fs_box_op failed ({rc})")
+    return J
+
+
+def ray_op(tau, S, I_bc: float, op: str = "parabolic"):
+    """One characteristic of operator op: intensities at its points."""
+    tau = _f64(tau); S = _f64(S)
+    I = np.zeros_like(tau)
+    lib().orc_ray_op(_KINDS[op], int(tau.size), _d(tau), _d(S), float(I_bc), _d(I))
+    return I
+
+
+def lstar_stencil(chi, n_mu: int, n_phi: int, op: str = "linear", threads: int | None = None):
+    """Nearest-neighbour Lambda* of operator op: array (27, Nz, Ny, Nx); component
+    c = (dz+1)*9 + (dy+1)*3 + (dx+1) holds Lambda_op[v, v + (dx, dy, dz)] (x, y periodic)."""
+    chi = _f64(chi)
+    Nz, Ny, Nx = chi.shape
+    out = np.zeros((27,) + chi.shape)
+    rc = lib().orc_lstar_stencil_box(Nx, Ny, Nz, n_mu, n_phi, _d(chi), _KINDS[op], _d(out),
+                                     threads or default_threads())
+    if rc != 0:
+        raise RuntimeError(f"orc_lstar_stencil_box failed ({rc})")
+    return out
+
+
+def stencil_matrix(st):
+    """The (N x N) sparse matrix of a 27-point stencil (27, Nz, Ny, Nx); entries of
+    components that land on the same voxel (x or y period below 3) are summed;
+    neighbours beyond the top or bottom layer do not exist."""
+    import scipy.sparse as sp
+    _, Nz, Ny, Nx = st.shape
+    k, y, x = np.meshgrid(np.arange(Nz), np.arange(Ny), np.arange(Nx), indexing="ij")
+    v = (k * Ny + y) * Nx + x
+    rows, cols, vals = [], [], []
+    for c in range(27):
+        dz, dy, dx = c // 9 - 1, (c // 3) % 3 - 1, c % 3 - 1
+        ku = k + dz
+        ok = (ku >= 0) & (ku < Nz)
+        u = (ku * Ny + (y + dy) % Ny) * Nx + (x + dx) % Nx
+        rows.append(v[ok]); cols.append(u[ok]); vals.append(st[c][ok])
+    n = Nx * Ny * Nz
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
 
 
 def fs_box_dirs(chi, S, I_top: float, I_bot: float, n_mu: int, n_phi: int, dirs, kind: str = "linear",

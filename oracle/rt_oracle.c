@@ -477,6 +477,213 @@ int orc_box_template(int Nz, double mu, double phi, int cap,
     return orc_trace_box(Nz, n3[0], n3[1], n3[2], cap, di, dj, kk, s, t0);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Operators and the nearest-neighbour Lambda* (Sec. 2, eq. alo; Sec. 3:    */
+/* the paper's runs use a non-local Lambda*).                              */
+/*                                                                          */
+/* The formal solution is linear in S: I_p = I_{p-1} ex_p + a_p S_{p-1}     */
+/* + b_p S_p + g_p S_{p+1} along a characteristic.  Two operators are       */
+/* used: op = parabolic, the formal solution itself (Lambda), and op =      */
+/* linear, linear interpolation at every point (the operator whose          */
+/* diagonal is the default Lambda*).  The nearest-neighbour Lambda* is      */
+/* Lambda_op restricted to the 27 voxels u with |u - v| <= 1 per axis:      */
+/*   Lambda*_{v,u} = sum_d w_d sum_{m: v_m = v} s_m dI_m/dS_u / sum s_m.     */
+/* dI_m/dS_u is the sum, over the points p whose update uses S_u, of that   */
+/* weight times the attenuation from p to m.  A voxel more than three       */
+/* points upstream of m differs from v_m by 2 or more along some axis (each */
+/* step of a straight ray moves at least one coordinate by one, never back),*/
+/* and points downstream of m + 1 do not enter I_m, so only the points      */
+/* m - 3 .. m + 1 can be neighbours that contribute.                        */
+/* Components c = (dz+1)*9 + (dy+1)*3 + (dx+1) with (dx,dy,dz) = u - v      */
+/* (periodic in x and y; dz = +1 is the next layer down).                   */
+/* ------------------------------------------------------------------------ */
+
+/* Weights of point p of a characteristic with M points for operator op.
+   p = 0 is the entry half-segment: I_0 = I_bc ex_0 + b_0 S_0. */
+static void orc_point_op(int op, int M, const double *tau, int p, double *ex, double *a, double *b, double *g)
+{
+    if (p == 0) {
+        double D0 = 0.5 * tau[0];
+        *ex = exp(-D0);
+        *a = 0.0;
+        *b = -expm1(-D0);
+        *g = 0.0;
+        return;
+    }
+    int last = (p == M - 1);
+    double D = 0.5 * (tau[p - 1] + tau[p]);
+    double Dp = last ? 0.0 : 0.5 * (tau[p] + tau[p + 1]);
+    *ex = exp(-D);
+    if (op == ORC_LSTAR_PARABOLIC) {
+        orc_weights(D, Dp, last, a, b, g);
+        return;
+    }
+    if (D > 0.0) {
+        double e0, e1, e2;
+        orc_moments(D, &e0, &e1, &e2);
+        *a = e0 - e1 / D;
+        *b = e1 / D;
+    } else {
+        *a = 0.0;
+        *b = 0.0;
+    }
+    *g = 0.0;
+}
+
+/* Formal solution of operator op along one characteristic (I only). */
+void orc_ray_op(int op, int M, const double *tau, const double *S, double I_bc, double *I)
+{
+    for (int p = 0; p < M; p++) {
+        double ex, a, b, g;
+        orc_point_op(op, M, tau, p, &ex, &a, &b, &g);
+        if (p == 0) {
+            I[0] = I_bc * ex + b * S[0];
+        } else {
+            double Sn = (p + 1 < M) ? S[p + 1] : 0.0;
+            I[p] = I[p - 1] * ex + a * S[p - 1] + b * S[p] + g * Sn;
+        }
+    }
+}
+
+/* J = Lambda_op S + boundary term on the periodic box (single thread; used
+   on small grids to build operator columns). */
+int orc_fs_box_op(int Nx, int Ny, int Nz, int n_mu, int n_phi, const double *chi, const double *S,
+                  double I_top, double I_bot, int op, double *J)
+{
+    int ndir = n_mu * n_phi;
+    long nvox = (long)Nx * Ny * Nz;
+    double *mu = (double *)malloc(sizeof(double) * ndir);
+    double *ph = (double *)malloc(sizeof(double) * ndir);
+    double *w = (double *)malloc(sizeof(double) * ndir);
+    double *num = (double *)malloc(sizeof(double) * nvox);
+    double *den = (double *)malloc(sizeof(double) * nvox);
+    orc_quadrature(n_mu, n_phi, mu, ph, w);
+    memset(J, 0, sizeof(double) * nvox);
+    int err = 0;
+    for (int d = 0; d < ndir && !err; d++) {
+        double n3[3];
+        orc_direction_vector(mu[d], ph[d], n3);
+        orc_path p;
+        if (orc_make_path(Nz, n3, &p) <= 0) {
+            err = -2;
+            orc_free_path(&p);
+            break;
+        }
+        int M = p.M;
+        double *tau = (double *)malloc(sizeof(double) * M);
+        double *Sv = (double *)malloc(sizeof(double) * M);
+        double *I = (double *)malloc(sizeof(double) * M);
+        long *vid = (long *)malloc(sizeof(long) * M);
+        memset(num, 0, sizeof(double) * nvox);
+        memset(den, 0, sizeof(double) * nvox);
+        for (int y0 = 0; y0 < Ny; y0++)
+            for (int x0 = 0; x0 < Nx; x0++) {
+                for (int m = 0; m < M; m++) {
+                    long v = ((long)p.kk[m] * Ny + wrap(y0 + p.dj[m], Ny)) * Nx + wrap(x0 + p.di[m], Nx);
+                    vid[m] = v;
+                    tau[m] = chi[v] * p.s[m];
+                    Sv[m] = S[v];
+                }
+                orc_ray_op(op, M, tau, Sv, (mu[d] < 0.0) ? I_top : I_bot, I);
+                for (int m = 0; m < M; m++) {
+                    num[vid[m]] += p.s[m] * I[m];
+                    den[vid[m]] += p.s[m];
+                }
+            }
+        for (long v = 0; v < nvox; v++)
+            if (den[v] > 0.0) J[v] += w[d] * num[v] / den[v];
+        free(tau); free(Sv); free(I); free(vid);
+        orc_free_path(&p);
+    }
+    free(num); free(den); free(mu); free(ph); free(w);
+    return err;
+}
+
+/* Nearest-neighbour Lambda* of operator op: out[c * nvox + v], c as above. */
+int orc_lstar_stencil_box(int Nx, int Ny, int Nz, int n_mu, int n_phi, const double *chi, int op, double *out,
+                          int nthreads)
+{
+    int ndir = n_mu * n_phi;
+    long nvox = (long)Nx * Ny * Nz;
+    double *mu = (double *)malloc(sizeof(double) * ndir);
+    double *ph = (double *)malloc(sizeof(double) * ndir);
+    double *w = (double *)malloc(sizeof(double) * ndir);
+    orc_quadrature(n_mu, n_phi, mu, ph, w);
+    memset(out, 0, sizeof(double) * 27 * nvox);
+    if (nthreads <= 0) nthreads = 1;
+    double *acc = (double *)calloc((size_t)nthreads * 27 * nvox, sizeof(double));
+    int err = 0;
+#pragma omp parallel num_threads(nthreads)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *num = (double *)malloc(sizeof(double) * 27 * nvox);
+        double *den = (double *)malloc(sizeof(double) * nvox);
+        double *mine = acc + (size_t)tid * 27 * nvox;
+#pragma omp for schedule(static, 1)
+        for (int d = 0; d < ndir; d++) {
+            double n3[3];
+            orc_direction_vector(mu[d], ph[d], n3);
+            orc_path p;
+            if (orc_make_path(Nz, n3, &p) <= 0) {
+#pragma omp atomic write
+                err = -2;
+                orc_free_path(&p);
+                continue;
+            }
+            int M = p.M;
+            double *tau = (double *)malloc(sizeof(double) * M);
+            double *ex = (double *)malloc(sizeof(double) * M);
+            double *wa = (double *)malloc(sizeof(double) * M);
+            double *wb = (double *)malloc(sizeof(double) * M);
+            double *wg = (double *)malloc(sizeof(double) * M);
+            long *vid = (long *)malloc(sizeof(long) * M);
+            memset(num, 0, sizeof(double) * 27 * nvox);
+            memset(den, 0, sizeof(double) * nvox);
+            for (int y0 = 0; y0 < Ny; y0++)
+                for (int x0 = 0; x0 < Nx; x0++) {
+                    for (int m = 0; m < M; m++) {
+                        long v = ((long)p.kk[m] * Ny + wrap(y0 + p.dj[m], Ny)) * Nx + wrap(x0 + p.di[m], Nx);
+                        vid[m] = v;
+                        tau[m] = chi[v] * p.s[m];
+                    }
+                    for (int q = 0; q < M; q++) orc_point_op(op, M, tau, q, &ex[q], &wa[q], &wb[q], &wg[q]);
+                    for (int m = 0; m < M; m++) {
+                        den[vid[m]] += p.s[m];
+                        for (int j = -1; j <= 3; j++) {
+                            int u = m - j; /* point whose voxel carries the S */
+                            if (u < 0 || u >= M) continue;
+                            int dx = p.di[u] - p.di[m], dy = p.dj[u] - p.dj[m], dz = p.kk[u] - p.kk[m];
+                            if (dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1) continue;
+                            /* dI_m/dS_u: updates of points u-1, u, u+1 (those up to m) */
+                            double coef = 0.0;
+                            for (int q = (u > 0 ? u - 1 : 0); q <= m && q <= u + 1; q++) {
+                                double wq = (q == u + 1) ? wa[q] : (q == u) ? wb[q] : wg[q];
+                                double att = 1.0;
+                                for (int r = q + 1; r <= m; r++) att *= ex[r];
+                                coef += wq * att;
+                            }
+                            int c = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+                            num[(size_t)c * nvox + vid[m]] += p.s[m] * coef;
+                        }
+                    }
+                }
+            for (int c = 0; c < 27; c++)
+                for (long v = 0; v < nvox; v++)
+                    if (den[v] > 0.0) mine[(size_t)c * nvox + v] += w[d] * num[(size_t)c * nvox + v] / den[v];
+            free(tau); free(ex); free(wa); free(wb); free(wg); free(vid);
+            orc_free_path(&p);
+        }
+        free(num); free(den);
+    }
+    for (int t = 0; t < nthreads; t++)
+        for (long i = 0; i < 27 * nvox; i++) out[i] += acc[(size_t)t * 27 * nvox + i];
+    free(acc); free(mu); free(ph); free(w);
+    return err;
+}
+
 /*
  * x,y-homogeneous reduction: when chi and S depend on the layer only, every
  * ray of a direction sees the same sequence of values, so J of a layer is the

@@ -51,6 +51,16 @@ class BoxProblem:
             self.fs(np.zeros(self.shape), want_lstar=True)
         return self._lstar
 
+    def lstar_stencil(self):
+        """Nearest-neighbour Lambda* (27, Nz, Ny, Nx) of the operator selected by kind."""
+        from . import lstar_stencil
+        return lstar_stencil(self.chi, self.n_mu, self.n_phi, self.kind, self.threads)
+
+    def lstar_nonlocal(self):
+        """The nearest-neighbour Lambda* as a sparse matrix."""
+        from . import stencil_matrix
+        return stencil_matrix(self.lstar_stencil())
+
 
 class Plane1DProblem(BoxProblem):
     """x,y-homogeneous box reduced to its layers: chi, eps, B of shape (Nz,)."""
@@ -142,8 +152,8 @@ def ng_extrapolate(x0, x1, x2, x3):
 
 
 def ali(prob, tol=1e-8, max_iter=10000, ng=True, ng_start=4, ng_every=4, J0=None,
-        lstar=None, record=False):
-    """Operator-splitting (ALI) iteration with a diagonal Lambda* (Sec. 2.2, eq. (alo)).
+        lstar=None, record=False, inner_jacobi=0):
+    """Operator-splitting (ALI) iteration (Sec. 2.2, eq. (alo)).
 
     Each step: J_fs = Lambda S_old (+ boundary term);
                [1 - Lambda*(1-eps)] J_new = J_fs - Lambda*(1-eps) J_old;
@@ -151,9 +161,15 @@ def ali(prob, tol=1e-8, max_iter=10000, ng=True, ng_start=4, ng_every=4, J0=None
     Stops when max |J_new - J_old| / |J_new| < tol.  Ng acceleration is applied
     to the last four iterates every ``ng_every`` plain steps once ``ng_start``
     steps have been taken; the iterate history restarts after each application.
-    ``lstar`` overrides the diagonal (e.g. zeros for plain Lambda iteration, or
-    a full matrix for the Lambda* = Lambda special case).
+    ``lstar`` overrides the diagonal (e.g. zeros for plain Lambda iteration, a
+    full matrix for the Lambda* = Lambda special case, or a scipy sparse matrix
+    such as the nearest-neighbour Lambda*).  With a sparse Lambda* the OS
+    system is solved exactly, or, with ``inner_jacobi`` = k > 0, by k Jacobi
+    sweeps on [1 - Lambda*(1-eps)] dJ = J_fs - J_old started from the
+    diagonal solution (one of the OS solvers of Sec. 3).
     """
+    import scipy.sparse as sps
+    import scipy.sparse.linalg as spla
     eps, B = prob.eps, prob.B
     L = prob.lstar() if lstar is None else lstar
     J = B.copy() if J0 is None else np.array(J0, dtype=np.float64)
@@ -162,9 +178,23 @@ def ali(prob, tol=1e-8, max_iter=10000, ng=True, ng_start=4, ng_every=4, J0=None
     trace = []
     converged = False
     it = 0
+    if sps.issparse(L):
+        om = (1.0 - eps).ravel()
+        A = (sps.identity(J.size, format="csr") - L @ sps.diags(om)).tocsr()
+        Adiag = A.diagonal()
+        Aoff = (A - sps.diags(Adiag)).tocsr()
     for it in range(1, max_iter + 1):
         Jfs = prob.fs(S)
-        if np.ndim(L) == 2 and L.shape[0] == J.size:
+        if sps.issparse(L):
+            r = (Jfs - J).ravel()
+            if inner_jacobi > 0:
+                x = r / Adiag
+                for _ in range(inner_jacobi):
+                    x = (r - Aoff @ x) / Adiag
+            else:
+                x = spla.spsolve(A.tocsc(), r)
+            Jn = J + x.reshape(J.shape)
+        elif np.ndim(L) == 2 and L.shape[0] == J.size:
             # full-matrix Lambda*: solve [1 - Lambda*(1-eps)] J_new = J_fs - Lambda*(1-eps) J_old
             A = np.eye(J.size) - L * (1.0 - eps.ravel())[None, :]
             rhs = Jfs.ravel() - L @ ((1.0 - eps.ravel()) * J.ravel())
