@@ -80,6 +80,16 @@ typedef enum { RT_FP64 = 0, RT_FP32 = 1 } rt_prec;
                                      (e.g. 257 x 257); the flag forces it for
                                      any box grid (results differ only in the
                                      summation order).                         */
+#define RT_F_LSTAR_NONLOCAL 0x4u  /* box: the ALI uses the nearest-neighbour
+                                     Lambda* (Sec. 2, Sec. 3: the non-local
+                                     operator of the paper's runs) -- the
+                                     operator selected by RT_F_LSTAR_PARABOLIC
+                                     restricted to the 27 neighbours of each
+                                     voxel (see rt_lstar_stencil) -- and solves
+                                     the operator-splitting system with Jacobi
+                                     sweeps (rt_solve_opts.os_sweeps).  The
+                                     state's lstar array still receives the
+                                     diagonal.                                 */
 
 typedef struct rt_grid *rt_grid_t;
 
@@ -214,6 +224,10 @@ typedef struct {
                              (rt_set_preconditioner): propose a learned
                              correction after every net_every-th step
                              (0 = never); see rt_set_preconditioner             */
+    int32_t os_sweeps;    /* grids with RT_F_LSTAR_NONLOCAL: Jacobi sweeps of
+                             the operator-splitting system per step, started
+                             from the diagonal solution (0 = library default
+                             4); ignored otherwise                              */
 } rt_solve_opts;
 
 typedef struct {
@@ -229,9 +243,12 @@ typedef struct {
 } rt_solve_report;
 
 /*
- * One ALI step (Sec. 2.2 eq. alo with the diagonal Lambda*): formal solution
+ * One ALI step (Sec. 2.2 eq. alo with the diagonal Lambda*, or with the
+ * nearest-neighbour Lambda* on RT_F_LSTAR_NONLOCAL grids): formal solution
  * of the current S (building Lambda* first when lstar_valid == 0), the
- * pointwise operator-splitting update of J, S = (1-eps)J + eps B, the
+ * operator-splitting update of J (pointwise for the diagonal Lambda*; for the
+ * non-local one, J_new = J_old + dJ with dJ from os_sweeps Jacobi sweeps of
+ * [1 - Lambda*(1-eps)] dJ = J_fs - J_old), S = (1-eps)J + eps B, the
  * per-wavelength norm max_v |dJ/J| into state->rel_change, and -- when the
  * schedule in opts says so -- the Ng extrapolation of the last four iterates.
  * Asynchronous on `stream`.  For RT_FP32 grids the formal solution of the
@@ -240,6 +257,26 @@ typedef struct {
  * Errors: RT_E_INVALID, RT_E_HIP.
  */
 rt_status rt_ali_step(rt_grid_t grid, rt_state *state, const rt_solve_opts *opts, void *stream);
+
+/*
+ * The nearest-neighbour Lambda* of a box grid (Sec. 2, Sec. 3): for each voxel
+ * v and each of its 27 neighbours u = v + (dx, dy, dz) (x, y periodic), the
+ * part of the operator element Lambda[v][u] that characteristics carry
+ * directly from u to v (points at most three apart along a characteristic;
+ * on periods longer than a characteristic's horizontal reach within the
+ * neighbourhood this is the whole element).  The operator is the
+ * linear-interpolation one, or the formal solution itself with
+ * RT_F_LSTAR_PARABOLIC; component 13 (the voxel itself) is the diagonal
+ * Lambda* of rt_formal_solution.  Elements of neighbours beyond the top or
+ * bottom layer are 0.
+ *   chi  device [n_lambda][Nz][Ny][Nx], grid precision
+ *   out  device [n_lambda][27][Nz][Ny][Nx], grid precision, component
+ *        c = (dz+1)*9 + (dy+1)*3 + (dx+1)
+ * Sums are accumulated in 64-bit fixed point (2^-52), so the result is
+ * bitwise reproducible.  Asynchronous on `stream`.  Errors: RT_E_INVALID,
+ * RT_E_UNSUPPORTED (spherical grids), RT_E_NOMEM, RT_E_HIP.
+ */
+rt_status rt_lstar_stencil(rt_grid_t grid, int32_t n_lambda, const void *chi, void *out, void *stream);
 
 /*
  * RT_SOLVER_ALI: runs ALI steps until every wavelength has max_v |dJ/J| < tol

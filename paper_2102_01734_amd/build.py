@@ -17,7 +17,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "librt3d.so")
 
 SOURCES = ["geometry.cpp", "sphere_geometry.cpp", "schedule.cpp", "fs_box.hip", "fs_sphere.hip", "ali.hip", "unet.hip", "krylov.hip",
-           "rt_api.cpp"]
+           "lstar_nl.hip", "rt_api.cpp"]
 ARCH = os.environ.get("RT3D_ARCH", "gfx950")
 CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -241,10 +241,27 @@ __global__ void __launch_bounds__(256) ali_update_kernel(AliUpdateArgs a)
     const int lam = a.lambda_of[b];
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double rel = 0.0, res = 0.0;
+    if (a.rfs_out) {  // uniform over the launch: no thread reaches the block reductions
+        if (v < a.n_vox) {
+            const int64_t i = (int64_t)lam * a.n_vox + v;
+            double jfs = a.J_anchor ? a.J_anchor[i] : 0.0;
+            if (a.part) {
+                const TP *part = reinterpret_cast<const TP *>(a.part);
+                const int s1 = a.slot_begin[b + 1];
+                double acc = 0.0;
+                for (int s = a.slot_begin[b]; s < s1; ++s) acc += (double)part[(int64_t)a.slot_ids[s] * a.n_vox + v];
+                jfs += acc;
+            }
+            a.rfs_out[i] = jfs - a.J[i];
+        }
+        return;
+    }
     if (v < a.n_vox) {
         const int64_t i = (int64_t)lam * a.n_vox + v;
         double jfs = a.J_anchor ? a.J_anchor[i] : 0.0;
-        if (a.part) {
+        if (a.rfs_in) {
+            jfs = a.J[i] + a.rfs_in[i];
+        } else if (a.part) {
             const TP *part = reinterpret_cast<const TP *>(a.part);
             const int s1 = a.slot_begin[b + 1];
             double acc = 0.0;
@@ -261,7 +278,7 @@ __global__ void __launch_bounds__(256) ali_update_kernel(AliUpdateArgs a)
         if (a.net_r) a.net_r[i] = (float)rr;
         double den = 1.0 - (1.0 - e) * L;
         den = den < 1e-12 ? 1e-12 : den;
-        const double jn = jo + (jfs - jo) / den;
+        const double jn = a.dJ ? jo + a.dJ[i] : jo + (jfs - jo) / den;
         a.J[i] = jn;
         if (a.hist) a.hist[i] = jn;
         const double dj = fabs(jn - jo);

@@ -45,6 +45,10 @@ struct AliUpdateArgs {
     double *rel_change;         // out: per wavelength max |dJ/J| (atomic max)
     double *resid;              // out: per wavelength max |J_fs - J_old| / |J_old| (atomic max), or null
     float *net_r;               // out: (J_fs - J_old) / J_old per voxel (network input), or null
+    // operator-splitting system solved outside (non-local Lambda*):
+    double *rfs_out;            // if set: only write J_fs - J_old here and return
+    const double *rfs_in;       // if set: J_fs = J_old + rfs_in (part and J_anchor unused)
+    const double *dJ;           // if set: J_new = J_old + dJ instead of the diagonal solution
 };
 
 hipError_t ali_update(const AliUpdateArgs &a, bool part_double, bool grid_double, bool next_double, int n_batch,

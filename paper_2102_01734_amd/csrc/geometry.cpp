@@ -133,6 +133,18 @@ std::string build_box_geometry(int Nx, int Ny, int Nz, int n_mu, int n_phi, BoxG
                 g.dxy.push_back(w);
                 g.s.push_back(s[m]);
                 g.brow.push_back(rel[(size_t)m]);
+                uint32_t packed = 0;
+                for (int j = -1; j <= 3; ++j) {
+                    const int u = m - j;
+                    uint32_t c = kNoComp;
+                    if (u >= 0 && u < M) {
+                        const int dx = di[u] - di[m], dy = dj[u] - dj[m], dz = kk[u] - kk[m];
+                        if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1)
+                            c = (uint32_t)((dz + 1) * 9 + (dy + 1) * 3 + (dx + 1));
+                    }
+                    packed |= c << (6 * (j + 1));
+                }
+                g.comp.push_back(packed);
                 g.di.push_back(di[m]);
                 g.dj.push_back(dj[m]);
                 g.kk.push_back(kk[m]);

@@ -1,0 +1,62 @@
+// lstar_nl.hpp -- nearest-neighbour (non-local) Lambda* on the box and the
+// Jacobi solver of the operator-splitting system it defines.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace rt3d {
+
+// Stencil components: c = (dz+1)*9 + (dy+1)*3 + (dx+1) for the neighbour
+// u = v + (dx, dy, dz) (x, y periodic; dz = +1 is the next layer down);
+// c = 13 is the voxel itself.
+constexpr int kStencil = 27;
+constexpr int kStencilCentre = 13;
+
+// Per visit of a template (StencilArgs::comp): the stencil components of the
+// voxels that the points m+1, m, m-1, m-2, m-3 of a characteristic lie in,
+// seen from the voxel of point m, 6 bits each (j + 1 = 0..4 for point m - j),
+// kNoComp (rt_internal.hpp) when that point is not a neighbour or does not
+// exist.
+
+struct StencilArgs {
+    int Nx, Ny, Nz;
+    int64_t n_vox;
+    const uint32_t *dxy;       // per visit: di mod Nx | (dj mod Ny) << 15 | layer-end flag
+    const double *s;           // per visit: path length
+    const uint32_t *comp;      // per visit: packed stencil components (see above)
+    const int64_t *dir_vbegin;
+    const int32_t *dir_M;
+    const double *dir_wmu;     // w_d |mu_d|
+    const double *dir_mu;
+    const void *chi;           // caller opacity [lambda][Nz][Ny][Nx], grid precision
+    const int32_t *lambda_of;  // batch entry -> wavelength
+    unsigned long long *acc;   // [lambda][27][n_vox] fixed point (2^-52), cleared by the caller
+};
+
+// Adds every characteristic's contributions to the stencil of the linear-
+// interpolation operator (parabolic = false) or of the formal solution
+// itself (parabolic = true), for n_batch wavelengths and all directions.
+hipError_t lstar_stencil_accumulate(const StencilArgs &a, bool grid_double, bool parabolic, int n_dir, int n_batch,
+                                    hipStream_t st);
+
+// out[lam][c][v] = acc[lam][c][v] * 2^-52 (T = float or double).
+hipError_t lstar_stencil_finish(const unsigned long long *acc, const int32_t *lambda_of, int64_t n_vox, int n_batch,
+                                void *out, bool out_double, hipStream_t st);
+
+// One Jacobi sweep of [1 - Lambda*(1-eps)] x = r per wavelength of the batch
+// (first: x = r / (1 - Lambda*_vv (1-eps_v)), the diagonal solution).
+struct OsJacobiArgs {
+    int Nx, Ny, Nz;
+    int64_t n_vox;
+    const int32_t *lambda_of;
+    const void *st;       // [lambda][27][n_vox], grid precision
+    const void *eps;      // [lambda][n_vox], grid precision
+    const double *r;      // [lambda][n_vox]
+    const double *x_in;   // [lambda][n_vox] (unused when first)
+    double *x_out;        // [lambda][n_vox]
+};
+hipError_t os_jacobi_sweep(const OsJacobiArgs &a, bool grid_double, bool first, int n_batch, hipStream_t st);
+
+}  // namespace rt3d

@@ -24,6 +24,7 @@
 #include "fs_box.hpp"
 #include "fs_sphere.hpp"
 #include "krylov.hpp"
+#include "lstar_nl.hpp"
 #include "rt_internal.hpp"
 #include "unet.hpp"
 
@@ -130,7 +131,11 @@ struct rt_grid {
     int n_dir = 0;
     int64_t n_visits = 0;
 
-    DevBuf goff, dxy, s, vbegin, M, wmu, mu, brow, span;
+    DevBuf goff, dxy, s, vbegin, M, wmu, mu, brow, span, comp;
+    // nearest-neighbour Lambda*: fixed-point sums, stencil [lambda][27][vox]
+    // (grid precision), OS right-hand side and Jacobi iterates [lambda][vox]
+    bool nonlocal = false;
+    DevBuf nl_acc, nl_st, os_r, os_x0, os_x1;
     int span_max = 0;   // largest per-layer row extent of any template
     bool band = false;  // the box sweep uses band tiles (see fs_box.hip)
     Variant var[2][2][2];  // [dbl][wj][wl]
@@ -659,6 +664,9 @@ static rt_status build_sphere_grid(rt_grid *g, const rt_grid_desc *desc)
     return flush(nd);
 }
 
+static rt_status compute_stencil(rt_grid *g, const void *chi, int n_lambda, int nb, const int32_t *lambda_of,
+                                 void *out, bool out_double, hipStream_t st);
+
 extern "C" {
 
 const char *rt_last_error(void) { return g_err.c_str(); }
@@ -735,10 +743,10 @@ rt_status rt_create_grid(const rt_grid_desc *desc, rt_grid_t *out)
         return fail(RT_E_INVALID, "unknown geometry %d", desc->geom);
     if (desc->prec != RT_FP32 && desc->prec != RT_FP64) return fail(RT_E_INVALID, "unknown precision %d", desc->prec);
     if (desc->n_lambda_max < 1) return fail(RT_E_INVALID, "n_lambda_max must be >= 1");
-    if (desc->flags & ~(RT_F_LSTAR_PARABOLIC | RT_F_BAND_TILES))
+    if (desc->flags & ~(RT_F_LSTAR_PARABOLIC | RT_F_BAND_TILES | RT_F_LSTAR_NONLOCAL))
         return fail(RT_E_INVALID, "unknown flags 0x%x", desc->flags);
-    if (desc->geom == RT_GEOM_SPHERICAL && (desc->flags & RT_F_BAND_TILES))
-        return fail(RT_E_INVALID, "RT_F_BAND_TILES applies to box grids only");
+    if (desc->geom == RT_GEOM_SPHERICAL && (desc->flags & (RT_F_BAND_TILES | RT_F_LSTAR_NONLOCAL)))
+        return fail(RT_E_INVALID, "RT_F_BAND_TILES and RT_F_LSTAR_NONLOCAL apply to box grids only");
     if (desc->geom == RT_GEOM_SPHERICAL) {
         const int64_t nv = (int64_t)desc->n[0] * desc->n[1] * desc->n[2];
         if (desc->n[0] < 1 || desc->n[1] < 1 || desc->n[2] < 1) return fail(RT_E_INVALID, "grid sizes must be >= 1");
@@ -813,6 +821,10 @@ rt_status rt_create_grid(const rt_grid_desc *desc, rt_grid_t *out)
     HIPCHK(hipMemcpy(g->s.p, g->geo.s.data(), nvis * 8, hipMemcpyHostToDevice));
     HIPCHK(g->brow.ensure(nvis * 4));
     HIPCHK(hipMemcpy(g->brow.p, g->geo.brow.data(), nvis * 4, hipMemcpyHostToDevice));
+    HIPCHK(g->comp.ensure(nvis * 4));
+    HIPCHK(hipMemcpy(g->comp.p, g->geo.comp.data(), nvis * 4, hipMemcpyHostToDevice));
+    g->nonlocal = (desc->flags & RT_F_LSTAR_NONLOCAL) != 0;
+    if (g->n_dir > 65535) return fail(RT_E_INVALID, "more than 65535 directions");
     std::vector<int64_t> vb(g->n_dir);
     std::vector<int32_t> Ms(g->n_dir), sp(g->n_dir);
     std::vector<double> wmu(g->n_dir), mu(g->n_dir);
@@ -948,6 +960,23 @@ rt_status rt_set_launch_shape(rt_grid_t g, int32_t threads, int32_t rays)
         return RT_OK;
     }
     return fail(RT_E_INVALID, "no compiled launch shape %d threads x %d rays", threads, rays);
+}
+
+rt_status rt_lstar_stencil(rt_grid_t g, int32_t n_lambda, const void *chi, void *out, void *stream)
+{
+    if (!g) return fail(RT_E_INVALID, "grid is NULL");
+    if (g->sphere) return fail(RT_E_UNSUPPORTED, "the nearest-neighbour Lambda* is built on box grids");
+    if (n_lambda == 0) return RT_OK;
+    if (n_lambda < 0 || n_lambda > g->desc.n_lambda_max)
+        return fail(RT_E_INVALID, "n_lambda %d outside [0, %d]", n_lambda, g->desc.n_lambda_max);
+    if (!chi || !out) return fail(RT_E_INVALID, "chi and out must not be NULL");
+    std::vector<int32_t> lams(n_lambda);
+    for (int i = 0; i < n_lambda; ++i) lams[i] = i;
+    DevSchedule *sc = nullptr;
+    rt_status rs = get_schedule(g, variant(g, g->dbl, true, false).n_wg, lams, &sc);
+    if (rs != RT_OK) return rs;
+    return compute_stencil(g, chi, n_lambda, n_lambda, sc->lambda_of.as<int32_t>(), out, g->dbl,
+                           (hipStream_t)stream);
 }
 
 rt_status rt_launch_shape(rt_grid_t g, int32_t *threads, int32_t *rays, int32_t *bundles, int32_t *band)
@@ -1123,6 +1152,7 @@ static rt_status check_opts(const rt_solve_opts *o)
     if (o->net_every < 0) return fail(RT_E_INVALID, "opts->net_every must be >= 0");
     if (o->method != RT_SOLVER_ALI && o->method != RT_SOLVER_BICGSTAB)
         return fail(RT_E_INVALID, "unknown solver method %d", o->method);
+    if (o->os_sweeps < 0 || o->os_sweeps > 1000) return fail(RT_E_INVALID, "opts->os_sweeps outside [0, 1000]");
     return RT_OK;
 }
 
@@ -1143,6 +1173,12 @@ static rt_status ensure_state_buffers(rt_grid *g)
     HIPCHK(g->ng_blk.ensure(nl * 256 * 5 * 8));
     HIPCHK(g->ng_coef.ensure(nl * 3 * 8));
     HIPCHK(g->resid.ensure(nl * 8));
+    if (g->nonlocal) {
+        HIPCHK(g->nl_st.ensure(nl * kStencil * nv * esz));
+        HIPCHK(g->os_r.ensure(nl * nv * 8));
+        HIPCHK(g->os_x0.ensure(nl * nv * 8));
+        HIPCHK(g->os_x1.ensure(nl * nv * 8));
+    }
     if (g->net) {
         HIPCHK(g->net_r.ensure(nl * nv * 4));
         HIPCHK(g->J_save.ensure(nl * nv * 8));
@@ -1152,11 +1188,80 @@ static rt_status ensure_state_buffers(rt_grid *g)
     return RT_OK;
 }
 
+static int os_sweeps_of(const rt_solve_opts *o) { return o->os_sweeps > 0 ? o->os_sweeps : 4; }
+
+// Nearest-neighbour Lambda* of the wavelengths in `lams` from the caller's
+// opacity: clear the fixed-point sums, accumulate every characteristic, and
+// convert into `out` ([lambda][27][vox], double or float).
+static rt_status compute_stencil(rt_grid *g, const void *chi, int n_lambda, int nb, const int32_t *lambda_of,
+                                 void *out, bool out_double, hipStream_t st)
+{
+    const int64_t per = (int64_t)kStencil * g->n_vox;
+    HIPCHK(g->nl_acc.ensure((size_t)n_lambda * per * 8));
+    for (int64_t off = 0; off < (int64_t)n_lambda * per; off += (int64_t)1 << 30) {
+        const int64_t cnt = std::min<int64_t>((int64_t)1 << 30, (int64_t)n_lambda * per - off);
+        HIPCHK(fill_u64(g->nl_acc.as<unsigned long long>() + off, 0ull, (int)cnt, st));
+    }
+    StencilArgs a{};
+    a.Nx = g->geo.Nx; a.Ny = g->geo.Ny; a.Nz = g->geo.Nz;
+    a.n_vox = g->n_vox;
+    a.dxy = g->dxy.as<uint32_t>();
+    a.s = g->s.as<double>();
+    a.comp = g->comp.as<uint32_t>();
+    a.dir_vbegin = g->vbegin.as<int64_t>();
+    a.dir_M = g->M.as<int32_t>();
+    a.dir_wmu = g->wmu.as<double>();
+    a.dir_mu = g->mu.as<double>();
+    a.chi = chi;
+    a.lambda_of = lambda_of;
+    a.acc = g->nl_acc.as<unsigned long long>();
+    HIPCHK(lstar_stencil_accumulate(a, g->dbl, g->para, g->n_dir, nb, st));
+    HIPCHK(lstar_stencil_finish(g->nl_acc.as<unsigned long long>(), lambda_of, g->n_vox, nb, out, out_double, st));
+    return RT_OK;
+}
+
+// The operator-splitting update.  Diagonal Lambda*: the fused pointwise
+// kernel.  Nearest-neighbour Lambda*: J_fs - J_old, `sweeps` Jacobi sweeps of
+// [1 - Lambda*(1-eps)] dJ = J_fs - J_old started from the diagonal solution,
+// then the same update kernel with that dJ (norms, Ng history, S, next input).
+static rt_status os_update(rt_grid *g, int n_lambda, AliUpdateArgs ua, bool part_double, bool grid_double,
+                           bool next_double, int nb, int sweeps, hipStream_t st)
+{
+    if (!g->nonlocal) {
+        HIPCHK(ali_update(ua, part_double, grid_double, next_double, nb, st));
+        return RT_OK;
+    }
+    (void)n_lambda;
+    AliUpdateArgs ra = ua;
+    ra.rfs_out = g->os_r.as<double>();
+    HIPCHK(ali_update(ra, part_double, grid_double, next_double, nb, st));
+    OsJacobiArgs ja{};
+    ja.Nx = g->geo.Nx; ja.Ny = g->geo.Ny; ja.Nz = g->geo.Nz;
+    ja.n_vox = g->n_vox;
+    ja.lambda_of = ua.lambda_of;
+    ja.st = g->nl_st.p;
+    ja.eps = ua.eps;
+    ja.r = g->os_r.as<double>();
+    double *x[2] = {g->os_x0.as<double>(), g->os_x1.as<double>()};
+    ja.x_in = nullptr;
+    ja.x_out = x[0];
+    HIPCHK(os_jacobi_sweep(ja, g->dbl, true, nb, st));
+    for (int k = 0; k < sweeps; ++k) {
+        ja.x_in = x[k % 2];
+        ja.x_out = x[(k + 1) % 2];
+        HIPCHK(os_jacobi_sweep(ja, g->dbl, false, nb, st));
+    }
+    ua.rfs_in = g->os_r.as<double>();
+    ua.dJ = x[sweeps % 2];
+    HIPCHK(ali_update(ua, part_double, grid_double, next_double, nb, st));
+    return RT_OK;
+}
+
 // The plain step (Lambda* known, no anchor, no Ng): clear the norms, formal
 // solution of the current S (FP64 grids) or of S - S_anchor (FP32 grids), and
 // the fused update.  Issues only kernel launches, so it can be captured.
 static rt_status plain_step_launches(rt_grid *g, rt_state *s, const std::vector<int32_t> &lams,
-                                     const int32_t *lambda_of, hipStream_t st, bool keep_hist = true)
+                                     const int32_t *lambda_of, hipStream_t st, int sweeps, bool keep_hist = true)
 {
     const int nl = s->n_lambda, nb = (int)lams.size();
     const int64_t nv = g->n_vox;
@@ -1187,15 +1292,14 @@ static rt_status plain_step_launches(rt_grid *g, rt_state *s, const std::vector<
     }
     ua.slot_begin = sc->slot_begin.as<int32_t>();
     ua.slot_ids = sc->slot_ids.as<int32_t>();
-    HIPCHK(ali_update(ua, g->dbl, g->dbl, g->dbl, nb, st));
-    return RT_OK;
+    return os_update(g, nl, ua, g->dbl, g->dbl, g->dbl, nb, sweeps, st);
 }
 
 // The plain step through a captured HIP graph: captured on first use for this
 // batch, Ng ring slot and state, then replayed.  Schedules and partial-slot
 // buffers are prepared before capture so the capture sees launches only.
 static rt_status graph_plain_step(rt_grid *g, rt_state *s, const std::vector<int32_t> &lams,
-                                  const int32_t *lambda_of, hipStream_t st)
+                                  const int32_t *lambda_of, hipStream_t st, int sweeps)
 {
     const Variant &v = variant(g, g->dbl, true, false);
     DevSchedule *sc = nullptr;
@@ -1204,9 +1308,9 @@ static rt_status graph_plain_step(rt_grid *g, rt_state *s, const std::vector<int
     DevBuf &pJ = g->dbl ? g->partJ64 : g->partJ;
     HIPCHK(pJ.ensure((size_t)sc->n_slots * g->n_vox * (g->dbl ? 8 : 4)));
     char buf[512];
-    snprintf(buf, sizeof buf, "%d|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%d|%d|%d:", g->hist_count % 4, (void *)s->J,
+    snprintf(buf, sizeof buf, "%d|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%d|%d|%d|%d:", g->hist_count % 4, (void *)s->J,
              (void *)s->S, s->lstar, s->eps, s->B, (void *)s->rel_change, pJ.p, (void *)st,
-             g->net ? g->net_r.p : nullptr, g->resid.p, s->n_lambda, v.lb, v.R);
+             g->net ? g->net_r.p : nullptr, g->resid.p, s->n_lambda, v.lb, v.R, g->nonlocal ? sweeps : -1);
     std::string key(buf);
     for (int l : lams) key += std::to_string(l) + ",";
     auto it = g->graphs.find(key);
@@ -1215,7 +1319,7 @@ static rt_status graph_plain_step(rt_grid *g, rt_state *s, const std::vector<int
         const bool prof = g->prof;
         g->prof = false;
         HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        rs = plain_step_launches(g, s, lams, lambda_of, st);
+        rs = plain_step_launches(g, s, lams, lambda_of, st, sweeps);
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(st, &graph);
         g->prof = prof;
@@ -1296,9 +1400,9 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
     const bool want_l = s->lstar_valid == 0;
     if (!want_l && (g->dbl || !anchor)) {
         if (o->use_graph && st != nullptr && !candidate)
-            rs = graph_plain_step(g, s, lams, lambda_of, st);
+            rs = graph_plain_step(g, s, lams, lambda_of, st, os_sweeps_of(o));
         else
-            rs = plain_step_launches(g, s, lams, lambda_of, st, !candidate);
+            rs = plain_step_launches(g, s, lams, lambda_of, st, os_sweeps_of(o), !candidate);
         if (rs != RT_OK) return rs;
         ++*fs_count;
         if (g->dbl) ++*fs64_count;
@@ -1319,6 +1423,11 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
     ua.rel_change = s->rel_change;
     ua.next_pad = g->fld.p;
     DevSchedule *sc = nullptr;
+    const int sweeps = os_sweeps_of(o);
+    if (want_l && g->nonlocal) {
+        rs = compute_stencil(g, s->chi, nl, nb, lambda_of, g->nl_st.p, g->dbl, st);
+        if (rs != RT_OK) return rs;
+    }
 
     if (g->dbl) {
         const bool joint = want_l && variant(g, true, true, true).ok;
@@ -1338,7 +1447,8 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
         ua.part = g->partJ64.p;
         ua.slot_begin = sc->slot_begin.as<int32_t>();
         ua.slot_ids = sc->slot_ids.as<int32_t>();
-        HIPCHK(ali_update(ua, true, true, true, nb, st));
+        rs = os_update(g, nl, ua, true, true, true, nb, sweeps, st);
+        if (rs != RT_OK) return rs;
     } else {
         if (want_l) {
             rs = run_fs(g, false, false, true, lams, g->fld.p, nullptr, g->partJ, g->partL, &sc, st);
@@ -1370,7 +1480,8 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
             ua.part = nullptr;
             ua.slot_begin = sc->slot_begin.as<int32_t>();
             ua.slot_ids = sc->slot_ids.as<int32_t>();
-            HIPCHK(ali_update(ua, false, false, false, nb, st));
+            rs = os_update(g, nl, ua, false, false, false, nb, sweeps, st);
+            if (rs != RT_OK) return rs;
         } else {
             rs = run_fs(g, false, true, false, lams, g->fld.p, nullptr, g->partJ, g->partL, &sc, st);
             if (rs != RT_OK) return rs;
@@ -1378,7 +1489,8 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
             ua.part = g->partJ.p;
             ua.slot_begin = sc->slot_begin.as<int32_t>();
             ua.slot_ids = sc->slot_ids.as<int32_t>();
-            HIPCHK(ali_update(ua, false, false, false, nb, st));
+            rs = os_update(g, nl, ua, false, false, false, nb, sweeps, st);
+            if (rs != RT_OK) return rs;
         }
     }
     s->lstar_valid = 1;

@@ -16,6 +16,10 @@ constexpr uint32_t kLayerEnd = 0x80000000u;
 constexpr int kOffBits = 15;                    // di', dj' each < 2^15
 constexpr uint32_t kOffMask = (1u << kOffBits) - 1u;
 constexpr int kMaxSide = 1 << kOffBits;
+// Per-visit stencil components of the nearest-neighbour Lambda*: 6 bits per
+// point m+1, m, m-1, m-2, m-3 (component (dz+1)*9 + (dy+1)*3 + (dx+1) of
+// that point's voxel seen from the voxel of point m), kNoComp if none.
+constexpr uint32_t kNoComp = 63;
 
 // One direction of the angle quadrature and its characteristic template.
 struct Direction {
@@ -37,6 +41,7 @@ struct BoxGeometry {
     std::vector<uint32_t> dxy;   // di mod Nx | (dj mod Ny) << 15 | layer-end flag
     std::vector<double> s;       // path length inside the voxel
     std::vector<int32_t> brow;   // dj - (smallest dj of the visits in the same layer)
+    std::vector<uint32_t> comp;  // stencil components of the points m+1 .. m-3 (kNoComp: none)
     std::vector<int32_t> di, dj, kk;  // unwrapped offsets and layer (tests, tools)
 };
 

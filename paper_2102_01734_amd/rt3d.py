@@ -18,6 +18,7 @@ RT_GEOM_BOX_PERIODIC_XY, RT_GEOM_SPHERICAL = 0, 1
 RT_FP64, RT_FP32 = 0, 1
 RT_F_LSTAR_PARABOLIC = 0x1
 RT_F_BAND_TILES = 0x2
+RT_F_LSTAR_NONLOCAL = 0x4
 
 STATUS_NAMES = {0: "RT_OK", 1: "RT_E_INVALID", 2: "RT_E_NOMEM", 3: "RT_E_HIP", 4: "RT_E_NOT_CONVERGED",
                 5: "RT_E_NUMERIC", 6: "RT_E_UNSUPPORTED"}
@@ -39,7 +40,8 @@ class RtState(ctypes.Structure):
 class RtSolveOpts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("ng_every", ctypes.c_int32), ("ng_start", ctypes.c_int32), ("reanchor", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("method", ctypes.c_int32), ("net_every", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("method", ctypes.c_int32), ("net_every", ctypes.c_int32),
+                ("os_sweeps", ctypes.c_int32)]
 
 
 class RtSolveReport(ctypes.Structure):
@@ -86,6 +88,8 @@ def lib() -> ctypes.CDLL:
     L.rt_set_launch_shape.restype = ctypes.c_int
     L.rt_launch_shape.argtypes = [vp] + [ctypes.POINTER(i32)] * 4
     L.rt_launch_shape.restype = ctypes.c_int
+    L.rt_lstar_stencil.argtypes = [vp, i32, vp, vp, vp]
+    L.rt_lstar_stencil.restype = ctypes.c_int
     L.rt_profile_enable.argtypes = [vp, i32]
     L.rt_profile_enable.restype = ctypes.c_int
     L.rt_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32), i64p]
@@ -177,6 +181,11 @@ def rt_autotune(grid: int, n_lambda: int, chi: int, S: int, stream: Optional[int
 
 def rt_set_launch_shape(grid: int, threads: int, rays: int) -> None:
     _check(lib().rt_set_launch_shape(ctypes.c_void_p(grid), int(threads), int(rays)), "rt_set_launch_shape")
+
+
+def rt_lstar_stencil(grid: int, n_lambda: int, chi: int, out: int, stream: Optional[int]) -> None:
+    _check(lib().rt_lstar_stencil(ctypes.c_void_p(grid), int(n_lambda), ctypes.c_void_p(chi), ctypes.c_void_p(out),
+                                  ctypes.c_void_p(stream or None)), "rt_lstar_stencil")
 
 
 def rt_launch_shape(grid: int) -> dict:
@@ -291,7 +300,8 @@ class Grid:
     (n_lambda, Nz, Ny, Nx), of dtype float32 (prec "f32") or float64 ("f64")."""
 
     def __init__(self, Nx: int, Ny: int, Nz: int, n_mu: int, n_phi: int, prec: str = "f32",
-                 n_lambda_max: int = 1, lstar: str = "linear", band_tiles: bool = False):
+                 n_lambda_max: int = 1, lstar: str = "linear", band_tiles: bool = False,
+                 nonlocal_lstar: bool = False):
         d = RtGridDesc()
         d.struct_size = ctypes.sizeof(RtGridDesc)
         d.geom = RT_GEOM_BOX_PERIODIC_XY
@@ -299,7 +309,8 @@ class Grid:
         d.n_mu, d.n_phi = n_mu, n_phi
         d.n_lambda_max = n_lambda_max
         d.prec = RT_FP32 if prec == "f32" else RT_FP64
-        d.flags = (RT_F_LSTAR_PARABOLIC if lstar == "parabolic" else 0) | (RT_F_BAND_TILES if band_tiles else 0)
+        d.flags = ((RT_F_LSTAR_PARABOLIC if lstar == "parabolic" else 0) | (RT_F_BAND_TILES if band_tiles else 0)
+                   | (RT_F_LSTAR_NONLOCAL if nonlocal_lstar else 0))
         self.desc = d
         self.shape = (Nz, Ny, Nx)
         self.nbc = 2
@@ -374,6 +385,15 @@ class Grid:
     def set_launch_shape(self, threads, rays):
         rt_set_launch_shape(self.handle, threads, rays)
 
+    def lstar_stencil(self, chi, stream=None):
+        """Nearest-neighbour Lambda* (n_lambda, 27, Nz, Ny, Nx) for the opacity chi."""
+        import torch
+        n = chi.shape[0]
+        c = self._check_field(chi, n, "chi")
+        out = torch.empty((n, 27) + tuple(chi.shape[1:]), dtype=chi.dtype, device=chi.device)
+        rt_lstar_stencil(self.handle, n, c, out.data_ptr(), _stream_ptr(stream))
+        return out
+
     def launch_shape(self):
         """dict(threads, rays, bundles, band) of the single-output sweep."""
         return rt_launch_shape(self.handle)
@@ -402,13 +422,14 @@ class Grid:
 
     @staticmethod
     def opts(tol=1e-8, max_iter=1000, ng_every=4, ng_start=4, reanchor=0, use_graph=False, net_every=0,
-             method="ali"):
+             method="ali", os_sweeps=0):
         o = RtSolveOpts()
         o.struct_size = ctypes.sizeof(RtSolveOpts)
         o.tol, o.max_iter, o.ng_every, o.ng_start, o.reanchor = tol, max_iter, ng_every, ng_start, reanchor
         o.use_graph = int(bool(use_graph))
         o.net_every = int(net_every)
         o.method = {"ali": 0, "bicgstab": 1}[method]
+        o.os_sweeps = int(os_sweeps)
         return o
 
     def set_preconditioner(self, blob):
