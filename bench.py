@@ -126,22 +126,27 @@ def one_gpu_share(case, shape, n_gpus: int = 8, reps: int = 3):
             "vdu_per_s": case.n_vox * len(dirs) / wall}
 
 
-def time_to_solution(case, net_every: int = 12, tol: float = 1e-6):
+def time_to_solution(case, net_every: int = 12, tol: float = 1e-6, shape=None):
     """Wall seconds of rt_solve to the stopping tolerance `tol` (which lands below
     1e-5 relative error on this workload) for plain double-precision Ng-ALI,
-    single-precision defect-corrected Ng-ALI, and the latter with the learned
-    correction; each with its max relative J error against a double-precision
-    solution iterated 80 steps past convergence to 1e-9 change."""
+    single-precision defect-corrected Ng-ALI, the latter with the learned
+    correction, Ng-ALI with the nearest-neighbour Lambda* (single and double
+    precision; the stencil build is inside the timed call) and BiCGStab (the
+    single-precision runs use the launch shape tuned for the throughput line); each
+    with its max relative J error against a double-precision Ng-ALI solution
+    iterated to 1e-9 change (at most 80 steps)."""
     import torch
 
     import paper_2102_01734_amd as rt
     blob_path = os.path.join(ROOT, "paper_2102_01734_amd", "data", "precond_box.rtun")
     blob = open(blob_path, "rb").read()
 
-    def run(prec, tol_, max_iter, net=0, method="ali"):
+    def run(prec, tol_, max_iter, net=0, method="ali", nonlocal_lstar=False):
         dt = torch.float32 if prec == "f32" else torch.float64
         dev = dict(dtype=dt, device="cuda")
-        g = rt.Grid(case.Nx, case.Ny, case.Nz, case.n_mu, case.n_phi, prec, 1)
+        g = rt.Grid(case.Nx, case.Ny, case.Nz, case.n_mu, case.n_phi, prec, 1, nonlocal_lstar=nonlocal_lstar)
+        if prec == "f32" and shape:
+            g.set_launch_shape(*shape)  # the single-precision sweep shape tuned for the throughput line
         if net:
             g.set_preconditioner(blob)
         st = g.new_state(*(torch.tensor(a, **dev) for a in (case.chi, case.eps, case.B, case.I_bc)))
@@ -160,11 +165,13 @@ def time_to_solution(case, net_every: int = 12, tol: float = 1e-6):
     ref, _, rref, _ = run("f64", 1e-9, 80)
     out = {"tol": tol, "target_error": 1e-5,
            "reference": f"double-precision Ng-ALI, {rref.iters} steps (last max |dJ/J| {rref.max_rel_change:.1e})"}
-    for name, prec, net, method, tol_m in (("plain_f64_ng_ali", "f64", 0, "ali", tol),
-                                           ("f32_defect_corrected_ng_ali", "f32", 0, "ali", tol),
-                                           ("f32_learned", "f32", net_every, "ali", tol),
-                                           ("bicgstab_f64", "f64", 0, "bicgstab", 1e-8)):
-        J, status, rep, wall = run(prec, tol_m, 300, net, method)
+    for name, prec, net, method, tol_m, nl in (("plain_f64_ng_ali", "f64", 0, "ali", tol, False),
+                                               ("f32_defect_corrected_ng_ali", "f32", 0, "ali", tol, False),
+                                               ("f32_learned", "f32", net_every, "ali", tol, False),
+                                               ("f32_nonlocal_ng_ali", "f32", 0, "ali", tol, True),
+                                               ("f64_nonlocal_ng_ali", "f64", 0, "ali", tol, True),
+                                               ("bicgstab_f64", "f64", 0, "bicgstab", 1e-8, False)):
+        J, status, rep, wall = run(prec, tol_m, 300, net, method, nl)
         err = float(((J - ref).abs() / ref.abs()).max())
         out[name] = {"seconds": wall, "steps": rep.iters, "formal_solutions": rep.n_fs, "fp64_fs": rep.n_fs64,
                      "status": status, "max_rel_error": err, "tol": tol_m}
@@ -174,6 +181,7 @@ def time_to_solution(case, net_every: int = 12, tol: float = 1e-6):
     out["speedup_f32_vs_plain"] = base / out["f32_defect_corrected_ng_ali"]["seconds"]
     out["speedup_learned_vs_plain"] = base / out["f32_learned"]["seconds"]
     out["speedup_bicgstab_vs_plain"] = base / out["bicgstab_f64"]["seconds"]
+    out["speedup_f32_nonlocal_vs_plain"] = base / out["f32_nonlocal_ng_ali"]["seconds"]
     return out
 
 
@@ -367,7 +375,7 @@ def main():
     if case.n_lambda == 1:
         out["one_gpu_share"] = one_gpu_share(case, shape)
     if not args.no_solve and case.n_lambda == 1:
-        out["time_to_solution"] = time_to_solution(case)
+        out["time_to_solution"] = time_to_solution(case, shape=shape)
     if not args.no_cpu_baseline and case.n_lambda == 1:
         n_sub = args.cpu_dirs or max(8, min(case.n_dir, round(4.1e8 / case.n_vox)))
         out["cpu_baseline"] = cpu_baseline(case, n_sub)
