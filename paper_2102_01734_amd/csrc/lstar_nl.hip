@@ -113,13 +113,15 @@ __global__ void __launch_bounds__(256) lstar_stencil_kernel(StencilArgs a)
         const double Dp = last ? 0.0 : half_sum(t_cur, t_nxt);
         double ex, wa, wb, wg;
         if (PARA) {
-            const PointW<double> pw = point_weights<double>(D, Dp, last);
+            const PointW<double> pw = point_weights<double>(D, Dp, last);  // full double series
             ex = pw.ex; wa = pw.a; wb = pw.b; wg = pw.g;
         } else {
+            // single-precision grids keep the stencil in float: the shorter
+            // moment series of the float sweep suffices there
             const double Dv = D < kMinStep ? kMinStep : D;
             double e0, e1, e2;
-            kernel_moments<true>(Dv, ex, e0, e1, e2);
-            wb = e1 / Dv;
+            kernel_moments<sizeof(G) == 8>(Dv, ex, e0, e1, e2);
+            wb = e1 * rcp_f64(Dv);
             wa = e0 - wb;
             wg = 0.0;
         }
