@@ -94,36 +94,53 @@ def cpu_baseline(case, n_sub: int):
 def one_gpu_share(case, shape, n_gpus: int = 8, reps: int = 3):
     """One GPU's part of an n_gpus solid-angle decomposition: the single-precision
     formal solution over shard 0 of the visit-balanced direction shards (no
-    all-reduce, which this one-GPU run cannot show)."""
+    all-reduce, which this one-GPU run cannot show).  Two layouts are timed:
+    the full run's launch shape (whole-layer tiles; few directions leave one
+    workgroup per direction and the shallowest sets the time) and band tiles
+    autotuned on the shard's own directions (many row bundles per direction);
+    the faster one is reported."""
     import torch
 
     import paper_2102_01734_amd as rt
     import synthetic as sy
     dev = dict(dtype=torch.float32, device="cuda")
-    g = rt.Grid(case.Nx, case.Ny, case.Nz, case.n_mu, case.n_phi, "f32", 1)
-    if shape:
-        g.set_launch_shape(*shape)
     chi = torch.tensor(case.chi, **dev)
     S = torch.tensor(sy.random_source(case.chi.shape, seed=7, lo=0.2, hi=1.0, dtype="f32"), **dev)
     Ib = torch.tensor(case.I_bc, **dev)
     M = [rt.rt_box_template(case.Nz, case.n_mu, case.n_phi, d)["s"].size for d in range(case.n_dir)]
-    shards = [g.shard_directions(n_gpus, k) for k in range(n_gpus)]
-    loads = [sum(M[d] for d in s) for s in shards]
-    dirs = shards[0]
-    g.formal_solution_dirs(chi, S, dirs, I_bc=Ib)
-    torch.cuda.synchronize()
-    rt.rt_profile_read(g.handle)
-    rt.rt_profile_enable(g.handle, True)
-    t0 = time.perf_counter()
-    for _ in range(reps):
+
+    def timed(band):
+        g = rt.Grid(case.Nx, case.Ny, case.Nz, case.n_mu, case.n_phi, "f32", 1, band_tiles=band)
+        shards = [g.shard_directions(n_gpus, k) for k in range(n_gpus)]
+        dirs = shards[0]
+        if band:
+            g.autotune_dirs(chi[:1].contiguous(), S[:1].contiguous(), dirs)
+        elif shape:
+            g.set_launch_shape(*shape)
+        ls = g.launch_shape()
         g.formal_solution_dirs(chi, S, dirs, I_bc=Ib)
-    torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) / reps
-    fs_ms, n, _ = rt.rt_profile_read(g.handle)
-    g.close()
+        torch.cuda.synchronize()
+        rt.rt_profile_read(g.handle)
+        rt.rt_profile_enable(g.handle, True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g.formal_solution_dirs(chi, S, dirs, I_bc=Ib)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / reps
+        fs_ms, n, _ = rt.rt_profile_read(g.handle)
+        g.close()
+        return shards, dirs, wall, fs_ms / max(n, 1), ls
+
+    shards, dirs, wall_l, k_l, ls_l = timed(False)
+    _, _, wall_b, k_b, ls_b = timed(True)
+    loads = [sum(M[d] for d in s) for s in shards]
+    wall, kern, ls = (wall_b, k_b, ls_b) if wall_b < wall_l else (wall_l, k_l, ls_l)
     return {"gpus": n_gpus, "directions": int(len(dirs)), "visit_imbalance": max(loads) / (sum(loads) / n_gpus),
-            "ms_per_fs": wall * 1e3, "kernel_ms": fs_ms / max(n, 1),
-            "vdu_per_s": case.n_vox * len(dirs) / wall}
+            "ms_per_fs": wall * 1e3, "kernel_ms": kern,
+            "vdu_per_s": case.n_vox * len(dirs) / wall,
+            "launch_shape": {"threads": ls["threads"], "rays_per_thread": ls["rays"], "bundles": ls["bundles"],
+                             "tiles": "band" if ls["band"] else "layer"},
+            "layer_tiles_ms_per_fs": wall_l * 1e3, "band_tiles_ms_per_fs": wall_b * 1e3}
 
 
 def time_to_solution(case, net_every: int = 12, tol: float = 1e-6, shape=None):

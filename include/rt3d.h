@@ -389,6 +389,17 @@ rt_status rt_autotune(rt_grid_t grid, int32_t n_lambda, const void *chi, const v
                       int32_t *rays_out, void *stream);
 
 /*
+ * rt_autotune on the formal solution over a subset of the directions (as
+ * rt_formal_solution_dirs takes them: host, strictly increasing indices), for
+ * a grid that will sweep only that share, e.g. one GPU's directions of a
+ * solid-angle decomposition (Sec. 4): few directions need more ray bundles
+ * per direction (RT_F_BAND_TILES shapes) to keep every CU busy.  Errors as
+ * rt_autotune and rt_formal_solution_dirs.
+ */
+rt_status rt_autotune_dirs(rt_grid_t grid, int32_t n_lambda, const void *chi, const void *S, int32_t n_dirs,
+                           const int32_t *dirs, int32_t *threads_out, int32_t *rays_out, void *stream);
+
+/*
  * Fixes the launch shape of the grid's single-output formal-solution kernel
  * to one of the compiled shapes (threads = workgroup size bound, rays = rays
  * per thread), e.g. one that rt_autotune chose in an earlier process, so that

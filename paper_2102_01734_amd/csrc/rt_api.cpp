@@ -881,8 +881,8 @@ rt_status rt_destroy_grid(rt_grid_t grid)
     return RT_OK;
 }
 
-rt_status rt_autotune(rt_grid_t g, int32_t n_lambda, const void *chi, const void *S, int32_t *threads_out,
-                      int32_t *rays_out, void *stream)
+static rt_status autotune(rt_grid *g, int32_t n_lambda, const void *chi, const void *S,
+                         const std::vector<int32_t> *subset, int32_t *threads_out, int32_t *rays_out, void *stream)
 {
     if (!g) return fail(RT_E_INVALID, "grid is NULL");
     if (n_lambda < 1 || n_lambda > g->desc.n_lambda_max)
@@ -919,10 +919,10 @@ rt_status rt_autotune(rt_grid_t g, int32_t n_lambda, const void *chi, const void
         DevSchedule *sc = nullptr;
         DevBuf &pJ = dbl ? g->partJ64 : g->partJ;
         DevBuf &pL = dbl ? g->partL64 : g->partL;
-        rs = run_fs_with(g, v, lams, g->fs_fld.p, nullptr, pJ, pL, &sc, st);  // warm-up
+        rs = run_fs_with(g, v, lams, g->fs_fld.p, nullptr, pJ, pL, &sc, st, subset);  // warm-up
         if (rs != RT_OK) break;
         if (hipEventRecord(e0, st) != hipSuccess) { rs = fail(RT_E_HIP, "event record failed"); break; }
-        rs = run_fs_with(g, v, lams, g->fs_fld.p, nullptr, pJ, pL, &sc, st);
+        rs = run_fs_with(g, v, lams, g->fs_fld.p, nullptr, pJ, pL, &sc, st, subset);
         if (rs != RT_OK) break;
         if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
             rs = fail(RT_E_HIP, "event timing failed");
@@ -941,6 +941,26 @@ rt_status rt_autotune(rt_grid_t g, int32_t n_lambda, const void *chi, const void
     if (threads_out) *threads_out = best.lb;
     if (rays_out) *rays_out = best.R;
     return RT_OK;
+}
+
+rt_status rt_autotune(rt_grid_t g, int32_t n_lambda, const void *chi, const void *S, int32_t *threads_out,
+                      int32_t *rays_out, void *stream)
+{
+    return autotune(g, n_lambda, chi, S, nullptr, threads_out, rays_out, stream);
+}
+
+rt_status rt_autotune_dirs(rt_grid_t g, int32_t n_lambda, const void *chi, const void *S, int32_t n_dirs,
+                           const int32_t *dirs, int32_t *threads_out, int32_t *rays_out, void *stream)
+{
+    if (!g) return fail(RT_E_INVALID, "grid is NULL");
+    if (g->sphere) return fail(RT_E_UNSUPPORTED, "launch shapes apply to the box sweep only");
+    if (n_dirs < 1 || !dirs) return fail(RT_E_INVALID, "need at least one direction");
+    std::vector<int32_t> sub(dirs, dirs + n_dirs);
+    for (int32_t i = 0; i < n_dirs; ++i) {
+        if (sub[i] < 0 || sub[i] >= g->n_dir) return fail(RT_E_INVALID, "direction %d out of range", sub[i]);
+        if (i > 0 && sub[i] <= sub[i - 1]) return fail(RT_E_INVALID, "directions must be strictly increasing");
+    }
+    return autotune(g, n_lambda, chi, S, &sub, threads_out, rays_out, stream);
 }
 
 rt_status rt_set_launch_shape(rt_grid_t g, int32_t threads, int32_t rays)

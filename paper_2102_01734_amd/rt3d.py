@@ -84,6 +84,9 @@ def lib() -> ctypes.CDLL:
         getattr(L, f).restype = ctypes.c_int
     L.rt_autotune.argtypes = [vp, i32, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32), vp]
     L.rt_autotune.restype = ctypes.c_int
+    L.rt_autotune_dirs.argtypes = [vp, i32, vp, vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                   ctypes.POINTER(i32), vp]
+    L.rt_autotune_dirs.restype = ctypes.c_int
     L.rt_set_launch_shape.argtypes = [vp, i32, i32]
     L.rt_set_launch_shape.restype = ctypes.c_int
     L.rt_launch_shape.argtypes = [vp] + [ctypes.POINTER(i32)] * 4
@@ -176,6 +179,17 @@ def rt_autotune(grid: int, n_lambda: int, chi: int, S: int, stream: Optional[int
     t, r = ctypes.c_int32(), ctypes.c_int32()
     _check(lib().rt_autotune(ctypes.c_void_p(grid), int(n_lambda), ctypes.c_void_p(chi), ctypes.c_void_p(S),
                              ctypes.byref(t), ctypes.byref(r), ctypes.c_void_p(stream or None)), "rt_autotune")
+    return t.value, r.value
+
+
+def rt_autotune_dirs(grid: int, n_lambda: int, chi: int, S: int, dirs, stream: Optional[int]):
+    """rt_autotune over a direction subset; returns (threads, rays per thread) kept."""
+    import numpy as np
+    d = np.ascontiguousarray(dirs, dtype=np.int32)
+    t, r = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().rt_autotune_dirs(ctypes.c_void_p(grid), int(n_lambda), ctypes.c_void_p(chi), ctypes.c_void_p(S),
+                                  int(d.size), d.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(t),
+                                  ctypes.byref(r), ctypes.c_void_p(stream or None)), "rt_autotune_dirs")
     return t.value, r.value
 
 
@@ -381,6 +395,11 @@ class Grid:
         n = chi.shape[0]
         return rt_autotune(self.handle, n, self._check_field(chi, n, "chi"), self._check_field(S, n, "S"),
                            _stream_ptr(stream))
+
+    def autotune_dirs(self, chi, S, dirs, stream=None):
+        n = chi.shape[0]
+        return rt_autotune_dirs(self.handle, n, self._check_field(chi, n, "chi"), self._check_field(S, n, "S"),
+                                dirs, _stream_ptr(stream))
 
     def set_launch_shape(self, threads, rays):
         rt_set_launch_shape(self.handle, threads, rays)

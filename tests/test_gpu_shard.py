@@ -69,3 +69,27 @@ def test_shard_arguments_are_checked():
     with pytest.raises(rt.RtError):
         sph.shard_directions(2, 0)
     sph.close()
+
+
+def test_autotune_on_a_share_with_band_tiles(orc):
+    """rt_autotune_dirs on one shard of a band-tile grid keeps a band shape and
+    the shard's partial J: the oracle's formal solution over the same
+    directions; bad direction lists are refused."""
+    import paper_2102_01734_amd as rt
+    torch = torch_cuda()
+    case = sy.random_box(40, 37, 6, 4, 8, seed=25, dtype="f32")
+    S = sy.random_source(case.chi.shape, seed=26, dtype="f32")
+    g = make_grid(case, band_tiles=True)
+    chi, St, Ib = to_dev(case.chi, "f32"), to_dev(S, "f32"), to_dev(case.I_bc, "f32")
+    dirs = g.shard_directions(4, 1)
+    threads, rays = g.autotune_dirs(chi, St, dirs)
+    ls = g.launch_shape()
+    assert ls["band"] and (ls["threads"], ls["rays"]) == (threads, rays)
+    Jp, _ = g.formal_solution_dirs(chi, St, dirs, I_bc=Ib)
+    torch.cuda.synchronize()
+    for bad in ([3, 1], [0, 32], []):
+        with pytest.raises(rt.RtError):
+            g.autotune_dirs(chi, St, np.array(bad, np.int32))
+    g.close()
+    Jo, _ = orc.fs_box_dirs(case.chi[0], S[0], case.I_bc[0, 0], case.I_bc[0, 1], 4, 8, dirs)
+    np.testing.assert_allclose(Jp.cpu().numpy()[0], Jo, rtol=2e-5, atol=1e-6 * np.abs(Jo).max())
