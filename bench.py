@@ -243,7 +243,7 @@ def bench_sphere(args, w):
     dev = dict(dtype=torch.float32, device="cuda")
     t0 = time.perf_counter()
     g = rt.SphereGrid(case.Nr, case.Nt, case.Np, case.r_core, case.r_out, case.n_mu, case.n_phi, "f32",
-                      case.n_lambda, source_distance=case.source_distance)
+                      case.n_lambda, source_distance=case.source_distance, host_cache=args.host_cache)
     t_build = time.perf_counter() - t0
     info = g.info()
     st = g.new_state(torch.tensor(case.chi, **dev), torch.tensor(case.eps, **dev), torch.tensor(case.B, **dev),
@@ -276,7 +276,8 @@ def bench_sphere(args, w):
                                "step = one ALI iteration over the batch",
                    "voxels": case.n_vox, "directions": case.n_dir, "wavelengths": case.n_lambda,
                    "vdu_per_step": vdu, "visits_per_vdu": info["n_visits"] / (case.n_vox * case.n_dir),
-                   "cache_chunks": info["n_workgroups"], "cache_build_s": t_build},
+                   "cache_chunks": info["n_workgroups"], "cache_build_s": t_build,
+                   "cache_bytes": g.cache_bytes()},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS, "traffic": None,
                      "kernel": "fs_sphere_kernel<float,float,J> + sphere_gather (per chunk)",
@@ -299,6 +300,8 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-solution comparison")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--shape", default=None, help="fix the launch shape THREADS,RAYS instead of autotuning")
+    ap.add_argument("--host-cache", action="store_true",
+                    help="sphere workload: keep the geometry cache in host memory and stream it (SmallGPU mode)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (HBM counter calibration)")
     args = ap.parse_args()

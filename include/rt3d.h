@@ -90,6 +90,15 @@ typedef enum { RT_FP64 = 0, RT_FP32 = 1 } rt_prec;
                                      sweeps (rt_solve_opts.os_sweeps).  The
                                      state's lstar array still receives the
                                      diagonal.                                 */
+#define RT_F_HOST_CACHE 0x8u      /* sphere: keep every chunk of the geometry
+                                     cache in pinned host memory and stream it
+                                     to the GPU for each formal solution (the
+                                     paper's SmallGPU mode, Sec. 5).  Without
+                                     the flag, chunks stay in device memory
+                                     while it lasts and only the rest is
+                                     streamed.  Streamed grids run their ALI
+                                     steps without graph capture.  Results are
+                                     bitwise those of a device-resident cache. */
 
 typedef struct rt_grid *rt_grid_t;
 
@@ -420,6 +429,13 @@ rt_status rt_set_launch_shape(rt_grid_t grid, int32_t threads, int32_t rays);
  * 0.  Any out pointer may be NULL.  RT_E_UNSUPPORTED on spherical grids.
  */
 rt_status rt_launch_shape(rt_grid_t grid, int32_t *threads, int32_t *rays, int32_t *bundles, int32_t *band);
+
+/*
+ * Bytes of the grid's geometry cache held in device memory and in pinned
+ * host memory (streamed chunks of a spherical grid; 0 for box grids, whose
+ * cache is one template per direction).  Any out pointer may be NULL.
+ */
+rt_status rt_cache_bytes(rt_grid_t grid, int64_t *device_bytes, int64_t *host_bytes);
 
 /*
  * Measurement hooks.  While enabled, every formal-solution kernel launch of

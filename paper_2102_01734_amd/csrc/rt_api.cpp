@@ -97,8 +97,12 @@ struct DevSchedule {
     DevBuf wg_begin, items, slot_begin, slot_ids, lambda_of;
 };
 
-// Device copy of one chunk of the spherical geometry cache, bundle-major
-// (chunk-local indices; see fs_sphere.hpp).
+// One chunk of the spherical geometry cache, bundle-major (chunk-local
+// indices; see fs_sphere.hpp).  Either resident in device memory (one
+// buffer per array) or, when device memory runs short or the grid asks for
+// it, packed into one pinned host block that is streamed through a device
+// staging buffer for every formal solution (the paper's SmallGPU mode,
+// Sec. 5: caches kept on the host and sent to the GPU per solid angle).
 struct SphereChunkDev {
     SphereChunk info;
     int64_t n_chars = 0, n_visits = 0, n_bundles = 0, n_entries = 0;
@@ -108,7 +112,51 @@ struct SphereChunkDev {
     DevBuf vox;           // int32 [n_entries]
     DevBuf s, w;          // geometry type [n_entries]
     DevBuf row, idx;      // CSR voxel -> entries: int32 [n_vox + 1], int32 [n_visits]
+    // host placement: the same eight arrays packed at 256-byte aligned offsets
+    void *host = nullptr;
+    size_t bytes = 0;     // packed size (either placement)
+    size_t off[8] = {};
+    ~SphereChunkDev()
+    {
+        if (host) (void)hipHostFree(host);
+    }
 };
+
+// Device pointers of a chunk's arrays (staged chunks: inside the staging buffer).
+struct ChunkPtrs {
+    const int64_t *bundle_begin;
+    const int32_t *char_len;
+    const double *char_g;
+    const int32_t *vox;
+    const void *s, *w;
+    const int32_t *row, *idx;
+};
+
+static ChunkPtrs chunk_ptrs(const SphereChunkDev &ch, const void *stage)
+{
+    ChunkPtrs p{};
+    if (ch.host) {
+        const char *b = static_cast<const char *>(stage);
+        p.bundle_begin = reinterpret_cast<const int64_t *>(b + ch.off[0]);
+        p.char_len = reinterpret_cast<const int32_t *>(b + ch.off[1]);
+        p.char_g = reinterpret_cast<const double *>(b + ch.off[2]);
+        p.vox = reinterpret_cast<const int32_t *>(b + ch.off[3]);
+        p.s = b + ch.off[4];
+        p.w = b + ch.off[5];
+        p.row = reinterpret_cast<const int32_t *>(b + ch.off[6]);
+        p.idx = reinterpret_cast<const int32_t *>(b + ch.off[7]);
+    } else {
+        p.bundle_begin = ch.bundle_begin.as<int64_t>();
+        p.char_len = ch.char_len.as<int32_t>();
+        p.char_g = ch.char_g.as<double>();
+        p.vox = ch.vox.as<int32_t>();
+        p.s = ch.s.p;
+        p.w = ch.w.p;
+        p.row = ch.row.as<int32_t>();
+        p.idx = ch.idx.as<int32_t>();
+    }
+    return p;
+}
 
 struct rt_grid {
     rt_grid_desc desc{};
@@ -119,6 +167,13 @@ struct rt_grid {
     SphereCache sph;
     std::vector<std::unique_ptr<SphereChunkDev>> sph_chunks;
     DevBuf sph_outJ, sph_outL;  // per-visit contributions of one chunk
+    // streamed chunks: two staging buffers, a copy stream and its events
+    bool sph_host_cache = false;  // RT_F_HOST_CACHE: every chunk on the host
+    bool sph_streaming = false;   // some chunk lives on the host
+    DevBuf sph_stage[2];
+    hipStream_t sph_copy = nullptr;
+    hipEvent_t sph_copied[2] = {nullptr, nullptr}, sph_done[2] = {nullptr, nullptr};
+    int64_t cache_dev_bytes = 0, cache_host_bytes = 0;
     // layout of the formal-solution input: box (Nx, Ny, Nz); sphere (n_vox, 0, 1)
     int lx = 0, ly = 0, lz = 0;
     int nbc = 2;  // boundary values per wavelength in I_bc
@@ -169,6 +224,11 @@ struct rt_grid {
     }
     ~rt_grid()
     {
+        for (int i = 0; i < 2; ++i) {
+            if (sph_copied[i]) (void)hipEventDestroy(sph_copied[i]);
+            if (sph_done[i]) (void)hipEventDestroy(sph_done[i]);
+        }
+        if (sph_copy) (void)hipStreamDestroy(sph_copy);
         for (auto &e : prof_events) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
         drop_graphs();
         if (net) unet_destroy(net);
@@ -352,16 +412,44 @@ static rt_status run_fs_sphere(rt_grid *g, const Variant &v, const std::vector<i
         HIPCHK(hipEventCreate(&e1));
         HIPCHK(hipEventRecord(e0, st));
     }
-    for (size_t c = 0; c < g->sph_chunks.size(); ++c) {
+    // chunks kept on the host go through two staging buffers: the copy of the
+    // next one (copy stream) overlaps the sweep and gather of the current one
+    const size_t n_ch = g->sph_chunks.size();
+    std::vector<int> slot_of(n_ch, -1);
+    std::vector<size_t> host_order;
+    for (size_t c = 0; c < n_ch; ++c)
+        if (g->sph_chunks[c]->host) {
+            slot_of[c] = (int)(host_order.size() % 2);
+            host_order.push_back(c);
+        }
+    auto issue_copy = [&](size_t k) -> hipError_t {
+        const size_t c = host_order[k];
+        const int sl = slot_of[c];
         const SphereChunkDev &ch = *g->sph_chunks[c];
+        hipError_t e = hipStreamWaitEvent(g->sph_copy, g->sph_done[sl], 0);  // the buffer's last reader is done
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(g->sph_stage[sl].p, ch.host, ch.bytes, hipMemcpyHostToDevice, g->sph_copy);
+        if (e == hipSuccess) e = hipEventRecord(g->sph_copied[sl], g->sph_copy);
+        return e;
+    };
+    size_t next_copy = 0;
+    if (!host_order.empty()) {
+        HIPCHK(issue_copy(0));
+        next_copy = 1;
+    }
+    for (size_t c = 0; c < n_ch; ++c) {
+        const SphereChunkDev &ch = *g->sph_chunks[c];
+        const int sl = slot_of[c];
+        if (sl >= 0) HIPCHK(hipStreamWaitEvent(st, g->sph_copied[sl], 0));
+        const ChunkPtrs cp = chunk_ptrs(ch, sl >= 0 ? g->sph_stage[sl].p : nullptr);
         FsSphereArgs a{};
         a.n_bundles = ch.n_bundles;
-        a.bundle_begin = ch.bundle_begin.as<int64_t>();
-        a.char_len = ch.char_len.as<int32_t>();
-        a.char_g = ch.char_g.as<double>();
-        a.vox = ch.vox.as<int32_t>();
-        a.s = ch.s.p;
-        a.w = ch.w.p;
+        a.bundle_begin = cp.bundle_begin;
+        a.char_len = cp.char_len;
+        a.char_g = cp.char_g;
+        a.vox = cp.vox;
+        a.s = cp.s;
+        a.w = cp.w;
         a.lambda_of = sc->lambda_of.as<int32_t>();
         a.n_batch = nb;
         a.lam_stride = g->lx;
@@ -372,11 +460,13 @@ static rt_status run_fs_sphere(rt_grid *g, const Variant &v, const std::vector<i
         a.outL = wl ? g->sph_outL.p : nullptr;
         HIPCHK(fs_sphere_launch(a, dbl, g->sph_gdouble, wj, wl, g->para, st));
         if (wj)
-            HIPCHK(sphere_gather(g->sph_outJ.p, dbl, ch.row.as<int32_t>(), ch.idx.as<int32_t>(), g->n_vox, nb, partJ.p,
-                                 dbl, c > 0, st));
+            HIPCHK(sphere_gather(g->sph_outJ.p, dbl, cp.row, cp.idx, g->n_vox, nb, partJ.p, dbl, c > 0, st));
         if (wl)
-            HIPCHK(sphere_gather(g->sph_outL.p, dbl, ch.row.as<int32_t>(), ch.idx.as<int32_t>(), g->n_vox, nb, partL.p,
-                                 dbl, c > 0, st));
+            HIPCHK(sphere_gather(g->sph_outL.p, dbl, cp.row, cp.idx, g->n_vox, nb, partL.p, dbl, c > 0, st));
+        if (sl >= 0) {
+            HIPCHK(hipEventRecord(g->sph_done[sl], st));
+            if (next_copy < host_order.size()) HIPCHK(issue_copy(next_copy++));
+        }
     }
     if (g->prof) {
         HIPCHK(hipEventRecord(e1, st));
@@ -503,7 +593,7 @@ void prepare_sphere_direction(const SphereSpec &spec, double h, const std::vecto
 }
 
 template <typename TG>
-hipError_t upload_chunk(SphereChunkDev &ch, const std::vector<SphereDirCache> &dirs, int64_t n_vox)
+hipError_t upload_chunk(SphereChunkDev &ch, const std::vector<SphereDirCache> &dirs, int64_t n_vox, bool force_host)
 {
     // every characteristic of the chunk, longest first (ties in direction and trace order)
     struct Ref { int d; int64_t c, off, len; };
@@ -560,6 +650,34 @@ hipError_t upload_chunk(SphereChunkDev &ch, const std::vector<SphereDirCache> &d
             const int64_t m = (e - bb[(size_t)b]) / 64, c = (e - bb[(size_t)b]) % 64;
             if (m < clen[(size_t)(b * 64 + c)]) idx[(size_t)fill[(size_t)vx[(size_t)e]]++] = (int32_t)e;
         }
+    // placement: device memory while it lasts (a reserve stays free for the
+    // per-visit outputs, partial sums and state), else pinned host memory
+    const void *src[8] = {bb.data(), clen.data(), cg.data(), vx.data(), sv.data(), wv.data(), row.data(), idx.data()};
+    const size_t len[8] = {bb.size() * 8, clen.size() * 4, cg.size() * 8, vx.size() * 4,
+                           sv.size() * sizeof(TG), wv.size() * sizeof(TG), row.size() * 4, idx.size() * 4};
+    size_t total = 0;
+    for (int i = 0; i < 8; ++i) {
+        ch.off[i] = total;
+        total += (len[i] + 255) / 256 * 256;
+    }
+    ch.bytes = total;
+    bool to_host = force_host;
+    if (!to_host) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) return hipErrorOutOfMemory;
+        const size_t reserve = std::max<size_t>((size_t)2 << 30, std::min<size_t>((size_t)32 << 30, tot / 8));
+        to_host = fr < total + reserve;
+    }
+    if (to_host) {
+        hipError_t e = hipHostMalloc(&ch.host, total, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            ch.host = nullptr;
+            return e;
+        }
+        for (int i = 0; i < 8; ++i)
+            if (len[i]) std::memcpy(static_cast<char *>(ch.host) + ch.off[i], src[i], len[i]);
+        return hipSuccess;
+    }
     auto up = [](DevBuf &d, const void *src, size_t n) -> hipError_t {
         hipError_t e = d.ensure(n > 0 ? n : 16);
         if (e != hipSuccess || n == 0) return e;
@@ -621,8 +739,15 @@ static rt_status build_sphere_grid(rt_grid *g, const rt_grid_desc *desc)
         auto ch = std::make_unique<SphereChunkDev>();
         ch->info.dir_begin = chunk_dir0;
         ch->info.dir_end = dir_end;
-        hipError_t e = g->sph_gdouble ? upload_chunk<double>(*ch, pending, nvox) : upload_chunk<float>(*ch, pending, nvox);
+        hipError_t e = g->sph_gdouble ? upload_chunk<double>(*ch, pending, nvox, g->sph_host_cache)
+                                      : upload_chunk<float>(*ch, pending, nvox, g->sph_host_cache);
         if (e != hipSuccess) return fail(RT_E_HIP, "geometry upload: %s", hipGetErrorString(e));
+        if (ch->host) {
+            g->sph_streaming = true;
+            g->cache_host_bytes += (int64_t)ch->bytes;
+        } else {
+            g->cache_dev_bytes += (int64_t)ch->bytes;
+        }
         for (const auto &d : pending)
             for (int64_t l : d.len) ch->info.max_len = std::max<int64_t>(ch->info.max_len, l);
         sc.n_chars += ch->n_chars;
@@ -743,8 +868,10 @@ rt_status rt_create_grid(const rt_grid_desc *desc, rt_grid_t *out)
         return fail(RT_E_INVALID, "unknown geometry %d", desc->geom);
     if (desc->prec != RT_FP32 && desc->prec != RT_FP64) return fail(RT_E_INVALID, "unknown precision %d", desc->prec);
     if (desc->n_lambda_max < 1) return fail(RT_E_INVALID, "n_lambda_max must be >= 1");
-    if (desc->flags & ~(RT_F_LSTAR_PARABOLIC | RT_F_BAND_TILES | RT_F_LSTAR_NONLOCAL))
+    if (desc->flags & ~(RT_F_LSTAR_PARABOLIC | RT_F_BAND_TILES | RT_F_LSTAR_NONLOCAL | RT_F_HOST_CACHE))
         return fail(RT_E_INVALID, "unknown flags 0x%x", desc->flags);
+    if (desc->geom == RT_GEOM_BOX_PERIODIC_XY && (desc->flags & RT_F_HOST_CACHE))
+        return fail(RT_E_INVALID, "RT_F_HOST_CACHE applies to spherical grids only");
     if (desc->geom == RT_GEOM_SPHERICAL && (desc->flags & (RT_F_BAND_TILES | RT_F_LSTAR_NONLOCAL)))
         return fail(RT_E_INVALID, "RT_F_BAND_TILES and RT_F_LSTAR_NONLOCAL apply to box grids only");
     if (desc->geom == RT_GEOM_SPHERICAL) {
@@ -762,9 +889,21 @@ rt_status rt_create_grid(const rt_grid_desc *desc, rt_grid_t *out)
         g->n_vox = nv;
         g->lx = desc->n_lambda_max; g->ly = 0; g->lz = (int)nv;  // voxel-major pairs [v][n_lambda_max]
         g->nbc = 3;
+        g->sph_host_cache = (desc->flags & RT_F_HOST_CACHE) != 0;
         HIPCHK(hipGetDevice(&g->device));
         rt_status rs = build_sphere_grid(g.get(), desc);
         if (rs != RT_OK) return rs;
+        if (g->sph_streaming) {
+            size_t stage = 0;
+            for (const auto &ch : g->sph_chunks)
+                if (ch->host) stage = std::max(stage, ch->bytes);
+            for (int i = 0; i < 2; ++i) {
+                HIPCHK(g->sph_stage[i].ensure(stage));
+                HIPCHK(hipEventCreateWithFlags(&g->sph_copied[i], hipEventDisableTiming));
+                HIPCHK(hipEventCreateWithFlags(&g->sph_done[i], hipEventDisableTiming));
+            }
+            HIPCHK(hipStreamCreateWithFlags(&g->sph_copy, hipStreamNonBlocking));
+        }
         g->n_dir = (int)g->sph.dirs.size();
         g->n_visits = g->sph.n_visits;
         // per-visit output buffers at their largest size (double, n_lambda_max), so
@@ -997,6 +1136,16 @@ rt_status rt_lstar_stencil(rt_grid_t g, int32_t n_lambda, const void *chi, void 
     if (rs != RT_OK) return rs;
     return compute_stencil(g, chi, n_lambda, n_lambda, sc->lambda_of.as<int32_t>(), out, g->dbl,
                            (hipStream_t)stream);
+}
+
+rt_status rt_cache_bytes(rt_grid_t g, int64_t *device_bytes, int64_t *host_bytes)
+{
+    if (!g) return fail(RT_E_INVALID, "grid is NULL");
+    int64_t d = g->cache_dev_bytes, h = g->cache_host_bytes;
+    if (!g->sphere) d = (int64_t)(g->goff.bytes + g->dxy.bytes + g->s.bytes + g->brow.bytes + g->comp.bytes);
+    if (device_bytes) *device_bytes = d;
+    if (host_bytes) *host_bytes = h;
+    return RT_OK;
 }
 
 rt_status rt_launch_shape(rt_grid_t g, int32_t *threads, int32_t *rays, int32_t *bundles, int32_t *band)
@@ -1419,7 +1568,7 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
 
     const bool want_l = s->lstar_valid == 0;
     if (!want_l && (g->dbl || !anchor)) {
-        if (o->use_graph && st != nullptr && !candidate)
+        if (o->use_graph && st != nullptr && !candidate && !g->sph_streaming)
             rs = graph_plain_step(g, s, lams, lambda_of, st, os_sweeps_of(o));
         else
             rs = plain_step_launches(g, s, lams, lambda_of, st, os_sweeps_of(o), !candidate);

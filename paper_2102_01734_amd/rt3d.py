@@ -19,6 +19,7 @@ RT_FP64, RT_FP32 = 0, 1
 RT_F_LSTAR_PARABOLIC = 0x1
 RT_F_BAND_TILES = 0x2
 RT_F_LSTAR_NONLOCAL = 0x4
+RT_F_HOST_CACHE = 0x8
 
 STATUS_NAMES = {0: "RT_OK", 1: "RT_E_INVALID", 2: "RT_E_NOMEM", 3: "RT_E_HIP", 4: "RT_E_NOT_CONVERGED",
                 5: "RT_E_NUMERIC", 6: "RT_E_UNSUPPORTED"}
@@ -93,6 +94,8 @@ def lib() -> ctypes.CDLL:
     L.rt_launch_shape.restype = ctypes.c_int
     L.rt_lstar_stencil.argtypes = [vp, i32, vp, vp, vp]
     L.rt_lstar_stencil.restype = ctypes.c_int
+    L.rt_cache_bytes.argtypes = [vp, i64p, i64p]
+    L.rt_cache_bytes.restype = ctypes.c_int
     L.rt_profile_enable.argtypes = [vp, i32]
     L.rt_profile_enable.restype = ctypes.c_int
     L.rt_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32), i64p]
@@ -202,6 +205,13 @@ def rt_lstar_stencil(grid: int, n_lambda: int, chi: int, out: int, stream: Optio
                                   ctypes.c_void_p(stream or None)), "rt_lstar_stencil")
 
 
+def rt_cache_bytes(grid: int) -> dict:
+    """Geometry-cache bytes in device memory and in pinned host memory."""
+    d, h = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().rt_cache_bytes(ctypes.c_void_p(grid), ctypes.byref(d), ctypes.byref(h)), "rt_cache_bytes")
+    return dict(device=d.value, host=h.value)
+
+
 def rt_launch_shape(grid: int) -> dict:
     """Launch shape of the single-output sweep: threads, rays, bundles, band (bool)."""
     v = [ctypes.c_int32() for _ in range(4)]
@@ -269,7 +279,8 @@ def rt_precond_forward(grid: int, features: int, out: int, stream: Optional[int]
 
 
 def sphere_desc(Nr: int, Nt: int, Np: int, r_core: float, r_out: float, n_mu: int, n_phi: int, prec: str = "f32",
-                n_lambda_max: int = 1, lstar: str = "linear", source_distance: float = 0.0) -> RtGridDesc:
+                n_lambda_max: int = 1, lstar: str = "linear", source_distance: float = 0.0,
+                host_cache: bool = False) -> RtGridDesc:
     d = RtGridDesc()
     d.struct_size = ctypes.sizeof(RtGridDesc)
     d.geom = RT_GEOM_SPHERICAL
@@ -278,7 +289,7 @@ def sphere_desc(Nr: int, Nt: int, Np: int, r_core: float, r_out: float, n_mu: in
     d.n_mu, d.n_phi = n_mu, n_phi
     d.n_lambda_max = n_lambda_max
     d.prec = RT_FP32 if prec == "f32" else RT_FP64
-    d.flags = RT_F_LSTAR_PARABOLIC if lstar == "parabolic" else 0
+    d.flags = (RT_F_LSTAR_PARABOLIC if lstar == "parabolic" else 0) | (RT_F_HOST_CACHE if host_cache else 0)
     return d
 
 
@@ -413,6 +424,10 @@ class Grid:
         rt_lstar_stencil(self.handle, n, c, out.data_ptr(), _stream_ptr(stream))
         return out
 
+    def cache_bytes(self):
+        """dict(device, host): bytes of the geometry cache in each memory."""
+        return rt_cache_bytes(self.handle)
+
     def launch_shape(self):
         """dict(threads, rays, bundles, band) of the single-output sweep."""
         return rt_launch_shape(self.handle)
@@ -483,8 +498,10 @@ class SphereGrid(Grid):
     (I_out, I_core, J_sub)."""
 
     def __init__(self, Nr: int, Nt: int, Np: int, r_core: float, r_out: float, n_mu: int, n_phi: int,
-                 prec: str = "f32", n_lambda_max: int = 1, lstar: str = "linear", source_distance: float = 0.0):
-        d = sphere_desc(Nr, Nt, Np, r_core, r_out, n_mu, n_phi, prec, n_lambda_max, lstar, source_distance)
+                 prec: str = "f32", n_lambda_max: int = 1, lstar: str = "linear", source_distance: float = 0.0,
+                 host_cache: bool = False):
+        d = sphere_desc(Nr, Nt, Np, r_core, r_out, n_mu, n_phi, prec, n_lambda_max, lstar, source_distance,
+                        host_cache)
         self.desc = d
         self.shape = (Np, Nt, Nr)
         self.nbc = 3
