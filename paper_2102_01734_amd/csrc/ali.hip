@@ -277,7 +277,7 @@ __global__ void __launch_bounds__(256) ali_update_kernel(AliUpdateArgs a)
         if (!(res <= 1.0e308)) res = __builtin_inf();
         if (a.net_r) a.net_r[i] = (float)rr;
         double den = 1.0 - (1.0 - e) * L;
-        den = den < 1e-12 ? 1e-12 : den;
+        den = den < os_den_min<G>() ? os_den_min<G>() : den;
         const double jn = a.dJ ? jo + a.dJ[i] : jo + (jfs - jo) / den;
         a.J[i] = jn;
         if (a.hist) a.hist[i] = jn;

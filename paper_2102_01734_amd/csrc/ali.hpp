@@ -28,6 +28,17 @@ hipError_t cast_array(const TS *src, TD *dst, int64_t n, hipStream_t st);
 
 hipError_t fill_u64(unsigned long long *p, unsigned long long v, int n, hipStream_t st);
 
+// Smallest operator-splitting denominator 1 - (1-eps) Lambda*_vv.  Where
+// eps -> 0 and the medium is optically thick, Lambda* approaches 1; stored
+// in single precision it can round to exactly 1 (a pure-scattering medium
+// then gives a zero denominator), so single-precision data clamp at 1e-7
+// (about their rounding unit), double-precision data at 1e-12.
+template <typename G>
+__host__ __device__ constexpr double os_den_min()
+{
+    return sizeof(G) == 4 ? 1e-7 : 1e-12;
+}
+
 struct AliUpdateArgs {
     int Nx, Ny;
     int64_t n_vox;

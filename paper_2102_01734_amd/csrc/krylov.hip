@@ -11,6 +11,7 @@
 
 #include <cstdint>
 
+#include "ali.hpp"
 #include "krylov.hpp"
 
 namespace rt3d {
@@ -69,7 +70,7 @@ __device__ __forceinline__ double precond(const KVec &a, int64_t i)
     const double e = (double)reinterpret_cast<const G *>(a.eps)[i];
     const double L = (double)reinterpret_cast<const G *>(a.lstar)[i];
     const double m = 1.0 - (1.0 - e) * L;
-    return m < 1e-12 ? 1e-12 : m;
+    return m < os_den_min<G>() ? os_den_min<G>() : m;
 }
 
 template <typename G>

@@ -30,6 +30,7 @@
 
 #include <cstdint>
 
+#include "ali.hpp"
 #include "fs_point.hpp"
 #include "lstar_nl.hpp"
 #include "rt_internal.hpp"
@@ -190,7 +191,7 @@ __global__ void __launch_bounds__(256) os_jacobi_kernel(OsJacobiArgs a, int firs
     const G *__restrict__ st = reinterpret_cast<const G *>(a.st) + base * kStencil;
     const G *__restrict__ eps = reinterpret_cast<const G *>(a.eps) + base;
     double den = 1.0 - (double)st[kStencilCentre * n + v] * (1.0 - (double)eps[v]);
-    den = den < 1e-12 ? 1e-12 : den;
+    den = den < os_den_min<G>() ? os_den_min<G>() : den;
     double acc = a.r[base + v];
     if (!first) {
         const int Nx = a.Nx, Ny = a.Ny;

@@ -178,3 +178,21 @@ def test_batched_wavelengths_converge_independently(orc):
     for l in range(4):
         ref = _lu(orc, case, l)
         np.testing.assert_allclose(r["J"][l], ref["J"], rtol=1e-9)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_pure_scattering_slab_reaches_fixed_point(orc, prec):
+    """eps = 0 (pure scattering) on a stratified slab (tau 1e-4..1e2) lit from its
+    thin top: the solve converges to the layer reduction's direct solution
+    (single precision: within 1e-5 through the double anchors)."""
+    import dataclasses
+    case = sy.box_stratified(N=9, Nz=33, eps=0.0, dtype=prec, tau_max=1e2)
+    case = dataclasses.replace(case, I_bc=np.array([[1.0, 0.0]]))
+    r = gpu_solve(case, tol=1e-10, max_iter=4000)
+    prob = orc.Plane1DProblem(case.chi[0, :, 0, 0], case.eps[0, :, 0, 0], 1.0, 1.0, 0.0, case.n_mu, case.n_phi)
+    exact = orc.direct(prob)
+    Jg = r["J"][0]
+    err = np.max(np.abs(Jg - exact["J"][:, None, None]) / exact["J"][:, None, None])
+    print(f"pure scattering {prec}: status {r['status']}, steps {r['report'].iters}, error {err:.2e}")
+    assert r["status"] == 0
+    assert err < (1e-5 if prec == "f32" else 1e-8)
