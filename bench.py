@@ -46,6 +46,11 @@ WORKLOADS = {
 }
 
 
+def progress(msg: str) -> None:
+    """One progress line on stderr (stdout carries only the result line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def fs_source_hash() -> str:
     """Hash of the box sweep kernel's sources (the kernel file and its point arithmetic)."""
     h = hashlib.sha256()
@@ -194,6 +199,7 @@ def time_to_solution(case, net_every: int = 12, tol: float = 1e-6, shape=None):
         return J, status, rep, wall
 
     ref, _, rref, _ = run("f64", 1e-9, 80)
+    progress(f"time to solution: reference {rref.iters} steps")
     target = 1e-5
     out = {"tol": tol, "target_error": target, "f64_launch_shape": list(shape64),
            "reference": f"double-precision Ng-ALI, {rref.iters} steps (last max |dJ/J| {rref.max_rel_change:.1e})",
@@ -212,6 +218,7 @@ def time_to_solution(case, net_every: int = 12, tol: float = 1e-6, shape=None):
                                                ("bicgstab_f64", "f64", 0, "bicgstab", 1e-8, False)):
         J, status, rep, wall = run(prec, tol_m, 300, net, method, nl)
         err = err_of(J)
+        progress(f"time to solution: {name} {rep.iters} steps {wall:.2f} s error {err:.2e}")
         out[name] = {"seconds": wall, "steps": rep.iters, "formal_solutions": rep.n_fs, "fp64_fs": rep.n_fs64,
                      "status": status, "max_rel_error": err, "tol": tol_m}
         if net:
@@ -224,6 +231,7 @@ def time_to_solution(case, net_every: int = 12, tol: float = 1e-6, shape=None):
                 mid = (lo + hi) // 2
                 Jm, _, repm, wallm = run(prec, 1e-30, mid, net, method, nl)
                 em = err_of(Jm)
+                progress(f"time to solution: {name} limited to {mid} steps: error {em:.2e}, {wallm:.2f} s")
                 if em <= target:
                     hi = mid
                     best = (mid, wallm, em, repm.n_fs)
@@ -257,6 +265,7 @@ def bench_sphere(args, w):
     g = rt.SphereGrid(case.Nr, case.Nt, case.Np, case.r_core, case.r_out, case.n_mu, case.n_phi, "f32",
                       case.n_lambda, source_distance=case.source_distance, host_cache=args.host_cache)
     t_build = time.perf_counter() - t0
+    progress(f"spherical geometry cache built in {t_build:.1f} s")
     info = g.info()
     st = g.new_state(torch.tensor(case.chi, **dev), torch.tensor(case.eps, **dev), torch.tensor(case.B, **dev),
                      torch.tensor(case.I_bc, **dev))
@@ -347,6 +356,7 @@ def main():
     else:
         case = sy.box_lognormal(N=w["N"], n_mu=w["n_mu"], n_phi=w["n_phi"], field_seed=w.get("field_seed", 1),
                                 eps_seed=w.get("eps_seed", 101))
+    progress(f"workload {args.workload} generated")
     dev = dict(dtype=torch.float32, device="cuda")
     chi = torch.tensor(case.chi, **dev)
     eps = torch.tensor(case.eps, **dev)
@@ -361,6 +371,7 @@ def main():
     else:
         shape = g.autotune(chi[:1].contiguous(), S0[:1].contiguous()) if not args.no_autotune else None
     del S0
+    progress(f"launch shape {shape}")
     info = g.info()
     ls = g.launch_shape()
     st = g.new_state(chi, eps, B, Ibc)
@@ -434,8 +445,10 @@ def main():
     g.close()
     del st
     torch.cuda.synchronize()
+    progress(f"{args.steps} timed steps: {ms_per_step:.1f} ms per step")
     if case.n_lambda == 1:
         out["one_gpu_share"] = one_gpu_share(case, shape)
+        progress("one-GPU share timed")
     if not args.no_solve and case.n_lambda == 1:
         out["time_to_solution"] = time_to_solution(case, shape=shape)
     if not args.no_cpu_baseline and case.n_lambda == 1:
