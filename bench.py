@@ -181,6 +181,8 @@ def time_to_solution(case, net_every: int = 12, tol: float = 1e-6, shape=None):
         g = rt.Grid(case.Nx, case.Ny, case.Nz, case.n_mu, case.n_phi, prec, 1, nonlocal_lstar=nonlocal_lstar)
         if prec == "f32" and shape:
             g.set_launch_shape(*shape)  # the single-precision sweep shape tuned for the throughput line
+        if prec == "f32":
+            g.set_anchor_shape(*shape64)  # double-precision anchors as tuned on a double grid
         if prec == "f64":
             g.set_launch_shape(*shape64)
         if net:

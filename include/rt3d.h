@@ -421,6 +421,14 @@ rt_status rt_autotune_dirs(rt_grid_t grid, int32_t n_lambda, const void *chi, co
 rt_status rt_set_launch_shape(rt_grid_t grid, int32_t threads, int32_t rays);
 
 /*
+ * RT_FP32 box grids: fixes the launch shape of the double-precision anchor
+ * sweep (the defect-correction anchors of rt_solve), e.g. to the shape that
+ * rt_autotune picked on a double-precision grid of the same size.  Shapes
+ * and errors as rt_set_launch_shape; RT_E_INVALID on double-precision grids.
+ */
+rt_status rt_set_anchor_shape(rt_grid_t grid, int32_t threads, int32_t rays);
+
+/*
  * The launch shape that the grid's single-output formal-solution kernel
  * uses now (box grids): workgroup size bound, rays per thread, ray bundles
  * per direction (workgroups that share one direction, each with its own tile

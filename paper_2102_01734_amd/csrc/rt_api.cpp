@@ -1121,6 +1121,25 @@ rt_status rt_set_launch_shape(rt_grid_t g, int32_t threads, int32_t rays)
     return fail(RT_E_INVALID, "no compiled launch shape %d threads x %d rays", threads, rays);
 }
 
+rt_status rt_set_anchor_shape(rt_grid_t g, int32_t threads, int32_t rays)
+{
+    if (!g) return fail(RT_E_INVALID, "grid is NULL");
+    if (g->sphere) return fail(RT_E_UNSUPPORTED, "launch shapes apply to the box sweep only");
+    if (g->dbl) return fail(RT_E_INVALID, "double-precision grids have no anchor sweep");
+    const FsShape *sh = nullptr;
+    const int n = fs_box_shapes(&sh);
+    for (int i = 0; i < n; ++i) {
+        if (sh[i].lb != threads || sh[i].R != rays || sh[i].band != g->band) continue;
+        const Variant v = make_variant(g, true, true, false, threads, rays, sh[i].occ, sh[i].band);
+        if (!v.ok)
+            return fail(RT_E_INVALID, "shape %d x %d cannot hold the rays of a direction in double precision",
+                        threads, rays);
+        variant(g, true, true, false) = v;
+        return RT_OK;
+    }
+    return fail(RT_E_INVALID, "no compiled launch shape %d threads x %d rays", threads, rays);
+}
+
 rt_status rt_lstar_stencil(rt_grid_t g, int32_t n_lambda, const void *chi, void *out, void *stream)
 {
     if (!g) return fail(RT_E_INVALID, "grid is NULL");

@@ -89,6 +89,8 @@ def lib() -> ctypes.CDLL:
                                    ctypes.POINTER(i32), vp]
     L.rt_autotune_dirs.restype = ctypes.c_int
     L.rt_set_launch_shape.argtypes = [vp, i32, i32]
+    L.rt_set_anchor_shape.argtypes = [vp, i32, i32]
+    L.rt_set_anchor_shape.restype = ctypes.c_int
     L.rt_set_launch_shape.restype = ctypes.c_int
     L.rt_launch_shape.argtypes = [vp] + [ctypes.POINTER(i32)] * 4
     L.rt_launch_shape.restype = ctypes.c_int
@@ -183,6 +185,10 @@ def rt_autotune(grid: int, n_lambda: int, chi: int, S: int, stream: Optional[int
     _check(lib().rt_autotune(ctypes.c_void_p(grid), int(n_lambda), ctypes.c_void_p(chi), ctypes.c_void_p(S),
                              ctypes.byref(t), ctypes.byref(r), ctypes.c_void_p(stream or None)), "rt_autotune")
     return t.value, r.value
+
+
+def rt_set_anchor_shape(grid: int, threads: int, rays: int) -> None:
+    _check(lib().rt_set_anchor_shape(ctypes.c_void_p(grid), int(threads), int(rays)), "rt_set_anchor_shape")
 
 
 def rt_autotune_dirs(grid: int, n_lambda: int, chi: int, S: int, dirs, stream: Optional[int]):
@@ -414,6 +420,9 @@ class Grid:
 
     def set_launch_shape(self, threads, rays):
         rt_set_launch_shape(self.handle, threads, rays)
+
+    def set_anchor_shape(self, threads, rays):
+        rt_set_anchor_shape(self.handle, threads, rays)
 
     def lstar_stencil(self, chi, stream=None):
         """Nearest-neighbour Lambda* (n_lambda, 27, Nz, Ny, Nx) for the opacity chi."""

@@ -196,3 +196,24 @@ def test_pure_scattering_slab_reaches_fixed_point(orc, prec):
     print(f"pure scattering {prec}: status {r['status']}, steps {r['report'].iters}, error {err:.2e}")
     assert r["status"] == 0
     assert err < (1e-5 if prec == "f32" else 1e-8)
+
+
+def test_anchor_shape_changes_only_the_summation_order(orc):
+    """A fixed launch shape for the double-precision anchors of a single
+    precision grid: the solve reaches the same fixed point; double-precision
+    grids and uncompiled shapes are refused."""
+    import paper_2102_01734_amd as rt
+    case = sy.random_box(9, 9, 8, 4, 8, seed=47, dtype="f32", eps_dex=(-4, -2))
+    g = make_grid(case)
+    g.set_anchor_shape(1024, 4)
+    with pytest.raises(rt.RtError):
+        g.set_anchor_shape(100, 3)
+    r = gpu_solve(case, tol=1e-9, max_iter=3000, grid=g)
+    g.close()
+    ref = _lu(orc, case)
+    assert r["status"] == 0
+    assert np.max(np.abs(r["J"][0] - ref["J"]) / np.abs(ref["J"])) < 1e-5
+    g64 = make_grid(sy.random_box(9, 9, 8, 4, 8, seed=47, dtype="f64"))
+    with pytest.raises(rt.RtError):
+        g64.set_anchor_shape(1024, 4)
+    g64.close()
