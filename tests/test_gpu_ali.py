@@ -205,9 +205,11 @@ def test_anchor_shape_changes_only_the_summation_order(orc):
     import paper_2102_01734_amd as rt
     case = sy.random_box(9, 9, 8, 4, 8, seed=47, dtype="f32", eps_dex=(-4, -2))
     g = make_grid(case)
-    g.set_anchor_shape(1024, 4)
+    g.set_anchor_shape(1024, 1)
     with pytest.raises(rt.RtError):
-        g.set_anchor_shape(100, 3)
+        g.set_anchor_shape(100, 3)      # not compiled
+    with pytest.raises(rt.RtError):
+        g.set_anchor_shape(1024, 4)     # 81 rays cannot fill 4 ray slots per thread
     r = gpu_solve(case, tol=1e-9, max_iter=3000, grid=g)
     g.close()
     ref = _lu(orc, case)
@@ -215,5 +217,5 @@ def test_anchor_shape_changes_only_the_summation_order(orc):
     assert np.max(np.abs(r["J"][0] - ref["J"]) / np.abs(ref["J"])) < 1e-5
     g64 = make_grid(sy.random_box(9, 9, 8, 4, 8, seed=47, dtype="f64"))
     with pytest.raises(rt.RtError):
-        g64.set_anchor_shape(1024, 4)
+        g64.set_anchor_shape(1024, 1)
     g64.close()
