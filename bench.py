@@ -60,16 +60,21 @@ def fs_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(workload: str):
+def read_traffic(workload: str, ls: dict):
     """HBM bytes per launch from the committed counter summary, if it was taken
-    on the current kernel source; else None."""
+    on the current kernel source and launch shape (`ls` as Grid.launch_shape()
+    gives it); else None."""
     path = os.path.join(ROOT, "profiles", f"fs_box_{workload}_traffic.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     m_hash = re.search(r"fs_box\.hip sha256\[:16\]:\s*([0-9a-f]+)", txt)
     m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m_hash or not m_bytes or m_hash.group(1) != fs_source_hash():
+    m_shape = re.search(r"launch_shape:\s*(\d+),(\d+),(\d+),(band|layer)", txt)
+    if not m_hash or not m_bytes or not m_shape or m_hash.group(1) != fs_source_hash():
+        return None
+    here = (str(ls["threads"]), str(ls["rays"]), str(ls["bundles"]), "band" if ls["band"] else "layer")
+    if m_shape.groups() != here:
         return None
     return float(m_bytes.group(1))
 
@@ -100,10 +105,10 @@ def one_gpu_share(case, shape, n_gpus: int = 8, reps: int = 3):
     """One GPU's part of an n_gpus solid-angle decomposition: the single-precision
     formal solution over shard 0 of the visit-balanced direction shards (no
     all-reduce, which this one-GPU run cannot show).  Two layouts are timed:
-    the full run's launch shape (whole-layer tiles; few directions leave one
-    workgroup per direction and the shallowest sets the time) and band tiles
-    autotuned on the shard's own directions (many row bundles per direction);
-    the faster one is reported."""
+    the full run's launch shape (tuned on all directions: few directions leave
+    few workgroups per direction and the shallowest sets the time) and band
+    tiles autotuned on the shard's own directions (more row bundles per
+    direction); the faster one is reported."""
     import torch
 
     import paper_2102_01734_amd as rt
@@ -114,11 +119,11 @@ def one_gpu_share(case, shape, n_gpus: int = 8, reps: int = 3):
     Ib = torch.tensor(case.I_bc, **dev)
     M = [rt.rt_box_template(case.Nz, case.n_mu, case.n_phi, d)["s"].size for d in range(case.n_dir)]
 
-    def timed(band):
-        g = rt.Grid(case.Nx, case.Ny, case.Nz, case.n_mu, case.n_phi, "f32", 1, band_tiles=band)
+    def timed(tune_on_share):
+        g = rt.Grid(case.Nx, case.Ny, case.Nz, case.n_mu, case.n_phi, "f32", 1, band_tiles=tune_on_share)
         shards = [g.shard_directions(n_gpus, k) for k in range(n_gpus)]
         dirs = shards[0]
-        if band:
+        if tune_on_share:
             g.autotune_dirs(chi[:1].contiguous(), S[:1].contiguous(), dirs)
         elif shape:
             g.set_launch_shape(*shape)
@@ -145,7 +150,7 @@ def one_gpu_share(case, shape, n_gpus: int = 8, reps: int = 3):
             "vdu_per_s": case.n_vox * len(dirs) / wall,
             "launch_shape": {"threads": ls["threads"], "rays_per_thread": ls["rays"], "bundles": ls["bundles"],
                              "tiles": "band" if ls["band"] else "layer"},
-            "layer_tiles_ms_per_fs": wall_l * 1e3, "band_tiles_ms_per_fs": wall_b * 1e3}
+            "full_run_shape_ms_per_fs": wall_l * 1e3, "share_tuned_band_ms_per_fs": wall_b * 1e3}
 
 
 def time_to_solution(case, net_every: int = 12, tol: float = 1e-6, shape=None):
@@ -171,7 +176,9 @@ def time_to_solution(case, net_every: int = 12, tol: float = 1e-6, shape=None):
     chi64 = torch.tensor(case.chi[:1], dtype=torch.float64, device="cuda")
     S64 = torch.tensor(sy.random_source(case.chi[:1].shape, seed=7, lo=0.2, hi=1.0), dtype=torch.float64,
                        device="cuda")
-    shape64 = g64.autotune(chi64, S64)
+    g64.autotune(chi64, S64)
+    ls64 = g64.launch_shape()
+    shape64 = (ls64["threads"], ls64["rays"], bool(ls64["band"]))
     g64.close()
     del chi64, S64
 
@@ -322,7 +329,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-solution comparison")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
-    ap.add_argument("--shape", default=None, help="fix the launch shape THREADS,RAYS instead of autotuning")
+    ap.add_argument("--shape", default=None, help="fix the launch shape THREADS,RAYS[,BAND] (BAND 1: row-band tiles) instead of autotuning")
     ap.add_argument("--host-cache", action="store_true",
                     help="sphere workload: keep the geometry cache in host memory and stream it (SmallGPU mode)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -370,8 +377,13 @@ def main():
     if args.shape:
         shape = tuple(int(v) for v in args.shape.split(","))
         g.set_launch_shape(*shape)
+    elif not args.no_autotune:
+        g.autotune(chi[:1].contiguous(), S0[:1].contiguous())
+    if args.shape or not args.no_autotune:
+        ls0 = g.launch_shape()
+        shape = (ls0["threads"], ls0["rays"], bool(ls0["band"]))   # reproduced exactly on the other grids
     else:
-        shape = g.autotune(chi[:1].contiguous(), S0[:1].contiguous()) if not args.no_autotune else None
+        shape = None
     del S0
     progress(f"launch shape {shape}")
     info = g.info()
@@ -400,7 +412,7 @@ def main():
     fs_ms_launch = fs_ms / max(fs_launches, 1)
     points_launch = fs_points / max(fs_launches, 1)
     achieved = FLOPS_PER_POINT * points_launch / (fs_ms_launch * 1e-3) / 1e12
-    traffic = read_traffic(args.workload)
+    traffic = read_traffic(args.workload, ls)
 
     out = {
         "metric": "voxel-direction updates/s (formal solution)",

@@ -387,7 +387,11 @@ rt_status rt_sphere_tracks(const rt_grid_desc *desc, int32_t dir, double *h_out,
  * that can hold one direction's rays, on the caller's fields (n_lambda
  * wavelengths of chi and S, device, as in rt_formal_solution, zero boundary
  * intensity), and keeps the fastest for all later formal solutions and ALI
- * steps of this grid.  The shape changes only how directions are grouped
+ * steps of this grid.  Row-band tile shapes compete on every box grid (their
+ * flush covers only the rows a bundle reaches, which can beat whole-layer
+ * tiles even where those fit); whole-layer shapes only on grids without
+ * RT_F_BAND_TILES whose layer fits the LDS.  rt_launch_shape reports which
+ * kind was kept.  The shape changes only how directions are grouped
  * into workgroup partial sums, i.e. the summation order of J (differences
  * at the rounding level of the grid precision).  Blocks.  Box grids only
  * (RT_E_UNSUPPORTED on spherical grids).
@@ -416,17 +420,28 @@ rt_status rt_autotune_dirs(rt_grid_t grid, int32_t n_lambda, const void *chi, co
  * than the bound when a direction has fewer rays.  RT_E_INVALID if no
  * compiled shape matches or the shape cannot hold one direction's rays in
  * the device's LDS; RT_E_UNSUPPORTED on spherical grids.  Does not launch
- * anything.
+ * anything.  Where a shape is compiled for both tile kinds, the grid's own
+ * kind (row bands with RT_F_BAND_TILES or a layer beyond the LDS, else whole
+ * layers) is taken; rt_set_launch_shape_tiles names the kind.
  */
 rt_status rt_set_launch_shape(rt_grid_t grid, int32_t threads, int32_t rays);
 
 /*
+ * rt_set_launch_shape with the tile kind named: band = 1 for row-band tiles,
+ * 0 for whole-layer tiles (as rt_launch_shape reports it), so that a shape
+ * kept by rt_autotune can be set again exactly.  Whole-layer tiles on a grid
+ * that needs row bands are RT_E_INVALID; other errors as rt_set_launch_shape.
+ */
+rt_status rt_set_launch_shape_tiles(rt_grid_t grid, int32_t threads, int32_t rays, int32_t band);
+
+/*
  * RT_FP32 box grids: fixes the launch shape of the double-precision anchor
  * sweep (the defect-correction anchors of rt_solve), e.g. to the shape that
- * rt_autotune picked on a double-precision grid of the same size.  Shapes
- * and errors as rt_set_launch_shape; RT_E_INVALID on double-precision grids.
+ * rt_autotune picked on a double-precision grid of the same size (band as
+ * rt_set_launch_shape_tiles takes it).  Shapes and errors as
+ * rt_set_launch_shape_tiles; RT_E_INVALID on double-precision grids.
  */
-rt_status rt_set_anchor_shape(rt_grid_t grid, int32_t threads, int32_t rays);
+rt_status rt_set_anchor_shape(rt_grid_t grid, int32_t threads, int32_t rays, int32_t band);
 
 /*
  * The launch shape that the grid's single-output formal-solution kernel

@@ -1052,7 +1052,9 @@ static rt_status autotune(rt_grid *g, int32_t n_lambda, const void *chi, const v
     g->prof = false;
     rt_status rs = RT_OK;
     for (int i = 0; i < n && rs == RT_OK; ++i) {
-        if (sh[i].band != g->band) continue;
+        // band tiles compete on every grid (their flush covers only the rows a
+        // bundle reaches); layer tiles only where the grid is not in band mode
+        if (g->band && !sh[i].band) continue;
         const Variant v = make_variant(g, dbl, true, false, sh[i].lb, sh[i].R, sh[i].occ, sh[i].band);
         if (!v.ok) continue;
         DevSchedule *sc = nullptr;
@@ -1102,42 +1104,48 @@ rt_status rt_autotune_dirs(rt_grid_t g, int32_t n_lambda, const void *chi, const
     return autotune(g, n_lambda, chi, S, &sub, threads_out, rays_out, stream);
 }
 
+static rt_status set_shape(rt_grid *g, bool dbl, int32_t threads, int32_t rays, int band)
+{
+    const FsShape *sh = nullptr;
+    const int n = fs_box_shapes(&sh);
+    for (int pass = 0; pass < 2; ++pass)  // the grid's own tile kind first when band < 0
+        for (int i = 0; i < n; ++i) {
+            if (sh[i].lb != threads || sh[i].R != rays) continue;
+            if (band >= 0 ? sh[i].band != (band != 0) : (sh[i].band != g->band) != (pass == 1)) continue;
+            if (g->band && !sh[i].band) continue;
+            const Variant v = make_variant(g, dbl, true, false, threads, rays, sh[i].occ, sh[i].band);
+            if (!v.ok) continue;
+            variant(g, dbl, true, false) = v;
+            return RT_OK;
+        }
+    return fail(RT_E_INVALID, "no compiled launch shape %d threads x %d rays%s that holds the rays of a direction",
+                threads, rays, band < 0 ? "" : (band ? " (band tiles)" : " (layer tiles)"));
+}
+
+rt_status rt_set_launch_shape_tiles(rt_grid_t g, int32_t threads, int32_t rays, int32_t band)
+{
+    if (!g) return fail(RT_E_INVALID, "grid is NULL");
+    if (g->sphere) return fail(RT_E_UNSUPPORTED, "launch shapes apply to the box sweep only");
+    rt_status rs = set_shape(g, g->dbl, threads, rays, band ? 1 : 0);
+    if (rs == RT_OK) g->tuned = true;
+    return rs;
+}
+
 rt_status rt_set_launch_shape(rt_grid_t g, int32_t threads, int32_t rays)
 {
     if (!g) return fail(RT_E_INVALID, "grid is NULL");
     if (g->sphere) return fail(RT_E_UNSUPPORTED, "launch shapes apply to the box sweep only");
-    const FsShape *sh = nullptr;
-    const int n = fs_box_shapes(&sh);
-    for (int i = 0; i < n; ++i) {
-        if (sh[i].lb != threads || sh[i].R != rays || sh[i].band != g->band) continue;
-        const Variant v = make_variant(g, g->dbl, true, false, threads, rays, sh[i].occ, sh[i].band);
-        if (!v.ok)
-            return fail(RT_E_INVALID, "shape %d x %d cannot hold the %d rays of a direction on this device", threads,
-                        rays, g->geo.Nx * g->geo.Ny);
-        variant(g, g->dbl, true, false) = v;
-        g->tuned = true;
-        return RT_OK;
-    }
-    return fail(RT_E_INVALID, "no compiled launch shape %d threads x %d rays", threads, rays);
+    rt_status rs = set_shape(g, g->dbl, threads, rays, -1);
+    if (rs == RT_OK) g->tuned = true;
+    return rs;
 }
 
-rt_status rt_set_anchor_shape(rt_grid_t g, int32_t threads, int32_t rays)
+rt_status rt_set_anchor_shape(rt_grid_t g, int32_t threads, int32_t rays, int32_t band)
 {
     if (!g) return fail(RT_E_INVALID, "grid is NULL");
     if (g->sphere) return fail(RT_E_UNSUPPORTED, "launch shapes apply to the box sweep only");
     if (g->dbl) return fail(RT_E_INVALID, "double-precision grids have no anchor sweep");
-    const FsShape *sh = nullptr;
-    const int n = fs_box_shapes(&sh);
-    for (int i = 0; i < n; ++i) {
-        if (sh[i].lb != threads || sh[i].R != rays || sh[i].band != g->band) continue;
-        const Variant v = make_variant(g, true, true, false, threads, rays, sh[i].occ, sh[i].band);
-        if (!v.ok)
-            return fail(RT_E_INVALID, "shape %d x %d cannot hold the rays of a direction in double precision",
-                        threads, rays);
-        variant(g, true, true, false) = v;
-        return RT_OK;
-    }
-    return fail(RT_E_INVALID, "no compiled launch shape %d threads x %d rays", threads, rays);
+    return set_shape(g, true, threads, rays, band ? 1 : 0);
 }
 
 rt_status rt_lstar_stencil(rt_grid_t g, int32_t n_lambda, const void *chi, void *out, void *stream)

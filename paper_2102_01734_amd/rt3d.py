@@ -89,7 +89,9 @@ def lib() -> ctypes.CDLL:
                                    ctypes.POINTER(i32), vp]
     L.rt_autotune_dirs.restype = ctypes.c_int
     L.rt_set_launch_shape.argtypes = [vp, i32, i32]
-    L.rt_set_anchor_shape.argtypes = [vp, i32, i32]
+    L.rt_set_anchor_shape.argtypes = [vp, i32, i32, i32]
+    L.rt_set_launch_shape_tiles.argtypes = [vp, i32, i32, i32]
+    L.rt_set_launch_shape_tiles.restype = ctypes.c_int
     L.rt_set_anchor_shape.restype = ctypes.c_int
     L.rt_set_launch_shape.restype = ctypes.c_int
     L.rt_launch_shape.argtypes = [vp] + [ctypes.POINTER(i32)] * 4
@@ -187,8 +189,9 @@ def rt_autotune(grid: int, n_lambda: int, chi: int, S: int, stream: Optional[int
     return t.value, r.value
 
 
-def rt_set_anchor_shape(grid: int, threads: int, rays: int) -> None:
-    _check(lib().rt_set_anchor_shape(ctypes.c_void_p(grid), int(threads), int(rays)), "rt_set_anchor_shape")
+def rt_set_anchor_shape(grid: int, threads: int, rays: int, band: int) -> None:
+    _check(lib().rt_set_anchor_shape(ctypes.c_void_p(grid), int(threads), int(rays), int(band)),
+           "rt_set_anchor_shape")
 
 
 def rt_autotune_dirs(grid: int, n_lambda: int, chi: int, S: int, dirs, stream: Optional[int]):
@@ -204,6 +207,11 @@ def rt_autotune_dirs(grid: int, n_lambda: int, chi: int, S: int, dirs, stream: O
 
 def rt_set_launch_shape(grid: int, threads: int, rays: int) -> None:
     _check(lib().rt_set_launch_shape(ctypes.c_void_p(grid), int(threads), int(rays)), "rt_set_launch_shape")
+
+
+def rt_set_launch_shape_tiles(grid: int, threads: int, rays: int, band: int) -> None:
+    _check(lib().rt_set_launch_shape_tiles(ctypes.c_void_p(grid), int(threads), int(rays), int(band)),
+           "rt_set_launch_shape_tiles")
 
 
 def rt_lstar_stencil(grid: int, n_lambda: int, chi: int, out: int, stream: Optional[int]) -> None:
@@ -418,11 +426,15 @@ class Grid:
         return rt_autotune_dirs(self.handle, n, self._check_field(chi, n, "chi"), self._check_field(S, n, "S"),
                                 dirs, _stream_ptr(stream))
 
-    def set_launch_shape(self, threads, rays):
-        rt_set_launch_shape(self.handle, threads, rays)
+    def set_launch_shape(self, threads, rays, band=None):
+        """band None: the grid's own tile kind; True/False: row bands / whole layers."""
+        if band is None:
+            rt_set_launch_shape(self.handle, threads, rays)
+        else:
+            rt_set_launch_shape_tiles(self.handle, threads, rays, 1 if band else 0)
 
-    def set_anchor_shape(self, threads, rays):
-        rt_set_anchor_shape(self.handle, threads, rays)
+    def set_anchor_shape(self, threads, rays, band=False):
+        rt_set_anchor_shape(self.handle, threads, rays, 1 if band else 0)
 
     def lstar_stencil(self, chi, stream=None):
         """Nearest-neighbour Lambda* (n_lambda, 27, Nz, Ny, Nx) for the opacity chi."""

@@ -198,14 +198,15 @@ def test_pure_scattering_slab_reaches_fixed_point(orc, prec):
     assert err < (1e-5 if prec == "f32" else 1e-8)
 
 
-def test_anchor_shape_changes_only_the_summation_order(orc):
-    """A fixed launch shape for the double-precision anchors of a single
-    precision grid: the solve reaches the same fixed point; double-precision
-    grids and uncompiled shapes are refused."""
+@pytest.mark.parametrize("band", [False, True])
+def test_anchor_shape_changes_only_the_summation_order(orc, band):
+    """A fixed launch shape (whole-layer or row-band tiles) for the
+    double-precision anchors of a single precision grid: the solve reaches the
+    same fixed point; double-precision grids and uncompiled shapes are refused."""
     import paper_2102_01734_amd as rt
     case = sy.random_box(9, 9, 8, 4, 8, seed=47, dtype="f32", eps_dex=(-4, -2))
     g = make_grid(case)
-    g.set_anchor_shape(1024, 1)
+    g.set_anchor_shape(1024, 1, band=band)
     with pytest.raises(rt.RtError):
         g.set_anchor_shape(100, 3)      # not compiled
     with pytest.raises(rt.RtError):

@@ -161,6 +161,39 @@ def test_band_autotune_keeps_results():
     np.testing.assert_allclose(J1, J0, rtol=2e-6, atol=1e-7 * np.abs(J0).max())
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_band_shape_on_a_layer_grid(orc, prec):
+    """A grid whose layer fits a whole-layer tile can still run band tiles (the
+    autotuner times both kinds): a shape compiled for both kinds is set with
+    its kind named, matches the oracle, and is reproduced bitwise on a second
+    grid; whole-layer tiles are refused on a grid that needs bands."""
+    import paper_2102_01734_amd as rt
+    case = sy.random_box(31, 23, 9, 4, 8, seed=23, dtype=prec)
+    S = sy.random_source(case.chi.shape, seed=24, dtype=prec)
+    Jo, _ = _oracle_fs(orc, case, S, "linear")
+    tol = dict(rtol=1e-12) if prec == "f64" else dict(rtol=2e-5, atol=1e-6 * np.abs(Jo).max())
+    out = []
+    for band in (False, True, True):
+        g = make_grid(case)
+        assert not g.launch_shape()["band"]
+        g.set_launch_shape(1024, 2, band=band)
+        ls = g.launch_shape()
+        assert (ls["threads"], ls["rays"], ls["band"]) == (1024, 2, band)
+        J, _ = gpu_fs(case, S, grid=g, want_lstar=False)
+        g.close()
+        np.testing.assert_allclose(J, Jo, **tol)
+        out.append(J)
+    assert np.array_equal(out[1], out[2])
+    g = make_grid(case)
+    g.set_launch_shape(1024, 2)               # unnamed kind: the grid's own (whole layers)
+    assert not g.launch_shape()["band"]
+    g.close()
+    gb = make_grid(case, band_tiles=True)
+    with pytest.raises(rt.RtError):
+        gb.set_launch_shape(1024, 2, band=False)
+    gb.close()
+
+
 def test_band_tiles_refused_when_a_row_band_cannot_fit():
     """64 polar angles reach 45 rows per layer: 1000-voxel rows leave no band
     that fits the LDS of a CU, so the grid is refused (nothing launched)."""

@@ -158,7 +158,10 @@ def test_autotune_keeps_results(orc):
     g = make_grid(case)
     J0, _ = gpu_fs(case, S, grid=g, want_lstar=False)
     threads, rays = g.autotune(to_dev(case.chi, "f32"), to_dev(S, "f32"))
-    assert threads * rays >= case.Nx * case.Ny
+    ls = g.launch_shape()
+    assert (ls["threads"], ls["rays"]) == (threads, rays)
+    if not ls["band"]:     # whole-layer tiles: the bundles hold every ray of a direction
+        assert threads * rays * ls["bundles"] >= case.Nx * case.Ny
     J1, _ = gpu_fs(case, S, grid=g, want_lstar=False)
     g.close()
     np.testing.assert_allclose(J1, J0, rtol=2e-6, atol=1e-7 * np.abs(J0).max())
