@@ -191,6 +191,9 @@ struct rt_grid {
     // (grid precision), OS right-hand side and Jacobi iterates [lambda][vox]
     bool nonlocal = false;
     DevBuf nl_acc, nl_st, os_r, os_x0, os_x1;
+    // the stencil of an ALI step runs on a side stream beside its formal solutions
+    hipStream_t nl_side = nullptr;
+    hipEvent_t nl_fork = nullptr, nl_join = nullptr;
     int span_max = 0;   // largest per-layer row extent of any template
     bool band = false;  // the box sweep uses band tiles (see fs_box.hip)
     Variant var[2][2][2];  // [dbl][wj][wl]
@@ -229,6 +232,9 @@ struct rt_grid {
             if (sph_done[i]) (void)hipEventDestroy(sph_done[i]);
         }
         if (sph_copy) (void)hipStreamDestroy(sph_copy);
+        if (nl_fork) (void)hipEventDestroy(nl_fork);
+        if (nl_join) (void)hipEventDestroy(nl_join);
+        if (nl_side) (void)hipStreamDestroy(nl_side);
         for (auto &e : prof_events) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
         drop_graphs();
         if (net) unet_destroy(net);
@@ -1620,41 +1626,71 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
     ua.next_pad = g->fld.p;
     DevSchedule *sc = nullptr;
     const int sweeps = os_sweeps_of(o);
-    if (want_l && g->nonlocal) {
-        rs = compute_stencil(g, s->chi, nl, nb, lambda_of, g->nl_st.p, g->dbl, st);
-        if (rs != RT_OK) return rs;
+    // The stencil needs only chi and is read only by the OS update: it runs
+    // on a side stream, ready from the start of the step and enqueued after
+    // the step's sweeps (so that the first sweep's persistent workgroups are
+    // placed before its many small ones), and is joined before the update.
+    // The atomic-bound stencil build then shares the CUs with the first
+    // ALU-bound sweep; a later sweep waits for CUs until the stencil drains.
+    // Its sums are integers, so the result does not depend on the overlap.
+    bool stencil_pending = want_l && g->nonlocal, stencil_forked = false;
+    if (stencil_pending) {
+        if (!g->nl_side) HIPCHK(hipStreamCreateWithFlags(&g->nl_side, hipStreamNonBlocking));
+        if (!g->nl_fork) HIPCHK(hipEventCreateWithFlags(&g->nl_fork, hipEventDisableTiming));
+        if (!g->nl_join) HIPCHK(hipEventCreateWithFlags(&g->nl_join, hipEventDisableTiming));
+        HIPCHK(g->nl_acc.ensure((size_t)nl * kStencil * (size_t)nv * 8));  // no reallocation once forked
+        HIPCHK(hipEventRecord(g->nl_fork, st));  // chi and the work before this step are ready
     }
+    auto fork_stencil = [&]() -> rt_status {
+        if (!stencil_pending || stencil_forked) return RT_OK;
+        HIPCHK(hipStreamWaitEvent(g->nl_side, g->nl_fork, 0));
+        rt_status r = compute_stencil(g, s->chi, nl, nb, lambda_of, g->nl_st.p, g->dbl, g->nl_side);
+        if (r != RT_OK) return r;
+        HIPCHK(hipEventRecord(g->nl_join, g->nl_side));
+        stencil_forked = true;
+        return RT_OK;
+    };
+    auto join_stencil = [&]() -> rt_status {
+        rt_status r = fork_stencil();
+        if (r != RT_OK) return r;
+        if (stencil_forked) HIPCHK(hipStreamWaitEvent(st, g->nl_join, 0));
+        return RT_OK;
+    };
 
     if (g->dbl) {
         const bool joint = want_l && variant(g, true, true, true).ok;
+        DevSchedule *scL = nullptr;
         if (want_l && !joint) {
-            rs = run_fs(g, true, false, true, lams, g->fld.p, s->I_bc, g->partJ64, g->partL64, &sc, st);
+            rs = run_fs(g, true, false, true, lams, g->fld.p, s->I_bc, g->partJ64, g->partL64, &scL, st);
             if (rs != RT_OK) return rs;
-            HIPCHK(reduce_partials<double, double>(g->partL64.as<double>(), sc->slot_begin.as<int32_t>(), sc->slot_ids.as<int32_t>(),
-                                                   sc->lambda_of.as<int32_t>(), nb, (double *)s->lstar, nv, st));
             ++*fs_count; ++*fs64_count;
         }
         rs = run_fs(g, true, true, joint, lams, g->fld.p, s->I_bc, g->partJ64, g->partL64, &sc, st);
         if (rs != RT_OK) return rs;
+        rs = fork_stencil();
+        if (rs != RT_OK) return rs;
         ++*fs_count; ++*fs64_count;
+        if (scL)  // after the J sweep, so that it does not wait behind the stencil for CUs
+            HIPCHK(reduce_partials<double, double>(g->partL64.as<double>(), scL->slot_begin.as<int32_t>(),
+                                                   scL->slot_ids.as<int32_t>(), scL->lambda_of.as<int32_t>(), nb,
+                                                   (double *)s->lstar, nv, st));
         if (joint)
             HIPCHK(reduce_partials<double, double>(g->partL64.as<double>(), sc->slot_begin.as<int32_t>(), sc->slot_ids.as<int32_t>(),
                                                    sc->lambda_of.as<int32_t>(), nb, (double *)s->lstar, nv, st));
         ua.part = g->partJ64.p;
         ua.slot_begin = sc->slot_begin.as<int32_t>();
         ua.slot_ids = sc->slot_ids.as<int32_t>();
+        rs = join_stencil();
+        if (rs != RT_OK) return rs;
         rs = os_update(g, nl, ua, true, true, true, nb, sweeps, st);
         if (rs != RT_OK) return rs;
     } else {
-        if (want_l) {
-            rs = run_fs(g, false, false, true, lams, g->fld.p, nullptr, g->partJ, g->partL, &sc, st);
-            if (rs != RT_OK) return rs;
-            HIPCHK(reduce_partials<float, float>(g->partL.as<float>(), sc->slot_begin.as<int32_t>(), sc->slot_ids.as<int32_t>(),
-                                                 sc->lambda_of.as<int32_t>(), nb, (float *)s->lstar, nv, st));
-            ++*fs_count;
-        }
         ua.S_anchor = g->S_anchor.as<double>();
         ua.J_anchor = g->J_anchor.as<double>();
+        // The anchor's inputs (which the Lambda*-only sweep does not read) are
+        // prepared first and the Lambda* reduction follows the anchor sweep, so
+        // that the two sweeps are queued back to back.
+        const void *ibc = nullptr;
         if (anchor) {
             // double-precision anchor: S_a = S, J_a = Lambda S_a + Lambda_bc
             if (s->iter == 0)
@@ -1663,12 +1699,30 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
             else
                 HIPCHK(pad_field<double, double>(s->S, nullptr, g->fld64.as<double>(), Nx, Ny, Nz, nl, 1, st));
             HIPCHK(hipMemcpyAsync(g->S_anchor.p, s->S, (size_t)nl * nv * 8, hipMemcpyDeviceToDevice, st));
-            const void *ibc = nullptr;
             if (s->I_bc) {
                 HIPCHK(cast_array<float, double>((const float *)s->I_bc, g->ibc64.as<double>(), (int64_t)g->nbc * nl, st));
                 ibc = g->ibc64.p;
             }
+        }
+        DevSchedule *scL = nullptr;
+        if (want_l) {
+            rs = run_fs(g, false, false, true, lams, g->fld.p, nullptr, g->partJ, g->partL, &scL, st);
+            if (rs != RT_OK) return rs;
+            ++*fs_count;
+        }
+        auto reduce_lstar = [&]() -> rt_status {
+            if (scL)
+                HIPCHK(reduce_partials<float, float>(g->partL.as<float>(), scL->slot_begin.as<int32_t>(),
+                                                     scL->slot_ids.as<int32_t>(), scL->lambda_of.as<int32_t>(), nb,
+                                                     (float *)s->lstar, nv, st));
+            return RT_OK;
+        };
+        if (anchor) {
             rs = run_fs(g, true, true, false, lams, g->fld64.p, ibc, g->partJ64, g->partL64, &sc, st);
+            if (rs != RT_OK) return rs;
+            rs = fork_stencil();
+            if (rs != RT_OK) return rs;
+            rs = reduce_lstar();
             if (rs != RT_OK) return rs;
             HIPCHK(reduce_partials<double, double>(g->partJ64.as<double>(), sc->slot_begin.as<int32_t>(), sc->slot_ids.as<int32_t>(),
                                                    sc->lambda_of.as<int32_t>(), nb, g->J_anchor.as<double>(), nv, st));
@@ -1676,15 +1730,23 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
             ua.part = nullptr;
             ua.slot_begin = sc->slot_begin.as<int32_t>();
             ua.slot_ids = sc->slot_ids.as<int32_t>();
+            rs = join_stencil();
+            if (rs != RT_OK) return rs;
             rs = os_update(g, nl, ua, false, false, false, nb, sweeps, st);
             if (rs != RT_OK) return rs;
         } else {
+            rs = reduce_lstar();
+            if (rs != RT_OK) return rs;
             rs = run_fs(g, false, true, false, lams, g->fld.p, nullptr, g->partJ, g->partL, &sc, st);
+            if (rs != RT_OK) return rs;
+            rs = fork_stencil();
             if (rs != RT_OK) return rs;
             ++*fs_count;
             ua.part = g->partJ.p;
             ua.slot_begin = sc->slot_begin.as<int32_t>();
             ua.slot_ids = sc->slot_ids.as<int32_t>();
+            rs = join_stencil();
+            if (rs != RT_OK) return rs;
             rs = os_update(g, nl, ua, false, false, false, nb, sweeps, st);
             if (rs != RT_OK) return rs;
         }
