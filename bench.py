@@ -15,6 +15,7 @@ time, against the vector ALU peak), its HBM traffic when counters taken on
 the current kernel source are on file, and the oracle's CPU rate on a sample.
 """
 import argparse
+import glob
 import hashlib
 import json
 import os
@@ -61,22 +62,20 @@ def fs_source_hash() -> str:
 
 
 def read_traffic(workload: str, ls: dict):
-    """HBM bytes per launch from the committed counter summary, if it was taken
-    on the current kernel source and launch shape (`ls` as Grid.launch_shape()
-    gives it); else None."""
-    path = os.path.join(ROOT, "profiles", f"fs_box_{workload}_traffic.md")
-    if not os.path.exists(path):
-        return None
-    txt = open(path).read()
-    m_hash = re.search(r"fs_box\.hip sha256\[:16\]:\s*([0-9a-f]+)", txt)
-    m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    m_shape = re.search(r"launch_shape:\s*(\d+),(\d+),(\d+),(band|layer)", txt)
-    if not m_hash or not m_bytes or not m_shape or m_hash.group(1) != fs_source_hash():
-        return None
+    """HBM bytes per launch from a committed counter summary of this workload
+    (profiles/fs_box_<workload>_traffic*.md) taken on the current kernel source
+    and on this launch shape (`ls` as Grid.launch_shape() gives it); else None."""
     here = (str(ls["threads"]), str(ls["rays"]), str(ls["bundles"]), "band" if ls["band"] else "layer")
-    if m_shape.groups() != here:
-        return None
-    return float(m_bytes.group(1))
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"fs_box_{workload}_traffic*.md"))):
+        txt = open(path).read()
+        m_hash = re.search(r"fs_box\.hip sha256\[:16\]:\s*([0-9a-f]+)", txt)
+        m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+        m_shape = re.search(r"launch_shape:\s*(\d+),(\d+),(\d+),(band|layer)", txt)
+        if not m_hash or not m_bytes or not m_shape or m_hash.group(1) != fs_source_hash():
+            continue
+        if m_shape.groups() == here:
+            return float(m_bytes.group(1))
+    return None
 
 
 def cpu_baseline(case, n_sub: int):
