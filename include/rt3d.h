@@ -40,7 +40,13 @@
  *     library never frees them.  The grid handle owns its geometry tables,
  *     partial-sum buffers and scratch; rt_destroy_grid frees all of them.
  *   - stream: a hipStream_t cast to void* (NULL = the default stream).  Work is
- *     enqueued asynchronously on it unless stated otherwise.
+ *     enqueued asynchronously on it unless stated otherwise.  Part of a call's
+ *     work may run on a stream the grid owns (the nearest-neighbour Lambda*
+ *     build of an ALI step): it starts after the work enqueued on `stream`
+ *     before the call, and work enqueued on `stream` after the call waits
+ *     for it, as if it had been enqueued on `stream` itself.
+ *   - Device: a grid belongs to the device that is current when it is
+ *     created; make that device current for every call on the grid.
  *   - Errors: every call returns an rt_status; arguments are validated before
  *     anything is launched.  rt_last_error() returns a message for the most
  *     recent failure on the calling thread.  A handle must not be used from two
