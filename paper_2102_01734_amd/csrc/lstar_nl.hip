@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(256) lstar_stencil_kernel(StencilArgs a)
         for (int j = 0; j < 5; ++j) {
             if (!PARA && j == 0) continue;  // no downwind weight in the linear operator
             const uint32_t c = (comps >> (6 * j)) & 63u;
-            if (c == kNoComp) continue;
+            if (c == kNoComp || (a.skip_centre && c == (uint32_t)kStencilCentre)) continue;
             const long long f = __double2ll_rn(cw * Gv[j] * 0x1p52);
             if (f != 0) atomicAdd(&acc[(int64_t)c * a.n_vox + v], (unsigned long long)f);
         }
@@ -153,27 +153,33 @@ hipError_t lstar_stencil_accumulate(const StencilArgs &a, bool grid_double, bool
 
 template <typename T>
 __global__ void __launch_bounds__(256) stencil_finish_kernel(const unsigned long long *__restrict__ acc,
-                                                             const int32_t *__restrict__ lambda_of, int64_t n,
-                                                             T *__restrict__ out)
+                                                             const int32_t *__restrict__ lambda_of, int64_t n_vox,
+                                                             const T *__restrict__ centre, T *__restrict__ out)
 {
+    const int64_t n = (int64_t)kStencil * n_vox;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int64_t base = (int64_t)lambda_of[blockIdx.y] * n;
-    out[base + i] = (T)((double)(long long)acc[base + i] * 0x1p-52);
+    const int64_t lam = lambda_of[blockIdx.y];
+    const int64_t base = lam * n;
+    const int64_t c0 = (int64_t)kStencilCentre * n_vox;
+    if (centre && i >= c0 && i < c0 + n_vox)
+        out[base + i] = centre[lam * n_vox + (i - c0)];
+    else
+        out[base + i] = (T)((double)(long long)acc[base + i] * 0x1p-52);
 }
 
 hipError_t lstar_stencil_finish(const unsigned long long *acc, const int32_t *lambda_of, int64_t n_vox, int n_batch,
-                                void *out, bool out_double, hipStream_t st)
+                                const void *centre, void *out, bool out_double, hipStream_t st)
 {
     if (n_vox <= 0 || n_batch <= 0) return hipSuccess;
     const int64_t n = (int64_t)kStencil * n_vox;
     dim3 grid((unsigned)((n + 255) / 256), (unsigned)n_batch);
     if (out_double)
-        hipLaunchKernelGGL((stencil_finish_kernel<double>), grid, dim3(256), 0, st, acc, lambda_of, n,
-                           reinterpret_cast<double *>(out));
+        hipLaunchKernelGGL((stencil_finish_kernel<double>), grid, dim3(256), 0, st, acc, lambda_of, n_vox,
+                           reinterpret_cast<const double *>(centre), reinterpret_cast<double *>(out));
     else
-        hipLaunchKernelGGL((stencil_finish_kernel<float>), grid, dim3(256), 0, st, acc, lambda_of, n,
-                           reinterpret_cast<float *>(out));
+        hipLaunchKernelGGL((stencil_finish_kernel<float>), grid, dim3(256), 0, st, acc, lambda_of, n_vox,
+                           reinterpret_cast<const float *>(centre), reinterpret_cast<float *>(out));
     return hipGetLastError();
 }
 

@@ -33,6 +33,7 @@ struct StencilArgs {
     const void *chi;           // caller opacity [lambda][Nz][Ny][Nx], grid precision
     const int32_t *lambda_of;  // batch entry -> wavelength
     unsigned long long *acc;   // [lambda][27][n_vox] fixed point (2^-52), cleared by the caller
+    int skip_centre;           // 1: leave the centre component (the diagonal Lambda*) out
 };
 
 // Adds every characteristic's contributions to the stencil of the linear-
@@ -41,9 +42,11 @@ struct StencilArgs {
 hipError_t lstar_stencil_accumulate(const StencilArgs &a, bool grid_double, bool parabolic, int n_dir, int n_batch,
                                     hipStream_t st);
 
-// out[lam][c][v] = acc[lam][c][v] * 2^-52 (T = float or double).
+// out[lam][c][v] = acc[lam][c][v] * 2^-52 (T = float or double); with
+// `centre` (T, [lambda][n_vox]: a diagonal Lambda* of the same operator) the
+// centre component is copied from it instead.
 hipError_t lstar_stencil_finish(const unsigned long long *acc, const int32_t *lambda_of, int64_t n_vox, int n_batch,
-                                void *out, bool out_double, hipStream_t st);
+                                const void *centre, void *out, bool out_double, hipStream_t st);
 
 // One Jacobi sweep of [1 - Lambda*(1-eps)] x = r per wavelength of the batch
 // (first: x = r / (1 - Lambda*_vv (1-eps_v)), the diagonal solution).

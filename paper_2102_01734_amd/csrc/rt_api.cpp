@@ -1392,11 +1392,13 @@ static rt_status ensure_state_buffers(rt_grid *g)
 
 static int os_sweeps_of(const rt_solve_opts *o) { return o->os_sweeps > 0 ? o->os_sweeps : 4; }
 
-// Nearest-neighbour Lambda* of the wavelengths in `lams` from the caller's
-// opacity: clear the fixed-point sums, accumulate every characteristic, and
-// convert into `out` ([lambda][27][vox], double or float).
-static rt_status compute_stencil(rt_grid *g, const void *chi, int n_lambda, int nb, const int32_t *lambda_of,
-                                 void *out, bool out_double, hipStream_t st)
+// Nearest-neighbour Lambda* of the batch from the caller's opacity, in two
+// parts: clear the fixed-point sums and accumulate every characteristic
+// (without the centre component when skip_centre), then convert into `out`
+// ([lambda][27][vox], double or float), the centre taken from `centre` (the
+// diagonal Lambda* of the same operator, [lambda][vox]) when given.
+static rt_status accumulate_stencil(rt_grid *g, const void *chi, int n_lambda, int nb, const int32_t *lambda_of,
+                                    bool skip_centre, hipStream_t st)
 {
     const int64_t per = (int64_t)kStencil * g->n_vox;
     HIPCHK(g->nl_acc.ensure((size_t)n_lambda * per * 8));
@@ -1417,9 +1419,25 @@ static rt_status compute_stencil(rt_grid *g, const void *chi, int n_lambda, int 
     a.chi = chi;
     a.lambda_of = lambda_of;
     a.acc = g->nl_acc.as<unsigned long long>();
+    a.skip_centre = skip_centre ? 1 : 0;
     HIPCHK(lstar_stencil_accumulate(a, g->dbl, g->para, g->n_dir, nb, st));
-    HIPCHK(lstar_stencil_finish(g->nl_acc.as<unsigned long long>(), lambda_of, g->n_vox, nb, out, out_double, st));
     return RT_OK;
+}
+
+static rt_status finish_stencil(rt_grid *g, int nb, const int32_t *lambda_of, const void *centre, void *out,
+                                bool out_double, hipStream_t st)
+{
+    HIPCHK(lstar_stencil_finish(g->nl_acc.as<unsigned long long>(), lambda_of, g->n_vox, nb, centre, out, out_double,
+                                st));
+    return RT_OK;
+}
+
+static rt_status compute_stencil(rt_grid *g, const void *chi, int n_lambda, int nb, const int32_t *lambda_of,
+                                 void *out, bool out_double, hipStream_t st)
+{
+    rt_status rs = accumulate_stencil(g, chi, n_lambda, nb, lambda_of, false, st);
+    if (rs != RT_OK) return rs;
+    return finish_stencil(g, nb, lambda_of, nullptr, out, out_double, st);
 }
 
 // The operator-splitting update.  Diagonal Lambda*: the fused pointwise
@@ -1644,17 +1662,20 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
     auto fork_stencil = [&]() -> rt_status {
         if (!stencil_pending || stencil_forked) return RT_OK;
         HIPCHK(hipStreamWaitEvent(g->nl_side, g->nl_fork, 0));
-        rt_status r = compute_stencil(g, s->chi, nl, nb, lambda_of, g->nl_st.p, g->dbl, g->nl_side);
+        rt_status r = accumulate_stencil(g, s->chi, nl, nb, lambda_of, true, g->nl_side);
         if (r != RT_OK) return r;
         HIPCHK(hipEventRecord(g->nl_join, g->nl_side));
         stencil_forked = true;
         return RT_OK;
     };
+    // after the step's diagonal Lambda* is reduced into s->lstar: it is the
+    // stencil's centre component (the same sum over the same points)
     auto join_stencil = [&]() -> rt_status {
         rt_status r = fork_stencil();
         if (r != RT_OK) return r;
-        if (stencil_forked) HIPCHK(hipStreamWaitEvent(st, g->nl_join, 0));
-        return RT_OK;
+        if (!stencil_forked) return RT_OK;
+        HIPCHK(hipStreamWaitEvent(st, g->nl_join, 0));
+        return finish_stencil(g, nb, lambda_of, s->lstar, g->nl_st.p, g->dbl, st);
     };
 
     if (g->dbl) {
