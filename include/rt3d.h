@@ -95,7 +95,9 @@ typedef enum { RT_FP64 = 0, RT_FP32 = 1 } rt_prec;
                                      the operator-splitting system with Jacobi
                                      sweeps (rt_solve_opts.os_sweeps).  The
                                      state's lstar array still receives the
-                                     diagonal.                                 */
+                                     diagonal, and is the stencil's centre
+                                     component (the same sum; on RT_FP32 grids
+                                     in the sweep's float rounding).           */
 #define RT_F_HOST_CACHE 0x8u      /* sphere: keep every chunk of the geometry
                                      cache in pinned host memory and stream it
                                      to the GPU for each formal solution (the
