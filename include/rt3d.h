@@ -244,7 +244,7 @@ typedef struct {
     int32_t os_sweeps;    /* grids with RT_F_LSTAR_NONLOCAL: Jacobi sweeps of
                              the operator-splitting system per step, started
                              from the diagonal solution (0 = library default
-                             4); ignored otherwise                              */
+                             16); ignored otherwise                             */
 } rt_solve_opts;
 
 typedef struct {

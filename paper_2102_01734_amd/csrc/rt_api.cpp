@@ -1390,7 +1390,7 @@ static rt_status ensure_state_buffers(rt_grid *g)
     return RT_OK;
 }
 
-static int os_sweeps_of(const rt_solve_opts *o) { return o->os_sweeps > 0 ? o->os_sweeps : 4; }
+static int os_sweeps_of(const rt_solve_opts *o) { return o->os_sweeps > 0 ? o->os_sweeps : 16; }
 
 // Nearest-neighbour Lambda* of the batch from the caller's opacity, in two
 // parts: clear the fixed-point sums and accumulate every characteristic
