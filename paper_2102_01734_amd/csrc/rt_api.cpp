@@ -1691,7 +1691,7 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
         rs = fork_stencil();
         if (rs != RT_OK) return rs;
         ++*fs_count; ++*fs64_count;
-        if (scL)  // after the J sweep, so that it does not wait behind the stencil for CUs
+        if (scL)  // after the J sweep, so that the two sweeps are queued back to back
             HIPCHK(reduce_partials<double, double>(g->partL64.as<double>(), scL->slot_begin.as<int32_t>(),
                                                    scL->slot_ids.as<int32_t>(), scL->lambda_of.as<int32_t>(), nb,
                                                    (double *)s->lstar, nv, st));
