@@ -148,6 +148,13 @@ def test_sphere_rejects_box_only_calls():
     g = make_grid(case)
     with pytest.raises(rt.RtError):
         g.set_launch_shape(768, 22)
+    for band in (False, True):
+        with pytest.raises(rt.RtError) as e:
+            g.set_launch_shape(768, 11, band=band)
+        assert e.value.status == rt.rt3d.RT_E_UNSUPPORTED
+        with pytest.raises(rt.RtError) as e:
+            g.set_anchor_shape(768, 11, band=band)
+        assert e.value.status == rt.rt3d.RT_E_UNSUPPORTED
     chi = to_dev(case.chi, "f32")
     with pytest.raises(rt.RtError):
         g.autotune(chi, chi)
