@@ -28,7 +28,7 @@ def test_traffic_is_read_only_for_the_launch_shape_it_was_taken_on():
     of the same kernel source and launch shape; any other shape reports null."""
     sys.path.insert(0, ROOT)
     import bench
-    on_file = {(768, 11, 2, 1), (1024, 17, 2, 1)}
+    on_file = {(768, 11, 2, 1), (1024, 17, 2, 1), (512, 17, 2, 1)}
     for t, r, nb, band in on_file:
         b = bench.read_traffic("lognormal129", {"threads": t, "rays": r, "bundles": nb, "band": band})
         assert b is not None and 5e10 < b < 1e12
