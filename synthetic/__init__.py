@@ -252,3 +252,18 @@ def random_sphere(Nr: int, Nt: int, Np: int, n_mu: int, n_phi: int, seed: int, d
     I_bc = _round(np.stack([rng.uniform(0.0, 0.3, size=n_lambda), rng.uniform(0.5, 1.5, size=n_lambda),
                             rng.uniform(0.5, 2.0, size=n_lambda)], axis=1), dtype)
     return SphereCase(name, Nr, Nt, Np, 1.0, 2.0, n_mu, n_phi, source_distance, chi, e, B, I_bc, dtype)
+
+
+def fingerprint(case) -> str:
+    """SHA-256 (hex) of a workload's input arrays and quadrature: the key under
+    which a stored solution of that workload is filed.  Inputs only: the arrays
+    are hashed as float64 in C order together with their shape."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("chi", "eps", "B", "I_bc"):
+        a = np.ascontiguousarray(getattr(case, name), dtype=np.float64)
+        h.update(name.encode())
+        h.update(np.asarray(a.shape, dtype=np.int64).tobytes())
+        h.update(a.tobytes())
+    h.update(np.asarray([case.n_mu, case.n_phi], dtype=np.int64).tobytes())
+    return h.hexdigest()
