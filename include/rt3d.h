@@ -137,6 +137,12 @@ typedef struct {
  * Blocks until the upload is complete.  Errors: RT_E_INVALID (descriptor),
  * RT_E_UNSUPPORTED (box layer larger than the on-chip tile allows),
  * RT_E_NOMEM, RT_E_HIP.  *out is NULL on error.
+ * RT_E_NOMEM: a box grid whose working set -- geometry, the partial sums of a
+ * formal solution with J and Lambda* of n_lambda_max wavelengths, the padded
+ * inputs, the ALI state (Ng history, double anchors on RT_FP32 grids) and,
+ * with RT_F_LSTAR_NONLOCAL, the stencil -- exceeds the free device memory is
+ * refused before anything is allocated.  Every entry point returns
+ * RT_E_NOMEM when a device or pinned-host allocation fails later on.
  */
 rt_status rt_create_grid(const rt_grid_desc *desc, rt_grid_t *out);
 
@@ -196,7 +202,21 @@ rt_status rt_formal_solution_dirs(rt_grid_t grid, int32_t n_lambda, const void *
  */
 rt_status rt_shard_directions(rt_grid_t grid, int32_t n_shards, int32_t shard, int32_t *dirs_out, int32_t *n_out);
 
-/* State of the ALI iteration for a batch of wavelengths. */
+/*
+ * State of the ALI iteration for a batch of wavelengths.
+ * The caller owns every array.  Besides them, a grid keeps scratch that
+ * belongs to the state it stepped last: the padded formal-solution inputs,
+ * the Ng history (the last four iterates), on RT_FP32 grids the double
+ * anchor (S_a, J_a = Lambda S_a + Lambda_bc), and with RT_F_LSTAR_NONLOCAL the
+ * nearest-neighbour stencil.  A step on a state whose array pointers or
+ * n_lambda differ from those of the previous step (or the first step after
+ * a BiCGStab solve on the grid) rebuilds all of it from that state: S from
+ * J, a new anchor, the stencil from chi, and an empty Ng history -- the path
+ * to the fixed point changes, the fixed point does not.  Several states can
+ * therefore share one grid, stepped alternately.  After changing J, chi, eps
+ * or B in place between steps, set iter = 0 (and lstar_valid = 0 if chi
+ * changed), which restarts the same way.
+ */
 typedef struct {
     uint32_t struct_size; /* sizeof(rt_state)                                   */
     int32_t n_lambda;     /* 1 .. n_lambda_max                                  */
@@ -208,7 +228,8 @@ typedef struct {
                              rt_formal_solution; NULL = 0                       */
     double *J;            /* device [n_lambda][vox] double: current iterate;
                              on entry the start value (e.g. B), on exit the
-                             result.  Resuming from any J is allowed.           */
+                             result.  Resuming from any J is allowed (iter = 0
+                             for a J the library did not write last).           */
     double *S;            /* device [n_lambda][vox] double: S = (1-eps)J + eps B
                              of the returned J (written by the library)         */
     void *lstar;          /* device [n_lambda][vox] grid precision: Lambda*     */

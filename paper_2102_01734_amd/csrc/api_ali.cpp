@@ -205,8 +205,16 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
     if (rs != RT_OK) return rs;
     const int32_t *lambda_of = lam_sc->lambda_of.as<int32_t>();
 
+    // The grid's per-state scratch (padded inputs, Ng history, double
+    // anchor, nearest-neighbour stencil) belongs to the state stepped last;
+    // a different state starts all of it afresh from its own arrays.
+    const bool switched = !g->owned_by(s);
+    if (switched) {
+        g->take_ownership(s);
+        g->hist_count = 0;
+    }
     // (re)initialisation: padded opacity, S from J, fresh Ng history
-    if (s->iter == 0 || s->chi != g->chi_src) {
+    if (s->iter == 0 || switched || s->chi != g->chi_src) {
         if (g->dbl) {
             HIPCHK(pad_field<double, double>((const double *)s->chi, nullptr, g->fld.as<double>(), Nx, Ny, Nz, nl, 0, st));
         } else {
@@ -215,12 +223,24 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
         }
         g->chi_src = s->chi;
     }
-    if (s->iter == 0) {
+    if (s->iter == 0 || switched) {
         g->hist_count = 0;
         if (g->dbl)
             HIPCHK(source_update<double, double>(s->J, (const double *)s->eps, (const double *)s->B, s->S, nullptr,
                                                  g->fld.as<double>(), Nx, Ny, nv, lambda_of, nb, st));
         anchor = true;
+    }
+    if (!g->dbl && !g->anchor_ok) anchor = true;
+    const bool want_l = s->lstar_valid == 0;
+    // A state whose Lambda* is already known (from BiCGStab, or set by the
+    // caller) but whose stencil this grid has not built: build it here, in
+    // full, before the step.
+    if (g->nonlocal && !want_l && !g->nl_ok) {
+        rs = accumulate_stencil(g, s->chi, nl, nb, lambda_of, false, st);
+        if (rs != RT_OK) return rs;
+        rs = finish_stencil(g, nb, lambda_of, nullptr, g->nl_st.p, g->dbl, st);
+        if (rs != RT_OK) return rs;
+        g->nl_ok = true;
     }
 
     // Ng extrapolation of the last four iterates, due before this step's formal solution
@@ -245,7 +265,6 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
         ++*ng_count;
     }
 
-    const bool want_l = s->lstar_valid == 0;
     if (!want_l && (g->dbl || !anchor)) {
         if (o->use_graph && st != nullptr && !candidate && !g->sph_streaming)
             rs = graph_plain_step(g, s, lams, lambda_of, st, os_sweeps_of(o));
@@ -401,6 +420,8 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
         }
     }
     s->lstar_valid = 1;
+    if (g->nonlocal && want_l) g->nl_ok = true;
+    if (anchor) g->anchor_ok = true;
     if (!candidate) g->hist_count++;
     s->iter++;
     return RT_OK;

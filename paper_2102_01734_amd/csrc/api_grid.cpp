@@ -340,6 +340,30 @@ rt_status rt_sphere_tracks(const rt_grid_desc *desc, int32_t dir, double *h_out,
     return RT_OK;
 }
 
+// Device bytes a box grid uses at most for its geometry, the partial sums
+// of a formal solution with J and Lambda* of n_lambda_max wavelengths (a
+// schedule opens at most n_wg + n_lambda slots), both padded-input copies,
+// the ALI state (Ng ring, double anchors and their sweep on FP32 grids) and
+// the nearest-neighbour stencil.
+static int64_t box_device_bytes(rt_grid *g)
+{
+    const int64_t nl = g->desc.n_lambda_max, nv = g->n_vox, nvis = g->n_visits, nd = g->n_dir;
+    const int64_t esz = g->dbl ? 8 : 4;
+    int64_t nwg = 0;
+    for (int j = 0; j < 2; ++j)
+        for (int l = 0; l < 2; ++l) nwg = std::max<int64_t>(nwg, variant(g, g->dbl, j, l).n_wg);
+    int64_t b = nvis * (4 + 4 + 8 + 4 + 4) + nd * (8 + 4 + 8 + 8 + 4);
+    b += 2 * (nwg + nl) * nv * esz;   // J and Lambda* slots
+    b += 2 * 8 * nl * nv * esz;       // padded (chi, S) inputs: formal solution and ALI
+    b += 4 * nl * nv * 8;             // Ng ring
+    if (!g->dbl) {
+        int64_t nwg64 = variant(g, true, true, false).n_wg;
+        b += (nwg64 + nl) * nv * 8 + 8 * nl * nv * 8 + 2 * nl * nv * 8;  // anchor sweep, its input, S_a, J_a
+    }
+    if (g->nonlocal) b += 27 * nl * nv * (esz + 8) + 3 * nl * nv * 8;
+    return b;
+}
+
 rt_status rt_create_grid(const rt_grid_desc *desc, rt_grid_t *out)
 {
     if (!out) return fail(RT_E_INVALID, "out is NULL");
@@ -433,17 +457,6 @@ rt_status rt_create_grid(const rt_grid_desc *desc, rt_grid_t *out)
     if (prop.maxSharedMemoryPerMultiProcessor > 0 && (size_t)prop.maxSharedMemoryPerMultiProcessor < g->max_lds)
         g->max_lds = prop.maxSharedMemoryPerMultiProcessor;
 
-    const size_t nvis = (size_t)g->n_visits;
-    HIPCHK(g->goff.ensure(nvis * 4));
-    HIPCHK(g->dxy.ensure(nvis * 4));
-    HIPCHK(g->s.ensure(nvis * 8));
-    HIPCHK(hipMemcpy(g->goff.p, g->geo.goff.data(), nvis * 4, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(g->dxy.p, g->geo.dxy.data(), nvis * 4, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(g->s.p, g->geo.s.data(), nvis * 8, hipMemcpyHostToDevice));
-    HIPCHK(g->brow.ensure(nvis * 4));
-    HIPCHK(hipMemcpy(g->brow.p, g->geo.brow.data(), nvis * 4, hipMemcpyHostToDevice));
-    HIPCHK(g->comp.ensure(nvis * 4));
-    HIPCHK(hipMemcpy(g->comp.p, g->geo.comp.data(), nvis * 4, hipMemcpyHostToDevice));
     g->nonlocal = (desc->flags & RT_F_LSTAR_NONLOCAL) != 0;
     if (g->n_dir > 65535) return fail(RT_E_INVALID, "more than 65535 directions");
     std::vector<int64_t> vb(g->n_dir);
@@ -457,16 +470,6 @@ rt_status rt_create_grid(const rt_grid_desc *desc, rt_grid_t *out)
         wmu[d] = g->geo.dirs[d].w * std::fabs(g->geo.dirs[d].mu);
         mu[d] = g->geo.dirs[d].mu;
     }
-    HIPCHK(g->vbegin.ensure(g->n_dir * 8));
-    HIPCHK(g->M.ensure(g->n_dir * 4));
-    HIPCHK(g->wmu.ensure(g->n_dir * 8));
-    HIPCHK(g->mu.ensure(g->n_dir * 8));
-    HIPCHK(hipMemcpy(g->vbegin.p, vb.data(), g->n_dir * 8, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(g->M.p, Ms.data(), g->n_dir * 4, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(g->wmu.p, wmu.data(), g->n_dir * 8, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(g->mu.p, mu.data(), g->n_dir * 8, hipMemcpyHostToDevice));
-    HIPCHK(g->span.ensure(g->n_dir * 4));
-    HIPCHK(hipMemcpy(g->span.p, sp.data(), g->n_dir * 4, hipMemcpyHostToDevice));
 
     // whole-layer tiles where they fit, else (or when asked for) band tiles
     auto setup_all = [&]() {
@@ -489,6 +492,38 @@ rt_status rt_create_grid(const rt_grid_desc *desc, rt_grid_t *out)
                     "layer of %d x %d voxels (row span %d per layer) fits neither a layer tile nor a band tile in "
                     "%zu bytes of LDS",
                     g->geo.Nx, g->geo.Ny, g->span_max, g->max_lds);
+    // refuse, before anything is allocated, a grid whose working set cannot fit
+    const int64_t need = box_device_bytes(g.get());
+    size_t free_b = 0, total_b = 0;
+    HIPCHK(hipMemGetInfo(&free_b, &total_b));
+    if (need > (int64_t)free_b)
+        return fail(RT_E_NOMEM,
+                    "grid needs about %.1f GB of device memory (geometry, partial sums, padded inputs and ALI state "
+                    "for %d wavelengths); %.1f GB free",
+                    need * 1e-9, desc->n_lambda_max, (double)free_b * 1e-9);
+
+    const size_t nvis = (size_t)g->n_visits;
+    HIPCHK(g->goff.ensure(nvis * 4));
+    HIPCHK(g->dxy.ensure(nvis * 4));
+    HIPCHK(g->s.ensure(nvis * 8));
+    HIPCHK(hipMemcpy(g->goff.p, g->geo.goff.data(), nvis * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(g->dxy.p, g->geo.dxy.data(), nvis * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(g->s.p, g->geo.s.data(), nvis * 8, hipMemcpyHostToDevice));
+    HIPCHK(g->brow.ensure(nvis * 4));
+    HIPCHK(hipMemcpy(g->brow.p, g->geo.brow.data(), nvis * 4, hipMemcpyHostToDevice));
+    HIPCHK(g->comp.ensure(nvis * 4));
+    HIPCHK(hipMemcpy(g->comp.p, g->geo.comp.data(), nvis * 4, hipMemcpyHostToDevice));
+    HIPCHK(g->vbegin.ensure(g->n_dir * 8));
+    HIPCHK(g->M.ensure(g->n_dir * 4));
+    HIPCHK(g->wmu.ensure(g->n_dir * 8));
+    HIPCHK(g->mu.ensure(g->n_dir * 8));
+    HIPCHK(hipMemcpy(g->vbegin.p, vb.data(), g->n_dir * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(g->M.p, Ms.data(), g->n_dir * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(g->wmu.p, wmu.data(), g->n_dir * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(g->mu.p, mu.data(), g->n_dir * 8, hipMemcpyHostToDevice));
+    HIPCHK(g->span.ensure(g->n_dir * 4));
+    HIPCHK(hipMemcpy(g->span.p, sp.data(), g->n_dir * 4, hipMemcpyHostToDevice));
+
     *out = g.release();
     clear_error();
     return RT_OK;

@@ -43,7 +43,9 @@ rt_status solve_bicgstab(rt_grid *g, rt_state *s, const rt_solve_opts *o, rt_sol
         HIPCHK(pad_field<float, double>((const float *)s->chi, nullptr, fpad, lx, ly, lz, nl, 0, st));
         HIPCHK(pad_field<float, float>((const float *)s->chi, nullptr, g->fld.as<float>(), lx, ly, lz, nl, 0, st));
     }
-    g->chi_src = nullptr;  // the ALI inputs are re-initialised by the next ALI step
+    // BiCGStab uses the padded inputs as scratch: the next ALI step, of any
+    // state, starts its per-state scratch afresh
+    g->release_ownership();
     DevSchedule *sc = nullptr;
     if (s->lstar_valid == 0) {
         if (g->dbl) {

@@ -175,6 +175,32 @@ struct rt_grid {
     DevBuf J_anchor, S_anchor, hist, ng_blk, ng_coef;
     int hist_count = 0;
     const void *chi_src = nullptr;
+    // the state the per-state scratch above belongs to (its array pointers
+    // and batch size), whether its double anchor (FP32 grids) and its
+    // nearest-neighbour stencil (nl_st) are in place
+    const void *own[8] = {};
+    bool anchor_ok = false, nl_ok = false;
+    bool owned_by(const rt_state *st) const
+    {
+        const void *k[8] = {st->chi, st->eps, st->B, st->I_bc, st->J, st->S, st->lstar,
+                            reinterpret_cast<const void *>((intptr_t)st->n_lambda)};
+        return std::equal(k, k + 8, own);
+    }
+    void take_ownership(const rt_state *st)
+    {
+        const void *k[8] = {st->chi, st->eps, st->B, st->I_bc, st->J, st->S, st->lstar,
+                            reinterpret_cast<const void *>((intptr_t)st->n_lambda)};
+        std::copy(k, k + 8, own);
+        anchor_ok = nl_ok = false;
+        chi_src = nullptr;
+    }
+    void release_ownership()
+    {
+        std::fill(own, own + 8, nullptr);
+        anchor_ok = nl_ok = false;
+        chi_src = nullptr;
+        hist_count = 0;
+    }
     // captured plain ALI steps, keyed by batch, ring slot and state pointers
     std::map<std::string, hipGraphExec_t> graphs;
     // BiCGStab vectors and reduction scratch

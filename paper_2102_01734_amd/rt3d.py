@@ -292,6 +292,20 @@ def rt_precond_forward(grid: int, features: int, out: int, stream: Optional[int]
                                     ctypes.c_void_p(stream or None)), "rt_precond_forward")
 
 
+def box_desc(Nx: int, Ny: int, Nz: int, n_mu: int, n_phi: int, prec: str = "f32", n_lambda_max: int = 1,
+             lstar: str = "linear", band_tiles: bool = False, nonlocal_lstar: bool = False) -> RtGridDesc:
+    d = RtGridDesc()
+    d.struct_size = ctypes.sizeof(RtGridDesc)
+    d.geom = RT_GEOM_BOX_PERIODIC_XY
+    d.n[0], d.n[1], d.n[2] = Nx, Ny, Nz
+    d.n_mu, d.n_phi = n_mu, n_phi
+    d.n_lambda_max = n_lambda_max
+    d.prec = RT_FP32 if prec == "f32" else RT_FP64
+    d.flags = ((RT_F_LSTAR_PARABOLIC if lstar == "parabolic" else 0) | (RT_F_BAND_TILES if band_tiles else 0)
+               | (RT_F_LSTAR_NONLOCAL if nonlocal_lstar else 0))
+    return d
+
+
 def sphere_desc(Nr: int, Nt: int, Np: int, r_core: float, r_out: float, n_mu: int, n_phi: int, prec: str = "f32",
                 n_lambda_max: int = 1, lstar: str = "linear", source_distance: float = 0.0,
                 host_cache: bool = False) -> RtGridDesc:
@@ -341,15 +355,7 @@ class Grid:
     def __init__(self, Nx: int, Ny: int, Nz: int, n_mu: int, n_phi: int, prec: str = "f32",
                  n_lambda_max: int = 1, lstar: str = "linear", band_tiles: bool = False,
                  nonlocal_lstar: bool = False):
-        d = RtGridDesc()
-        d.struct_size = ctypes.sizeof(RtGridDesc)
-        d.geom = RT_GEOM_BOX_PERIODIC_XY
-        d.n[0], d.n[1], d.n[2] = Nx, Ny, Nz
-        d.n_mu, d.n_phi = n_mu, n_phi
-        d.n_lambda_max = n_lambda_max
-        d.prec = RT_FP32 if prec == "f32" else RT_FP64
-        d.flags = ((RT_F_LSTAR_PARABOLIC if lstar == "parabolic" else 0) | (RT_F_BAND_TILES if band_tiles else 0)
-                   | (RT_F_LSTAR_NONLOCAL if nonlocal_lstar else 0))
+        d = box_desc(Nx, Ny, Nz, n_mu, n_phi, prec, n_lambda_max, lstar, band_tiles, nonlocal_lstar)
         self.desc = d
         self.shape = (Nz, Ny, Nx)
         self.nbc = 2
