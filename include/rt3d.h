@@ -500,6 +500,31 @@ rt_status rt_cache_bytes(rt_grid_t grid, int64_t *device_bytes, int64_t *host_by
 rt_status rt_profile_enable(rt_grid_t grid, int32_t enable);
 rt_status rt_profile_read(rt_grid_t grid, double *fs_ms, int32_t *fs_launches, int64_t *fs_points);
 
+/* Size of the fixed device scratch of rt_formal_solution_noalloc (per GPU). */
+#define RT_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/*
+ * rt_formal_solution for callers that cannot allocate device memory: code
+ * being captured into a HIP graph, serving loops and harnesses that forbid
+ * hipMalloc.  Same arguments, outputs and errors as rt_formal_solution (box
+ * grids; RT_E_UNSUPPORTED on spherical grids).  Every scratch buffer of the
+ * call -- the work schedule, the padded (chi, S) input and the workgroup
+ * partial sums -- lives in one fixed device array of RT_NOALLOC_SCRATCH_BYTES
+ * that the library holds on each GPU it runs on until the process ends (set
+ * up by rt_create_grid); the call itself allocates no device memory and
+ * frees none.  When the partial sums of the grid's usual workgroup count do
+ * not fit, fewer persistent workgroups are launched (results then differ
+ * from rt_formal_solution's in the summation order only); a call whose
+ * padded input plus one workgroup's partial sums per ray bundle exceed the
+ * array is refused with RT_E_INVALID before anything is enqueued.  All calls
+ * on one GPU share the array: calls that overlap in time on one GPU (e.g.
+ * on two streams, or from two threads) race and give wrong results.
+ * The work schedule is copied from host memory the grid keeps; nothing in
+ * the array needs to start at zero.
+ */
+rt_status rt_formal_solution_noalloc(rt_grid_t grid, int32_t n_lambda, const void *chi, const void *S,
+                                     const void *I_bc, void *J_out, void *lstar_out, void *stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *rt_last_error(void);
 

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "librt3d.so")
 
 SOURCES = ["geometry.cpp", "sphere_geometry.cpp", "schedule.cpp", "fs_box.hip", "fs_sphere.hip", "ali.hip", "unet.hip",
            "krylov.hip", "lstar_nl.hip", "api_grid.cpp", "api_launch.cpp", "api_stencil.cpp", "api_ali.cpp",
-           "api_krylov.cpp"]
+           "api_krylov.cpp", "api_noalloc.hip"]
 ARCH = os.environ.get("RT3D_ARCH", "gfx950")
 CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -456,6 +456,12 @@ rt_status rt_create_grid(const rt_grid_desc *desc, rt_grid_t *out)
     g->max_lds = prop.sharedMemPerBlock;
     if (prop.maxSharedMemoryPerMultiProcessor > 0 && (size_t)prop.maxSharedMemoryPerMultiProcessor < g->max_lds)
         g->max_lds = prop.maxSharedMemoryPerMultiProcessor;
+    {
+        rt_status rs = noalloc_scratch_setup(g->device, &g->na_scratch);
+        if (rs != RT_OK) return rs;
+    }
+    g->iota_lams.resize((size_t)desc->n_lambda_max);
+    for (int i = 0; i < desc->n_lambda_max; ++i) g->iota_lams[(size_t)i] = i;
 
     g->nonlocal = (desc->flags & RT_F_LSTAR_NONLOCAL) != 0;
     if (g->n_dir > 65535) return fail(RT_E_INVALID, "more than 65535 directions");

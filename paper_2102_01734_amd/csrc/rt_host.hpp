@@ -208,6 +208,12 @@ struct rt_grid {
     // learned ALI correction
     UNetDev *net = nullptr;
     DevBuf net_r, net_f, net_out, J_save, resid;
+    // rt_formal_solution_noalloc: this device's copy of the fixed scratch
+    // array, the schedules planned for it (host copies, kept for the
+    // asynchronous uploads) and the batch indices 0 .. n_lambda_max-1
+    void *na_scratch = nullptr;
+    std::map<std::string, std::unique_ptr<Schedule>> na_sched;
+    std::vector<int32_t> iota_lams;
     // measurement hooks
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
@@ -259,6 +265,10 @@ rt_status finish_stencil(rt_grid *g, int nb, const int32_t *lambda_of, const voi
                          bool out_double, hipStream_t st);
 rt_status compute_stencil(rt_grid *g, const void *chi, int n_lambda, int nb, const int32_t *lambda_of, void *out,
                           bool out_double, hipStream_t st);
+
+// device address of this device's copy of the no-allocation scratch array,
+// looked up once per device (api_noalloc.hip)
+rt_status noalloc_scratch_setup(int device, void **out);
 
 // ALI state (api_ali.cpp) and the Krylov solver (api_krylov.cpp)
 rt_status check_state(rt_grid *g, const rt_state *s);

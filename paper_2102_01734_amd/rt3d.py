@@ -20,6 +20,7 @@ RT_F_LSTAR_PARABOLIC = 0x1
 RT_F_BAND_TILES = 0x2
 RT_F_LSTAR_NONLOCAL = 0x4
 RT_F_HOST_CACHE = 0x8
+RT_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 STATUS_NAMES = {0: "RT_OK", 1: "RT_E_INVALID", 2: "RT_E_NOMEM", 3: "RT_E_HIP", 4: "RT_E_NOT_CONVERGED",
                 5: "RT_E_NUMERIC", 6: "RT_E_UNSUPPORTED"}
@@ -110,6 +111,8 @@ def lib() -> ctypes.CDLL:
     L.rt_sphere_tracks.argtypes = [ctypes.POINTER(RtGridDesc), i32, dp, ctypes.POINTER(ctypes.c_int64),
                                    ctypes.POINTER(ctypes.c_int64), dp, ctypes.POINTER(ctypes.c_int64), ip, dp]
     L.rt_sphere_tracks.restype = ctypes.c_int
+    L.rt_formal_solution_noalloc.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+    L.rt_formal_solution_noalloc.restype = ctypes.c_int
     L.rt_formal_solution_dirs.argtypes = [vp, i32, vp, vp, vp, i32, ip, vp, vp, vp]
     L.rt_formal_solution_dirs.restype = ctypes.c_int
     L.rt_shard_directions.argtypes = [vp, i32, i32, ip, ctypes.POINTER(i32)]
@@ -167,6 +170,15 @@ def rt_formal_solution(grid: int, n_lambda: int, chi: int, S: int, I_bc: Optiona
                                     ctypes.c_void_p(I_bc or None), ctypes.c_void_p(J_out),
                                     ctypes.c_void_p(lstar_out or None), ctypes.c_void_p(stream or None)),
            "rt_formal_solution")
+
+
+def rt_formal_solution_noalloc(grid: int, n_lambda: int, chi: int, S: int, I_bc: Optional[int], J_out: int,
+                               lstar_out: Optional[int], stream: Optional[int]) -> None:
+    _check(lib().rt_formal_solution_noalloc(ctypes.c_void_p(grid), int(n_lambda), ctypes.c_void_p(chi),
+                                            ctypes.c_void_p(S), ctypes.c_void_p(I_bc or None),
+                                            ctypes.c_void_p(J_out), ctypes.c_void_p(lstar_out or None),
+                                            ctypes.c_void_p(stream or None)),
+           "rt_formal_solution_noalloc")
 
 
 def rt_ali_step(grid: int, state: RtState, opts: RtSolveOpts, stream: Optional[int]) -> None:
