@@ -61,12 +61,12 @@ def fs_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(workload: str, ls: dict):
+def read_traffic(workload: str, ls: dict, profiles_dir: str = os.path.join(ROOT, "profiles")):
     """HBM bytes per launch from a committed counter summary of this workload
     (profiles/fs_box_<workload>_traffic*.md) taken on the current kernel source
     and on this launch shape (`ls` as Grid.launch_shape() gives it); else None."""
     here = (str(ls["threads"]), str(ls["rays"]), str(ls["bundles"]), "band" if ls["band"] else "layer")
-    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"fs_box_{workload}_traffic*.md"))):
+    for path in sorted(glob.glob(os.path.join(profiles_dir, f"fs_box_{workload}_traffic*.md"))):
         txt = open(path).read()
         m_hash = re.search(r"fs_box\.hip sha256\[:16\]:\s*([0-9a-f]+)", txt)
         m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)

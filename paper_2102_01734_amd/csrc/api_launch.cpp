@@ -32,7 +32,7 @@ static ChunkPtrs chunk_ptrs(const SphereChunkDev &ch, const void *stage)
 }
 // Resident-workgroup count and LDS size of one launch shape; ok = false when
 // the shape cannot hold all rays of a bundle or its tiles do not fit.
-Variant make_variant(rt_grid *g, bool dbl, bool wj, bool wl, int lb, int R, int occ, bool band)
+Variant make_variant(rt_grid *g, bool dbl, bool wj, bool wl, int lb, int R, int occ, bool band, bool allow_spill)
 {
     Variant v;
     v.dbl = dbl; v.wj = wj; v.wl = wl; v.lb = lb; v.R = R; v.band = band;
@@ -79,7 +79,12 @@ Variant make_variant(rt_grid *g, bool dbl, bool wj, bool wl, int lb, int R, int 
     }
     v.lds = (size_t)(v.tile_words + v.nthr) * esz * nout;
     if (v.lds > g->max_lds) return v;
-    const int res = fs_box_occupancy(dbl, wj, wl, g->para, band, lb, R, v.nthr, v.lds);
+    int res = fs_box_occupancy(dbl, wj, wl, g->para, band, lb, R, v.nthr, v.lds);
+    if (res < 0) {
+        // the kernel keeps part of its state in scratch memory: only when asked
+        if (!allow_spill) return v;
+        res = -res;
+    }
     if (res <= 0) return v;
     v.n_wg = res * g->n_cu;
     v.n_wg -= v.n_wg % v.nb;  // equal classes of workgroups per bundle
@@ -88,21 +93,28 @@ Variant make_variant(rt_grid *g, bool dbl, bool wj, bool wl, int lb, int R, int 
     return v;
 }
 
-// Default shape: 1024-thread workgroups.  Layer tiles: the fewest rays per
+// Default shape among those compiled for every output combination: shapes
+// whose kernels keep everything in registers first (any that spill only if
+// none fits).  Layer tiles: the widest workgroups, then the fewest rays per
 // thread.  Band tiles: the fewest bundles (widest bands, least flush traffic
-// per ray), then the fewest rays per thread.
+// per ray), then the widest workgroups, then the fewest rays per thread.
 void setup_variant(rt_grid *g, bool dbl, bool wj, bool wl)
 {
     const FsShape *sh = nullptr;
     const int n = fs_box_shapes(&sh);
     Variant &best = variant(g, dbl, wj, wl);
     best = Variant();
-    for (int i = 0; i < n; ++i) {
-        if (!sh[i].full || sh[i].lb != 1024 || sh[i].band != g->band) continue;
-        Variant v = make_variant(g, dbl, wj, wl, sh[i].lb, sh[i].R, sh[i].occ, sh[i].band);
-        if (!v.ok) continue;
-        if (!g->band) { best = v; return; }
-        if (!best.ok || v.nb < best.nb) best = v;
+    for (int pass = 0; pass < 2 && !best.ok; ++pass) {
+        for (int i = 0; i < n; ++i) {
+            if (!sh[i].full || sh[i].band != g->band) continue;
+            Variant v = make_variant(g, dbl, wj, wl, sh[i].lb, sh[i].R, sh[i].occ, sh[i].band, pass == 1);
+            if (!v.ok) continue;
+            bool better = !best.ok;
+            if (!better && g->band && v.nb != best.nb) better = v.nb < best.nb;
+            else if (!better && v.lb != best.lb) better = v.lb > best.lb;
+            else if (!better) better = v.R < best.R;
+            if (better) best = v;
+        }
     }
 }
 
@@ -364,7 +376,7 @@ static rt_status autotune(rt_grid *g, int32_t n_lambda, const void *chi, const v
         // band tiles compete on every grid (their flush covers only the rows a
         // bundle reaches); layer tiles only where the grid is not in band mode
         if (g->band && !sh[i].band) continue;
-        const Variant v = make_variant(g, dbl, true, false, sh[i].lb, sh[i].R, sh[i].occ, sh[i].band);
+        const Variant v = make_variant(g, dbl, true, false, sh[i].lb, sh[i].R, sh[i].occ, sh[i].band, false);
         if (!v.ok) continue;
         DevSchedule *sc = nullptr;
         DevBuf &pJ = dbl ? g->partJ64 : g->partJ;
@@ -422,7 +434,7 @@ static rt_status set_shape(rt_grid *g, bool dbl, int32_t threads, int32_t rays, 
             if (sh[i].lb != threads || sh[i].R != rays) continue;
             if (band >= 0 ? sh[i].band != (band != 0) : (sh[i].band != g->band) != (pass == 1)) continue;
             if (g->band && !sh[i].band) continue;
-            const Variant v = make_variant(g, dbl, true, false, threads, rays, sh[i].occ, sh[i].band);
+            const Variant v = make_variant(g, dbl, true, false, threads, rays, sh[i].occ, sh[i].band, true);
             if (!v.ok) continue;
             variant(g, dbl, true, false) = v;
             return RT_OK;

@@ -89,7 +89,6 @@ fs_box_kernel(FsBoxArgs a)
     T *tJ = reinterpret_cast<T *>(smem_raw);
     T *tL = tJ + (WJ ? TW + nthr : 0);
     constexpr int ES = 2 * (int)sizeof(T);  // bytes per (chi, S) pair
-    constexpr int kPad = 1 << 31;          // xy0 flag: slot beyond the last ray
 
     for (int i = tid; i < TW + nthr; i += nthr) {
         if (WJ) tJ[i] = T(0);
@@ -117,26 +116,36 @@ fs_box_kernel(FsBoxArgs a)
         q_lo = bundle * a.bundle_rays;
         q_n = min(a.bundle_rays, NxNy - q_lo);
     }
-    int xy0[R];    // x0 | (y0 - yb) << 16 | kPad
+    // Two constants per ray j of this thread: vb[j], the byte offset of its
+    // origin in the padded field (the per-visit part of the address is
+    // scalar), and tw[j] = x0 << 19 | (tile word of its origin) * sizeof(T):
+    // its high field decides the x wrap of a visit by one unsigned comparison
+    // with a scalar, its low field (< 2^19: LDS bytes) is the tile address
+    // before the visit's scalar offset.  Rows are relative to the bundle's
+    // first row yb for band tiles.  Only the last slot of a thread can be a
+    // padding slot (padj).
+    const uint32_t row_bytes = (uint32_t)(2 * Nx * ES);
+    const int gshift = BAND ? (int)((uint32_t)yb * row_bytes) : 0;
+    constexpr uint32_t kTileMask = (1u << 19) - 1u;
+    int vb[R];
+    uint32_t tw[R];
+    bool padj = false;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         int l = tid + j * nthr;
-        int pad = 0;
-        while (l >= q_n) { l -= q_n; pad = kPad; }
+        bool pad = false;
+        while (l >= q_n) { l -= q_n; pad = true; }
         const int q = q_lo + l;
         const int y0 = q / Nx;
         const int x0 = q - y0 * Nx;
-        xy0[j] = x0 | ((y0 - yb) << 16) | pad;
+        const uint32_t yr = (uint32_t)(y0 - yb);
+        vb[j] = (int)(yr * row_bytes + (uint32_t)x0 * ES);
+        tw[j] = ((uint32_t)x0 << 19) | ((yr * (uint32_t)Nx + (uint32_t)x0) * (uint32_t)sizeof(T));
+        if (j == R - 1) padj = pad;
     }
-    // byte offset of ray j's origin in the padded field (recomputed: saves R
-    // registers); with band tiles the bundle's first row yb goes into the
-    // scalar (per visit) part of the address
-    const uint32_t row_bytes = (uint32_t)(2 * Nx * ES);
-    const int gshift = BAND ? (int)((uint32_t)yb * row_bytes) : 0;
-    auto vbase = [&](int j) {
-        const uint32_t x0 = (uint32_t)xy0[j] & 0xffffu, y0 = ((uint32_t)xy0[j] >> 16) & 0x7fffu;
-        return (int)(__umul24(y0, row_bytes) + x0 * ES);
-    };
+    unsigned char *const tJb = reinterpret_cast<unsigned char *>(tJ);
+    unsigned char *const tLb = reinterpret_cast<unsigned char *>(tL);
+    const uint32_t pad_addr = (uint32_t)(TW + tid) * (uint32_t)sizeof(T);
     __syncthreads();
 
     const uint32_t slice_bytes = (uint32_t)(a.pad_stride * ES);
@@ -150,15 +159,15 @@ fs_box_kernel(FsBoxArgs a)
         T *__restrict__ pJ = WJ ? reinterpret_cast<T *>(a.partJ) + (int64_t)item.slot * a.n_vox : nullptr;
         T *__restrict__ pL = WL ? reinterpret_cast<T *>(a.partL) + (int64_t)item.slot * a.n_vox : nullptr;
         const bool first = item.first != 0;
-        const int64_t vb = a.dir_vbegin[d];
+        const int64_t vbeg = a.dir_vbegin[d];
         const int M = a.dir_M[d];
         const double wmu = a.dir_wmu[d];
         const bool down = a.dir_mu[d] < 0.0;
         const T Ibc = a.I_bc ? reinterpret_cast<const T *>(a.I_bc)[2 * lam + (down ? 0 : 1)] : T(0);
-        const int32_t *__restrict__ goff = a.goff + vb;
-        const uint32_t *__restrict__ dxy = a.dxy + vb;
-        const double *__restrict__ sv = a.s + vb;
-        const int32_t *__restrict__ brow = BAND ? a.brow + vb : nullptr;
+        const int32_t *__restrict__ goff = a.goff + vbeg;
+        const uint32_t *__restrict__ dxy = a.dxy + vbeg;
+        const double *__restrict__ sv = a.s + vbeg;
+        const int32_t *__restrict__ brow = BAND ? a.brow + vbeg : nullptr;
         const int span = BAND ? a.dir_span[d] : 0;
 
         if (BAND && first) {
@@ -215,46 +224,90 @@ fs_box_kernel(FsBoxArgs a)
             layer += dlayer;
             __syncthreads();
         };
-        // tile index of ray j at a visit with horizontal offsets packed in w
-        // (and, for band tiles, relative row r); wrap by an unsigned minimum
-        // (x - N underflows when x < N).  Padding slots go to this thread's own
-        // word past the tile, so no two lanes ever update the same word in one
-        // step.
-        auto tile_index = [&](int j, uint32_t w, int r) {
-            const uint32_t x0 = (uint32_t)xy0[j] & 0xffffu, y0 = ((uint32_t)xy0[j] >> 16) & 0x7fffu;
-            uint32_t xl = x0 + (w & kOffMask);
-            xl = min(xl, xl - (uint32_t)Nx);
-            uint32_t yl;
+        // Scalar part of a visit's tile addresses: byte offset of the visit's
+        // horizontal offsets (dx, and the relative row r or dy), the x-wrap
+        // threshold (Nx - dx) << 19 on tw, and for layer tiles the y-wrap
+        // threshold on the tile address.
+        struct TileStep {
+            uint32_t off, thx, thy;
+        };
+        auto tile_step = [&](uint32_t w, int r) {
+            const uint32_t dx = w & kOffMask;
+            TileStep s;
+            s.thx = ((uint32_t)Nx - dx) << 19;
             if (BAND) {
-                yl = y0 + (uint32_t)r;
+                s.off = ((uint32_t)r * (uint32_t)Nx + dx) * (uint32_t)sizeof(T);
+                s.thy = 0;
             } else {
-                yl = y0 + ((w >> kOffBits) & kOffMask);
-                yl = min(yl, yl - (uint32_t)Ny);
+                const uint32_t dy = (w >> kOffBits) & kOffMask;
+                s.off = (dy * (uint32_t)Nx + dx) * (uint32_t)sizeof(T);
+                s.thy = ((uint32_t)Ny - dy) * (uint32_t)Nx * (uint32_t)sizeof(T);
             }
-            const int idx = (int)__umul24(yl, (uint32_t)Nx) + (int)xl;
-            return (j == R - 1 && xy0[j] < 0) ? TW + tid : idx;
+            return s;
+        };
+        // LDS byte address of ray j's voxel at a visit; padding slots go to
+        // this thread's own word past the tile, so no two lanes ever update
+        // the same word in one step
+        auto tile_addr = [&](int j, const TileStep &s) {
+            const uint32_t base = tw[j] & kTileMask;
+            uint32_t a4 = base + s.off - (tw[j] >= s.thx ? (uint32_t)Nx * (uint32_t)sizeof(T) : 0u);
+            if (!BAND) a4 -= base >= s.thy ? (uint32_t)NxNy * (uint32_t)sizeof(T) : 0u;
+            return (j == R - 1 && padj) ? pad_addr : a4;
         };
         // the visit weight, zero for a padding slot
-        auto ray_weight = [&](int j, T cw) { return (j == R - 1 && xy0[j] < 0) ? T(0) : cw; };
+        auto ray_weight = [&](int j, T cw) { return (j == R - 1 && padj) ? T(0) : cw; };
+        auto tile_add = [&](unsigned char *tile, uint32_t addr, T v) {
+            T *w = reinterpret_cast<T *>(tile + addr);
+            *w += v;
+        };
 
-        // first point: entry half-segment with constant S
+        // Single-precision sweeps carry along each ray, from one visit to the
+        // next, the sources of the previous and current points (Sp, Sc), the
+        // opacity of the current point (Xc) and the optical step from the
+        // previous point to the current one (Dc): each visit then reads only
+        // the next point's (chi, S) pair and forms one optical depth.  Double
+        // sweeps (twice the registers per value) read the previous, current
+        // and next pairs at every visit instead.
+        constexpr bool CARRY = sizeof(T) == 4;
+        T Sp[CARRY ? R : 1], Sc[CARRY ? R : 1], Xc[CARRY ? R : 1];
+        double Dc[CARRY ? R : 1];
+        int g_p = 0;
+        double s_p = 0.0;
+
+        // first point: entry half-segment with constant S; the second point's
+        // pair is read too (the first optical step between points needs it)
         int g_c = goff[0] * ES + gshift;
         double s_c = sv[0];
         uint32_t w_c = dxy[0];
         int r_c = BAND ? brow[0] : 0;
+        int g_n = g_c;
+        double s_n = s_c;
+        if (M > 1) {
+            g_n = goff[1] * ES + gshift;
+            s_n = sv[1];
+        }
         {
             const T cw = T(wmu * s_c);
+            const TileStep ts = tile_step(w_c, r_c);
 #pragma unroll
             for (int j = 0; j < R; ++j) {
                 gprev[j] = T(0);
-                const Pair<T> fc = ld_pair<T>(rf, vbase(j), g_c);
+                const Pair<T> f0 = ld_pair<T>(rf, vb[j], g_c);
+                const double t0 = seg_depth_pos((double)f0.chi, s_c);
                 T ex, e0;
-                entry_weights<T>(0.5 * seg_depth((double)fc.chi, s_c), ex, e0);
-                I[j] = WJ ? Ibc * ex + fc.S * e0 : T(0);
-                const int idx = tile_index(j, w_c, r_c);
+                entry_weights<T>(0.5 * t0, ex, e0);
+                I[j] = WJ ? Ibc * ex + f0.S * e0 : T(0);
+                const uint32_t ad = tile_addr(j, ts);
                 const T cj = ray_weight(j, cw);
-                if (WJ) tJ[idx] += cj * I[j];
-                if (WL) tL[idx] += cj * e0;
+                if (WJ) tile_add(tJb, ad, cj * I[j]);
+                if (WL) tile_add(tLb, ad, cj * e0);
+                if constexpr (CARRY) {
+                    const Pair<T> f1 = ld_pair<T>(rf, vb[j], g_n);
+                    Sp[j] = f0.S;
+                    Sc[j] = f1.S;
+                    Xc[j] = f1.chi;
+                    Dc[j] = half_sum(t0, seg_depth_pos((double)f1.chi, s_n));
+                }
             }
             __syncthreads();
             if (w_c & kLayerEnd) flush_layer(w_c, r_c);
@@ -262,34 +315,46 @@ fs_box_kernel(FsBoxArgs a)
 
         // one point of every ray of this thread; LAST: the final point, which
         // has no downwind neighbour
-        int g_p = 0, g_n = 0;
-        double s_p = 0.0, s_n = 0.0;
         auto step = [&](auto last_tag) {
             constexpr bool LAST = decltype(last_tag)::value;
             const T cw = T(wmu * s_c);
+            const TileStep ts = tile_step(w_c, r_c);
             // software pipeline over the rays of this thread: the loads of
             // ray j+1 are in flight while ray j is computed
-            const int vo0 = vbase(0);
-            Pair<T> np = ld_pair<T>(rf, vo0, g_p);
-            Pair<T> nc = ld_pair<T>(rf, vo0, g_c);
-            Pair<T> nn = LAST ? Pair<T>{T(0), T(0)} : ld_pair<T>(rf, vo0, g_n);
+            const Pair<T> zero{T(0), T(0)};
+            Pair<T> nn = LAST ? zero : ld_pair<T>(rf, vb[0], g_n);
+            Pair<T> np = CARRY ? zero : ld_pair<T>(rf, vb[0], g_p);
+            Pair<T> nc = CARRY ? zero : ld_pair<T>(rf, vb[0], g_c);
 #pragma unroll
             for (int j = 0; j < R; ++j) {
-                const Pair<T> fp = np, fc = nc, fn = nn;
+                const Pair<T> fn = nn, fp = np, fc = nc;
                 if (j + 1 < R) {
-                    const int vo = vbase(j + 1);
-                    np = ld_pair<T>(rf, vo, g_p);
-                    nc = ld_pair<T>(rf, vo, g_c);
-                    nn = LAST ? Pair<T>{T(0), T(0)} : ld_pair<T>(rf, vo, g_n);
+                    if (!LAST) nn = ld_pair<T>(rf, vb[j + 1], g_n);
+                    if (!CARRY) {
+                        np = ld_pair<T>(rf, vb[j + 1], g_p);
+                        nc = ld_pair<T>(rf, vb[j + 1], g_c);
+                    }
                 }
-                const double tc = seg_depth((double)fc.chi, s_c);
-                const double D = half_sum(seg_depth((double)fp.chi, s_p), tc);
-                const double Dp = LAST ? 0.0 : half_sum(tc, seg_depth((double)fn.chi, s_n));
-                const PointW<T> pw = point_weights<T>(D, Dp, LAST);
-                if (WJ) I[j] = I[j] * pw.ex + pw.a * fp.S + pw.b * fc.S + (LAST ? T(0) : pw.g * fn.S);
-                const int idx = tile_index(j, w_c, r_c);
+                double D, Dp = 0.0;
+                T S_prev, S_cur;
+                if constexpr (CARRY) {
+                    D = Dc[j];
+                    S_prev = Sp[j];
+                    S_cur = Sc[j];
+                    // the current depth unclamped: Dp >= kMinStep / 2 all the same
+                    if (!LAST) Dp = half_sum(seg_depth((double)Xc[j], s_c), seg_depth_pos((double)fn.chi, s_n));
+                } else {
+                    const double tc = seg_depth_pos((double)fc.chi, s_c);
+                    D = half_sum(seg_depth_pos((double)fp.chi, s_p), tc);
+                    if (!LAST) Dp = half_sum(tc, seg_depth_pos((double)fn.chi, s_n));
+                    S_prev = fp.S;
+                    S_cur = fc.S;
+                }
+                const PointW<T> pw = point_weights_pos<T, LAST>(D, Dp);
+                if (WJ) I[j] = I[j] * pw.ex + pw.a * S_prev + pw.b * S_cur + (LAST ? T(0) : pw.g * fn.S);
+                const uint32_t ad = tile_addr(j, ts);
                 const T cj = ray_weight(j, cw);
-                if (WJ) tJ[idx] += cj * I[j];
+                if (WJ) tile_add(tJb, ad, cj * I[j]);
                 if (WL) {
                     T dloc;
                     if (PARA) {
@@ -298,27 +363,41 @@ fs_box_kernel(FsBoxArgs a)
                     } else {
                         dloc = pw.dlin;
                     }
-                    tL[idx] += cj * dloc;
+                    tile_add(tLb, ad, cj * dloc);
+                }
+                if constexpr (CARRY && !LAST) {
+                    Sp[j] = Sc[j];
+                    Sc[j] = fn.S;
+                    Xc[j] = fn.chi;
+                    Dc[j] = Dp;
                 }
             }
             __syncthreads();
             if (w_c & kLayerEnd) flush_layer(w_c, r_c);
         };
 
-        for (int m = 1; m < M; ++m) {
-            // window of template entries: previous (p), current (c), next (n)
-            g_p = g_c; s_p = s_c;
-            g_c = goff[m] * ES + gshift;
-            s_c = sv[m];
+        // template entries of the current visit (c) and the next one (n); the
+        // final point is taken after the loop, so that the loop body has a
+        // single path (no merge of the carried per-ray state)
+        for (int m = 1; m + 1 < M; ++m) {
+            g_p = g_c;
+            s_p = s_c;
+            g_c = g_n;
+            s_c = s_n;
             w_c = dxy[m];
             if (BAND) r_c = brow[m];
-            if (m + 1 < M) {
-                g_n = goff[m + 1] * ES + gshift;
-                s_n = sv[m + 1];
-                step(std::false_type{});
-            } else {
-                step(std::true_type{});
-            }
+            g_n = goff[m + 1] * ES + gshift;
+            s_n = sv[m + 1];
+            step(std::false_type{});
+        }
+        if (M > 1) {
+            g_p = g_c;
+            s_p = s_c;
+            g_c = g_n;
+            s_c = s_n;
+            w_c = dxy[M - 1];
+            if (BAND) r_c = brow[M - 1];
+            step(std::true_type{});
         }
     }
 }
@@ -337,12 +416,17 @@ fs_box_kernel(FsBoxArgs a)
 // the latency of the double-precision point arithmetic.  Band-tile shapes
 // serve layers too wide for a whole-layer tile (and grids that ask for band
 // tiles); their bundle count follows from the LDS left per workgroup.
-#define RT_FS_SHAPES_FULL(X) X(1024, 1, 1) X(1024, 2, 1) X(1024, 4, 1) X(1024, 8, 1) X(1024, 12, 1) X(1024, 17, 1) X(1024, 24, 1)
+#define RT_FS_SHAPES_FULL(X)                                                                                 \
+    X(1024, 1, 1) X(1024, 2, 1) X(1024, 4, 1) X(1024, 8, 1) X(1024, 12, 1) X(1024, 17, 1) X(1024, 24, 1) \
+        X(768, 6, 1) X(768, 11, 1)
 #define RT_FS_SHAPES_TUNE(X)                                                                                     \
-    X(768, 2, 1) X(768, 6, 1) X(768, 11, 1) X(768, 22, 1) X(768, 32, 1) X(512, 33, 1) X(256, 5, 1) X(256, 17, 1) \
-        X(256, 34, 1) X(512, 3, 2) X(512, 9, 2) X(512, 17, 2)
-#define RT_FS_SHAPES_BAND_FULL(X) X(1024, 1, 1) X(1024, 2, 1) X(1024, 4, 1) X(1024, 8, 1) X(1024, 12, 1) X(1024, 17, 1)
-#define RT_FS_SHAPES_BAND_TUNE(X) X(768, 11, 1) X(768, 22, 1) X(512, 9, 2) X(512, 17, 2)
+    X(768, 2, 1) X(768, 8, 1) X(768, 22, 1) X(768, 32, 1) X(512, 33, 1) X(256, 5, 1) X(256, 17, 1) X(256, 34, 1) \
+        X(512, 3, 2) X(512, 7, 2) X(512, 9, 2) X(512, 17, 2)
+#define RT_FS_SHAPES_BAND_FULL(X)                                                                            \
+    X(1024, 1, 1) X(1024, 2, 1) X(1024, 4, 1) X(1024, 8, 1) X(1024, 12, 1) X(1024, 17, 1) X(768, 6, 1) \
+        X(768, 11, 1)
+#define RT_FS_SHAPES_BAND_TUNE(X) \
+    X(768, 8, 1) X(768, 10, 1) X(896, 10, 1) X(768, 22, 1) X(512, 6, 2) X(512, 7, 2) X(512, 9, 2) X(512, 17, 2)
 
 static const FsShape kShapes[] = {
 #define RT_LIST(lb, r, o) {lb, r, true, o, false},
@@ -375,14 +459,17 @@ static hipError_t launch_one(const FsBoxArgs &a, int n_wg, int nthr, size_t lds,
     return hipGetLastError();
 }
 
+// Resident workgroups per CU; negative when the compiled kernel spills
+// registers to scratch memory (the host then prefers other shapes).
 template <typename T, int LB, int R, bool WJ, bool WL, bool PARA, int OCC, bool BAND>
 static int occ_one(int nthr, size_t lds)
 {
+    const auto k = fs_box_kernel<T, LB, R, WJ, WL, PARA, OCC, BAND>;
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fs_box_kernel<T, LB, R, WJ, WL, PARA, OCC, BAND>, nthr,
-                                                     lds) != hipSuccess)
-        return 0;
-    return n;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, nthr, lds) != hipSuccess) return 0;
+    hipFuncAttributes attr{};
+    if (hipFuncGetAttributes(&attr, (const void *)k) != hipSuccess) return 0;
+    return attr.localSizeBytes > 0 ? -n : n;
 }
 
 template <typename T, int LB, int R, int OCC, bool BAND>

@@ -56,6 +56,8 @@ int fs_box_shapes(const FsShape **out);
 hipError_t fs_box_launch(const FsBoxArgs &a, bool is_double, bool want_j, bool want_l, bool parabolic_lstar,
                          bool band, int lb, int R, int n_wg, int nthr, size_t lds_bytes, hipStream_t stream);
 
+// Resident workgroups per CU of a shape; negative if its kernel spills
+// registers (the magnitude is then still the occupancy).
 int fs_box_occupancy(bool is_double, bool want_j, bool want_l, bool parabolic_lstar, bool band, int lb, int R,
                      int nthr, size_t lds_bytes);
 

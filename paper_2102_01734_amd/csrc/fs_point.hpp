@@ -24,19 +24,27 @@ __device__ __forceinline__ double half_sum(double a, double b)
     return 0.5 * (a + b);
 }
 
+// 1/x from the hardware reciprocal estimate refined by Newton steps
+// r <- r + r (1 - x r), each of which doubles the correct bits: two steps for
+// double results, one when the weights are rounded to single precision.
+template <bool FULL = true>
 __device__ __forceinline__ double rcp_f64(double x)
 {
     double r = __builtin_amdgcn_rcp(x);
     double e = __builtin_fma(-x, r, 1.0);
     r = __builtin_fma(r, e, r);
+    if (!FULL) return r;
     e = __builtin_fma(-x, r, 1.0);
     return __builtin_fma(r, e, r);
 }
 
-// exp(-D) for 1/4 <= D: x = -D = n ln2 + r with |r| <= ln2/2, exp(r) by its
-// Taylor polynomial (degree 12 for double results, 9 when the weights feed a
-// single-precision recurrence), scaled by 2^n.  D is clamped at 745, where
-// the result is already below the smallest subnormal.
+// exp(-D) for 1/4 <= D, with the Cody-Waite argument reduction: x = -D =
+// n ln2 + r, |r| <= ln2/2, where n ln2 is subtracted in two parts (ln2 split
+// into a high part with trailing zero bits, so that n times it is exact, and
+// the low remainder; the split of the fdlibm exponential), exp(r) by its
+// degree-12 Taylor polynomial for double results (for single-precision ones,
+// see below), scaled by 2^n.  D is clamped at 745, where the result is
+// already below the smallest subnormal.
 template <bool FULL>
 __device__ __forceinline__ double exp_neg(double D)
 {
@@ -45,13 +53,29 @@ __device__ __forceinline__ double exp_neg(double D)
     double r = __builtin_fma(-n, 6.93147180369123816490e-01, x);
     r = __builtin_fma(-n, 1.90821492927058770002e-10, r);
     double p;
-    if (FULL) {
+    if (!FULL) {
+        // single-precision results: exp(r) = exp(r/16)^16, with exp(r/16)
+        // (|r/16| <= 0.0217) from its degree-6 Taylor polynomial (truncation
+        // below 1e-14 relative after the squarings, rounding ~3e-15); fewer
+        // non-trivial constants than the degree-12 polynomial in r
+        const double s = __builtin_ldexp(r, -4);
+        p = __builtin_fma(s, 1.0 / 720.0, 1.0 / 120.0);
+        p = __builtin_fma(p, s, 1.0 / 24.0);
+        p = __builtin_fma(p, s, 1.0 / 6.0);
+        p = __builtin_fma(p, s, 0.5);
+        p = __builtin_fma(p, s, 1.0);
+        p = __builtin_fma(p, s, 1.0);
+        p = p * p;
+        p = p * p;
+        p = p * p;
+        p = p * p;
+        return __builtin_ldexp(p, (int)n);
+    }
+    {
         p = 1.0 / 479001600.0;
         p = __builtin_fma(p, r, 1.0 / 39916800.0);
         p = __builtin_fma(p, r, 1.0 / 3628800.0);
         p = __builtin_fma(p, r, 1.0 / 362880.0);
-    } else {
-        p = 1.0 / 362880.0;
     }
     p = __builtin_fma(p, r, 1.0 / 40320.0);
     p = __builtin_fma(p, r, 1.0 / 5040.0);
@@ -68,10 +92,11 @@ __device__ __forceinline__ double exp_neg(double D)
 // Attenuation moments over an optical step D > 0:
 //   ex = exp(-D), e0 = 1 - ex, e1 = D - e0, e2 = D^2 - 2 e1.
 // Below D = 1/4, e2 comes from its Taylor series 2 D^3 sum_j (-D)^j/(j+3)!
-// (12 terms for double results, 8 for single-precision ones), and e1, e0, ex
-// follow from it without cancellation; from 1/4 up the closed forms are used.
-// The series is evaluated on every lane (it is short); the exponential only
-// where some lane of the wave needs it.
+// (12 terms for double results; 7 for single-precision ones, whose first
+// omitted term is below 1e-10 of e2 at D = 1/4), and e1, e0, ex follow from
+// it without cancellation; from 1/4 up the closed forms are used.  The series
+// and the exponential are separate branches (a wave whose steps straddle 1/4
+// runs both).
 template <bool FULL>
 __device__ __forceinline__ void kernel_moments(double D, double &ex, double &e0, double &e1, double &e2)
 {
@@ -81,11 +106,11 @@ __device__ __forceinline__ void kernel_moments(double D, double &ex, double &e0,
         p = __builtin_fma(-D, p, 1.0 / 6227020800.0);  // 1/13!
         p = __builtin_fma(-D, p, 1.0 / 479001600.0);   // 1/12!
         p = __builtin_fma(-D, p, 1.0 / 39916800.0);    // 1/11!
+        p = __builtin_fma(-D, p, 1.0 / 3628800.0);     // 1/10!
+        p = __builtin_fma(-D, p, 1.0 / 362880.0);      // 1/9!
     } else {
-        p = 1.0 / 39916800.0;                          // 1/11!
+        p = 1.0 / 362880.0;                            // 1/9!
     }
-    p = __builtin_fma(-D, p, 1.0 / 3628800.0);     // 1/10!
-    p = __builtin_fma(-D, p, 1.0 / 362880.0);      // 1/9!
     p = __builtin_fma(-D, p, 1.0 / 40320.0);       // 1/8!
     p = __builtin_fma(-D, p, 1.0 / 5040.0);        // 1/7!
     p = __builtin_fma(-D, p, 1.0 / 720.0);         // 1/6!
@@ -154,6 +179,48 @@ __device__ __forceinline__ PointW<T> point_weights(double D, double Dp, bool las
         w.a = lin ? al_t : ap_t;
     }
     return w;
+}
+
+// point_weights for optical steps that are already at least kMinStep / 2
+// (optical depths clamped at kMinStep where they are formed): no clamping
+// here.  LAST: the final point of a ray (linear weights; Dp is not read).
+template <typename T, bool LAST>
+__device__ __forceinline__ PointW<T> point_weights_pos(double D, double Dp)
+{
+    constexpr bool FULL = sizeof(T) == 8;
+    double ex, e0, e1, e2;
+    kernel_moments<FULL>(D, ex, e0, e1, e2);
+    const double Dq = LAST ? D : Dp;
+    const double Ds = D + Dq;
+    const double r = rcp_f64<FULL>(D * Dq * Ds);
+    const double bl = e1 * ((Dq * Ds) * r);  // e1 / D
+    const bool lin = LAST || (Dp < 0.5 * D) || (Dp * e0 <= __builtin_fma(D, e1, -e2));
+    PointW<T> w;
+    w.ex = T(ex);
+    w.dlin = T(bl);
+    if (LAST) {
+        w.b = T(bl);
+        w.g = T(0);
+        w.a = T(e0 - bl);
+        return w;
+    }
+    const double bp = __builtin_fma(Ds, e1, -e2) * (Ds * r);
+    const double gp = (e2 - D * e1) * (D * r);
+    const double b = lin ? bl : bp;
+    const double g = lin ? 0.0 : gp;
+    w.b = T(b);
+    w.g = T(g);
+    w.a = T(e0 - b - g);
+    return w;
+}
+
+// Optical depth chi s of a segment, at least kMinStep: a vacuum segment
+// (Listing 1 step 4a) then contributes a step of 1e-100 instead of 0, which
+// changes the intensity by less than 1e-100 S; NaN propagates.
+__device__ __forceinline__ double seg_depth_pos(double chi, double s)
+{
+    const double t = seg_depth(chi, s);
+    return t < kMinStep ? kMinStep : t;
 }
 
 // Entry half-segment: constant S from the entry point to the first point.

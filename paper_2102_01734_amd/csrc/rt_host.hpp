@@ -245,7 +245,10 @@ inline Variant &variant(rt_grid *g, bool dbl, bool wj, bool wl) { return g->var[
 // functions shared between the modules
 // ---------------------------------------------------------------------------
 // launch shapes and schedules (api_launch.cpp)
-Variant make_variant(rt_grid *g, bool dbl, bool wj, bool wl, int lb, int R, int occ = 1, bool band = false);
+// ok = false for shapes that cannot hold a bundle's rays, whose tiles do not
+// fit, or (unless allow_spill) whose kernel spills registers
+Variant make_variant(rt_grid *g, bool dbl, bool wj, bool wl, int lb, int R, int occ = 1, bool band = false,
+                     bool allow_spill = false);
 void setup_variant(rt_grid *g, bool dbl, bool wj, bool wl);
 rt_status get_schedule(rt_grid *g, int n_wg, const std::vector<int32_t> &lambdas, DevSchedule **out,
                        const std::vector<int32_t> *subset = nullptr, const Variant *v = nullptr);

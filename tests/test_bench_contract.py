@@ -23,15 +23,21 @@ def test_bench_lists_its_workloads():
         assert w in r.stdout
 
 
-def test_traffic_is_read_only_for_the_launch_shape_it_was_taken_on():
-    """The HBM traffic in the bench line comes from a committed counter summary
-    of the same kernel source and launch shape; any other shape reports null."""
+def test_traffic_is_read_only_for_the_launch_shape_it_was_taken_on(tmp_path):
+    """The HBM traffic in the bench line comes from a counter summary of the
+    same kernel source and launch shape; any other shape, workload or kernel
+    source reports null."""
     sys.path.insert(0, ROOT)
     import bench
-    on_file = {(768, 11, 2, 1), (1024, 17, 2, 1), (512, 17, 2, 1)}
-    for t, r, nb, band in on_file:
-        b = bench.read_traffic("lognormal129", {"threads": t, "rays": r, "bundles": nb, "band": band})
-        assert b is not None and 5e10 < b < 1e12
-    assert bench.read_traffic("lognormal129", {"threads": 768, "rays": 11, "bundles": 2, "band": 0}) is None
-    assert bench.read_traffic("lognormal129", {"threads": 512, "rays": 9, "bundles": 4, "band": 1}) is None
-    assert bench.read_traffic("no_such_workload", {"threads": 768, "rays": 11, "bundles": 2, "band": 1}) is None
+    src = bench.fs_source_hash()
+    for name, shape, hbm, h in (("a", "768,11,2,band", 1.08e11, src), ("b", "1024,17,2,band", 2.77e11, src),
+                                ("c", "512,9,4,band", 3.0e11, "0123456789abcdef")):
+        (tmp_path / f"fs_box_lognormal129_traffic_{name}.md").write_text(
+            f"fs_box.hip sha256[:16]: {h}\nhbm_bytes_per_launch: {hbm:e}\nlaunch_shape: {shape}\n")
+    rd = lambda w, t, r, nb, band: bench.read_traffic(w, {"threads": t, "rays": r, "bundles": nb, "band": band},
+                                                      str(tmp_path))  # noqa: E731
+    assert rd("lognormal129", 768, 11, 2, 1) == 1.08e11
+    assert rd("lognormal129", 1024, 17, 2, 1) == 2.77e11
+    assert rd("lognormal129", 768, 11, 2, 0) is None      # other tile kind
+    assert rd("lognormal129", 512, 9, 4, 1) is None       # taken on another kernel source
+    assert rd("no_such_workload", 768, 11, 2, 1) is None
