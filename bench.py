@@ -2,17 +2,23 @@
 """Throughput benchmark of the radiative-transfer hot path on one MI355X.
 
 One step = one operator-splitting (ALI) iteration through the C ABI
-(rt_ali_step): single-precision formal solution of all 2048 directions on the
-129^3 periodic box with log-normal opacity, the fixed-order reduction of the
-workgroup partial sums, the operator-splitting update of J and S, the
-per-wavelength convergence norm, and Ng extrapolation every fourth step.
-The metric is voxel-direction updates per second (VDU/s): voxels x directions
-x wavelengths of one formal solution, divided by the time of one step.
+(rt_ali_step), replayed as a captured HIP graph: the single-precision formal
+solution of every (wavelength, direction) item in one persistent launch, the
+fixed-order reduction of the workgroup partial sums, the operator-splitting
+update of J and S (double precision), the per-wavelength convergence norm,
+and Ng extrapolation (double precision) every fourth step.  The default
+workload is the wavelength batch: 64 wavelengths of uneven optical depth on
+the 129^3 periodic box with 1024 directions.  The metric is voxel-direction
+updates per second (VDU/s): voxels x directions x wavelengths of one formal
+solution, divided by the time of one step.
 
 Prints one JSON line: the throughput, the roofline position of the timed
 kernel (algorithmic flops of a characteristic point over its measured launch
-time, against the vector ALU peak), its HBM traffic when counters taken on
-the current kernel source are on file, and the oracle's CPU rate on a sample.
+time against the vector ALU peak, and algorithmic bytes of a voxel-direction
+update against the HBM peak), its HBM traffic when counters taken on the
+current kernel source and launch shape are on file, the oracle's CPU rate on
+a sample, and -- as extra keys -- the single-wavelength 129^3 x 2048 line,
+one GPU's share of a solid-angle split and the time to solution.
 """
 import argparse
 import glob
@@ -34,6 +40,11 @@ FLOPS_PER_POINT = 38
 # = 39.3e12 lane-ops/s, i.e. 78.6 TFLOP/s counting an FMA as 2 (the FP64
 # vector peak; non-packed FP32 issues at the same rate).
 PEAK_TFLOPS = 78.6
+# HBM3E peak of MI355X and the algorithmic bytes of one voxel-direction update
+# of a single-precision sweep: chi and S of the voxel read once per direction.
+PEAK_HBM_GBS = 8000.0
+BYTES_PER_VDU = 8
+GOLDEN_129 = os.path.join(ROOT, "tests", "golden", "box129_fixed_point.npz")
 
 WORKLOADS = {
     "lognormal129": dict(N=129, n_mu=32, n_phi=64),
@@ -78,26 +89,35 @@ def read_traffic(workload: str, ls: dict, profiles_dir: str = os.path.join(ROOT,
     return None
 
 
-def cpu_baseline(case, n_sub: int):
-    """The oracle, as it stands, on a bounded sample: all voxels, n_sub of the
-    directions spread over the sphere, all host threads."""
+def cpu_baseline(case, n_sub: int, n_sub_1: int, lam: int = 0):
+    """The oracle, as it stands, on a bounded sample of wavelength `lam`: all
+    voxels, n_sub of the directions spread over the sphere on all host
+    threads, and n_sub_1 of them on one thread."""
     import numpy as np
 
     import oracle
     import synthetic as sy
     nd = case.n_dir
-    dirs = np.unique(np.linspace(0, nd - 1, n_sub).round().astype(np.int32))
-    S = sy.random_source(case.chi.shape, seed=7, lo=0.2, hi=1.0, dtype="f32")[0]
+    S = sy.random_source(case.chi.shape[1:], seed=7, lo=0.2, hi=1.0, dtype="f32")
+    chi = case.chi[lam]
     threads = oracle.default_threads()
-    oracle.fs_box_dirs(case.chi[0][:2], S[:2], 0.0, 1.0, case.n_mu, case.n_phi, dirs[:1], threads=threads)
-    t0 = time.perf_counter()
-    oracle.fs_box_dirs(case.chi[0], S, case.I_bc[0, 0], case.I_bc[0, 1], case.n_mu, case.n_phi, dirs,
-                       threads=threads)
-    wall = time.perf_counter() - t0
-    vdu = case.n_vox * dirs.size
-    return {"value": vdu / wall, "unit": "VDU/s", "cores": threads, "kind": "oracle",
-            "sample": f"one FP64 formal solution of {dirs.size} of the {nd} directions over all "
-                      f"{case.n_vox} voxels ({wall:.1f} s wall)"}
+    oracle.fs_box_dirs(chi[:2], S[:2], 0.0, 1.0, case.n_mu, case.n_phi, np.array([0], np.int32), threads=threads)
+
+    def timed(n, th):
+        dirs = np.unique(np.linspace(0, nd - 1, n).round().astype(np.int32))
+        t0 = time.perf_counter()
+        oracle.fs_box_dirs(chi, S, case.I_bc[lam, 0], case.I_bc[lam, 1], case.n_mu, case.n_phi, dirs, threads=th)
+        wall = time.perf_counter() - t0
+        return case.n_vox * dirs.size / wall, dirs.size, wall
+
+    v, nd_all, wall = timed(n_sub, threads)
+    v1, nd_1, wall1 = timed(n_sub_1, 1)
+    what = f"wavelength {lam} of {case.n_lambda}, " if case.n_lambda > 1 else ""
+    return {"value": v, "unit": "VDU/s", "cores": threads, "kind": "oracle",
+            "sample": f"one FP64 formal solution of {what}{nd_all} of the {nd} directions over all "
+                      f"{case.n_vox} voxels ({wall:.1f} s wall on {threads} threads)",
+            "single_core": {"value": v1, "unit": "VDU/s", "cores": 1,
+                            "sample": f"{nd_1} of the {nd} directions, all voxels ({wall1:.1f} s wall)"}}
 
 
 def one_gpu_share(case, shape, n_gpus: int = 8, reps: int = 3):
@@ -206,14 +226,24 @@ def time_to_solution(case, net_every: int = 12, tol: float = 1e-6, shape=None):
         g.close()
         return J, status, rep, wall
 
-    ref, _, rref, _ = run("f64", 1e-9, 80)
-    progress(f"time to solution: reference {rref.iters} steps")
+    gpu_ref, _, rref, _ = run("f64", 1e-9, 80)
+    progress(f"time to solution: GPU double-precision reference {rref.iters} steps")
     target = 1e-5
     out = {"tol": tol, "target_error": target, "f64_launch_shape": list(shape64),
-           "reference": f"double-precision Ng-ALI, {rref.iters} steps (last max |dJ/J| {rref.max_rel_change:.1e})",
            "protocol": "seconds = wall time of rt_solve stopped at max|dJ/J| < tol; seconds_to_target = wall time "
                        "of a fresh rt_solve limited to the fewest steps (iterations) whose J is within the target "
                        "of the reference (binary search over the step limit; error evaluation not timed)"}
+    golden = load_golden(case)
+    if golden is not None:
+        ref = torch.tensor(golden["J"], dtype=torch.float64, device="cuda")[None]
+        out["reference"] = (f"oracle fixed point (FP64 CPU, {golden['steps']} steps of non-local Ng-ALI, residual "
+                            f"max|Lambda S(J) + Lambda_bc - J|/J {golden['residual']:.1e}), stored in float32")
+        out["gpu_fp64_reference_error"] = float(((gpu_ref - ref).abs() / ref.abs()).max())
+        out["gpu_fp64_reference"] = f"double-precision Ng-ALI on the GPU, {rref.iters} steps"
+    else:
+        ref = gpu_ref
+        out["reference"] = (f"double-precision Ng-ALI on the GPU, {rref.iters} steps (last max |dJ/J| "
+                            f"{rref.max_rel_change:.1e}); unverified: no oracle fixed point of this workload on file")
 
     def err_of(J):
         return float(((J - ref).abs() / ref.abs()).max())
@@ -258,6 +288,20 @@ def time_to_solution(case, net_every: int = 12, tol: float = 1e-6, shape=None):
         out["speedup_to_target_vs_plain"] = {k: b0 / v["seconds_to_target"] for k, v in out.items()
                                              if isinstance(v, dict) and "seconds_to_target" in v}
     return out
+
+
+def load_golden(case):
+    """The oracle's stored fixed point of this workload (written by
+    tests/golden/make_box129_fixed_point.py), if its input fingerprint matches."""
+    import numpy as np
+
+    import synthetic as sy
+    if not os.path.exists(GOLDEN_129):
+        return None
+    with np.load(GOLDEN_129, allow_pickle=False) as z:
+        if str(z["fingerprint"]) != sy.fingerprint(case):
+            return None
+        return {"J": z["J"].astype(np.float64), "steps": int(z["steps"]), "residual": float(z["residual"])}
 
 
 def bench_sphere(args, w):
@@ -317,16 +361,105 @@ def bench_sphere(args, w):
     print(json.dumps(out), flush=True)
 
 
+def box_line(case, name: str, steps: int, warmup: int, shape_arg=None, autotune=True):
+    """Throughput of ALI steps on a box workload, replayed as captured HIP
+    graphs on one stream, with the sweep's launch time from event nodes in
+    the graph.  Returns (result dict, tuned shape)."""
+    import torch
+
+    import paper_2102_01734_amd as rt
+    import synthetic as sy
+    dev = dict(dtype=torch.float32, device="cuda")
+    chi = torch.tensor(case.chi, **dev)
+    eps = torch.tensor(case.eps, **dev)
+    B = torch.tensor(case.B, **dev)
+    Ibc = torch.tensor(case.I_bc, **dev)
+    g = rt.Grid(case.Nx, case.Ny, case.Nz, case.n_mu, case.n_phi, "f32", case.n_lambda)
+    # launch-shape autotuning (setup, not timed): on up to 8 wavelengths spread
+    # over the batch, so that a batch is tuned on its own mix of optical depths
+    if shape_arg:
+        g.set_launch_shape(*shape_arg)
+    elif autotune:
+        pick = sorted(set(round(x) for x in torch.linspace(0, case.n_lambda - 1, min(8, case.n_lambda)).tolist()))
+        S0 = torch.tensor(sy.random_source((len(pick),) + case.chi.shape[1:], seed=7, lo=0.2, hi=1.0, dtype="f32"),
+                          **dev)
+        g.autotune(chi[pick].contiguous(), S0)
+        del S0
+    ls = g.launch_shape()
+    shape = (ls["threads"], ls["rays"], bool(ls["band"]))
+    progress(f"{name}: launch shape {shape}, {ls['bundles']} bundles")
+    info = g.info()
+    st = g.new_state(chi, eps, B, Ibc)
+    opts = g.opts(tol=1e-30, max_iter=1, ng_every=4, ng_start=4, use_graph=True)
+    s = torch.cuda.Stream()
+    rt.rt_profile_enable(g.handle, True)  # before the warm-up: the profiled graph is captured there
+    with torch.cuda.stream(s):
+        for _ in range(warmup):
+            g.ali_step(st, opts, stream=s)
+    s.synchronize()
+    torch.cuda.synchronize()
+    rt.rt_profile_read(g.handle)
+    t0 = time.perf_counter()
+    with torch.cuda.stream(s):
+        for _ in range(steps):
+            g.ali_step(st, opts, stream=s)
+    s.synchronize()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fs_ms, fs_launches, fs_points = rt.rt_profile_read(g.handle)
+    rt.rt_profile_enable(g.handle, False)
+    rel = g.state_tensors(st)["rel_change"].cpu().numpy()
+    g.close()
+    del st
+    torch.cuda.synchronize()
+
+    ms_per_step = (t1 - t0) * 1e3 / steps
+    vdu = case.vdu_per_fs()
+    fs_ms_launch = fs_ms / max(fs_launches, 1)
+    points_launch = fs_points / max(fs_launches, 1)
+    achieved = FLOPS_PER_POINT * points_launch / (fs_ms_launch * 1e-3) / 1e12
+    hbm = BYTES_PER_VDU * vdu / (fs_ms_launch * 1e-3) / 1e9
+    traffic = read_traffic(name, ls)
+    progress(f"{name}: {steps} timed steps, {ms_per_step:.1f} ms per step, sweep {fs_ms_launch:.1f} ms")
+    if case.n_lambda == 1:
+        wl = (f"box {case.Nx}^3 periodic x,y, {case.n_mu}x{case.n_phi} directions, stratified opacity (tau 1e-4..1e4) "
+              "x log-normal perturbation (1 dex, l=8), eps 1e-6..1 per voxel; step = one ALI iteration (FP32 formal "
+              "solution + reduction + FP64 update + norm, Ng every 4), HIP-graph replay")
+    else:
+        wl = (f"box {case.Nx}^3 periodic x,y, {case.n_mu}x{case.n_phi} directions, {case.n_lambda} wavelengths "
+              "(opacity scale 10^U(-3,3), eps 10^U(-5,-1) per wavelength) in one persistent launch per step; step = "
+              "one ALI iteration over the batch (FP32 formal solution, FP64 update, Ng and norms), HIP-graph replay")
+    out = {
+        "metric": "voxel-direction updates/s (formal solution)", "value": vdu / (ms_per_step * 1e-3),
+        "unit": "VDU/s", "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl, "name": name, "voxels": case.n_vox, "directions": case.n_dir,
+                   "wavelengths": case.n_lambda, "vdu_per_step": vdu,
+                   "visits_per_vdu": points_launch / vdu, "workgroups": info["n_workgroups"],
+                   "launch_shape": {"threads": ls["threads"], "rays_per_thread": ls["rays"],
+                                    "bundles": ls["bundles"], "tiles": "band" if ls["band"] else "layer"}},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_TFLOPS, "traffic": traffic,
+                     "hbm": {"achieved": hbm, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": hbm / PEAK_HBM_GBS,
+                             "bytes_per_vdu": BYTES_PER_VDU},
+                     "kernel": "fs_box_kernel<float,J>", "kernel_ms_per_launch": fs_ms_launch,
+                     "launches": fs_launches, "flops_per_point": FLOPS_PER_POINT,
+                     "points_per_launch": points_launch, "vdu_per_launch": vdu},
+        "last_rel_change": float(rel.max()),
+    }
+    return out, shape
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="lognormal129", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-dirs", type=int, default=None,
-                    help="directions in the CPU-baseline sample (default: about 4e8 voxel-directions)")
+    ap.add_argument("--workload", default="batched129", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-solution comparison")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="batched workload: skip the single-wavelength line, the one-GPU share and time to solution")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--shape", default=None, help="fix the launch shape THREADS,RAYS[,BAND] (BAND 1: row-band tiles) instead of autotuning")
     ap.add_argument("--host-cache", action="store_true",
@@ -353,120 +486,43 @@ def main():
                           "launches": 3}), flush=True)
         return
 
-    import paper_2102_01734_amd as rt
     import synthetic as sy
 
     w = WORKLOADS[args.workload]
     if "Nr" in w:
         return bench_sphere(args, w)
-    if "n_lambda" in w:
-        case = sy.box_batched(N=w["N"], n_lambda=w["n_lambda"], n_mu=w["n_mu"], n_phi=w["n_phi"])
-    else:
-        case = sy.box_lognormal(N=w["N"], n_mu=w["n_mu"], n_phi=w["n_phi"], field_seed=w.get("field_seed", 1),
-                                eps_seed=w.get("eps_seed", 101))
+
+    def make(wname):
+        ww = WORKLOADS[wname]
+        if "n_lambda" in ww:
+            return sy.box_batched(N=ww["N"], n_lambda=ww["n_lambda"], n_mu=ww["n_mu"], n_phi=ww["n_phi"])
+        return sy.box_lognormal(N=ww["N"], n_mu=ww["n_mu"], n_phi=ww["n_phi"], field_seed=ww.get("field_seed", 1),
+                                eps_seed=ww.get("eps_seed", 101))
+
+    case = make(args.workload)
     progress(f"workload {args.workload} generated")
-    dev = dict(dtype=torch.float32, device="cuda")
-    chi = torch.tensor(case.chi, **dev)
-    eps = torch.tensor(case.eps, **dev)
-    B = torch.tensor(case.B, **dev)
-    Ibc = torch.tensor(case.I_bc, **dev)
-    g = rt.Grid(case.Nx, case.Ny, case.Nz, case.n_mu, case.n_phi, "f32", case.n_lambda)
-    # launch-shape autotuning on this workload (part of setup, not timed)
-    S0 = torch.tensor(sy.random_source(case.chi.shape, seed=7, lo=0.2, hi=1.0, dtype="f32"), **dev)
-    if args.shape:
-        shape = tuple(int(v) for v in args.shape.split(","))
-        g.set_launch_shape(*shape)
-    elif not args.no_autotune:
-        g.autotune(chi[:1].contiguous(), S0[:1].contiguous())
-    if args.shape or not args.no_autotune:
-        ls0 = g.launch_shape()
-        shape = (ls0["threads"], ls0["rays"], bool(ls0["band"]))   # reproduced exactly on the other grids
+    shape_arg = tuple(int(v) for v in args.shape.split(",")) if args.shape else None
+    out, shape = box_line(case, args.workload, args.steps, args.warmup, shape_arg, not args.no_autotune)
+
+    # the single-wavelength 129^3 x 2048 line and what runs on it
+    single = case if case.n_lambda == 1 else None
+    if case.n_lambda > 1 and not args.no_extra:
+        single = make("lognormal129")
+        line1, shape1 = box_line(single, "lognormal129", 10, 3, None, not args.no_autotune)
+        out["lognormal129"] = {k: line1[k] for k in ("value", "unit", "ms_per_step", "config", "roofline")}
     else:
-        shape = None
-    del S0
-    progress(f"launch shape {shape}")
-    info = g.info()
-    ls = g.launch_shape()
-    st = g.new_state(chi, eps, B, Ibc)
-    opts = g.opts(tol=1e-30, max_iter=1, ng_every=4, ng_start=4)
-
-    for _ in range(args.warmup):
-        g.ali_step(st, opts)
-    torch.cuda.synchronize()
-    rt.rt_profile_read(g.handle)
-    rt.rt_profile_enable(g.handle, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        g.ali_step(st, opts)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    fs_ms, fs_launches, fs_points = rt.rt_profile_read(g.handle)
-    rt.rt_profile_enable(g.handle, False)
-    rel = g.state_tensors(st)["rel_change"].cpu().numpy()
-
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    vdu_per_step = case.vdu_per_fs()
-    value = vdu_per_step / (ms_per_step * 1e-3)
-    fs_ms_launch = fs_ms / max(fs_launches, 1)
-    points_launch = fs_points / max(fs_launches, 1)
-    achieved = FLOPS_PER_POINT * points_launch / (fs_ms_launch * 1e-3) / 1e12
-    traffic = read_traffic(args.workload, ls)
-
-    out = {
-        "metric": "voxel-direction updates/s (formal solution)",
-        "value": value,
-        "unit": "VDU/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {
-            "workload": (f"box {case.Nx}^3 periodic x,y, {case.n_mu}x{case.n_phi} directions, stratified "
-                         "opacity (tau 1e-4..1e4) x log-normal perturbation (1 dex, l=8), eps 1e-6..1 per voxel; "
-                         "step = one ALI iteration (FP32 formal solution + reduction + update + norm, Ng every 4)")
-            if case.n_lambda == 1 else
-            (f"box {case.Nx}^3 periodic x,y, {case.n_mu}x{case.n_phi} directions, {case.n_lambda} wavelengths "
-             "(opacity scale 10^U(-3,3), eps 10^U(-5,-1) per wavelength) in one launch per step; "
-             "step = one ALI iteration over the batch"),
-            "voxels": case.n_vox, "directions": case.n_dir, "wavelengths": case.n_lambda,
-            "vdu_per_step": vdu_per_step, "visits_per_vdu": fs_points / max(fs_launches, 1) / vdu_per_step,
-            "workgroups": info["n_workgroups"],
-            "launch_shape": {"threads": ls["threads"], "rays_per_thread": ls["rays"], "bundles": ls["bundles"],
-                             "tiles": "band" if ls["band"] else "layer"},
-        },
-        "roofline": {
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_TFLOPS,
-            "traffic": traffic,
-            "kernel": "fs_box_kernel<float,J>",
-            "kernel_ms_per_launch": fs_ms_launch,
-            "launches": fs_launches,
-            "flops_per_point": FLOPS_PER_POINT,
-            "points_per_launch": points_launch,
-        },
-        "last_rel_change": float(rel.max()),
-    }
-    g.close()
-    del st
-    torch.cuda.synchronize()
-    progress(f"{args.steps} timed steps: {ms_per_step:.1f} ms per step")
-    if case.n_lambda == 1:
-        out["one_gpu_share"] = one_gpu_share(case, shape)
+        shape1 = shape
+    if single is not None and not (case.n_lambda > 1 and args.no_extra):
+        out["one_gpu_share"] = one_gpu_share(single, shape1)
         progress("one-GPU share timed")
-    if not args.no_solve and case.n_lambda == 1:
-        out["time_to_solution"] = time_to_solution(case, shape=shape)
-    if not args.no_cpu_baseline and case.n_lambda == 1:
-        n_sub = args.cpu_dirs or max(8, min(case.n_dir, round(4.1e8 / case.n_vox)))
-        out["cpu_baseline"] = cpu_baseline(case, n_sub)
+        if not args.no_solve:
+            out["time_to_solution"] = time_to_solution(single, shape=shape1)
+    if not args.no_cpu_baseline:
+        # about 4e8 voxel-directions on all threads, 3.4e7 on one
+        n_sub = max(8, min(case.n_dir, round(4.1e8 / case.n_vox)))
+        n_sub_1 = max(2, min(case.n_dir, round(3.4e7 / case.n_vox)))
+        out["cpu_baseline"] = cpu_baseline(case, n_sub, n_sub_1)
+        progress("CPU baseline timed")
     print(json.dumps(out), flush=True)
 
 

@@ -491,11 +491,15 @@ rt_status rt_cache_bytes(rt_grid_t grid, int64_t *device_bytes, int64_t *host_by
 
 /*
  * Measurement hooks.  While enabled, every formal-solution kernel launch of
- * this grid is bracketed by HIP events recorded on the launch stream.
- * rt_profile_read waits for those events and returns the summed kernel time
- * (ms), the number of launches and the number of characteristic points they
- * evaluated (visits x rays, summed over work items) since the previous read,
- * then starts a new interval.  Out pointers may be NULL.
+ * this grid is bracketed by HIP events recorded on the launch stream; plain
+ * ALI steps run as HIP graphs (use_graph) are captured with two one-wave
+ * kernels around their sweep that store the device wall clock, and the time
+ * of each replay is collected before that graph is replayed again (the call
+ * then waits for the previous replay) and by rt_profile_read.  rt_profile_read waits for those events and
+ * returns the summed kernel time (ms), the number of launches and the number
+ * of characteristic points they evaluated (visits x rays, summed over work
+ * items) since the previous read, then starts a new interval.  Out pointers
+ * may be NULL.
  */
 rt_status rt_profile_enable(rt_grid_t grid, int32_t enable);
 rt_status rt_profile_read(rt_grid_t grid, double *fs_ms, int32_t *fs_launches, int64_t *fs_points);

@@ -159,6 +159,19 @@ hipError_t fill_u64(unsigned long long *p, unsigned long long v, int n, hipStrea
     return hipGetLastError();
 }
 
+// Stores the device's constant-rate wall clock: stream-ordered time stamps
+// around a kernel inside a captured graph.
+__global__ void wall_stamp_kernel(unsigned long long *p)
+{
+    if (threadIdx.x == 0) *p = (unsigned long long)wall_clock64();
+}
+
+hipError_t wall_stamp(unsigned long long *p, hipStream_t st)
+{
+    hipLaunchKernelGGL(wall_stamp_kernel, dim3(1), dim3(64), 0, st, p);
+    return hipGetLastError();
+}
+
 __device__ __forceinline__ void atomic_max_nonneg(double *addr, double v)
 {
     // non-negative doubles (and NaN, whose bits sort above +inf) order like

@@ -28,6 +28,10 @@ hipError_t cast_array(const TS *src, TD *dst, int64_t n, hipStream_t st);
 
 hipError_t fill_u64(unsigned long long *p, unsigned long long v, int n, hipStream_t st);
 
+// p[0] = the device wall clock (hipDeviceAttributeWallClockRate kHz) when the
+// one-wave stamp kernel runs, in stream order.
+hipError_t wall_stamp(unsigned long long *p, hipStream_t st);
+
 // Smallest operator-splitting denominator 1 - (1-eps) Lambda*_vv.  Where
 // eps -> 0 and the medium is optically thick, Lambda* approaches 1; stored
 // in single precision it can round to exactly 1 (a pure-scattering medium

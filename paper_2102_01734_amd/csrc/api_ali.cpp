@@ -161,28 +161,42 @@ static rt_status graph_plain_step(rt_grid *g, rt_state *s, const std::vector<int
              g->net ? g->net_r.p : nullptr, g->resid.p, s->n_lambda, v.lb, v.R, g->nonlocal ? sweeps : -1);
     std::string key(buf);
     for (int l : lams) key += std::to_string(l) + ",";
+    const bool prof = g->prof;
+    if (prof) key += "|timed";
     auto it = g->graphs.find(key);
     if (it == g->graphs.end()) {
         if (g->graphs.size() > 32) g->drop_graphs();
-        const bool prof = g->prof;
-        g->prof = false;
-        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        rs = plain_step_launches(g, s, lams, lambda_of, st, sweeps);
-        hipGraph_t graph = nullptr;
-        hipError_t e = hipStreamEndCapture(st, &graph);
-        g->prof = prof;
-        if (rs != RT_OK) {
-            if (graph) (void)hipGraphDestroy(graph);
-            return rs;
+        rt_grid::GraphStep gs;
+        gs.stream = st;
+        if (prof) {  // wall-clock stamps around the sweep (see run_fs_with)
+            if (!g->wall_khz) HIPCHK(hipDeviceGetAttribute(&g->wall_khz, hipDeviceAttributeWallClockRate, g->device));
+            if (g->wall_khz <= 0) return fail(RT_E_HIP, "device reports no wall-clock rate");
+            gs.stamps = std::make_shared<DevBuf>();
+            HIPCHK(gs.stamps->ensure(2 * sizeof(unsigned long long)));
+            g->cap_stamps = gs.stamps->as<unsigned long long>();
+            g->cap_points = 0;
         }
-        HIPCHK(e);
+        g->prof = false;
+        hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) rs = plain_step_launches(g, s, lams, lambda_of, st, sweeps);
+        hipGraph_t graph = nullptr;
+        if (e == hipSuccess) e = hipStreamEndCapture(st, &graph);
+        g->prof = prof;
+        gs.points = g->cap_points;
+        g->cap_stamps = nullptr;
         hipGraphExec_t exec = nullptr;
-        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
+        if (e == hipSuccess && rs == RT_OK) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (rs != RT_OK) return rs;
         HIPCHK(e);
-        it = g->graphs.emplace(key, exec).first;
+        gs.exec = exec;
+        it = g->graphs.emplace(key, gs).first;
+    } else {
+        rs = collect_graph_time(g, it->second);  // the previous replay's sweep time
+        if (rs != RT_OK) return rs;
     }
-    HIPCHK(hipGraphLaunch(it->second, st));
+    HIPCHK(hipGraphLaunch(it->second.exec, st));
+    if (it->second.stamps) it->second.pending = true;
     return RT_OK;
 }
 

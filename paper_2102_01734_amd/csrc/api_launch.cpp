@@ -327,10 +327,30 @@ rt_status run_fs_with(rt_grid *g, const Variant &v, const std::vector<int32_t> &
         HIPCHK(hipEventRecord(e1, st));
         g->prof_events.push_back({e0, e1});
         g->prof_points += sc->points;
+    } else if (g->cap_stamps) {
+        // inside the capture of a profiled ALI step: wall-clock stamps around the sweep
+        HIPCHK(wall_stamp(g->cap_stamps, st));
+        HIPCHK(fs_box_launch(a, dbl, wj, wl, g->para, v.band, v.lb, v.R, sc->n_wg, v.nthr, v.lds, st));
+        HIPCHK(wall_stamp(g->cap_stamps + 1, st));
+        g->cap_points += sc->points;
+        g->cap_stamps = nullptr;
     } else {
         HIPCHK(fs_box_launch(a, dbl, wj, wl, g->para, v.band, v.lb, v.R, sc->n_wg, v.nthr, v.lds, st));
     }
     *sched_out = sc;
+    return RT_OK;
+}
+
+rt_status collect_graph_time(rt_grid *g, rt_grid::GraphStep &gs)
+{
+    if (!gs.pending) return RT_OK;
+    gs.pending = false;
+    unsigned long long ts[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(ts, gs.stamps->p, sizeof ts, hipMemcpyDeviceToHost, gs.stream));
+    HIPCHK(hipStreamSynchronize(gs.stream));
+    g->prof_graph_ms += (double)(ts[1] - ts[0]) / (double)g->wall_khz;
+    g->prof_graph_launches++;
+    g->prof_points += gs.points;
     return RT_OK;
 }
 
@@ -499,11 +519,17 @@ rt_status rt_profile_read(rt_grid_t g, double *fs_ms, int32_t *fs_launches, int6
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
     }
-    if (fs_ms) *fs_ms = ms;
-    if (fs_launches) *fs_launches = (int32_t)g->prof_events.size();
+    for (auto &kv : g->graphs) {
+        rt_status rs = collect_graph_time(g, kv.second);
+        if (rs != RT_OK) return rs;
+    }
+    if (fs_ms) *fs_ms = ms + g->prof_graph_ms;
+    if (fs_launches) *fs_launches = (int32_t)g->prof_events.size() + g->prof_graph_launches;
     if (fs_points) *fs_points = g->prof_points;
     g->prof_events.clear();
     g->prof_points = 0;
+    g->prof_graph_ms = 0.0;
+    g->prof_graph_launches = 0;
     return RT_OK;
 }
 

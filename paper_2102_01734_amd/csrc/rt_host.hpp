@@ -202,7 +202,25 @@ struct rt_grid {
         hist_count = 0;
     }
     // captured plain ALI steps, keyed by batch, ring slot and state pointers
-    std::map<std::string, hipGraphExec_t> graphs;
+    // Captured plain ALI steps.  With the measurement hooks on, the sweep of
+    // a captured step is bracketed by two wall-clock stamp kernels writing
+    // into the graph's own `stamps` (two uint64); the time of a replay is
+    // collected before the next replay of the same graph and by
+    // rt_profile_read.
+    struct GraphStep {
+        hipGraphExec_t exec = nullptr;
+        hipStream_t stream = nullptr;
+        std::shared_ptr<DevBuf> stamps;
+        int64_t points = 0;
+        bool pending = false;
+    };
+    std::map<std::string, GraphStep> graphs;
+    // stamps to write around the next box sweep of a capture, and its points
+    unsigned long long *cap_stamps = nullptr;
+    int64_t cap_points = 0;
+    int wall_khz = 0;  // device wall-clock rate
+    double prof_graph_ms = 0.0;
+    int32_t prof_graph_launches = 0;
     // BiCGStab vectors and reduction scratch
     DevBuf kvec, kblk, kout, kc;
     // learned ALI correction
@@ -220,7 +238,7 @@ struct rt_grid {
     int64_t prof_points = 0;
     void drop_graphs()
     {
-        for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second.exec);
         graphs.clear();
     }
     ~rt_grid()
@@ -245,6 +263,9 @@ inline Variant &variant(rt_grid *g, bool dbl, bool wj, bool wl) { return g->var[
 // functions shared between the modules
 // ---------------------------------------------------------------------------
 // launch shapes and schedules (api_launch.cpp)
+// Adds the sweep time of a profiled graph replay (waits for it).
+rt_status collect_graph_time(rt_grid *g, rt_grid::GraphStep &gs);
+
 // ok = false for shapes that cannot hold a bundle's rays, whose tiles do not
 // fit, or (unless allow_spill) whose kernel spills registers
 Variant make_variant(rt_grid *g, bool dbl, bool wj, bool wl, int lb, int R, int occ = 1, bool band = false,

@@ -220,3 +220,38 @@ def test_anchor_shape_changes_only_the_summation_order(orc, band):
     with pytest.raises(rt.RtError):
         g64.set_anchor_shape(1024, 1)
     g64.close()
+
+
+def test_profiled_graph_steps_report_sweep_times_and_equal_unprofiled():
+    """With the measurement hooks on, captured ALI steps carry event nodes
+    around their sweep: every replay's sweep time is reported, and the
+    iterates equal those of unprofiled graph replays bitwise."""
+    import paper_2102_01734_amd as rt
+    torch = torch_cuda()
+    case = sy.random_box(21, 17, 9, 4, 8, seed=77, dtype="f32", eps_dex=(-3, -1))
+    out = []
+    for prof in (False, True):
+        g = make_grid(case)
+        st = g.new_state(to_dev(case.chi, "f32"), to_dev(case.eps, "f32"), to_dev(case.B, "f32"),
+                         to_dev(case.I_bc, "f32"))
+        s = torch.cuda.Stream()
+        rt.rt_profile_enable(g.handle, prof)
+        opts = g.opts(tol=1e-30, max_iter=1, use_graph=True)
+        with torch.cuda.stream(s):
+            for _ in range(2):  # Lambda* + anchor step, first graph capture
+                g.ali_step(st, opts, stream=s)
+        s.synchronize()
+        rt.rt_profile_read(g.handle)
+        with torch.cuda.stream(s):
+            for _ in range(7):
+                g.ali_step(st, opts, stream=s)
+        s.synchronize()
+        ms, n, pts = rt.rt_profile_read(g.handle)
+        if prof:
+            # seven plain steps: seven sweeps timed (Ng is applied before a step's sweep)
+            assert n == 7 and ms > 0.0 and pts > 0
+        else:
+            assert n == 0
+        out.append(g.state_tensors(st)["J"].cpu().numpy())
+        g.close()
+    assert np.array_equal(out[0], out[1])
