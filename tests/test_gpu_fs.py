@@ -7,7 +7,8 @@ Tolerances:
 * single-precision grids: the recurrence and the J accumulation are float;
   per point the intensity picks up a relative error of a few 2^-24 and the
   attenuation damps older errors, so J stays within ~1e-6 of the double
-  result; the tests allow 2e-5 relative (plus 1e-6 of max|J| absolute).
+  result; the tests allow 5e-6 relative (plus 1e-7 of max|J| absolute, for
+  the faint voxels next to the unlit top boundary).
 """
 import numpy as np
 import pytest
@@ -57,8 +58,9 @@ def test_fs_fp32_matches_oracle(orc, shape):
     S = sy.random_source(case.chi.shape, seed=4, dtype="f32")
     J, L = gpu_fs(case, S)
     Jo, Lo = _oracle_fs(orc, case, S, "linear")
-    np.testing.assert_allclose(J, Jo, rtol=2e-5, atol=1e-6 * np.abs(Jo).max())
-    np.testing.assert_allclose(L, Lo, rtol=2e-5, atol=1e-7)
+    print("max rel err J", float(np.max(np.abs(J - Jo) / np.abs(Jo))), "Lambda*", float(np.max(np.abs(L - Lo) / Lo)))
+    np.testing.assert_allclose(J, Jo, rtol=5e-6, atol=1e-7 * np.abs(Jo).max())
+    np.testing.assert_allclose(L, Lo, rtol=5e-6, atol=1e-8)
 
 
 def test_fs_vacuum_and_opaque_voxels(orc):
@@ -241,3 +243,68 @@ def test_ray_bundle_shapes_match_single_workgroup_sweeps(orc, prec, shape):
     np.testing.assert_allclose(J1, J0, rtol=tol, atol=tol * np.abs(J0).max())
     Jo, _ = _oracle_fs(orc, case, S, "linear")
     np.testing.assert_allclose(J1, Jo, rtol=1e-12 if prec == "f64" else 2e-5, atol=1e-6 * np.abs(Jo).max())
+
+
+# Launch shapes of the single-precision sweep that the autotuner chooses among
+# on the 129^3 workloads (row-band tiles; threads, rays per thread): the timed
+# benchmark lines run 768 x 11 with two bundles.
+TIMED_SHAPES = [(768, 11), (768, 10), (896, 10), (512, 7)]
+
+
+@pytest.fixture(scope="module")
+def full_size_case(orc):
+    """129^3 x 2048 log-normal workload, a source field, and the oracle's J and
+    Lambda* at 1028 voxels: the four x/y corners (where rays wrap round the
+    period) of every layer, plus 512 random voxels."""
+    case = sy.box_lognormal()
+    S = sy.random_source(case.chi.shape, seed=77, lo=0.2, hi=1.0, dtype="f32")
+    N = case.Nx
+    k = np.arange(case.Nz)[:, None]
+    corners = np.array([0, N - 1, (N - 1) * N, N * N - 1])[None, :]
+    vox = (k * N * N + corners).ravel()
+    rng = np.random.default_rng(5)
+    vox = np.unique(np.concatenate([vox, rng.integers(0, case.n_vox, 512)]))
+    print(f"oracle at {vox.size} voxels of 129^3 x 2048", flush=True)
+    Jo, Lo = orc.fs_box_sampled(case.chi[0], S[0], case.I_bc[0, 0], case.I_bc[0, 1], case.n_mu, case.n_phi, vox)
+    return case, S, vox, Jo, Lo
+
+
+@pytest.mark.parametrize("shape", TIMED_SHAPES)
+def test_fs_full_size_at_timed_shapes(full_size_case, shape):
+    """The benchmark's 129^3 x 2048 single-precision launch at the band shapes
+    the autotuner picks from, against the oracle at every layer's wrap corners
+    and at random voxels."""
+    case, S, vox, Jo, Lo = full_size_case
+    print(f"fs full-size 129^3 x 2048 f32 at {shape} band", flush=True)
+    g = make_grid(case)
+    g.set_launch_shape(*shape, band=True)
+    J, _ = gpu_fs(case, S, grid=g, want_lstar=False)   # the J-only sweep runs the set shape
+    ls = g.launch_shape()
+    g.close()
+    assert (ls["threads"], ls["rays"], ls["band"]) == (*shape, 1)
+    Jg = J[0].ravel()[vox]
+    print(f"  {ls['bundles']} bundles: max rel err J {float(np.max(np.abs(Jg - Jo) / np.abs(Jo))):.2e}")
+    np.testing.assert_allclose(Jg, Jo, rtol=5e-6, atol=1e-7 * np.abs(Jo).max())
+    assert np.all(np.isfinite(J))
+
+
+def test_batched_64_wavelengths_at_the_timed_shape(orc):
+    """The 64-wavelength batch (129^3, 32x32 directions, single precision) at
+    the benchmark's launch shape (768 x 11, band tiles; J-only sweep): four
+    wavelengths of very different opacity scale against the oracle at 256
+    voxels each."""
+    case = sy.box_batched()
+    S = sy.random_source(case.chi.shape[1:], seed=63, lo=0.2, hi=1.0, dtype="f32")
+    S = np.ascontiguousarray(np.broadcast_to(S, case.chi.shape))
+    print("batched 64 x 129^3 x 1024 f32 at 768 x 11 band", flush=True)
+    g = make_grid(case)
+    g.set_launch_shape(768, 11, band=True)
+    J, _ = gpu_fs(case, S, grid=g, want_lstar=False)
+    g.close()
+    rng = np.random.default_rng(9)
+    vox = np.unique(rng.integers(0, case.n_vox, 256))
+    for l in (0, 21, 42, 63):
+        Jo, _ = orc.fs_box_sampled(case.chi[l], S[l], case.I_bc[l, 0], case.I_bc[l, 1], case.n_mu, case.n_phi, vox)
+        Jg = J[l].ravel()[vox]
+        print(f"  wavelength {l}: max rel err J {float(np.max(np.abs(Jg - Jo) / np.abs(Jo))):.2e}")
+        np.testing.assert_allclose(Jg, Jo, rtol=5e-6, atol=1e-7 * np.abs(Jo).max())

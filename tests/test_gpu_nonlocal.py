@@ -203,3 +203,40 @@ def test_nonlocal_arguments():
     with pytest.raises(rt.RtError) as e:
         rt.rt3d.rt_create_grid(d)
     assert e.value.status == rt.rt3d.RT_E_INVALID
+
+
+@pytest.mark.parametrize("op", ["linear", "parabolic"])
+def test_stencil_jacobi_dominance_full_size(op):
+    """Jacobi sweeps on [1 - Lambda*(1-eps)] dJ = r converge when every row is
+    diagonally dominant: sum_{u != v} |L_vu| (1 - eps_u) < 1 - L_vv (1 - eps_v).
+    On the 129^3 x 2048 workload (eps down to 1e-6): the linear operator's
+    stencil (non-negative, rows summing to at most 1) satisfies it everywhere;
+    for the parabolic one (negative weights) the largest ratio is printed and
+    must stay below 1 as well."""
+    torch = torch_cuda()
+    case = sy.box_lognormal()
+    print(f"stencil dominance 129^3 x 2048 {op}", flush=True)
+    g = _grid(case, lstar=op)
+    chi = to_dev(case.chi, "f32")
+    st = g.lstar_stencil(chi)[0].double()              # (27, Nz, Ny, Nx)
+    torch.cuda.synchronize()
+    g.close()
+    om = 1.0 - to_dev(case.eps, "f64")[0]              # (Nz, Ny, Nx)
+    Nz = om.shape[0]
+    off = torch.zeros_like(om)
+    for c in range(27):
+        if c == 13:
+            continue
+        dz, dy, dx = c // 9 - 1, (c // 3) % 3 - 1, c % 3 - 1
+        # (1 - eps) of the neighbour u = v + (dx, dy, dz); no neighbour beyond the top/bottom layer
+        omu = torch.roll(om, shifts=(-dy, -dx), dims=(1, 2))
+        omu = torch.roll(omu, shifts=-dz, dims=0)
+        if dz == 1:
+            omu[Nz - 1] = 0.0
+        elif dz == -1:
+            omu[0] = 0.0
+        off += st[c].abs() * omu
+    den = 1.0 - st[13] * om
+    ratio = float((off / den).max())
+    print(f"  max_v sum_u!=v |L_vu|(1-eps_u) / (1 - L_vv(1-eps_v)) = {ratio:.6f}")
+    assert ratio < 1.0
