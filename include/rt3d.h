@@ -83,8 +83,10 @@ typedef enum { RT_FP64 = 0, RT_FP32 = 1 } rt_prec;
                                      in a band of rows of the layer instead of
                                      the whole layer.  Used by itself for layers
                                      whose tile does not fit the LDS of a CU
-                                     (e.g. 257 x 257); the flag forces it for
-                                     any box grid (results differ only in the
+                                     (e.g. 257 x 257), or fits only with
+                                     kernels that spill registers (e.g.
+                                     129 x 129); the flag forces it for any box
+                                     grid (results differ only in the
                                      summation order).                         */
 #define RT_F_LSTAR_NONLOCAL 0x4u  /* box: the ALI uses the nearest-neighbour
                                      Lambda* (Sec. 2, Sec. 3: the non-local
@@ -311,7 +313,13 @@ rt_status rt_ali_step(rt_grid_t grid, rt_state *state, const rt_solve_opts *opts
  *   out  device [n_lambda][27][Nz][Ny][Nx], grid precision, component
  *        c = (dz+1)*9 + (dy+1)*3 + (dx+1)
  * Sums are accumulated in 64-bit fixed point (2^-52), so the result is
- * bitwise reproducible.  Asynchronous on `stream`.  Errors: RT_E_INVALID,
+ * bitwise reproducible.  Per wavelength and direction, workgroups gather
+ * the contributions of bundles of ray rows in LDS and add each target row to
+ * device memory once per layer; layers too wide for that (more than 2048
+ * voxels a row, or a tile of two rows beyond the LDS), or any grid when the
+ * environment variable RT3D_STENCIL_PER_CHARACTERISTIC=1 is set at grid
+ * creation, add every contribution to device memory directly.  Both give
+ * bitwise the same result.  Asynchronous on `stream`.  Errors: RT_E_INVALID,
  * RT_E_UNSUPPORTED (spherical grids), RT_E_NOMEM, RT_E_HIP.
  */
 rt_status rt_lstar_stencil(rt_grid_t grid, int32_t n_lambda, const void *chi, void *out, void *stream);

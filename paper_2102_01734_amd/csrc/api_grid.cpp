@@ -477,6 +477,43 @@ rt_status rt_create_grid(const rt_grid_desc *desc, rt_grid_t *out)
         mu[d] = g->geo.dirs[d].mu;
     }
 
+    // stencil components and LDS planes of the row-window Lambda* kernel
+    std::vector<int8_t> planes((size_t)2 * g->n_dir * kPlaneStride, (int8_t)-1);
+    g->nl_rows = true;
+    for (int d = 0; d < g->n_dir; ++d) {
+        const Direction &dir = g->geo.dirs[d];
+        bool used[kStencil] = {};
+        int step = 0;
+        for (int m = 0; m < dir.M; ++m) {
+            const size_t i = (size_t)(dir.vbegin + m);
+            const uint32_t packed = g->geo.comp[i];
+            for (int j = g->para ? 0 : 1; j < 5; ++j) {
+                const uint32_t c = (packed >> (6 * j)) & 63u;
+                if (c != kNoComp) used[c] = true;
+            }
+            if (g->geo.dxy[i] & kLayerEnd) {
+                step = 0;
+                continue;
+            }
+            const int db = g->geo.brow[i + 1] - g->geo.brow[i];
+            if (db < -1 || db > 1 || (db != 0 && step != 0 && db != step)) g->nl_rows = false;
+            if (db != 0) step = db;
+        }
+        for (int skip = 0; skip < 2; ++skip) {
+            int8_t *tab = planes.data() + ((size_t)skip * g->n_dir + d) * kPlaneStride;
+            int p = 0;
+            for (int c = 0; c < kStencil; ++c) {
+                if (!used[c] || (skip && c == kStencilCentre)) continue;
+                tab[c] = (int8_t)p;
+                tab[32 + p] = (int8_t)c;
+                ++p;
+            }
+            g->nl_np[skip] = std::max(g->nl_np[skip], p);
+        }
+    }
+    if (const char *e = std::getenv("RT3D_STENCIL_PER_CHARACTERISTIC"))
+        if (e[0] == '1') g->nl_rows = false;
+
     // whole-layer tiles where they fit, else (or when asked for) band tiles
     auto setup_all = [&]() {
         for (int d = 0; d < 2; ++d)
@@ -487,11 +524,29 @@ rt_status rt_create_grid(const rt_grid_desc *desc, rt_grid_t *out)
         const bool anchor_ok = g->dbl || variant(g.get(), true, true, false).ok;
         return self_ok && anchor_ok;
     };
+    auto spills = [&]() {
+        for (int d = 0; d < 2; ++d)
+            for (int j = 0; j < 2; ++j)
+                for (int l = 0; l < 2; ++l) {
+                    const Variant &v = variant(g.get(), d, j, l);
+                    if ((j || l) && v.ok && v.spill) return true;
+                }
+        return false;
+    };
     g->band = (desc->flags & RT_F_BAND_TILES) != 0;
     bool ok = setup_all();
-    if (!ok && !g->band) {
+    g->layer_ok = !g->band && ok;
+    if (!g->band && (!ok || spills())) {
+        // layer tiles that do not fit, or fit only with kernels that spill
+        // registers: band tiles instead where they fit without spilling
         g->band = true;
-        ok = setup_all();
+        const bool ok_band = setup_all();
+        if (ok_band && (!ok || !spills())) {
+            ok = true;
+        } else {
+            g->band = false;
+            ok = setup_all();
+        }
     }
     if (!ok)
         return fail(RT_E_UNSUPPORTED,
@@ -529,6 +584,8 @@ rt_status rt_create_grid(const rt_grid_desc *desc, rt_grid_t *out)
     HIPCHK(hipMemcpy(g->mu.p, mu.data(), g->n_dir * 8, hipMemcpyHostToDevice));
     HIPCHK(g->span.ensure(g->n_dir * 4));
     HIPCHK(hipMemcpy(g->span.p, sp.data(), g->n_dir * 4, hipMemcpyHostToDevice));
+    HIPCHK(g->nl_planes.ensure(planes.size()));
+    HIPCHK(hipMemcpy(g->nl_planes.p, planes.data(), planes.size(), hipMemcpyHostToDevice));
 
     *out = g.release();
     clear_error();

@@ -84,6 +84,7 @@ Variant make_variant(rt_grid *g, bool dbl, bool wj, bool wl, int lb, int R, int 
         // the kernel keeps part of its state in scratch memory: only when asked
         if (!allow_spill) return v;
         res = -res;
+        v.spill = true;
     }
     if (res <= 0) return v;
     v.n_wg = res * g->n_cu;
@@ -394,8 +395,8 @@ static rt_status autotune(rt_grid *g, int32_t n_lambda, const void *chi, const v
     rt_status rs = RT_OK;
     for (int i = 0; i < n && rs == RT_OK; ++i) {
         // band tiles compete on every grid (their flush covers only the rows a
-        // bundle reaches); layer tiles only where the grid is not in band mode
-        if (g->band && !sh[i].band) continue;
+        // bundle reaches); layer tiles wherever they fit
+        if (!g->layer_ok && !sh[i].band) continue;
         const Variant v = make_variant(g, dbl, true, false, sh[i].lb, sh[i].R, sh[i].occ, sh[i].band, false);
         if (!v.ok) continue;
         DevSchedule *sc = nullptr;
@@ -453,7 +454,7 @@ static rt_status set_shape(rt_grid *g, bool dbl, int32_t threads, int32_t rays, 
         for (int i = 0; i < n; ++i) {
             if (sh[i].lb != threads || sh[i].R != rays) continue;
             if (band >= 0 ? sh[i].band != (band != 0) : (sh[i].band != g->band) != (pass == 1)) continue;
-            if (g->band && !sh[i].band) continue;
+            if (!g->layer_ok && !sh[i].band) continue;
             const Variant v = make_variant(g, dbl, true, false, threads, rays, sh[i].occ, sh[i].band, true);
             if (!v.ok) continue;
             variant(g, dbl, true, false) = v;

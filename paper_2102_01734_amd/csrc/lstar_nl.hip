@@ -21,13 +21,26 @@
 // adds w_d |mu_d| s_m G_j to component c_j of its voxel (the path-length
 // weighted mean over the voxel's visits, sum of s = 1/|mu_d|).
 //
-// One thread follows one characteristic (there is no tile: the sums go to
-// HBM).  The sums are fixed-point integers (2^-52 units) added with 64-bit
-// integer atomics: integer addition is associative, so the result is bitwise
-// independent of the order in which characteristics arrive.  |sum| <= 1 per
-// element, so 2^52 leaves ample headroom below 2^63.
+// The sums are fixed-point integers (2^-52 units): integer addition is
+// associative, so the result is bitwise independent of the order in which
+// contributions arrive.  |sum| <= 1 per element, so 2^52 leaves ample
+// headroom below 2^63.
+//
+// Row-window kernel: a workgroup takes one wavelength, one direction and a
+// bundle of H consecutive ray rows (all Nx rays of each row), its rays in
+// lockstep.  At visit m every ray of bundle row yr adds to target row
+// yr + brow_m of the current layer (brow: the visit's row above the lowest
+// row the template reaches in that layer), so the live target rows form a
+// window of H rows that moves by at most one row per visit and only one way
+// within a layer.  The window lives in LDS as H + 1 circular rows of Nx
+// words for each stencil component the direction uses; contributions go in
+// with LDS integer atomics.  A row that leaves the window (and every live row
+// at the end of a layer) is added to HBM with one 64-bit atomic per non-zero
+// word and cleared.  Layers too wide for such a tile fall back to one thread
+// per characteristic with a global atomic per contribution.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "ali.hpp"
@@ -135,10 +148,277 @@ __global__ void __launch_bounds__(256) lstar_stencil_kernel(StencilArgs a)
     }
 }
 
-hipError_t lstar_stencil_accumulate(const StencilArgs &a, bool grid_double, bool parabolic, int n_dir, int n_batch,
-                                    hipStream_t st)
+constexpr int kFlushWords = 4;
+
+template <typename G, bool PARA, int R>
+__global__ void __launch_bounds__(1024) lstar_stencil_rows_kernel(StencilArgs a)
+{
+    extern __shared__ unsigned long long tile[];  // [plane][H + 1 circular rows][Nx]
+    const int Nx = a.Nx, Ny = a.Ny, H = a.rows, W = H + 1, P = a.planes;
+    const int64_t NxNy = (int64_t)Nx * Ny;
+    const int nthr = (int)blockDim.x, tid = (int)threadIdx.x;
+    const int d = blockIdx.y;
+    const int lam = a.lambda_of[blockIdx.z];
+    const int yb = (int)blockIdx.x * H;
+    const G *__restrict__ chi = reinterpret_cast<const G *>(a.chi) + (int64_t)lam * a.n_vox;
+    unsigned long long *__restrict__ acc = a.acc + (int64_t)lam * kStencil * a.n_vox;
+    const int64_t vb = a.dir_vbegin[d];
+    const int M = a.dir_M[d];
+    const double wmu = a.dir_wmu[d];
+    const int dl = a.dir_mu[d] < 0.0 ? 1 : -1;
+    const uint32_t *__restrict__ dxy = a.dxy + vb;
+    const double *__restrict__ sv = a.s + vb;
+    const uint32_t *__restrict__ comp = a.comp + vb;
+    const int32_t *__restrict__ brow = a.brow + vb;
+    const int8_t *__restrict__ plane_of = a.dir_plane + (int64_t)d * kPlaneStride;
+    const int8_t *__restrict__ comp_of = plane_of + 32;
+
+    __shared__ int64_t coff[kStencil];  // plane -> offset of its component in the sums
+    for (int i = tid; i < P * W * Nx; i += nthr) tile[i] = 0;
+    if (tid < P) coff[tid] = comp_of[tid] >= 0 ? (int64_t)comp_of[tid] * a.n_vox : 0;
+    const int fdp = nthr / Nx, fdx = nthr - fdp * Nx;  // flush stride in planes and columns
+    const int fp0 = tid / Nx, fx0 = tid - fp0 * Nx;
+
+    // ray slots: slot tid + r nthr is ray (x0, yb + yr) of the bundle
+    int x0[R], y0[R], yr[R];
+    bool act[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int l = tid + r * nthr;
+        yr[r] = l / Nx;
+        x0[r] = l - yr[r] * Nx;
+        y0[r] = yb + yr[r];
+        act[r] = yr[r] < H && y0[r] < Ny;
+        if (!act[r]) { x0[r] = 0; y0[r] = 0; yr[r] = 0; }  // follows ray (0, 0) without adding
+    }
+    auto col = [&](int x, uint32_t w) { x += (int)(w & kOffMask); return x >= Nx ? x - Nx : x; };
+    auto row = [&](int y, uint32_t w) { y += (int)((w >> kOffBits) & kOffMask); return y >= Ny ? y - Ny : y; };
+    // first absolute row of the window's relative row 0 in the layer of visit word w at relative row br
+    auto row_base = [&](uint32_t w, int br) {
+        int j = ((int)((w >> kOffBits) & kOffMask) - br) % Ny;
+        return j < 0 ? j + Ny : j;
+    };
+
+    int k_cur = dl > 0 ? 0 : a.Nz - 1;
+    uint32_t w_cur = dxy[0];
+    int br_cur = brow[0];
+    int k_nxt = k_cur + ((w_cur & kLayerEnd) ? dl : 0);
+    uint32_t w_nxt = M > 1 ? dxy[1] : 0u;
+    int slot[R], x_cur[R], x_nxt[R];
+    double t_cur[R], t_nxt[R], Gv[R][5];  // G_-1, G_0, G_1, G_2, G_3 per ray
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        slot[r] = (yr[r] + br_cur) % W;
+        x_cur[r] = col(x0[r], w_cur);
+        t_cur[r] = seg_depth((double)chi[(int64_t)k_cur * NxNy + (int64_t)row(y0[r], w_cur) * Nx + x_cur[r]], sv[0]);
+        x_nxt[r] = 0;
+        t_nxt[r] = 0.0;
+        if (M > 1) {
+            x_nxt[r] = col(x0[r], w_nxt);
+            t_nxt[r] = seg_depth((double)chi[(int64_t)k_nxt * NxNy + (int64_t)row(y0[r], w_nxt) * Nx + x_nxt[r]],
+                                 sv[1]);
+        }
+#pragma unroll
+        for (int j = 0; j < 5; ++j) Gv[r][j] = 0.0;
+    }
+    __syncthreads();  // tile cleared, component offsets set
+    // a row of P x Nx words that fits kFlushWords words a thread is flushed
+    // from a per-thread list of tile and sum offsets, its LDS reads issued
+    // together; wider rows by a strided loop
+    const bool f_list = P * Nx <= kFlushWords * nthr;
+    int f_lds[kFlushWords];
+    int64_t f_glob[kFlushWords];
+#pragma unroll
+    for (int j = 0; j < kFlushWords; ++j) {
+        const int i = tid + j * nthr;
+        const int p = i / Nx, x = i - p * Nx;
+        f_lds[j] = p < P ? p * W * Nx + x : -1;
+        f_glob[j] = p < P ? coff[p] + x : 0;
+    }
+
+    // adds w |mu| s_m G_j of every active ray to its target word of component c_j
+    auto add = [&](double cw, uint32_t comps) {
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            if (!PARA && j == 0) continue;  // no downwind weight in the linear operator
+            const uint32_t c = (comps >> (6 * j)) & 63u;
+            if (c == kNoComp) continue;
+            const int p = plane_of[c];
+            if (p < 0) continue;
+            unsigned long long *plane = tile + (int64_t)p * W * Nx;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const long long f = __double2ll_rn(cw * Gv[r][j] * 0x1p52);
+                if (act[r] && f != 0) atomicAdd(&plane[slot[r] * Nx + x_cur[r]], (unsigned long long)f);
+            }
+        }
+    };
+    // adds relative row rel of layer k (row 0 at absolute row jb) to HBM and
+    // clears it; thread tid takes the words tid, tid + nthr, ... of the row's
+    // P x Nx words (plane-major), stepping plane and column without division
+    auto flush = [&](int rel, int k, int jb) {
+        unsigned long long *trow = tile + (rel % W) * Nx;
+        const int64_t base = (int64_t)k * NxNy + (int64_t)((yb + jb + rel) % Ny) * Nx;
+        if (f_list) {
+            unsigned long long v[kFlushWords];
+#pragma unroll
+            for (int j = 0; j < kFlushWords; ++j) v[j] = f_lds[j] >= 0 ? trow[f_lds[j]] : 0ull;
+#pragma unroll
+            for (int j = 0; j < kFlushWords; ++j)
+                if (v[j] != 0ull) {
+                    trow[f_lds[j]] = 0ull;
+                    atomicAdd(&acc[f_glob[j] + base], v[j]);
+                }
+            return;
+        }
+        int p = fp0, x = fx0;
+        while (p < P) {
+            unsigned long long *t = trow + p * W * Nx + x;
+            const unsigned long long v = *t;
+            if (v != 0ull) {
+                *t = 0ull;
+                atomicAdd(&acc[coff[p] + base + x], v);
+            }
+            x += fdx;
+            p += fdp;
+            if (x >= Nx) {
+                x -= Nx;
+                ++p;
+            }
+        }
+    };
+    // after visit m: at a layer end every live row leaves; else the row that the next visit no longer reaches
+    auto advance = [&](int m) {
+        if (w_cur & kLayerEnd) {
+            __syncthreads();
+            const int jb = row_base(w_cur, br_cur);
+            for (int rr = 0; rr < H; ++rr) flush(br_cur + rr, k_cur, jb);
+            __syncthreads();
+            if (m + 1 < M) {
+                const int br_n = brow[m + 1];
+#pragma unroll
+                for (int r = 0; r < R; ++r) slot[r] = (yr[r] + br_n) % W;
+            }
+            return;
+        }
+        const int br_n = brow[m + 1];
+        if (br_n == br_cur) return;
+        __syncthreads();
+        const bool up = br_n > br_cur;
+        flush(up ? br_cur : br_cur + H - 1, k_cur, row_base(w_cur, br_cur));
+#pragma unroll
+        for (int r = 0; r < R; ++r) slot[r] = up ? (slot[r] + 1 == W ? 0 : slot[r] + 1) : (slot[r] == 0 ? W - 1 : slot[r] - 1);
+    };
+
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        double ex0, e00;
+        entry_weights<double>(0.5 * t_cur[r], ex0, e00);
+        Gv[r][1] = e00;
+    }
+    add(wmu * sv[0], comp[0]);
+    advance(0);
+    br_cur = M > 1 ? brow[1] : br_cur;
+    for (int m = 1; m < M; ++m) {
+        w_cur = w_nxt;
+        k_cur = k_nxt;
+        k_nxt = k_cur + ((w_cur & kLayerEnd) ? dl : 0);
+        const bool last = m + 1 == M;
+        if (!last) w_nxt = dxy[m + 1];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double t_prev = t_cur[r];
+            x_cur[r] = x_nxt[r];
+            t_cur[r] = t_nxt[r];
+            if (!last) {
+                x_nxt[r] = col(x0[r], w_nxt);
+                t_nxt[r] = seg_depth(
+                    (double)chi[(int64_t)k_nxt * NxNy + (int64_t)row(y0[r], w_nxt) * Nx + x_nxt[r]], sv[m + 1]);
+            }
+            const double D = half_sum(t_prev, t_cur[r]);
+            const double Dp = last ? 0.0 : half_sum(t_cur[r], t_nxt[r]);
+            double ex, wa, wb, wg;
+            if (PARA) {
+                const PointW<double> pw = point_weights<double>(D, Dp, last);
+                ex = pw.ex; wa = pw.a; wb = pw.b; wg = pw.g;
+            } else {
+                const double Dv = D < kMinStep ? kMinStep : D;
+                double e0, e1, e2;
+                kernel_moments<sizeof(G) == 8>(Dv, ex, e0, e1, e2);
+                wb = e1 * rcp_f64(Dv);
+                wa = e0 - wb;
+                wg = 0.0;
+            }
+            Gv[r][4] = ex * Gv[r][3];
+            Gv[r][3] = ex * Gv[r][2];
+            Gv[r][2] = ex * Gv[r][1] + wa;
+            Gv[r][1] = ex * Gv[r][0] + wb;
+            Gv[r][0] = wg;
+        }
+        add(wmu * sv[m], comp[m]);
+        advance(m);
+        if (!last) br_cur = brow[m + 1];
+    }
+}
+
+// Tile rows per workgroup for the row-window kernel: about 800 rays (two per
+// thread), within half the LDS (two workgroups per CU) where possible;
+// measured on a 129 x 129 layer against 4..16 rows and one to four rays per
+// thread, on both operators.  The bundles are then evened out.  0 when not
+// even one row fits.
+static int stencil_rows(const StencilArgs &a, size_t max_lds)
+{
+    const size_t row_bytes = (size_t)a.planes * a.Nx * 8;
+    const size_t fixed = 256;  // the kernel's static LDS (component offsets)
+    if (row_bytes == 0 || max_lds < 2 * fixed || a.Nx > 2048) return 0;
+    int h = std::max(1, (800 + a.Nx / 2) / a.Nx);
+    const int fit2 = (int)((max_lds / 2 - fixed) / row_bytes) - 1;
+    const int fit1 = (int)((max_lds - fixed) / row_bytes) - 1;
+    h = std::min(h, fit2 >= 1 ? fit2 : fit1);
+    h = std::min(h, a.Ny);
+    if (h < 1) return 0;
+    const int nb = (a.Ny + h - 1) / h;
+    return (a.Ny + nb - 1) / nb;
+}
+
+template <typename G, bool PARA, int R>
+static hipError_t launch_rows(const StencilArgs &a, int n_dir, int n_batch, hipStream_t st)
+{
+    const int rays = a.rows * a.Nx;
+    const int nthr = ((rays + R - 1) / R + 63) / 64 * 64;
+    const size_t lds = (size_t)a.planes * (a.rows + 1) * a.Nx * 8;
+    auto k = lstar_stencil_rows_kernel<G, PARA, R>;
+    hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    dim3 grid((unsigned)((a.Ny + a.rows - 1) / a.rows), (unsigned)n_dir, (unsigned)n_batch);
+    hipLaunchKernelGGL(k, grid, dim3(nthr), lds, st, a);
+    return hipGetLastError();
+}
+
+template <typename G, bool PARA>
+static hipError_t launch_rows_r(const StencilArgs &a, int n_dir, int n_batch, hipStream_t st)
+{
+    if (a.rows * a.Nx <= 512) return launch_rows<G, PARA, 1>(a, n_dir, n_batch, st);
+    return launch_rows<G, PARA, 2>(a, n_dir, n_batch, st);
+}
+
+hipError_t lstar_stencil_accumulate(const StencilArgs &a0, bool grid_double, bool parabolic, int n_dir, int n_batch,
+                                    size_t max_lds, hipStream_t st)
 {
     if (n_dir <= 0 || n_batch <= 0) return hipSuccess;
+    if (a0.dir_plane && a0.brow) {
+        StencilArgs a = a0;
+        a.rows = a.planes > 0 ? stencil_rows(a, max_lds) : 0;
+        if (a.planes == 0) return hipSuccess;  // no component is ever added
+        if (a.rows > 0) {
+            if (grid_double)
+                return parabolic ? launch_rows_r<double, true>(a, n_dir, n_batch, st)
+                                 : launch_rows_r<double, false>(a, n_dir, n_batch, st);
+            return parabolic ? launch_rows_r<float, true>(a, n_dir, n_batch, st)
+                             : launch_rows_r<float, false>(a, n_dir, n_batch, st);
+        }
+    }
+    const StencilArgs &a = a0;
     const int NxNy = a.Nx * a.Ny;
     dim3 grid((unsigned)((NxNy + 255) / 256), (unsigned)n_dir, (unsigned)n_batch);
     if (grid_double) {

@@ -34,13 +34,28 @@ struct StencilArgs {
     const int32_t *lambda_of;  // batch entry -> wavelength
     unsigned long long *acc;   // [lambda][27][n_vox] fixed point (2^-52), cleared by the caller
     int skip_centre;           // 1: leave the centre component (the diagonal Lambda*) out
+    // row-window kernel (used when dir_plane is set): per visit the row
+    // relative to the lowest template row of its layer; per direction
+    // kPlaneStride bytes: [0, 27) component -> tile plane (-1: never added,
+    // including the centre when skip_centre), [32, 32 + planes) plane ->
+    // component; planes: the largest plane count of any direction; rows:
+    // ray rows per workgroup (set by the launcher)
+    const int32_t *brow;
+    const int8_t *dir_plane;
+    int planes;
+    int rows;
 };
+
+constexpr int kPlaneStride = 64;
 
 // Adds every characteristic's contributions to the stencil of the linear-
 // interpolation operator (parabolic = false) or of the formal solution
 // itself (parabolic = true), for n_batch wavelengths and all directions.
+// max_lds: shared memory per workgroup (bytes); layers too wide for a tile of
+// two rows use a per-characteristic kernel with one global atomic per
+// contribution instead.
 hipError_t lstar_stencil_accumulate(const StencilArgs &a, bool grid_double, bool parabolic, int n_dir, int n_batch,
-                                    hipStream_t st);
+                                    size_t max_lds, hipStream_t st);
 
 // out[lam][c][v] = acc[lam][c][v] * 2^-52 (T = float or double); with
 // `centre` (T, [lambda][n_vox]: a diagonal Lambda* of the same operator) the

@@ -82,6 +82,7 @@ struct Variant {
     int tile_words = 0;
     size_t lds = 0;
     bool ok = false;
+    bool spill = false;  // the compiled kernel keeps part of its state in scratch memory
 };
 
 struct DevSchedule {
@@ -157,11 +158,20 @@ struct rt_grid {
     // (grid precision), OS right-hand side and Jacobi iterates [lambda][vox]
     bool nonlocal = false;
     DevBuf nl_acc, nl_st, os_r, os_x0, os_x1;
+    // per direction, the stencil components it adds to and their LDS planes in
+    // the row-window stencil kernel ([with centre, without][dir][kPlaneStride]),
+    // the plane counts, and whether every template's row offsets move by at
+    // most one row per visit, one way within a layer (else the per-
+    // characteristic kernel is used)
+    DevBuf nl_planes;
+    int nl_np[2] = {0, 0};
+    bool nl_rows = false;
     // the stencil of an ALI step runs on a side stream beside its formal solutions
     hipStream_t nl_side = nullptr;
     hipEvent_t nl_fork = nullptr, nl_join = nullptr;
     int span_max = 0;   // largest per-layer row extent of any template
     bool band = false;  // the box sweep uses band tiles (see fs_box.hip)
+    bool layer_ok = false;  // whole-layer tiles fit (and were not excluded by RT_F_BAND_TILES)
     Variant var[2][2][2];  // [dbl][wj][wl]
     bool tuned = false;
 

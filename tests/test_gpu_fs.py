@@ -193,14 +193,23 @@ def test_largest_layer_tile(orc, prec):
     """140 x 140 = 19600 voxels per layer is the largest square layer whose
     double tile (plus one scratch word for each of the 832 threads that hold
     its rays, 24 per thread) fits the 160 KiB of LDS of a CU: it runs on
-    layer tiles and matches the oracle; 141 x 141 switches to band tiles and
-    matches the oracle as well."""
+    layer tiles and matches the oracle; 141 x 141 refuses layer tiles and runs
+    on band tiles (the default of both, whose layer-tile kernels of so many
+    rays per thread spill registers) and matches the oracle as well."""
+    import paper_2102_01734_amd as rt
     for N, band in ((140, False), (141, True)):
         case = sy.random_box(N, N, 3, 2, 4, seed=61, dtype=prec)
         S = sy.random_source(case.chi.shape, seed=62, dtype=prec)
         print(f"largest tile {prec} {N}", flush=True)
         g = make_grid(case)
-        assert g.launch_shape()["band"] == band
+        assert g.launch_shape()["band"]
+        if band:
+            with pytest.raises(rt.RtError):
+                g.set_launch_shape(1024, 24, band=False)
+        else:
+            g.set_launch_shape(1024, 24, band=False)
+            ls = g.launch_shape()
+            assert (ls["threads"], ls["rays"], ls["band"]) == (1024, 24, False)
         J, L = gpu_fs(case, S, grid=g)
         g.close()
         Jo, Lo = _oracle_fs(orc, case, S, "linear")

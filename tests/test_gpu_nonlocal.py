@@ -86,6 +86,25 @@ def test_stencil_deterministic():
     assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("shape,op", [((33, 33, 12, 8, 16, "f32"), "linear"), ((40, 37, 6, 4, 8, "f64"), "parabolic"),
+                                      ((129, 17, 5, 4, 8, "f32"), "parabolic")])
+def test_stencil_row_window_equals_per_characteristic_bitwise(monkeypatch, shape, op):
+    """The row-window kernel (contributions gathered in LDS, one device add per
+    target word and layer) and the per-characteristic kernel (one device add
+    per contribution) add the same fixed-point integers: bitwise equal."""
+    Nx, Ny, Nz, n_mu, n_phi, prec = shape
+    print(f"stencil kernels {shape} {op}", flush=True)
+    case = sy.random_box(Nx, Ny, Nz, n_mu, n_phi, seed=Ny, dtype=prec, n_lambda=2)
+    g = _grid(case, lstar=op)
+    a = _stencil(g, case, prec)
+    g.close()
+    monkeypatch.setenv("RT3D_STENCIL_PER_CHARACTERISTIC", "1")
+    g = _grid(case, lstar=op)
+    b = _stencil(g, case, prec)
+    g.close()
+    assert np.array_equal(a, b)
+
+
 def test_stencil_full_size_properties():
     """129^3 x 2048 directions (single precision): the linear operator's stencil
     is non-negative, each row sums to at most 1, and its centre is the sweep's
