@@ -178,8 +178,9 @@ def time_to_solution(case, net_every: int = 12, tol: float = 1e-6, shape=None):
     itself (the fewest steps whose J is within 1e-5 of the reference, found by
     re-running with a step limit), for plain double-precision Ng-ALI,
     single-precision defect-corrected Ng-ALI, the latter with the learned
-    correction, Ng-ALI with the nearest-neighbour Lambda* (single and double
-    precision; the stencil build is inside the timed call) and BiCGStab (the
+    correction, Ng-ALI with the nearest-neighbour Lambda* (single precision
+    with Jacobi and with Gauss-Seidel OS sweeps, double precision with Jacobi;
+    the stencil build is inside the timed call) and BiCGStab (the
     single-precision runs use the launch shape tuned for the throughput line,
     the double-precision runs one tuned on a double-precision grid); each
     with its max relative J error against a double-precision Ng-ALI solution
@@ -201,7 +202,7 @@ def time_to_solution(case, net_every: int = 12, tol: float = 1e-6, shape=None):
     g64.close()
     del chi64, S64
 
-    def run(prec, tol_, max_iter, net=0, method="ali", nonlocal_lstar=False):
+    def run(prec, tol_, max_iter, net=0, method="ali", nonlocal_lstar=False, os_method="jacobi"):
         dt = torch.float32 if prec == "f32" else torch.float64
         dev = dict(dtype=dt, device="cuda")
         g = rt.Grid(case.Nx, case.Ny, case.Nz, case.n_mu, case.n_phi, prec, 1, nonlocal_lstar=nonlocal_lstar)
@@ -219,7 +220,7 @@ def time_to_solution(case, net_every: int = 12, tol: float = 1e-6, shape=None):
         t0 = time.perf_counter()
         with torch.cuda.stream(s):
             status, rep = g.solve(st, g.opts(tol=tol_, max_iter=max_iter, use_graph=True, net_every=net,
-                                             method=method), stream=s)
+                                             method=method, os_method=os_method), stream=s)
         s.synchronize()
         wall = time.perf_counter() - t0
         J = g.state_tensors(st)["J"].clone()
@@ -248,17 +249,22 @@ def time_to_solution(case, net_every: int = 12, tol: float = 1e-6, shape=None):
     def err_of(J):
         return float(((J - ref).abs() / ref.abs()).max())
 
-    for name, prec, net, method, tol_m, nl in (("plain_f64_ng_ali", "f64", 0, "ali", tol, False),
-                                               ("f32_defect_corrected_ng_ali", "f32", 0, "ali", tol, False),
-                                               ("f32_learned", "f32", net_every, "ali", tol, False),
-                                               ("f32_nonlocal_ng_ali", "f32", 0, "ali", tol, True),
-                                               ("f64_nonlocal_ng_ali", "f64", 0, "ali", tol, True),
-                                               ("bicgstab_f64", "f64", 0, "bicgstab", 1e-8, False)):
-        J, status, rep, wall = run(prec, tol_m, 300, net, method, nl)
+    gs = "gauss-seidel"
+    for name, prec, net, method, tol_m, nl, osm in (
+            ("plain_f64_ng_ali", "f64", 0, "ali", tol, False, "jacobi"),
+            ("f32_defect_corrected_ng_ali", "f32", 0, "ali", tol, False, "jacobi"),
+            ("f32_learned", "f32", net_every, "ali", tol, False, "jacobi"),
+            ("f32_nonlocal_ng_ali", "f32", 0, "ali", tol, True, "jacobi"),
+            ("f32_nonlocal_gs_ng_ali", "f32", 0, "ali", tol, True, gs),
+            ("f64_nonlocal_ng_ali", "f64", 0, "ali", tol, True, "jacobi"),
+            ("bicgstab_f64", "f64", 0, "bicgstab", 1e-8, False, "jacobi")):
+        J, status, rep, wall = run(prec, tol_m, 300, net, method, nl, osm)
         err = err_of(J)
         progress(f"time to solution: {name} {rep.iters} steps {wall:.2f} s error {err:.2e}")
         out[name] = {"seconds": wall, "steps": rep.iters, "formal_solutions": rep.n_fs, "fp64_fs": rep.n_fs64,
                      "status": status, "max_rel_error": err, "tol": tol_m}
+        if nl:
+            out[name]["os_sweeps"] = f"16 {osm}"
         if net:
             out[name].update(net_every=net, accepted=rep.n_net_accept, rejected=rep.n_net_reject)
         # fewest steps reaching the target error (errors fall with the step limit)
@@ -267,7 +273,7 @@ def time_to_solution(case, net_every: int = 12, tol: float = 1e-6, shape=None):
             best = (rep.iters, wall, err, rep.n_fs)
             while lo < hi:
                 mid = (lo + hi) // 2
-                Jm, _, repm, wallm = run(prec, 1e-30, mid, net, method, nl)
+                Jm, _, repm, wallm = run(prec, 1e-30, mid, net, method, nl, osm)
                 em = err_of(Jm)
                 progress(f"time to solution: {name} limited to {mid} steps: error {em:.2e}, {wallm:.2f} s")
                 if em <= target:

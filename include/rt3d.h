@@ -95,7 +95,8 @@ typedef enum { RT_FP64 = 0, RT_FP32 = 1 } rt_prec;
                                      restricted to the 27 neighbours of each
                                      voxel (see rt_lstar_stencil) -- and solves
                                      the operator-splitting system with Jacobi
-                                     sweeps (rt_solve_opts.os_sweeps).  The
+                                     or Gauss-Seidel sweeps
+                                     (rt_solve_opts.os_sweeps, os_method).  The
                                      state's lstar array still receives the
                                      diagonal, and is the stencil's centre
                                      component (the same sum; on RT_FP32 grids
@@ -264,11 +265,25 @@ typedef struct {
                              (rt_set_preconditioner): propose a learned
                              correction after every net_every-th step
                              (0 = never); see rt_set_preconditioner             */
-    int32_t os_sweeps;    /* grids with RT_F_LSTAR_NONLOCAL: Jacobi sweeps of
-                             the operator-splitting system per step, started
-                             from the diagonal solution (0 = library default
-                             16); ignored otherwise                             */
+    int32_t os_sweeps;    /* grids with RT_F_LSTAR_NONLOCAL: sweeps of the
+                             operator-splitting system per step, started from
+                             the diagonal solution (0 = library default 16);
+                             ignored otherwise                                  */
+    int32_t os_method;    /* those sweeps: RT_OS_JACOBI or RT_OS_GAUSS_SEIDEL
+                             (Sec. 3 names both): in place, over 18 colour
+                             classes in the order cz*9 + cy*3 + cx with
+                             cz = z mod 2, cx = x mod 2, cy = y mod 2, except
+                             the last column (row) of an odd periodic axis of
+                             length >= 3, which takes class 2.  Voxels of a
+                             class share no stencil coupling, so the sweep is
+                             the sequential Gauss-Seidel sweep in that voxel
+                             order (each class updated in parallel) and is
+                             bitwise reproducible.                              */
 } rt_solve_opts;
+
+/* rt_solve_opts.os_method */
+#define RT_OS_JACOBI 0
+#define RT_OS_GAUSS_SEIDEL 1
 
 typedef struct {
     int32_t iters;          /* ALI steps taken by this call                     */
@@ -287,8 +302,9 @@ typedef struct {
  * nearest-neighbour Lambda* on RT_F_LSTAR_NONLOCAL grids): formal solution
  * of the current S (building Lambda* first when lstar_valid == 0), the
  * operator-splitting update of J (pointwise for the diagonal Lambda*; for the
- * non-local one, J_new = J_old + dJ with dJ from os_sweeps Jacobi sweeps of
- * [1 - Lambda*(1-eps)] dJ = J_fs - J_old), S = (1-eps)J + eps B, the
+ * non-local one, J_new = J_old + dJ with dJ from os_sweeps Jacobi or
+ * Gauss-Seidel sweeps (os_method) of [1 - Lambda*(1-eps)] dJ = J_fs - J_old),
+ * S = (1-eps)J + eps B, the
  * per-wavelength norm max_v |dJ/J| into state->rel_change, and -- when the
  * schedule in opts says so -- the Ng extrapolation of the last four iterates.
  * Asynchronous on `stream`.  For RT_FP32 grids the formal solution of the

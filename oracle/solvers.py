@@ -14,7 +14,7 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = ["BoxProblem", "Plane1DProblem", "SphereProblem", "ali", "ng_extrapolate", "bicgstab",
-           "lambda_matrix", "direct", "lambda_iteration_radius"]
+           "lambda_matrix", "direct", "lambda_iteration_radius", "os_colours", "gauss_seidel"]
 
 
 class BoxProblem:
@@ -151,8 +151,53 @@ def ng_extrapolate(x0, x1, x2, x3):
     return (1.0 - a - b) * x0 + a * x1 + b * x2
 
 
+def os_colours(shape):
+    """Colour class of every voxel of an (Nz, Ny, Nx) box for the Gauss-Seidel
+    sweeps of the OS system: cz*9 + cy*3 + cx with cz = z mod 2, cx = x mod 2,
+    cy = y mod 2, except that on an odd periodic axis of length >= 3 the last
+    column (row) takes class 2, since it neighbours the first one across the
+    period.  (A reading: the paper names Gauss-Seidel without an ordering.)"""
+    Nz, Ny, Nx = shape
+
+    def periodic_axis(N):
+        c = np.arange(N) % 2
+        if N >= 3 and N % 2 == 1:
+            c[N - 1] = 2
+        return c
+
+    cz = np.arange(Nz) % 2
+    return cz[:, None, None] * 9 + periodic_axis(Ny)[None, :, None] * 3 + periodic_axis(Nx)[None, None, :]
+
+
+def _gs_plan(A, colours):
+    import scipy.sparse as sps
+    A = sps.csr_matrix(A)
+    d = A.diagonal()
+    off = (A - sps.diags(d)).tocsr()
+    cls = np.asarray(colours).ravel()
+    return d, [(idx, off[idx]) for idx in (np.flatnonzero(cls == c) for c in range(18)) if idx.size]
+
+
+def _gs_sweeps(plan, r, x, sweeps):
+    d, blocks = plan
+    x = np.array(x, dtype=np.float64)
+    for _ in range(sweeps):
+        for idx, rows in blocks:
+            x[idx] = (r[idx] - rows @ x) / d[idx]
+    return x
+
+
+def gauss_seidel(A, r, x, colours, sweeps):
+    """``sweeps`` Gauss-Seidel sweeps on A x = r (A sparse): each voxel v in
+    turn, in ascending colour class, takes x_v = (r_v - sum_{u != v} A_vu x_u)
+    / A_vv with the newest values of the others.  No two voxels of one class
+    are coupled (see os_colours), so the voxels of a class are updated
+    together."""
+    return _gs_sweeps(_gs_plan(A, colours), r, x, sweeps)
+
+
 def ali(prob, tol=1e-8, max_iter=10000, ng=True, ng_start=4, ng_every=4, J0=None,
-        lstar=None, record=False, inner_jacobi=0):
+        lstar=None, record=False, inner_jacobi=0, inner_gs=0):
     """Operator-splitting (ALI) iteration (Sec. 2.2, eq. (alo)).
 
     Each step: J_fs = Lambda S_old (+ boundary term);
@@ -166,7 +211,9 @@ def ali(prob, tol=1e-8, max_iter=10000, ng=True, ng_start=4, ng_every=4, J0=None
     such as the nearest-neighbour Lambda*).  With a sparse Lambda* the OS
     system is solved exactly, or, with ``inner_jacobi`` = k > 0, by k Jacobi
     sweeps on [1 - Lambda*(1-eps)] dJ = J_fs - J_old started from the
-    diagonal solution (one of the OS solvers of Sec. 3).
+    diagonal solution, or with ``inner_gs`` = k > 0 by k Gauss-Seidel sweeps
+    in colour order (see gauss_seidel) from the same start (the OS solvers of
+    Sec. 3).
     """
     import scipy.sparse as sps
     import scipy.sparse.linalg as spla
@@ -183,11 +230,14 @@ def ali(prob, tol=1e-8, max_iter=10000, ng=True, ng_start=4, ng_every=4, J0=None
         A = (sps.identity(J.size, format="csr") - L @ sps.diags(om)).tocsr()
         Adiag = A.diagonal()
         Aoff = (A - sps.diags(Adiag)).tocsr()
+        gs_plan = _gs_plan(A, os_colours(J.shape)) if inner_gs > 0 else None
     for it in range(1, max_iter + 1):
         Jfs = prob.fs(S)
         if sps.issparse(L):
             r = (Jfs - J).ravel()
-            if inner_jacobi > 0:
+            if inner_gs > 0:
+                x = _gs_sweeps(gs_plan, r, r / Adiag, inner_gs)
+            elif inner_jacobi > 0:
                 x = r / Adiag
                 for _ in range(inner_jacobi):
                     x = (r - Aoff @ x) / Adiag

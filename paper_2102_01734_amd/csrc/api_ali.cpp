@@ -32,6 +32,8 @@ rt_status check_opts(const rt_solve_opts *o)
     if (o->method != RT_SOLVER_ALI && o->method != RT_SOLVER_BICGSTAB)
         return fail(RT_E_INVALID, "unknown solver method %d", o->method);
     if (o->os_sweeps < 0 || o->os_sweeps > 1000) return fail(RT_E_INVALID, "opts->os_sweeps outside [0, 1000]");
+    if (o->os_method != RT_OS_JACOBI && o->os_method != RT_OS_GAUSS_SEIDEL)
+        return fail(RT_E_INVALID, "unknown operator-splitting method %d", o->os_method);
     return RT_OK;
 }
 
@@ -69,7 +71,8 @@ rt_status ensure_state_buffers(rt_grid *g)
 
 static int os_sweeps_of(const rt_solve_opts *o) { return o->os_sweeps > 0 ? o->os_sweeps : 16; }
 // The operator-splitting update.  Diagonal Lambda*: the fused pointwise
-// kernel.  Nearest-neighbour Lambda*: J_fs - J_old, `sweeps` Jacobi sweeps of
+// kernel.  Nearest-neighbour Lambda*: J_fs - J_old, `sweeps` Jacobi (or, when
+// the step's options ask for it, colour Gauss-Seidel) sweeps of
 // [1 - Lambda*(1-eps)] dJ = J_fs - J_old started from the diagonal solution,
 // then the same update kernel with that dJ (norms, Ng history, S, next input).
 static rt_status os_update(rt_grid *g, int n_lambda, AliUpdateArgs ua, bool part_double, bool grid_double,
@@ -94,13 +97,17 @@ static rt_status os_update(rt_grid *g, int n_lambda, AliUpdateArgs ua, bool part
     ja.x_in = nullptr;
     ja.x_out = x[0];
     HIPCHK(os_jacobi_sweep(ja, g->dbl, true, nb, st));
-    for (int k = 0; k < sweeps; ++k) {
-        ja.x_in = x[k % 2];
-        ja.x_out = x[(k + 1) % 2];
-        HIPCHK(os_jacobi_sweep(ja, g->dbl, false, nb, st));
+    if (g->os_gs) {
+        for (int k = 0; k < sweeps; ++k) HIPCHK(os_gs_sweep(ja, g->dbl, nb, st));
+    } else {
+        for (int k = 0; k < sweeps; ++k) {
+            ja.x_in = x[k % 2];
+            ja.x_out = x[(k + 1) % 2];
+            HIPCHK(os_jacobi_sweep(ja, g->dbl, false, nb, st));
+        }
     }
     ua.rfs_in = g->os_r.as<double>();
-    ua.dJ = x[sweeps % 2];
+    ua.dJ = g->os_gs ? x[0] : x[sweeps % 2];
     HIPCHK(ali_update(ua, part_double, grid_double, next_double, nb, st));
     return RT_OK;
 }
@@ -158,7 +165,8 @@ static rt_status graph_plain_step(rt_grid *g, rt_state *s, const std::vector<int
     char buf[512];
     snprintf(buf, sizeof buf, "%d|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%d|%d|%d|%d:", g->hist_count % 4, (void *)s->J,
              (void *)s->S, s->lstar, s->eps, s->B, (void *)s->rel_change, pJ.p, (void *)st,
-             g->net ? g->net_r.p : nullptr, g->resid.p, s->n_lambda, v.lb, v.R, g->nonlocal ? sweeps : -1);
+             g->net ? g->net_r.p : nullptr, g->resid.p, s->n_lambda, v.lb, v.R,
+             g->nonlocal ? (g->os_gs ? 1000000 + sweeps : sweeps) : -1);
     std::string key(buf);
     for (int l : lams) key += std::to_string(l) + ",";
     const bool prof = g->prof;
@@ -214,6 +222,7 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
     const int nb = (int)lams.size();
     rt_status rs = ensure_state_buffers(g);
     if (rs != RT_OK) return rs;
+    g->os_gs = o->os_method == RT_OS_GAUSS_SEIDEL;
     DevSchedule *lam_sc = nullptr;  // for lambda_of of the batch
     rs = get_schedule(g, variant(g, g->dbl, true, false).n_wg, lams, &lam_sc);
     if (rs != RT_OK) return rs;

@@ -464,27 +464,26 @@ hipError_t lstar_stencil_finish(const unsigned long long *acc, const int32_t *la
 }
 
 // ---------------------------------------------------------------------------
-// Jacobi sweep: x_v <- (r_v + sum_{c != centre} L_c(v) (1 - eps_u) x_u) / (1 - L_centre(v) (1 - eps_v)),
-// neighbours u in component order (a fixed order: reproducible)
+// Operator-splitting sweeps on [1 - Lambda*(1-eps)] x = r:
+//   x_v <- (r_v + sum_{c != centre} L_c(v) (1 - eps_u) x_u) / (1 - L_centre(v) (1 - eps_v)),
+// neighbours u in component order (a fixed order: reproducible).  Jacobi
+// reads x_in and writes x_out; Gauss-Seidel updates x in place, one colour
+// class at a time.
 // ---------------------------------------------------------------------------
 template <typename G>
-__global__ void __launch_bounds__(256) os_jacobi_kernel(OsJacobiArgs a, int first)
+__device__ __forceinline__ double os_row(const OsJacobiArgs &a, int64_t base, int x, int y, int k,
+                                         const double *__restrict__ xs, bool first)
 {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= a.n_vox) return;
     const int64_t n = a.n_vox;
-    const int64_t base = (int64_t)a.lambda_of[blockIdx.y] * n;
+    const int Nx = a.Nx, Ny = a.Ny;
+    const int64_t NxNy = (int64_t)Nx * Ny;
+    const int64_t v = (int64_t)k * NxNy + (int64_t)y * Nx + x;
     const G *__restrict__ st = reinterpret_cast<const G *>(a.st) + base * kStencil;
     const G *__restrict__ eps = reinterpret_cast<const G *>(a.eps) + base;
     double den = 1.0 - (double)st[kStencilCentre * n + v] * (1.0 - (double)eps[v]);
     den = den < os_den_min<G>() ? os_den_min<G>() : den;
     double acc = a.r[base + v];
     if (!first) {
-        const int Nx = a.Nx, Ny = a.Ny;
-        const int64_t NxNy = (int64_t)Nx * Ny;
-        const int k = (int)(v / NxNy);
-        const int rem = (int)(v - (int64_t)k * NxNy);
-        const int y = rem / Nx, x = rem - y * Nx;
         for (int c = 0; c < kStencil; ++c) {
             if (c == kStencilCentre) continue;
             const double L = (double)st[(int64_t)c * n + v];
@@ -496,10 +495,23 @@ __global__ void __launch_bounds__(256) os_jacobi_kernel(OsJacobiArgs a, int firs
             int xu = x + c % 3 - 1;
             xu = xu < 0 ? xu + Nx : (xu >= Nx ? xu - Nx : xu);
             const int64_t u = (int64_t)ku * NxNy + (int64_t)yu * Nx + xu;
-            acc += L * (1.0 - (double)eps[u]) * a.x_in[base + u];
+            acc += L * (1.0 - (double)eps[u]) * xs[base + u];
         }
     }
-    a.x_out[base + v] = acc / den;
+    return acc / den;
+}
+
+template <typename G>
+__global__ void __launch_bounds__(256) os_jacobi_kernel(OsJacobiArgs a, int first)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= a.n_vox) return;
+    const int64_t base = (int64_t)a.lambda_of[blockIdx.y] * a.n_vox;
+    const int64_t NxNy = (int64_t)a.Nx * a.Ny;
+    const int k = (int)(v / NxNy);
+    const int rem = (int)(v - (int64_t)k * NxNy);
+    const int y = rem / a.Nx, x = rem - y * a.Nx;
+    a.x_out[base + v] = os_row<G>(a, base, x, y, k, a.x_in, first != 0);
 }
 
 hipError_t os_jacobi_sweep(const OsJacobiArgs &a, bool grid_double, bool first, int n_batch, hipStream_t st)
@@ -511,6 +523,62 @@ hipError_t os_jacobi_sweep(const OsJacobiArgs &a, bool grid_double, bool first, 
     else
         hipLaunchKernelGGL((os_jacobi_kernel<float>), grid, dim3(256), 0, st, a, first ? 1 : 0);
     return hipGetLastError();
+}
+
+// One colour class: coordinates (cx + 2 i, cy + 2 j, cz + 2 l) for colours 0
+// and 1 of x and y, the last column (row) for colour 2; n[3] class sizes.
+struct OsColour {
+    int c[3];
+    int n[3];
+};
+
+template <typename G>
+__global__ void __launch_bounds__(256) os_gs_kernel(OsJacobiArgs a, OsColour col)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nxy = (int64_t)col.n[0] * col.n[1];
+    if (i >= nxy * col.n[2]) return;
+    const int iz = (int)(i / nxy);
+    const int rem = (int)(i - (int64_t)iz * nxy);
+    const int iy = rem / col.n[0], ix = rem - iy * col.n[0];
+    const int x = col.c[0] == 2 ? a.Nx - 1 : col.c[0] + 2 * ix;
+    const int y = col.c[1] == 2 ? a.Ny - 1 : col.c[1] + 2 * iy;
+    const int k = col.c[2] + 2 * iz;
+    const int64_t base = (int64_t)a.lambda_of[blockIdx.y] * a.n_vox;
+    const double xn = os_row<G>(a, base, x, y, k, a.x_out, false);
+    a.x_out[base + (int64_t)k * a.Nx * a.Ny + (int64_t)y * a.Nx + x] = xn;
+}
+
+// Size of colour class c along an axis of N voxels: parity classes 0 and 1,
+// and on a periodic axis of odd length >= 3 the last voxel in class 2 (it
+// neighbours voxel 0 across the period).
+static int colour_size(int N, int c, bool periodic)
+{
+    const bool odd_wrap = periodic && N >= 3 && (N & 1);
+    if (c == 2) return odd_wrap ? 1 : 0;
+    const int lim = odd_wrap ? N - 1 : N;
+    return lim > c ? (lim - c + 1) / 2 : 0;
+}
+
+hipError_t os_gs_sweep(const OsJacobiArgs &a, bool grid_double, int n_batch, hipStream_t st)
+{
+    if (a.n_vox <= 0 || n_batch <= 0) return hipSuccess;
+    for (int cz = 0; cz < 2; ++cz)
+        for (int cy = 0; cy < 3; ++cy)
+            for (int cx = 0; cx < 3; ++cx) {
+                OsColour col{{cx, cy, cz}, {colour_size(a.Nx, cx, true), colour_size(a.Ny, cy, true),
+                                            colour_size(a.Nz, cz, false)}};
+                const int64_t n = (int64_t)col.n[0] * col.n[1] * col.n[2];
+                if (n == 0) continue;
+                dim3 grid((unsigned)((n + 255) / 256), (unsigned)n_batch);
+                if (grid_double)
+                    hipLaunchKernelGGL((os_gs_kernel<double>), grid, dim3(256), 0, st, a, col);
+                else
+                    hipLaunchKernelGGL((os_gs_kernel<float>), grid, dim3(256), 0, st, a, col);
+                hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return e;
+            }
+    return hipSuccess;
 }
 
 }  // namespace rt3d

@@ -76,5 +76,11 @@ struct OsJacobiArgs {
     double *x_out;        // [lambda][n_vox]
 };
 hipError_t os_jacobi_sweep(const OsJacobiArgs &a, bool grid_double, bool first, int n_batch, hipStream_t st);
+// One Gauss-Seidel sweep, in place on x_out (x_in unused), over the 18
+// colour classes in the order cz * 9 + cy * 3 + cx, where cz = z mod 2 and
+// cx (cy) = x mod 2 (y mod 2), except the last column (row) of an odd
+// periodic axis of length >= 3, which takes class 2.  Voxels of one class
+// share no stencil coupling, so each class is updated in parallel.
+hipError_t os_gs_sweep(const OsJacobiArgs &a, bool grid_double, int n_batch, hipStream_t st);
 
 }  // namespace rt3d

@@ -164,6 +164,7 @@ struct rt_grid {
     // most one row per visit, one way within a layer (else the per-
     // characteristic kernel is used)
     DevBuf nl_planes;
+    bool os_gs = false;  // the current step's OS sweeps are Gauss-Seidel (set from its options)
     int nl_np[2] = {0, 0};
     bool nl_rows = false;
     // the stencil of an ALI step runs on a side stream beside its formal solutions

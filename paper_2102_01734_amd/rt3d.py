@@ -43,7 +43,7 @@ class RtSolveOpts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("ng_every", ctypes.c_int32), ("ng_start", ctypes.c_int32), ("reanchor", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("method", ctypes.c_int32), ("net_every", ctypes.c_int32),
-                ("os_sweeps", ctypes.c_int32)]
+                ("os_sweeps", ctypes.c_int32), ("os_method", ctypes.c_int32)]
 
 
 class RtSolveReport(ctypes.Structure):
@@ -495,7 +495,8 @@ class Grid:
 
     @staticmethod
     def opts(tol=1e-8, max_iter=1000, ng_every=4, ng_start=4, reanchor=0, use_graph=False, net_every=0,
-             method="ali", os_sweeps=0):
+             method="ali", os_sweeps=0, os_method="jacobi"):
+        """os_method: "jacobi" or "gauss-seidel" (colour order, see include/rt3d.h)."""
         o = RtSolveOpts()
         o.struct_size = ctypes.sizeof(RtSolveOpts)
         o.tol, o.max_iter, o.ng_every, o.ng_start, o.reanchor = tol, max_iter, ng_every, ng_start, reanchor
@@ -503,6 +504,7 @@ class Grid:
         o.net_every = int(net_every)
         o.method = {"ali": 0, "bicgstab": 1}[method]
         o.os_sweeps = int(os_sweeps)
+        o.os_method = {"jacobi": 0, "gauss-seidel": 1}[os_method]
         return o
 
     def set_preconditioner(self, blob):

@@ -41,7 +41,7 @@ def gpu_fs(case, S, lstar="linear", want_lstar=True, prec=None, grid=None, I_bc=
 
 
 def gpu_solve(case, tol=1e-10, max_iter=2000, ng_every=4, ng_start=4, lstar="linear", prec=None, reanchor=0,
-              grid=None):
+              grid=None, os_method="jacobi", os_sweeps=0):
     torch = torch_cuda()
     prec = prec or case.dtype
     g = grid or make_grid(case, lstar=lstar, prec=prec)
@@ -49,7 +49,7 @@ def gpu_solve(case, tol=1e-10, max_iter=2000, ng_every=4, ng_start=4, lstar="lin
     Ib = to_dev(case.I_bc, prec)
     st = g.new_state(chi, eps, B, Ib)
     status, rep = g.solve(st, g.opts(tol=tol, max_iter=max_iter, ng_every=ng_every, ng_start=ng_start,
-                                     reanchor=reanchor))
+                                     reanchor=reanchor, os_method=os_method, os_sweeps=os_sweeps))
     torch.cuda.synchronize()
     t = g.state_tensors(st)
     res = dict(J=t["J"].cpu().numpy(), S=t["S"].cpu().numpy(), lstar=t["lstar"].double().cpu().numpy(),

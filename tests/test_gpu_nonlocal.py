@@ -123,16 +123,20 @@ def test_stencil_full_size_properties():
     g.close()
 
 
+@pytest.mark.parametrize("method", ["jacobi", "gauss-seidel"])
 @pytest.mark.parametrize("op", ["linear", "parabolic"])
-def test_nonlocal_ali_steps_match_oracle_iterates(orc, op):
-    """J after 1, 3 and 6 steps (Ng between steps 4 and 5), 5 Jacobi sweeps per
-    step, equals the oracle's non-local ALI with the same sweeps."""
+def test_nonlocal_ali_steps_match_oracle_iterates(orc, op, method):
+    """J after 1, 3 and 6 steps (Ng between steps 4 and 5), 5 Jacobi or
+    Gauss-Seidel (colour order) sweeps per step, equals the oracle's non-local
+    ALI with the same sweeps.  11 x 11 is odd: the last column and row take
+    their own colour."""
     torch = torch_cuda()
     case = sy.random_box(11, 11, 6, 4, 8, seed=43, dtype="f64", eps_dex=(-4, -1))
     g = _grid(case, lstar=op)
     st = g.new_state(to_dev(case.chi, "f64"), to_dev(case.eps, "f64"), to_dev(case.B, "f64"),
                      to_dev(case.I_bc, "f64"))
-    opts = g.opts(tol=1e-30, max_iter=1, ng_every=4, ng_start=4, os_sweeps=5)
+    opts = g.opts(tol=1e-30, max_iter=1, ng_every=4, ng_start=4, os_sweeps=5, os_method=method)
+    inner = dict(inner_jacobi=5) if method == "jacobi" else dict(inner_gs=5)
     prob = orc.BoxProblem(case.chi[0], case.eps[0], case.B[0], case.I_bc[0, 0], case.I_bc[0, 1], 4, 8, kind=op)
     L = prob.lstar_nonlocal()
     done = 0
@@ -142,7 +146,7 @@ def test_nonlocal_ali_steps_match_oracle_iterates(orc, op):
             done += 1
         torch.cuda.synchronize()
         Jg = g.state_tensors(st)["J"].cpu().numpy()[0]
-        ref = orc.ali(prob, tol=1e-30, max_iter=n, ng=True, ng_start=4, ng_every=4, lstar=L, inner_jacobi=5)
+        ref = orc.ali(prob, tol=1e-30, max_iter=n, ng=True, ng_start=4, ng_every=4, lstar=L, **inner)
         np.testing.assert_allclose(Jg, ref["J"], rtol=1e-10)
     g.close()
 
@@ -163,17 +167,18 @@ def test_nonlocal_fp64_reaches_lu_fixed_point_in_fewer_steps(orc, op):
     assert r["report"].iters < r0["report"].iters
 
 
+@pytest.mark.parametrize("method", ["jacobi", "gauss-seidel"])
 @pytest.mark.parametrize("eps_dex", [(-2, 0), (-5, -3)])
-def test_nonlocal_fp32_defect_corrected_reaches_fixed_point(orc, eps_dex):
+def test_nonlocal_fp32_defect_corrected_reaches_fixed_point(orc, eps_dex, method):
     case = sy.random_box(9, 9, 8, 4, 8, seed=47, dtype="f32", eps_dex=eps_dex)
     g = _grid(case)
-    r = gpu_solve(case, tol=1e-9, max_iter=3000, grid=g)
+    r = gpu_solve(case, tol=1e-9, max_iter=3000, grid=g, os_method=method)
     g.close()
     prob = orc.BoxProblem(case.chi[0], case.eps[0], case.B[0], case.I_bc[0, 0], case.I_bc[0, 1], 4, 8)
     ref = orc.direct(prob)
     assert r["status"] == 0
     err = np.max(np.abs(r["J"][0] - ref["J"]) / np.abs(ref["J"]))
-    print("non-local fp32 fixed-point error", err, "steps", r["report"].iters)
+    print("non-local fp32", method, "fixed-point error", err, "steps", r["report"].iters)
     assert err < 1e-5
 
 
@@ -188,8 +193,9 @@ def test_nonlocal_batch_each_wavelength_reaches_its_fixed_point(orc):
         np.testing.assert_allclose(r["J"][l], orc.direct(prob)["J"], rtol=1e-9)
 
 
+@pytest.mark.parametrize("method", ["jacobi", "gauss-seidel"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_nonlocal_graph_replay_equals_eager_bitwise(prec):
+def test_nonlocal_graph_replay_equals_eager_bitwise(prec, method):
     torch = torch_cuda()
     case = sy.random_box(17, 13, 9, 4, 8, seed=57, dtype=prec, eps_dex=(-3, -1))
     out = []
@@ -200,7 +206,8 @@ def test_nonlocal_graph_replay_equals_eager_bitwise(prec):
         s = torch.cuda.Stream()
         with torch.cuda.stream(s):
             for _ in range(9):
-                g.ali_step(st, g.opts(tol=1e-30, max_iter=1, use_graph=use_graph, os_sweeps=3), stream=s)
+                g.ali_step(st, g.opts(tol=1e-30, max_iter=1, use_graph=use_graph, os_sweeps=3, os_method=method),
+                           stream=s)
         s.synchronize()
         out.append(g.state_tensors(st)["J"].cpu().numpy())
         g.close()
@@ -214,6 +221,10 @@ def test_nonlocal_arguments():
     st = g.new_state(to_dev(case.chi, "f64"), to_dev(case.eps, "f64"), to_dev(case.B, "f64"))
     with pytest.raises(rt.RtError):
         g.ali_step(st, g.opts(os_sweeps=-1))
+    o = g.opts()
+    o.os_method = 7
+    with pytest.raises(rt.RtError):
+        g.ali_step(st, o)
     with pytest.raises(rt.RtError):
         g.lstar_stencil(to_dev(np.zeros((2, 4, 9, 9)), "f64"))   # 2 > n_lambda_max
     g.close()

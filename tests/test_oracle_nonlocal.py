@@ -126,3 +126,98 @@ def test_many_jacobi_sweeps_equal_the_exact_os_solve():
     a = so.ali(prob, tol=1e-30, max_iter=3, ng=False, lstar=L)
     b = so.ali(prob, tol=1e-30, max_iter=3, ng=False, lstar=L, inner_jacobi=400)
     np.testing.assert_allclose(b["J"], a["J"], rtol=1e-12)
+
+
+def _os_system(Nx, Ny, Nz, n_mu, n_phi, op, seed, eps_dex=(-4, -1)):
+    import scipy.sparse as sps
+    case = sy.random_box(Nx, Ny, Nz, n_mu, n_phi, seed=seed, dtype="f64", eps_dex=eps_dex)
+    L = oracle.stencil_matrix(oracle.lstar_stencil(case.chi[0], n_mu, n_phi, op))
+    A = (sps.identity(L.shape[0], format="csr") - L @ sps.diags((1.0 - case.eps[0]).ravel())).tocsr()
+    r = np.random.default_rng(seed).uniform(-1.0, 1.0, L.shape[0])
+    return case, A, r
+
+
+@pytest.mark.parametrize("shape", [(3, 3, 3), (4, 4, 5), (3, 5, 4), (2, 7, 9), (5, 6, 6), (1, 3, 8), (4, 9, 3)])
+def test_os_colours_separate_every_stencil_neighbour(shape):
+    """No two distinct voxels that share a 27-point stencil coupling (x, y
+    periodic, z not) have the same Gauss-Seidel colour; brute force over all
+    voxel pairs of odd and even periods from 3 up."""
+    Nz, Ny, Nx = shape
+    col = so.os_colours(shape)
+    assert col.min() >= 0 and col.max() < 18
+    for k in range(Nz):
+        for y in range(Ny):
+            for x in range(Nx):
+                for dz in (-1, 0, 1):
+                    if not 0 <= k + dz < Nz:
+                        continue
+                    for dy in (-1, 0, 1):
+                        for dx in (-1, 0, 1):
+                            u = (k + dz, (y + dy) % Ny, (x + dx) % Nx)
+                            if u != (k, y, x):
+                                assert col[u] != col[k, y, x], (shape, (k, y, x), u)
+
+
+@pytest.mark.parametrize("op", ["linear", "parabolic"])
+def test_colour_gauss_seidel_is_the_sequential_sweep_in_colour_order(op):
+    """The class-parallel sweep equals the textbook Gauss-Seidel sweep over
+    single voxels, dense matrix, one voxel at a time in the order (colour,
+    voxel index)."""
+    case, A, r = _os_system(5, 4, 3, 2, 4, op, seed=61)
+    shape = case.chi[0].shape
+    col = so.os_colours(shape).ravel()
+    Ad = A.toarray()
+    order = sorted(range(r.size), key=lambda v: (col[v], v))
+    x = r / np.diag(Ad)
+    for sweeps in (1, 2):
+        ref = x.copy()
+        for _ in range(sweeps):
+            for v in order:
+                s = r[v]
+                for u in range(r.size):
+                    if u != v:
+                        s -= Ad[v, u] * ref[u]
+                ref[v] = s / Ad[v, v]
+        got = so.gauss_seidel(A, r, x, col, sweeps)
+        np.testing.assert_allclose(got, ref, rtol=1e-13, atol=1e-15)
+
+
+def test_gauss_seidel_converges_to_the_os_solution_faster_than_jacobi():
+    """On the OS system of the linear operator's stencil (an M-matrix: the
+    Stein-Rosenberg case), k Gauss-Seidel sweeps leave a smaller error than k
+    Jacobi sweeps from the same start, and many sweeps reach the exact
+    solution."""
+    import scipy.sparse as sps
+    import scipy.sparse.linalg as spla
+    case, A, r = _os_system(9, 8, 6, 4, 8, "linear", seed=62, eps_dex=(-5, -2))
+    exact = spla.spsolve(A.tocsc(), r)
+    d = A.diagonal()
+    off = (A - sps.diags(d)).tocsr()
+    col = so.os_colours(case.chi[0].shape)
+    x0 = r / d
+    scale = np.abs(exact).max()
+    errs_j, errs_g = [], []
+    xj = x0.copy()
+    for k in range(1, 17):
+        xj = (r - off @ xj) / d
+        if k in (2, 4, 8, 16):
+            errs_j.append(np.abs(xj - exact).max() / scale)
+            errs_g.append(np.abs(so.gauss_seidel(A, r, x0, col, k) - exact).max() / scale)
+    print("Jacobi", errs_j, "Gauss-Seidel", errs_g)
+    assert all(g < j for g, j in zip(errs_g, errs_j))
+    np.testing.assert_allclose(so.gauss_seidel(A, r, x0, col, 400), exact, rtol=1e-11, atol=1e-13 * scale)
+
+
+@pytest.mark.parametrize("op", ["linear", "parabolic"])
+def test_ali_with_gauss_seidel_sweeps_reaches_the_lu_fixed_point(op):
+    case = sy.random_box(7, 7, 5, 4, 8, seed=41, dtype="f64", eps_dex=(-4, -1))
+    prob = so.BoxProblem(case.chi[0], case.eps[0], case.B[0], case.I_bc[0, 0], case.I_bc[0, 1], 4, 8, kind=op)
+    ref = so.direct(prob)
+    L = prob.lstar_nonlocal()
+    r_jac = so.ali(prob, tol=1e-12, max_iter=5000, ng=False, lstar=L, inner_jacobi=3)
+    r_gs = so.ali(prob, tol=1e-12, max_iter=5000, ng=False, lstar=L, inner_gs=3)
+    for r in (r_jac, r_gs):
+        assert r["converged"]
+        np.testing.assert_allclose(r["J"], ref["J"], rtol=1e-9)
+    print("steps Jacobi", r_jac["iters"], "Gauss-Seidel", r_gs["iters"])
+    assert r_gs["iters"] <= r_jac["iters"]
