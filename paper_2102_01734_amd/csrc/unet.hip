@@ -1,16 +1,18 @@
 // unet.hip -- inference of the learned ALI correction network (gfx950).
 //
 // The 3^3 convolutions between feature maps of 16, 32 or 64 channels are
-// implicit GEMMs on the matrix cores: one wavefront computes 16 consecutive
-// output voxels of one (z, y) row times all output channels.  For every tap
-// and every 16-channel slice of the input, the A operand is the 16 voxels x
-// 16 input channels (bf16, channels last, one 8-byte load per lane) and the B
-// operand the 16 input x 16 output channels of the tap's weights; the
-// products accumulate in fp32 (v_mfma_f32_16x16x16_bf16).  Bias, ReLU and
-// the U-Net skip addition are fused into the store.  The small layers (3
-// input features, the 1-channel head) and the upsampling are plain VALU
-// kernels.  Activations never leave HBM between layers; at 129^3 with 16
-// channels a level-0 map is 68 MB.
+// implicit GEMMs on the matrix cores (v_mfma_f32_16x16x32_bf16): the
+// reduction index k runs over (tap, input channel), 27 CI values padded to a
+// multiple of 32, and one wavefront computes T tiles of 16 consecutive
+// output voxels (in flattened z, y, x order) times all output channels.  Per
+// 32-wide k chunk a lane loads 8 consecutive input channels of one tap for
+// its voxel (A, 16 bytes, channels last; zero for the padding taps and for
+// taps beyond the top or bottom layer) and 8 weights of one output channel
+// (B, 16 bytes); products accumulate in fp32.  Bias, ReLU and the U-Net skip
+// addition are fused into the store.  The small layers (3 input features,
+// the 1-channel head) and the upsampling are plain VALU kernels.
+// Activations never leave HBM between layers; at 129^3 with 16 channels a
+// level-0 map is 68 MB.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -21,7 +23,6 @@
 
 namespace rt3d {
 
-typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
@@ -62,71 +63,89 @@ struct ConvArgs {
     uint16_t *out;         // [vo][CO]
 };
 
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v8bf load8(const uint16_t *p, bool ok)
+{
+    v4u u = ok ? *reinterpret_cast<const v4u *>(p) : v4u{0u, 0u, 0u, 0u};
+    return __builtin_bit_cast(v8bf, u);
+}
+
+constexpr int kConvTiles = 2;  // 16-voxel tiles per wavefront
+
 template <int CI, int CO>
 __global__ void __launch_bounds__(256) conv_mfma_kernel(ConvArgs a)
 {
+    constexpr int T = kConvTiles;
+    constexpr int NB = CO / 16;
+    constexpr int NK = (27 * CI + 31) / 32;  // 32-wide chunks of (tap, channel)
     const int lane = threadIdx.x & 63;
     const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int tiles_x = (a.vo.nx + 15) / 16;
-    const int64_t total = (int64_t)tiles_x * a.vo.ny * a.vo.nz;
-    if (wave >= total) return;  // uniform per wavefront
-    const int tx = (int)(wave % tiles_x);
-    const int64_t r = wave / tiles_x;
-    const int y = (int)(r % a.vo.ny);
-    const int z = (int)(r / a.vo.ny);
-    const int x0 = tx * 16;
-    const int i = lane & 15;         // A row (output voxel x0 + i) / B column (output channel)
-    const int kq = (lane >> 4) * 4;  // first of the 4 k values this lane holds
-    const int xo = min(x0 + i, a.vo.nx - 1);
+    const int64_t nvo = a.vo.n();
+    const int64_t v0 = wave * (16 * T);
+    if (v0 >= nvo) return;  // uniform per wavefront
+    const int i = lane & 15;       // A row (voxel) / B column (output channel)
+    const int kq = (lane >> 4) * 8;  // first of the 8 k values of this lane in a chunk
     const int S = a.stride;
+    int xs[T], ys[T], zs[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        int64_t v = v0 + 16 * t + i;
+        v = v < nvo ? v : nvo - 1;  // loads of the tail tile repeat the last voxel; its stores are masked
+        const int64_t r = v / a.vo.nx;
+        xs[t] = (int)(v - r * a.vo.nx) * S - 1;
+        ys[t] = (int)(r % a.vo.ny) * S - 1;
+        zs[t] = (int)(r / a.vo.ny) * S - 1;
+    }
+    v4f acc[T][NB];
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) acc[t][c] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    v4f acc[CO / 16];
+    for (int j = 0; j < NK; ++j) {
+        const int k = j * 32 + kq;
+        const int tap = k / CI, c0 = k % CI;  // CI is a power of two
+        const bool tap_ok = tap < 27;
+        const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
+        v8bf B[NB];
 #pragma unroll
-    for (int c = 0; c < CO / 16; ++c) acc[c] = v4f{0.f, 0.f, 0.f, 0.f};
-
-    for (int dz = 0; dz < 3; ++dz) {
-        const int zi = z * S + dz - 1;
-        if (zi < 0 || zi >= a.vi.nz) continue;  // zero padding in z (uniform per wavefront)
-        for (int dy = 0; dy < 3; ++dy) {
-            const int yi = wrap(y * S + dy - 1, a.vi.ny);
-            for (int dx = 0; dx < 3; ++dx) {
-                const int xi = wrap(xo * S + dx - 1, a.vi.nx);
-                const int tap = (dz * 3 + dy) * 3 + dx;
-                const uint16_t *src = a.in + (((int64_t)zi * a.vi.ny + yi) * a.vi.nx + xi) * CI + kq;
-                const uint16_t *wt = a.w + ((int64_t)tap * CO + i) * CI + kq;
+        for (int cb = 0; cb < NB; ++cb)
+            B[cb] = load8(a.w + ((int64_t)(tap_ok ? tap : 0) * CO + cb * 16 + i) * CI + c0, tap_ok);
 #pragma unroll
-                for (int cc = 0; cc < CI / 16; ++cc) {
-                    const v4s A = *reinterpret_cast<const v4s *>(src + cc * 16);
+        for (int t = 0; t < T; ++t) {
+            const int zi = zs[t] + dz;
+            const bool ok = tap_ok && zi >= 0 && zi < a.vi.nz;
+            const int yi = wrap(ys[t] + dy, a.vi.ny);
+            const int xi = wrap(xs[t] + dx, a.vi.nx);
+            const v8bf A = load8(a.in + (((int64_t)(ok ? zi : 0) * a.vi.ny + yi) * a.vi.nx + xi) * CI + c0, ok);
 #pragma unroll
-                    for (int cb = 0; cb < CO / 16; ++cb) {
-                        const v4s B = *reinterpret_cast<const v4s *>(wt + (int64_t)cb * 16 * CI + cc * 16);
-                        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B, acc[cb], 0, 0, 0);
-                    }
-                }
+            for (int cb = 0; cb < NB; ++cb) acc[t][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B[cb], acc[t][cb], 0, 0, 0);
+        }
+    }
+    // D layout: lane holds rows kq/2 .. kq/2 + 3 (voxels) of column i (output channel)
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) {
+            const int co = cb * 16 + i;
+            const float b = a.bias[co];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t v = v0 + 16 * t + (lane >> 4) * 4 + r;
+                if (v >= nvo) continue;
+                float val = fmaxf(acc[t][cb][r] + b, 0.f);
+                if (a.skip) val += bf2f(a.skip[v * CO + co]);
+                a.out[v * CO + co] = f2bf(val);
             }
         }
-    }
-    // D layout: lane holds rows kq .. kq+3 (voxels) of column i (output channel)
-#pragma unroll
-    for (int cb = 0; cb < CO / 16; ++cb) {
-        const int co = cb * 16 + i;
-        const float b = a.bias[co];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int x = x0 + kq + j;
-            if (x >= a.vo.nx) continue;
-            const int64_t v = ((int64_t)z * a.vo.ny + y) * a.vo.nx + x;
-            float val = fmaxf(acc[cb][j] + b, 0.f);
-            if (a.skip) val += bf2f(a.skip[v * CO + co]);
-            a.out[v * CO + co] = f2bf(val);
-        }
-    }
 }
 
 template <int CI, int CO>
 static hipError_t conv_t(const ConvArgs &a, hipStream_t st)
 {
-    const int64_t waves = (int64_t)((a.vo.nx + 15) / 16) * a.vo.ny * a.vo.nz;
+    const int64_t waves = (a.vo.n() + 16 * kConvTiles - 1) / (16 * kConvTiles);
     hipLaunchKernelGGL((conv_mfma_kernel<CI, CO>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
@@ -191,14 +210,16 @@ __global__ void __launch_bounds__(256) head_kernel(const uint16_t *__restrict__ 
 
 // linear upsampling by 2 (align corners): fine index o takes the coarse
 // point o/2 (o even) or the mean of (o-1)/2 and (o+1)/2 (o odd); the upper
-// neighbour wraps in x, y and is clamped in z
+// neighbour wraps in x, y and is clamped in z.  One thread per fine voxel
+// and 8 channels (16-byte loads and stores; C is a multiple of 16).
 __global__ void __launch_bounds__(256) upsample_kernel(const uint16_t *__restrict__ in, Vol vc, uint16_t *__restrict__ out,
                                                        Vol vf, int C)
 {
+    const int groups = C / 8;
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= vf.n() * C) return;
-    const int c = (int)(id % C);
-    const int64_t v = id / C;
+    if (id >= vf.n() * groups) return;
+    const int c0 = (int)(id % groups) * 8;
+    const int64_t v = id / groups;
     const int x = (int)(v % vf.nx);
     const int64_t r = v / vf.nx;
     const int y = (int)(r % vf.ny);
@@ -207,15 +228,26 @@ __global__ void __launch_bounds__(256) upsample_kernel(const uint16_t *__restric
     xs[0] = x >> 1; xs[1] = (x & 1) ? wrap((x + 1) >> 1, vc.nx) : xs[0];
     ys[0] = y >> 1; ys[1] = (y & 1) ? wrap((y + 1) >> 1, vc.ny) : ys[0];
     zs[0] = z >> 1; zs[1] = (z & 1) ? min((z + 1) >> 1, vc.nz - 1) : zs[0];
-    float acc = 0.f;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int d = 0; d < 2; ++d)
-                acc += bf2f(in[(((int64_t)zs[a] * vc.ny + ys[b]) * vc.nx + xs[d]) * C + c]);
-    out[id] = f2bf(0.125f * acc);
+            for (int d = 0; d < 2; ++d) {
+                const v4u q = *reinterpret_cast<const v4u *>(
+                    in + (((int64_t)zs[a] * vc.ny + ys[b]) * vc.nx + xs[d]) * C + c0);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    acc[2 * e] += __uint_as_float(q[e] << 16);
+                    acc[2 * e + 1] += __uint_as_float(q[e] & 0xffff0000u);
+                }
+            }
+    v4u o;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        o[e] = (uint32_t)f2bf(0.125f * acc[2 * e]) | ((uint32_t)f2bf(0.125f * acc[2 * e + 1]) << 16);
+    *reinterpret_cast<v4u *>(out + v * C + c0) = o;
 }
 
 // ---------------------------------------------------------------------------
@@ -437,7 +469,7 @@ hipError_t unet_forward(UNetDev *u, const float *features, float *out, hipStream
     }
     for (int l = s.L - 1; l >= 1; --l) {
         const Vol vc = u->lv[l], vf = u->lv[l - 1];
-        const int64_t nup = vf.n() * C[l];
+        const int64_t nup = vf.n() * (C[l] / 8);
         hipLaunchKernelGGL(upsample_kernel, dim3((unsigned)((nup + 255) / 256)), dim3(256), 0, st, u->h[l], vc, u->up,
                            vf, C[l]);
         if ((e = hipGetLastError()) != hipSuccess) return e;
