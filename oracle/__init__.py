@@ -95,6 +95,9 @@ def lib():
                                     + [ctypes.c_double] * 2 + [_dp, _dp, _dp, ctypes.c_double, ctypes.c_int, _dp, _dp,
                                                                ctypes.c_int])
         L.orc_fs_sphere.restype = ctypes.c_int
+        L.orc_lstar_stencil_sphere.argtypes = ([ctypes.c_int] * 3 + [ctypes.c_double] * 2 + [ctypes.c_int] * 2
+                                               + [_dp, ctypes.c_int, _dp, ctypes.c_int])
+        L.orc_lstar_stencil_sphere.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -365,6 +368,36 @@ def fs_sphere(grid: SphereGrid, n_mu, n_phi, chi, S, Bv, I_out=0.0, dsrc=0.0, B_
     if rc != 0:
         raise RuntimeError(f"orc_fs_sphere failed ({rc})")
     return J, L
+
+
+def lstar_stencil_sphere(grid: SphereGrid, n_mu, n_phi, chi, op: str = "linear", threads=None):
+    """Nearest-neighbour Lambda* of operator op on the spherical grid: array (27, Np, Nt, Nr); component
+    c = (dp+1)*9 + (dt+1)*3 + (dr+1) holds the element for the neighbour (ir+dr, it+dt, ip+dp), phi periodic."""
+    chi = _f64(chi).ravel()
+    out = np.zeros(27 * grid.n_vox)
+    rc = lib().orc_lstar_stencil_sphere(grid.Nr, grid.Nt, grid.Np, grid.rc, grid.ro, n_mu, n_phi, _d(chi),
+                                        _KINDS[op], _d(out), threads or default_threads())
+    if rc != 0:
+        raise RuntimeError(f"orc_lstar_stencil_sphere failed ({rc})")
+    return out.reshape(27, grid.Np, grid.Nt, grid.Nr)
+
+
+def stencil_matrix_sphere(st):
+    """The sparse matrix of a spherical 27-point stencil (27, Np, Nt, Nr): phi periodic, r and theta bounded
+    (entries of components that land on the same voxel are summed)."""
+    import scipy.sparse as sp
+    _, Np, Nt, Nr = st.shape
+    p, t, r = np.meshgrid(np.arange(Np), np.arange(Nt), np.arange(Nr), indexing="ij")
+    v = (p * Nt + t) * Nr + r
+    rows, cols, vals = [], [], []
+    for c in range(27):
+        dp, dt, dr = c // 9 - 1, (c // 3) % 3 - 1, c % 3 - 1
+        tu, ru = t + dt, r + dr
+        ok = (tu >= 0) & (tu < Nt) & (ru >= 0) & (ru < Nr)
+        u = (((p + dp) % Np) * Nt + tu) * Nr + ru
+        rows.append(v[ok]); cols.append(u[ok]); vals.append(st[c][ok])
+    n = Nr * Nt * Np
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
 
 
 from .solvers import *  # noqa: E402,F401,F403

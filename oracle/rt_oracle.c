@@ -1116,3 +1116,98 @@ int orc_fs_sphere(int Nr, int Nt, int Np, double rc, double ro, int n_mu, int n_
     free(Jt); free(Lt);
     return err;
 }
+
+/*
+ * Nearest-neighbour Lambda* of operator op on the spherical grid:
+ * out[c * nvox + v], c = (dp+1)*9 + (dt+1)*3 + (dr+1) for the neighbour
+ * u = (ir+dr, it+dt, ip+dp) of v = (ir, it, ip) (phi periodic, r and theta
+ * not; Np >= 3).  As on the box, a point m of a characteristic takes
+ * dI_m/dS at the points m+1 .. m-3 of the same characteristic whose voxel is
+ * such a neighbour (Sec. 2: the paper's non-local operator), weighted like
+ * the formal solution's voxel average (s_m over the sum of s of the voxel's
+ * visits in that direction).  Points further upstream that still lie in a
+ * neighbour (possible where voxels are small against the ray spacing) and
+ * neighbours across the pole are not indices of this stencil.
+ */
+int orc_lstar_stencil_sphere(int Nr, int Nt, int Np, double rc, double ro, int n_mu, int n_phi, const double *chi,
+                             int op, double *out, int nthreads)
+{
+    if (Np < 3) return -4;
+    int ndir = n_mu * n_phi;
+    long nvox = (long)Nr * Nt * Np;
+    double h = orc_sph_spacing(Nr, Nt, Np, rc, ro);
+    memset(out, 0, sizeof(double) * 27 * nvox);
+    if (nthreads <= 0) nthreads = 1;
+    double *acc = (double *)calloc((size_t)nthreads * 27 * nvox, sizeof(double));
+    int err = 0;
+    int K = (int)ceil(ro / h) + 1;
+    int cap = 2 * ((2 * K + 1) * (2 * K + 1) + (int)nvox) + 16;
+#pragma omp parallel num_threads(nthreads)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *num = (double *)malloc(sizeof(double) * 27 * nvox);
+        double *den = (double *)malloc(sizeof(double) * nvox);
+        double *mine = acc + (size_t)tid * 27 * nvox;
+        double *chars = (double *)malloc(sizeof(double) * 8 * (size_t)cap);
+        int scap = 4 * (Nr + Nt + Np) + 20;
+        int *vox = (int *)malloc(sizeof(int) * scap);
+        double *s = (double *)malloc(sizeof(double) * scap), *t0s = (double *)malloc(sizeof(double) * scap);
+        double *tau = (double *)malloc(sizeof(double) * scap);
+        double *ex = (double *)malloc(sizeof(double) * scap), *wa = (double *)malloc(sizeof(double) * scap);
+        double *wb = (double *)malloc(sizeof(double) * scap), *wg = (double *)malloc(sizeof(double) * scap);
+#pragma omp for schedule(static, 1)
+        for (int d = 0; d < ndir; d++) {
+            int i = d / n_phi, j = d % n_phi;
+            double mu = -1.0 + (2.0 * i + 1.0) / n_mu, ph = 2.0 * M_PI * (j + 0.5) / n_phi, n[3];
+            orc_direction_vector(mu, ph, n);
+            double w = 1.0 / ((double)n_mu * n_phi);
+            int nc = orc_sph_rays(Nr, Nt, Np, rc, ro, h, n, cap, chars);
+            if (nc < 0) {
+#pragma omp atomic write
+                err = -3;
+                continue;
+            }
+            memset(num, 0, sizeof(double) * 27 * nvox);
+            memset(den, 0, sizeof(double) * nvox);
+            for (int c = 0; c < nc; c++) {
+                int M = orc_sph_char(Nr, Nt, Np, rc, ro, chars + 8 * (size_t)c, n, scap, vox, s, t0s);
+                if (M <= 0) continue;
+                for (int m = 0; m < M; m++) tau[m] = chi[vox[m]] * s[m];
+                for (int q = 0; q < M; q++) orc_point_op(op, M, tau, q, &ex[q], &wa[q], &wb[q], &wg[q]);
+                for (int m = 0; m < M; m++) {
+                    den[vox[m]] += s[m];
+                    int irm = vox[m] % Nr, itm = (vox[m] / Nr) % Nt, ipm = vox[m] / (Nr * Nt);
+                    for (int jj = -1; jj <= 3; jj++) {
+                        int u = m - jj;
+                        if (u < 0 || u >= M) continue;
+                        int dr = vox[u] % Nr - irm, dt = (vox[u] / Nr) % Nt - itm;
+                        int dp = wrap(vox[u] / (Nr * Nt) - ipm, Np);
+                        dp = dp == Np - 1 ? -1 : dp;
+                        if (dr < -1 || dr > 1 || dt < -1 || dt > 1 || dp < -1 || dp > 1) continue;
+                        double coef = 0.0;
+                        for (int q = (u > 0 ? u - 1 : 0); q <= m && q <= u + 1; q++) {
+                            double wq = (q == u + 1) ? wa[q] : (q == u) ? wb[q] : wg[q];
+                            double att = 1.0;
+                            for (int r = q + 1; r <= m; r++) att *= ex[r];
+                            coef += wq * att;
+                        }
+                        int cc = (dp + 1) * 9 + (dt + 1) * 3 + (dr + 1);
+                        num[(size_t)cc * nvox + vox[m]] += s[m] * coef;
+                    }
+                }
+            }
+            for (int cc = 0; cc < 27; cc++)
+                for (long v = 0; v < nvox; v++)
+                    if (den[v] > 0.0) mine[(size_t)cc * nvox + v] += w * num[(size_t)cc * nvox + v] / den[v];
+        }
+        free(num); free(den); free(chars); free(vox); free(s); free(t0s); free(tau);
+        free(ex); free(wa); free(wb); free(wg);
+    }
+    for (int t = 0; t < nthreads; t++)
+        for (long i2 = 0; i2 < 27 * nvox; i2++) out[i2] += acc[(size_t)t * 27 * nvox + i2];
+    free(acc);
+    return err;
+}

@@ -20,6 +20,8 @@ __all__ = ["BoxProblem", "Plane1DProblem", "SphereProblem", "ali", "ng_extrapola
 class BoxProblem:
     """One wavelength on the periodic box: chi, eps, B of shape (Nz, Ny, Nx)."""
 
+    periodic_axes = (False, True, True)
+
     def __init__(self, chi, eps, B, I_top, I_bot, n_mu, n_phi, kind="linear", threads=None):
         from . import fs_box
         self._fs_box = fs_box
@@ -114,6 +116,17 @@ class SphereProblem(BoxProblem):
         self.n_fs = 0
         self._lstar = None
 
+    periodic_axes = (True, False, False)
+
+    def lstar_stencil(self):
+        """Nearest-neighbour Lambda* (27, Np, Nt, Nr) of the operator selected by kind."""
+        from . import lstar_stencil_sphere
+        return lstar_stencil_sphere(self.grid, self.n_mu, self.n_phi, self.chi, self.kind, self.threads)
+
+    def lstar_nonlocal(self):
+        from . import stencil_matrix_sphere
+        return stencil_matrix_sphere(self.lstar_stencil())
+
     def fs(self, S, bc=True, want_lstar=False):
         self.n_fs += 1
         core = np.full(self.chi.size, self.I_core if bc else 0.0)
@@ -151,22 +164,21 @@ def ng_extrapolate(x0, x1, x2, x3):
     return (1.0 - a - b) * x0 + a * x1 + b * x2
 
 
-def os_colours(shape):
-    """Colour class of every voxel of an (Nz, Ny, Nx) box for the Gauss-Seidel
-    sweeps of the OS system: cz*9 + cy*3 + cx with cz = z mod 2, cx = x mod 2,
-    cy = y mod 2, except that on an odd periodic axis of length >= 3 the last
-    column (row) takes class 2, since it neighbours the first one across the
-    period.  (A reading: the paper names Gauss-Seidel without an ordering.)"""
-    Nz, Ny, Nx = shape
-
-    def periodic_axis(N):
+def os_colours(shape, periodic=(False, True, True)):
+    """Colour class of every voxel of a 3-axis grid for the Gauss-Seidel sweeps
+    of the OS system: c0*9 + c1*3 + c2 with c_i = index mod 2 along axis i,
+    except that on an odd periodic axis of length >= 3 the last index takes
+    class 2, since it neighbours the first one across the period.  The box
+    (Nz, Ny, Nx) is periodic in y and x; the sphere (Np, Nt, Nr) in phi.
+    (A reading: the paper names Gauss-Seidel without an ordering.)"""
+    def axis(N, per):
         c = np.arange(N) % 2
-        if N >= 3 and N % 2 == 1:
+        if per and N >= 3 and N % 2 == 1:
             c[N - 1] = 2
         return c
 
-    cz = np.arange(Nz) % 2
-    return cz[:, None, None] * 9 + periodic_axis(Ny)[None, :, None] * 3 + periodic_axis(Nx)[None, None, :]
+    a, b, c = (axis(N, per) for N, per in zip(shape, periodic))
+    return a[:, None, None] * 9 + b[None, :, None] * 3 + c[None, None, :]
 
 
 def _gs_plan(A, colours):
@@ -230,7 +242,7 @@ def ali(prob, tol=1e-8, max_iter=10000, ng=True, ng_start=4, ng_every=4, J0=None
         A = (sps.identity(J.size, format="csr") - L @ sps.diags(om)).tocsr()
         Adiag = A.diagonal()
         Aoff = (A - sps.diags(Adiag)).tocsr()
-        gs_plan = _gs_plan(A, os_colours(J.shape)) if inner_gs > 0 else None
+        gs_plan = _gs_plan(A, os_colours(J.shape, prob.periodic_axes)) if inner_gs > 0 else None
     for it in range(1, max_iter + 1):
         Jfs = prob.fs(S)
         if sps.issparse(L):

@@ -113,3 +113,106 @@ def test_irradiation_rule(orc):
     u = (xl - np.array([0.0, 0.0, dsrc * ro])) / math.sqrt(dist2)
     assert int(np.argmax(vals)) == int(np.argmax([n @ u for n in ns]))
     assert abs(max(vals) * w - (ro * (dsrc - 1)) ** 2 / dist2) < 1e-14
+
+
+# --------------------------------------------------------------------------
+# nearest-neighbour Lambda* on the spherical grid
+# --------------------------------------------------------------------------
+def _brute_force_sphere_stencil(orc, g, chi, n_mu, n_phi, op):
+    """The stencil from its definition, one point at a time: for every
+    characteristic and every point u, the formal solution of operator op with
+    a unit source at that single point (ray_op) gives dI_m/dS(point u) at the
+    points m = u-1 .. u+3; where u's voxel is an index neighbour of m's, it is
+    added to that component of m's voxel with the voxel-average weight."""
+    dirs, w = _dirs(orc, n_mu, n_phi)
+    nv = g.n_vox
+    out = np.zeros((27, nv))
+    chi = np.asarray(chi, dtype=np.float64).ravel()
+    for n3, wd in zip(dirs, w):
+        num = np.zeros((27, nv))
+        den = np.zeros(nv)
+        for ch in g.rays(n3):
+            vox, s, _ = g.segments(ch, n3)
+            M = vox.size
+            if M == 0:
+                continue
+            tau = chi[vox] * s
+            np.add.at(den, vox, s)
+            rt = [(v % g.Nr, (v // g.Nr) % g.Nt, v // (g.Nr * g.Nt)) for v in vox]
+            for u in range(M):
+                e = np.zeros(M)
+                e[u] = 1.0
+                I = orc.ray_op(tau, e, 0.0, op)
+                for m in range(max(u - 1, 0), min(u + 4, M)):
+                    dr, dt = rt[u][0] - rt[m][0], rt[u][1] - rt[m][1]
+                    dp = (rt[u][2] - rt[m][2]) % g.Np
+                    dp = -1 if dp == g.Np - 1 else dp
+                    if abs(dr) > 1 or abs(dt) > 1 or abs(dp) > 1:
+                        continue
+                    num[(dp + 1) * 9 + (dt + 1) * 3 + (dr + 1), vox[m]] += s[m] * I[m]
+        ok = den > 0
+        out[:, ok] += wd * num[:, ok] / den[ok]
+    return out.reshape(27, g.Np, g.Nt, g.Nr)
+
+
+@pytest.mark.parametrize("op", ["linear", "parabolic"])
+def test_sphere_stencil_equals_the_per_point_definition(orc, op):
+    g = orc.SphereGrid(3, 4, 6, 1.0, 2.0)
+    chi = np.random.default_rng(5).uniform(0.3, 3.0, g.n_vox)
+    st = orc.lstar_stencil_sphere(g, 2, 4, chi, op)
+    ref = _brute_force_sphere_stencil(orc, g, chi, 2, 4, op)
+    np.testing.assert_allclose(st, ref, rtol=1e-12, atol=1e-15)
+
+
+def test_sphere_linear_stencil_is_a_nonnegative_substochastic_part_holding_the_diagonal(orc):
+    """Linear operator: every element is non-negative, each row sums to at
+    most 1 (J of a unit source is at most 1), and the centre holds at least
+    the diagonal Lambda* of the formal solution (points of the same voxel
+    within the window add to it)."""
+    g = orc.SphereGrid(5, 6, 8, 1.0, 2.5)
+    chi = np.random.default_rng(6).uniform(0.1, 5.0, g.n_vox)
+    st = orc.lstar_stencil_sphere(g, 4, 4, chi, "linear")
+    _, L = orc.fs_sphere(g, 4, 4, chi, np.zeros(g.n_vox), np.zeros(g.n_vox), kind="linear")
+    assert st.min() >= 0.0
+    assert st.reshape(27, -1).sum(axis=0).max() <= 1.0 + 1e-12
+    centre = st[13].ravel()
+    assert np.all(centre >= L - 1e-14)
+    assert np.mean(np.abs(centre - L) <= 1e-14 * np.maximum(L, 1e-300)) > 0.5  # mostly the diagonal itself
+
+
+def test_sphere_nonlocal_ali_reaches_the_lu_fixed_point_in_fewer_steps(orc):
+    from oracle import solvers as so
+    g = orc.SphereGrid(4, 5, 6, 1.0, 2.5)
+    rng = np.random.default_rng(7)
+    chi = rng.uniform(0.5, 8.0, g.n_vox)
+    eps = 10.0 ** rng.uniform(-4, -1, g.n_vox)
+    prob = so.SphereProblem(g, chi, eps, 1.0, 0.0, 1.0, 2, 4)
+    ref = so.direct(prob)
+    L = prob.lstar_nonlocal()
+    r_diag = so.ali(prob, tol=1e-12, max_iter=5000, ng=False)
+    r_jac = so.ali(prob, tol=1e-12, max_iter=5000, ng=False, lstar=L, inner_jacobi=6)
+    r_gs = so.ali(prob, tol=1e-12, max_iter=5000, ng=False, lstar=L, inner_gs=6)
+    for r in (r_diag, r_jac, r_gs):
+        assert r["converged"]
+        np.testing.assert_allclose(r["J"], ref["J"], rtol=1e-9)
+    print("steps diagonal", r_diag["iters"], "Jacobi", r_jac["iters"], "Gauss-Seidel", r_gs["iters"])
+    assert r_jac["iters"] < r_diag["iters"] and r_gs["iters"] <= r_jac["iters"]
+
+
+@pytest.mark.parametrize("shape", [(6, 4, 3), (7, 5, 4), (3, 3, 3)])
+def test_sphere_os_colours_separate_every_stencil_neighbour(shape):
+    """phi (axis 0) periodic, theta and r bounded."""
+    from oracle import solvers as so
+    Np, Nt, Nr = shape
+    col = so.os_colours(shape, (True, False, False))
+    for p in range(Np):
+        for t in range(Nt):
+            for r in range(Nr):
+                for dp in (-1, 0, 1):
+                    for dt in (-1, 0, 1):
+                        for dr in (-1, 0, 1):
+                            if not (0 <= t + dt < Nt and 0 <= r + dr < Nr):
+                                continue
+                            u = ((p + dp) % Np, t + dt, r + dr)
+                            if u != (p, t, r):
+                                assert col[u] != col[p, t, r]
