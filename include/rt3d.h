@@ -88,7 +88,9 @@ typedef enum { RT_FP64 = 0, RT_FP32 = 1 } rt_prec;
                                      129 x 129); the flag forces it for any box
                                      grid (results differ only in the
                                      summation order).                         */
-#define RT_F_LSTAR_NONLOCAL 0x4u  /* box: the ALI uses the nearest-neighbour
+#define RT_F_LSTAR_NONLOCAL 0x4u  /* box or sphere (Nphi >= 3, geometry cache
+                                     in device memory): the ALI uses the
+                                     nearest-neighbour
                                      Lambda* (Sec. 2, Sec. 3: the non-local
                                      operator of the paper's runs) -- the
                                      operator selected by RT_F_LSTAR_PARABOLIC
@@ -98,9 +100,12 @@ typedef enum { RT_FP64 = 0, RT_FP32 = 1 } rt_prec;
                                      or Gauss-Seidel sweeps
                                      (rt_solve_opts.os_sweeps, os_method).  The
                                      state's lstar array still receives the
-                                     diagonal, and is the stencil's centre
-                                     component (the same sum; on RT_FP32 grids
-                                     in the sweep's float rounding).           */
+                                     diagonal; on box grids it is the
+                                     stencil's centre component (the same
+                                     sum; on RT_FP32 grids in the sweep's
+                                     float rounding), on spherical grids the
+                                     centre also holds the window points of a
+                                     characteristic that re-enters the voxel. */
 #define RT_F_HOST_CACHE 0x8u      /* sphere: keep every chunk of the geometry
                                      cache in pinned host memory and stream it
                                      to the GPU for each formal solution (the
@@ -144,8 +149,10 @@ typedef struct {
  * formal solution with J and Lambda* of n_lambda_max wavelengths, the padded
  * inputs, the ALI state (Ng history, double anchors on RT_FP32 grids) and,
  * with RT_F_LSTAR_NONLOCAL, the stencil -- exceeds the free device memory is
- * refused before anything is allocated.  Every entry point returns
- * RT_E_NOMEM when a device or pinned-host allocation fails later on.
+ * refused before anything is allocated; so is a spherical grid with
+ * RT_F_LSTAR_NONLOCAL whose geometry cache does not fit device memory.  Every
+ * entry point returns RT_E_NOMEM when a device or pinned-host allocation
+ * fails later on.
  */
 rt_status rt_create_grid(const rt_grid_desc *desc, rt_grid_t *out);
 
@@ -328,6 +335,13 @@ rt_status rt_ali_step(rt_grid_t grid, rt_state *state, const rt_solve_opts *opts
  *   chi  device [n_lambda][Nz][Ny][Nx], grid precision
  *   out  device [n_lambda][27][Nz][Ny][Nx], grid precision, component
  *        c = (dz+1)*9 + (dy+1)*3 + (dx+1)
+ * Spherical grids (Nphi >= 3, geometry cache in device memory): chi
+ * [n_lambda][Nphi][Ntheta][Nr], out [n_lambda][27][Nphi][Ntheta][Nr] with
+ * c = (dp+1)*9 + (dt+1)*3 + (dr+1) for the neighbour (ir+dr, it+dt, ip+dp),
+ * phi periodic, r and theta bounded; a point m of a characteristic takes
+ * dI_m/dS at its points m+1 .. m-3 that lie in such a neighbour (further
+ * points and neighbours across the pole are not elements of this stencil);
+ * one thread per characteristic adds with 64-bit fixed-point atomics.
  * Sums are accumulated in 64-bit fixed point (2^-52), so the result is
  * bitwise reproducible.  Per wavelength and direction, workgroups gather
  * the contributions of bundles of ray rows in LDS and add each target row to
@@ -335,8 +349,9 @@ rt_status rt_ali_step(rt_grid_t grid, rt_state *state, const rt_solve_opts *opts
  * voxels a row, or a tile of two rows beyond the LDS), or any grid when the
  * environment variable RT3D_STENCIL_PER_CHARACTERISTIC=1 is set at grid
  * creation, add every contribution to device memory directly.  Both give
- * bitwise the same result.  Asynchronous on `stream`.  Errors: RT_E_INVALID,
- * RT_E_UNSUPPORTED (spherical grids), RT_E_NOMEM, RT_E_HIP.
+ * bitwise the same result.  Asynchronous on `stream`.  Errors: RT_E_INVALID
+ * (also Nphi < 3 on a spherical grid), RT_E_UNSUPPORTED (a spherical cache
+ * streamed from host memory), RT_E_NOMEM, RT_E_HIP.
  */
 rt_status rt_lstar_stencil(rt_grid_t grid, int32_t n_lambda, const void *chi, void *out, void *stream);
 

@@ -187,7 +187,7 @@ def _gs_plan(A, colours):
     d = A.diagonal()
     off = (A - sps.diags(d)).tocsr()
     cls = np.asarray(colours).ravel()
-    return d, [(idx, off[idx]) for idx in (np.flatnonzero(cls == c) for c in range(18)) if idx.size]
+    return d, [(idx, off[idx]) for idx in (np.flatnonzero(cls == c) for c in range(27)) if idx.size]
 
 
 def _gs_sweeps(plan, r, x, sweeps):

@@ -87,7 +87,13 @@ static rt_status os_update(rt_grid *g, int n_lambda, AliUpdateArgs ua, bool part
     ra.rfs_out = g->os_r.as<double>();
     HIPCHK(ali_update(ra, part_double, grid_double, next_double, nb, st));
     OsJacobiArgs ja{};
-    ja.Nx = g->geo.Nx; ja.Ny = g->geo.Ny; ja.Nz = g->geo.Nz;
+    if (g->sphere) {  // x = r, y = theta (bounded), z = phi (periodic)
+        ja.Nx = g->desc.n[0]; ja.Ny = g->desc.n[1]; ja.Nz = g->desc.n[2];
+        ja.per[0] = 0; ja.per[1] = 0; ja.per[2] = 1;
+    } else {          // x, y periodic, z bounded
+        ja.Nx = g->geo.Nx; ja.Ny = g->geo.Ny; ja.Nz = g->geo.Nz;
+        ja.per[0] = 1; ja.per[1] = 1; ja.per[2] = 0;
+    }
     ja.n_vox = g->n_vox;
     ja.lambda_of = ua.lambda_of;
     ja.st = g->nl_st.p;
@@ -332,7 +338,10 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
     auto fork_stencil = [&]() -> rt_status {
         if (!stencil_pending || stencil_forked) return RT_OK;
         HIPCHK(hipStreamWaitEvent(g->nl_side, g->nl_fork, 0));
-        rt_status r = accumulate_stencil(g, s->chi, nl, nb, lambda_of, true, g->nl_side);
+        // box: the centre is the sweep's diagonal Lambda* (no other point of a
+        // characteristic within the stencil window lies in the same voxel);
+        // sphere: built here, since a characteristic can leave and re-enter a voxel
+        rt_status r = accumulate_stencil(g, s->chi, nl, nb, lambda_of, !g->sphere, g->nl_side);
         if (r != RT_OK) return r;
         HIPCHK(hipEventRecord(g->nl_join, g->nl_side));
         stencil_forked = true;
@@ -345,7 +354,7 @@ static rt_status ali_step_batch(rt_grid *g, rt_state *s, const rt_solve_opts *o,
         if (r != RT_OK) return r;
         if (!stencil_forked) return RT_OK;
         HIPCHK(hipStreamWaitEvent(st, g->nl_join, 0));
-        return finish_stencil(g, nb, lambda_of, s->lstar, g->nl_st.p, g->dbl, st);
+        return finish_stencil(g, nb, lambda_of, g->sphere ? nullptr : s->lstar, g->nl_st.p, g->dbl, st);
     };
 
     if (g->dbl) {

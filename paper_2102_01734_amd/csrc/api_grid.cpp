@@ -378,8 +378,12 @@ rt_status rt_create_grid(const rt_grid_desc *desc, rt_grid_t *out)
         return fail(RT_E_INVALID, "unknown flags 0x%x", desc->flags);
     if (desc->geom == RT_GEOM_BOX_PERIODIC_XY && (desc->flags & RT_F_HOST_CACHE))
         return fail(RT_E_INVALID, "RT_F_HOST_CACHE applies to spherical grids only");
-    if (desc->geom == RT_GEOM_SPHERICAL && (desc->flags & (RT_F_BAND_TILES | RT_F_LSTAR_NONLOCAL)))
-        return fail(RT_E_INVALID, "RT_F_BAND_TILES and RT_F_LSTAR_NONLOCAL apply to box grids only");
+    if (desc->geom == RT_GEOM_SPHERICAL && (desc->flags & RT_F_BAND_TILES))
+        return fail(RT_E_INVALID, "RT_F_BAND_TILES applies to box grids only");
+    if (desc->geom == RT_GEOM_SPHERICAL && (desc->flags & RT_F_LSTAR_NONLOCAL) && desc->n[2] < 3)
+        return fail(RT_E_INVALID, "RT_F_LSTAR_NONLOCAL on a spherical grid needs Nphi >= 3");
+    if (desc->geom == RT_GEOM_SPHERICAL && (desc->flags & RT_F_LSTAR_NONLOCAL) && (desc->flags & RT_F_HOST_CACHE))
+        return fail(RT_E_INVALID, "RT_F_LSTAR_NONLOCAL needs the geometry cache in device memory (no RT_F_HOST_CACHE)");
     if (desc->geom == RT_GEOM_SPHERICAL) {
         const int64_t nv = (int64_t)desc->n[0] * desc->n[1] * desc->n[2];
         if (desc->n[0] < 1 || desc->n[1] < 1 || desc->n[2] < 1) return fail(RT_E_INVALID, "grid sizes must be >= 1");
@@ -397,8 +401,11 @@ rt_status rt_create_grid(const rt_grid_desc *desc, rt_grid_t *out)
         g->nbc = 3;
         g->sph_host_cache = (desc->flags & RT_F_HOST_CACHE) != 0;
         HIPCHK(hipGetDevice(&g->device));
+        g->nonlocal = (desc->flags & RT_F_LSTAR_NONLOCAL) != 0;
         rt_status rs = build_sphere_grid(g.get(), desc);
         if (rs != RT_OK) return rs;
+        if (g->nonlocal && g->sph_streaming)
+            return fail(RT_E_NOMEM, "RT_F_LSTAR_NONLOCAL needs the whole geometry cache in device memory");
         if (g->sph_streaming) {
             size_t stage = 0;
             for (const auto &ch : g->sph_chunks)

@@ -5,7 +5,7 @@
 
 using namespace rt3d;
 
-static ChunkPtrs chunk_ptrs(const SphereChunkDev &ch, const void *stage)
+ChunkPtrs chunk_ptrs(const SphereChunkDev &ch, const void *stage)
 {
     ChunkPtrs p{};
     if (ch.host) {

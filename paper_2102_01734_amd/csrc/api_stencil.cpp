@@ -18,6 +18,30 @@ rt_status accumulate_stencil(rt_grid *g, const void *chi, int n_lambda, int nb, 
         const int64_t cnt = std::min<int64_t>((int64_t)1 << 30, (int64_t)n_lambda * per - off);
         HIPCHK(fill_u64(g->nl_acc.as<unsigned long long>() + off, 0ull, (int)cnt, st));
     }
+    if (g->sphere) {
+        for (const auto &chp : g->sph_chunks) {
+            const SphereChunkDev &ch = *chp;
+            if (ch.host)
+                return fail(RT_E_UNSUPPORTED, "the nearest-neighbour Lambda* needs the geometry cache in device memory");
+            const ChunkPtrs cp = chunk_ptrs(ch, nullptr);
+            SphereStencilArgs a{};
+            a.Nr = g->desc.n[0]; a.Nt = g->desc.n[1]; a.Np = g->desc.n[2];
+            a.n_vox = g->n_vox;
+            a.n_bundles = ch.n_bundles;
+            a.bundle_begin = cp.bundle_begin;
+            a.char_len = cp.char_len;
+            a.vox = cp.vox;
+            a.s = cp.s;
+            a.w = cp.w;
+            a.chi = chi;
+            a.lambda_of = lambda_of;
+            a.n_batch = nb;
+            a.acc = g->nl_acc.as<unsigned long long>();
+            a.skip_centre = skip_centre ? 1 : 0;
+            HIPCHK(lstar_stencil_sphere_accumulate(a, g->dbl, g->sph_gdouble, g->para, st));
+        }
+        return RT_OK;
+    }
     StencilArgs a{};
     a.Nx = g->geo.Nx; a.Ny = g->geo.Ny; a.Nz = g->geo.Nz;
     a.n_vox = g->n_vox;
@@ -60,15 +84,16 @@ extern "C" {
 rt_status rt_lstar_stencil(rt_grid_t g, int32_t n_lambda, const void *chi, void *out, void *stream)
 {
     if (!g) return fail(RT_E_INVALID, "grid is NULL");
-    if (g->sphere) return fail(RT_E_UNSUPPORTED, "the nearest-neighbour Lambda* is built on box grids");
     if (n_lambda == 0) return RT_OK;
     if (n_lambda < 0 || n_lambda > g->desc.n_lambda_max)
         return fail(RT_E_INVALID, "n_lambda %d outside [0, %d]", n_lambda, g->desc.n_lambda_max);
     if (!chi || !out) return fail(RT_E_INVALID, "chi and out must not be NULL");
+    if (g->sphere && g->desc.n[2] < 3)
+        return fail(RT_E_INVALID, "the spherical nearest-neighbour Lambda* needs Nphi >= 3");
     std::vector<int32_t> lams(n_lambda);
     for (int i = 0; i < n_lambda; ++i) lams[i] = i;
     DevSchedule *sc = nullptr;
-    rt_status rs = get_schedule(g, variant(g, g->dbl, true, false).n_wg, lams, &sc);
+    rt_status rs = get_schedule(g, g->sphere ? 0 : variant(g, g->dbl, true, false).n_wg, lams, &sc);
     if (rs != RT_OK) return rs;
     return compute_stencil(g, chi, n_lambda, n_lambda, sc->lambda_of.as<int32_t>(), out, g->dbl,
                            (hipStream_t)stream);

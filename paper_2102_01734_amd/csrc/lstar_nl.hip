@@ -431,6 +431,127 @@ hipError_t lstar_stencil_accumulate(const StencilArgs &a0, bool grid_double, boo
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// spherical grid: one thread per (characteristic, batch entry)
+// ---------------------------------------------------------------------------
+template <typename G, typename TG, bool PARA>
+__global__ void __launch_bounds__(256) lstar_stencil_sphere_kernel(SphereStencilArgs a)
+{
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int c = threadIdx.x & 63;
+    const int64_t bundle = wave / a.n_batch;
+    if (bundle >= a.n_bundles) return;
+    const int b = (int)(wave - bundle * a.n_batch);
+    const int len = a.char_len[bundle * 64 + c];
+    if (len <= 0) return;
+    const int lam = a.lambda_of[b];
+    const G *__restrict__ chi = reinterpret_cast<const G *>(a.chi) + (int64_t)lam * a.n_vox;
+    unsigned long long *__restrict__ acc = a.acc + (int64_t)lam * kStencil * a.n_vox;
+    const TG *__restrict__ sv = reinterpret_cast<const TG *>(a.s);
+    const TG *__restrict__ wv = reinterpret_cast<const TG *>(a.w);
+    const int64_t e0 = a.bundle_begin[bundle] + c;
+    const int Nr = a.Nr, Nt = a.Nt, Np = a.Np;
+
+    // voxel coordinates of the points m+1, m, m-1, m-2, m-3 (slot j+1 for point m-j)
+    int vr[5], vt[5], vp[5], vv[5];
+    auto set = [&](int slot, int v) {
+        vv[slot] = v;
+        vr[slot] = v % Nr;
+        const int q = v / Nr;
+        vt[slot] = q % Nt;
+        vp[slot] = q / Nt;
+    };
+#pragma unroll
+    for (int j = 0; j < 5; ++j) { vv[j] = -1; vr[j] = vt[j] = vp[j] = 0; }
+    // adds w G_j for every point m-j (slot j+1) that is an index neighbour of point m (slot 1)
+    auto add = [&](double cw, const double (&Gv)[5]) {
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            if (!PARA && j == 0) continue;  // no downwind weight in the linear operator
+            if (vv[j] < 0) continue;
+            const int dr = vr[j] - vr[1], dt = vt[j] - vt[1];
+            int dp = vp[j] - vp[1];
+            dp = dp < 0 ? dp + Np : dp;
+            dp = dp == Np - 1 ? -1 : dp;
+            if (dr < -1 || dr > 1 || dt < -1 || dt > 1 || dp > 1) continue;
+            const int comp = (dp + 1) * 9 + (dt + 1) * 3 + (dr + 1);
+            if (a.skip_centre && comp == kStencilCentre) continue;
+            const long long f = __double2ll_rn(cw * Gv[j] * 0x1p52);
+            if (f != 0) atomicAdd(&acc[(int64_t)comp * a.n_vox + vv[1]], (unsigned long long)f);
+        }
+    };
+
+    set(1, a.vox[e0]);
+    double t_cur = seg_depth((double)chi[vv[1]], (double)sv[e0]);
+    double t_nxt = 0.0;
+    if (len > 1) {
+        set(0, a.vox[e0 + 64]);
+        t_nxt = seg_depth((double)chi[vv[0]], (double)sv[e0 + 64]);
+    }
+    double Gv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // G_-1, G_0, G_1, G_2, G_3
+    {
+        double ex0, e00;
+        entry_weights<double>(0.5 * t_cur, ex0, e00);
+        Gv[1] = e00;
+        add((double)wv[e0], Gv);
+    }
+    for (int m = 1; m < len; ++m) {
+        const int64_t e = e0 + 64 * (int64_t)m;
+        const bool last = m + 1 == len;
+        // shift the window: point m becomes slot 1
+#pragma unroll
+        for (int j = 4; j >= 1; --j) {
+            vv[j] = vv[j - 1]; vr[j] = vr[j - 1]; vt[j] = vt[j - 1]; vp[j] = vp[j - 1];
+        }
+        const double t_prev = t_cur;
+        t_cur = t_nxt;
+        if (!last) {
+            set(0, a.vox[e + 64]);
+            t_nxt = seg_depth((double)chi[vv[0]], (double)sv[e + 64]);
+        } else {
+            vv[0] = -1;
+        }
+        const double D = half_sum(t_prev, t_cur);
+        const double Dp = last ? 0.0 : half_sum(t_cur, t_nxt);
+        double ex, wa, wb, wg;
+        if (PARA) {
+            const PointW<double> pw = point_weights<double>(D, Dp, last);
+            ex = pw.ex; wa = pw.a; wb = pw.b; wg = pw.g;
+        } else {
+            const double Dv = D < kMinStep ? kMinStep : D;
+            double e0m, e1, e2;
+            kernel_moments<sizeof(G) == 8>(Dv, ex, e0m, e1, e2);
+            wb = e1 * rcp_f64(Dv);
+            wa = e0m - wb;
+            wg = 0.0;
+        }
+        Gv[4] = ex * Gv[3];
+        Gv[3] = ex * Gv[2];
+        Gv[2] = ex * Gv[1] + wa;
+        Gv[1] = ex * Gv[0] + wb;
+        Gv[0] = wg;
+        add((double)wv[e], Gv);
+    }
+}
+
+hipError_t lstar_stencil_sphere_accumulate(const SphereStencilArgs &a, bool grid_double, bool geom_double,
+                                           bool parabolic, hipStream_t st)
+{
+    if (a.n_bundles <= 0 || a.n_batch <= 0) return hipSuccess;
+    const int64_t waves = a.n_bundles * a.n_batch;
+    const dim3 grid((unsigned)((waves + 3) / 4));
+#define RT_SPH_ST(G, TG, P) hipLaunchKernelGGL((lstar_stencil_sphere_kernel<G, TG, P>), grid, dim3(256), 0, st, a)
+    if (grid_double) {
+        if (geom_double) { if (parabolic) RT_SPH_ST(double, double, true); else RT_SPH_ST(double, double, false); }
+        else { if (parabolic) RT_SPH_ST(double, float, true); else RT_SPH_ST(double, float, false); }
+    } else {
+        if (geom_double) { if (parabolic) RT_SPH_ST(float, double, true); else RT_SPH_ST(float, double, false); }
+        else { if (parabolic) RT_SPH_ST(float, float, true); else RT_SPH_ST(float, float, false); }
+    }
+#undef RT_SPH_ST
+    return hipGetLastError();
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) stencil_finish_kernel(const unsigned long long *__restrict__ acc,
                                                              const int32_t *__restrict__ lambda_of, int64_t n_vox,
@@ -488,12 +609,15 @@ __device__ __forceinline__ double os_row(const OsJacobiArgs &a, int64_t base, in
             if (c == kStencilCentre) continue;
             const double L = (double)st[(int64_t)c * n + v];
             if (L == 0.0) continue;
-            const int ku = k + c / 9 - 1;
-            if (ku < 0 || ku >= a.Nz) continue;
+            int ku = k + c / 9 - 1;
+            if (a.per[2]) ku = ku < 0 ? ku + a.Nz : (ku >= a.Nz ? ku - a.Nz : ku);
+            else if (ku < 0 || ku >= a.Nz) continue;
             int yu = y + (c / 3) % 3 - 1;
-            yu = yu < 0 ? yu + Ny : (yu >= Ny ? yu - Ny : yu);
+            if (a.per[1]) yu = yu < 0 ? yu + Ny : (yu >= Ny ? yu - Ny : yu);
+            else if (yu < 0 || yu >= Ny) continue;
             int xu = x + c % 3 - 1;
-            xu = xu < 0 ? xu + Nx : (xu >= Nx ? xu - Nx : xu);
+            if (a.per[0]) xu = xu < 0 ? xu + Nx : (xu >= Nx ? xu - Nx : xu);
+            else if (xu < 0 || xu >= Nx) continue;
             const int64_t u = (int64_t)ku * NxNy + (int64_t)yu * Nx + xu;
             acc += L * (1.0 - (double)eps[u]) * xs[base + u];
         }
@@ -526,7 +650,7 @@ hipError_t os_jacobi_sweep(const OsJacobiArgs &a, bool grid_double, bool first, 
 }
 
 // One colour class: coordinates (cx + 2 i, cy + 2 j, cz + 2 l) for colours 0
-// and 1 of x and y, the last column (row) for colour 2; n[3] class sizes.
+// and 1, the last index of the axis for colour 2; n[3] class sizes.
 struct OsColour {
     int c[3];
     int n[3];
@@ -543,7 +667,7 @@ __global__ void __launch_bounds__(256) os_gs_kernel(OsJacobiArgs a, OsColour col
     const int iy = rem / col.n[0], ix = rem - iy * col.n[0];
     const int x = col.c[0] == 2 ? a.Nx - 1 : col.c[0] + 2 * ix;
     const int y = col.c[1] == 2 ? a.Ny - 1 : col.c[1] + 2 * iy;
-    const int k = col.c[2] + 2 * iz;
+    const int k = col.c[2] == 2 ? a.Nz - 1 : col.c[2] + 2 * iz;
     const int64_t base = (int64_t)a.lambda_of[blockIdx.y] * a.n_vox;
     const double xn = os_row<G>(a, base, x, y, k, a.x_out, false);
     a.x_out[base + (int64_t)k * a.Nx * a.Ny + (int64_t)y * a.Nx + x] = xn;
@@ -563,11 +687,11 @@ static int colour_size(int N, int c, bool periodic)
 hipError_t os_gs_sweep(const OsJacobiArgs &a, bool grid_double, int n_batch, hipStream_t st)
 {
     if (a.n_vox <= 0 || n_batch <= 0) return hipSuccess;
-    for (int cz = 0; cz < 2; ++cz)
+    for (int cz = 0; cz < 3; ++cz)
         for (int cy = 0; cy < 3; ++cy)
             for (int cx = 0; cx < 3; ++cx) {
-                OsColour col{{cx, cy, cz}, {colour_size(a.Nx, cx, true), colour_size(a.Ny, cy, true),
-                                            colour_size(a.Nz, cz, false)}};
+                OsColour col{{cx, cy, cz}, {colour_size(a.Nx, cx, a.per[0] != 0), colour_size(a.Ny, cy, a.per[1] != 0),
+                                            colour_size(a.Nz, cz, a.per[2] != 0)}};
                 const int64_t n = (int64_t)col.n[0] * col.n[1] * col.n[2];
                 if (n == 0) continue;
                 dim3 grid((unsigned)((n + 255) / 256), (unsigned)n_batch);

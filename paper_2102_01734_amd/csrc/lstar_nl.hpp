@@ -48,6 +48,30 @@ struct StencilArgs {
 
 constexpr int kPlaneStride = 64;
 
+// Nearest-neighbour Lambda* on a spherical grid, one chunk of the geometry
+// cache: one thread per characteristic and batch entry follows the
+// characteristic's visits (same recurrence as the box), and adds
+// w_m G_j (w_m the visit's voxel-averaging weight) to component
+// c = (dp+1)*9 + (dt+1)*3 + (dr+1) of its voxel for the points m+1 .. m-3
+// whose voxel is an index neighbour (phi periodic, r and theta bounded) with
+// one 64-bit fixed-point atomic each.
+struct SphereStencilArgs {
+    int Nr, Nt, Np;
+    int64_t n_vox;
+    int64_t n_bundles;
+    const int64_t *bundle_begin;  // entry of visit m of characteristic c of bundle b: bundle_begin[b] + 64 m + c
+    const int32_t *char_len;
+    const int32_t *vox;
+    const void *s, *w;            // geometry type
+    const void *chi;              // [lambda][n_vox], grid precision
+    const int32_t *lambda_of;
+    int n_batch;
+    unsigned long long *acc;      // [lambda][27][n_vox]
+    int skip_centre;
+};
+hipError_t lstar_stencil_sphere_accumulate(const SphereStencilArgs &a, bool grid_double, bool geom_double,
+                                           bool parabolic, hipStream_t st);
+
 // Adds every characteristic's contributions to the stencil of the linear-
 // interpolation operator (parabolic = false) or of the formal solution
 // itself (parabolic = true), for n_batch wavelengths and all directions.
@@ -66,7 +90,8 @@ hipError_t lstar_stencil_finish(const unsigned long long *acc, const int32_t *la
 // One Jacobi sweep of [1 - Lambda*(1-eps)] x = r per wavelength of the batch
 // (first: x = r / (1 - Lambda*_vv (1-eps_v)), the diagonal solution).
 struct OsJacobiArgs {
-    int Nx, Ny, Nz;
+    int Nx, Ny, Nz;        // voxel v = (z Ny + y) Nx + x (sphere: x = r, y = theta, z = phi)
+    int per[3];            // per axis x, y, z: 1 periodic, 0 bounded (box 1, 1, 0; sphere 0, 0, 1)
     int64_t n_vox;
     const int32_t *lambda_of;
     const void *st;       // [lambda][27][n_vox], grid precision
@@ -77,10 +102,10 @@ struct OsJacobiArgs {
 };
 hipError_t os_jacobi_sweep(const OsJacobiArgs &a, bool grid_double, bool first, int n_batch, hipStream_t st);
 // One Gauss-Seidel sweep, in place on x_out (x_in unused), over the 18
-// colour classes in the order cz * 9 + cy * 3 + cx, where cz = z mod 2 and
-// cx (cy) = x mod 2 (y mod 2), except the last column (row) of an odd
-// periodic axis of length >= 3, which takes class 2.  Voxels of one class
-// share no stencil coupling, so each class is updated in parallel.
+// colour classes in the order cz * 9 + cy * 3 + cx, where c = index mod 2
+// along each axis, except the last index of an odd periodic axis of length
+// >= 3, which takes class 2.  Voxels of one class share no stencil coupling,
+// so each class is updated in parallel.
 hipError_t os_gs_sweep(const OsJacobiArgs &a, bool grid_double, int n_batch, hipStream_t st);
 
 }  // namespace rt3d

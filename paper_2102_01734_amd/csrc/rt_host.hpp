@@ -294,6 +294,8 @@ rt_status formal_solution(rt_grid *g, int32_t n_lambda, const void *chi, const v
                           void *J_out, void *lstar_out, void *stream, const std::vector<int32_t> *subset);
 
 // nearest-neighbour Lambda* (api_stencil.cpp)
+// Device pointers of a chunk (stage: its staging copy for host-resident chunks, else null).
+ChunkPtrs chunk_ptrs(const SphereChunkDev &ch, const void *stage);
 rt_status accumulate_stencil(rt_grid *g, const void *chi, int n_lambda, int nb, const int32_t *lambda_of,
                              bool skip_centre, hipStream_t st);
 rt_status finish_stencil(rt_grid *g, int nb, const int32_t *lambda_of, const void *centre, void *out,

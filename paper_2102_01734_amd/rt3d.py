@@ -320,7 +320,7 @@ def box_desc(Nx: int, Ny: int, Nz: int, n_mu: int, n_phi: int, prec: str = "f32"
 
 def sphere_desc(Nr: int, Nt: int, Np: int, r_core: float, r_out: float, n_mu: int, n_phi: int, prec: str = "f32",
                 n_lambda_max: int = 1, lstar: str = "linear", source_distance: float = 0.0,
-                host_cache: bool = False) -> RtGridDesc:
+                host_cache: bool = False, nonlocal_lstar: bool = False) -> RtGridDesc:
     d = RtGridDesc()
     d.struct_size = ctypes.sizeof(RtGridDesc)
     d.geom = RT_GEOM_SPHERICAL
@@ -329,7 +329,8 @@ def sphere_desc(Nr: int, Nt: int, Np: int, r_core: float, r_out: float, n_mu: in
     d.n_mu, d.n_phi = n_mu, n_phi
     d.n_lambda_max = n_lambda_max
     d.prec = RT_FP32 if prec == "f32" else RT_FP64
-    d.flags = (RT_F_LSTAR_PARABOLIC if lstar == "parabolic" else 0) | (RT_F_HOST_CACHE if host_cache else 0)
+    d.flags = ((RT_F_LSTAR_PARABOLIC if lstar == "parabolic" else 0) | (RT_F_HOST_CACHE if host_cache else 0)
+               | (RT_F_LSTAR_NONLOCAL if nonlocal_lstar else 0))
     return d
 
 
@@ -455,7 +456,7 @@ class Grid:
         rt_set_anchor_shape(self.handle, threads, rays, 1 if band else 0)
 
     def lstar_stencil(self, chi, stream=None):
-        """Nearest-neighbour Lambda* (n_lambda, 27, Nz, Ny, Nx) for the opacity chi."""
+        """Nearest-neighbour Lambda* (n_lambda, 27, *grid shape) for the opacity chi."""
         import torch
         n = chi.shape[0]
         c = self._check_field(chi, n, "chi")
@@ -540,9 +541,9 @@ class SphereGrid(Grid):
 
     def __init__(self, Nr: int, Nt: int, Np: int, r_core: float, r_out: float, n_mu: int, n_phi: int,
                  prec: str = "f32", n_lambda_max: int = 1, lstar: str = "linear", source_distance: float = 0.0,
-                 host_cache: bool = False):
+                 host_cache: bool = False, nonlocal_lstar: bool = False):
         d = sphere_desc(Nr, Nt, Np, r_core, r_out, n_mu, n_phi, prec, n_lambda_max, lstar, source_distance,
-                        host_cache)
+                        host_cache, nonlocal_lstar)
         self.desc = d
         self.shape = (Np, Nt, Nr)
         self.nbc = 3

@@ -229,7 +229,7 @@ def test_nonlocal_arguments():
         g.lstar_stencil(to_dev(np.zeros((2, 4, 9, 9)), "f64"))   # 2 > n_lambda_max
     g.close()
     d = rt.rt3d.sphere_desc(9, 7, 8, 1.0, 2.0, 4, 4, "f64", 1)
-    d.flags |= rt.rt3d.RT_F_LSTAR_NONLOCAL
+    d.flags |= rt.rt3d.RT_F_LSTAR_NONLOCAL | rt.rt3d.RT_F_BAND_TILES   # band tiles are a box notion
     with pytest.raises(rt.RtError) as e:
         rt.rt3d.rt_create_grid(d)
     assert e.value.status == rt.rt3d.RT_E_INVALID

@@ -1,0 +1,127 @@
+"""The nearest-neighbour Lambda* on spherical grids (RT_F_LSTAR_NONLOCAL,
+rt_lstar_stencil) against the oracle.
+
+Tolerances: double-precision grids keep the geometry in double and sum each
+element in 64-bit fixed point (2^-52) from double per-point arithmetic, so
+the stencil agrees with the oracle's to ~1e-13 absolute; single-precision
+grids keep path lengths and averaging weights in float and store the stencil
+in float (relative 1e-6).  ALI iterates with the same OS sweeps agree to
+rounding on double grids; converged results are held to the LU fixed point.
+"""
+import numpy as np
+import pytest
+
+import synthetic as sy
+from tests.gpu_helpers import to_dev, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [  # (Nr, Nt, Np, n_mu, n_phi, prec)
+    (6, 5, 7, 4, 8, "f64"),
+    (9, 8, 12, 4, 8, "f64"),
+    (5, 4, 3, 2, 4, "f64"),
+    (9, 8, 12, 4, 8, "f32"),
+]
+
+
+def _grid(case, lstar="linear", prec=None):
+    import paper_2102_01734_amd as rt
+    return rt.SphereGrid(case.Nr, case.Nt, case.Np, case.r_core, case.r_out, case.n_mu, case.n_phi,
+                         prec or case.dtype, case.n_lambda, lstar=lstar, source_distance=case.source_distance,
+                         nonlocal_lstar=True)
+
+
+def _prob(orc, case, l=0, kind="linear"):
+    g = orc.SphereGrid(case.Nr, case.Nt, case.Np, case.r_core, case.r_out)
+    I_out, I_core, J_sub = case.I_bc[l]
+    return orc.SphereProblem(g, case.chi[l].ravel(), case.eps[l].ravel(), case.B[l].ravel(), I_out, I_core,
+                             case.n_mu, case.n_phi, dsrc=case.source_distance, J_sub=J_sub, kind=kind)
+
+
+@pytest.mark.parametrize("op", ["linear", "parabolic"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_sphere_stencil_matches_oracle(orc, op, shape):
+    Nr, Nt, Np, n_mu, n_phi, prec = shape
+    print(f"sphere stencil {shape} {op}", flush=True)
+    torch = torch_cuda()
+    case = sy.random_sphere(Nr, Nt, Np, n_mu, n_phi, seed=Nr + Np, dtype=prec, n_lambda=2)
+    g = _grid(case, lstar=op)
+    st = g.lstar_stencil(to_dev(case.chi, prec))
+    torch.cuda.synchronize()
+    st = st.double().cpu().numpy()
+    g.close()
+    og = orc.SphereGrid(Nr, Nt, Np, case.r_core, case.r_out)
+    for l in range(2):
+        ref = orc.lstar_stencil_sphere(og, n_mu, n_phi, case.chi[l], op)
+        if prec == "f64":
+            np.testing.assert_allclose(st[l], ref, rtol=1e-12, atol=1e-13)
+        else:
+            np.testing.assert_allclose(st[l], ref, rtol=1e-6, atol=1e-7 * np.abs(ref).max())
+
+
+def test_sphere_stencil_deterministic():
+    torch = torch_cuda()
+    case = sy.random_sphere(9, 8, 12, 4, 8, seed=3, dtype="f32")
+    g = _grid(case)
+    chi = to_dev(case.chi, "f32")
+    a = g.lstar_stencil(chi)
+    b = g.lstar_stencil(chi)
+    torch.cuda.synchronize()
+    g.close()
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("method", ["jacobi", "gauss-seidel"])
+def test_sphere_nonlocal_ali_steps_match_oracle_iterates(orc, method):
+    """J after 1, 3 and 6 steps (Ng between steps 4 and 5), 5 sweeps per step,
+    equals the oracle's non-local ALI with the same sweeps (Np = 7 is odd:
+    the last phi plane takes its own colour)."""
+    torch = torch_cuda()
+    case = sy.random_sphere(6, 5, 7, 4, 8, seed=44, dtype="f64", eps_dex=(-4, -1))
+    g = _grid(case)
+    st = g.new_state(*(to_dev(a, "f64") for a in (case.chi, case.eps, case.B, case.I_bc)))
+    opts = g.opts(tol=1e-30, max_iter=1, ng_every=4, ng_start=4, os_sweeps=5, os_method=method)
+    prob = _prob(orc, case)
+    L = prob.lstar_nonlocal()
+    inner = dict(inner_jacobi=5) if method == "jacobi" else dict(inner_gs=5)
+    done = 0
+    for n in (1, 3, 6):
+        while done < n:
+            g.ali_step(st, opts)
+            done += 1
+        torch.cuda.synchronize()
+        Jg = g.state_tensors(st)["J"].cpu().numpy()[0]
+        ref = orc.ali(prob, tol=1e-30, max_iter=n, ng=True, ng_start=4, ng_every=4, lstar=L, **inner)
+        np.testing.assert_allclose(Jg.ravel(), ref["J"].ravel(), rtol=1e-10)
+    g.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_sphere_nonlocal_reaches_the_lu_fixed_point_in_fewer_steps(orc, prec):
+    torch = torch_cuda()
+    case = sy.random_sphere(6, 5, 7, 4, 8, seed=45, dtype=prec, eps_dex=(-4, -1))
+    ref = orc.direct(_prob(orc, case))
+    steps = {}
+    for nl in (False, True):
+        import paper_2102_01734_amd as rt
+        g = rt.SphereGrid(case.Nr, case.Nt, case.Np, case.r_core, case.r_out, case.n_mu, case.n_phi, prec, 1,
+                          source_distance=case.source_distance, nonlocal_lstar=nl)
+        st = g.new_state(*(to_dev(a, prec) for a in (case.chi, case.eps, case.B, case.I_bc)))
+        status, rep = g.solve(st, g.opts(tol=1e-12 if prec == "f64" else 1e-9, max_iter=3000))
+        torch.cuda.synchronize()
+        J = g.state_tensors(st)["J"].cpu().numpy()[0].ravel()
+        g.close()
+        assert status == 0
+        np.testing.assert_allclose(J, ref["J"].ravel(), rtol=1e-9 if prec == "f64" else 1e-5)
+        steps[nl] = rep.iters
+    print("steps diagonal", steps[False], "non-local", steps[True])
+    assert steps[True] < steps[False]
+
+
+def test_sphere_nonlocal_arguments():
+    import paper_2102_01734_amd as rt
+    for kw in (dict(Np=2), dict(host_cache=True)):
+        Np = kw.get("Np", 6)
+        with pytest.raises(rt.RtError) as e:
+            rt.SphereGrid(4, 4, Np, 1.0, 2.0, 2, 4, "f64", 1, nonlocal_lstar=True, host_cache=kw.get("host_cache", False))
+        assert e.value.status == rt.rt3d.RT_E_INVALID
