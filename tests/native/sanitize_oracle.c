@@ -27,6 +27,8 @@ int orc_fs_1d_dirs(int Nz, int n_mu, int n_phi, const double *chi_k, const doubl
 int orc_fs_sphere(int Nr, int Nt, int Np, double rc, double ro, int n_mu, int n_phi, double dsrc, double B_sub,
                   const double *chi, const double *S, const double *Bv, double I_out, int lstar_kind, double *J,
                   double *lstar, int nthreads);
+int orc_lstar_stencil_sphere(int Nr, int Nt, int Np, double rc, double ro, int n_mu, int n_phi, const double *chi,
+                             int op, double *out, int nthreads);
 
 static int fails = 0;
 static long checks = 0;
@@ -133,6 +135,13 @@ int main(void)
         for (long v = 0; v < n; ++v) CHECK(isfinite(J[v]) && J[v] >= 0.0);
         CHECK(orc_fs_sphere(NR, NT, NP, 0.5, 2.0, 2, 4, 4.0, 1.0, chi, S, Bv, 0.0, 1, J, L, 2) == 0);
         for (long v = 0; v < n; ++v) CHECK(isfinite(J[v]) && J[v] >= 0.0);
+        double *st = malloc(sizeof(double) * 27 * n);
+        for (int op = 0; op < 2; ++op) {
+            CHECK(orc_lstar_stencil_sphere(NR, NT, NP, 1.0, 3.0, 2, 4, chi, op, st, 2) == 0);
+            for (long i = 0; i < 27 * n; ++i) CHECK(isfinite(st[i]));
+        }
+        CHECK(orc_lstar_stencil_sphere(NR, NT, 2, 1.0, 3.0, 2, 4, chi, 0, st, 2) != 0); /* Nphi < 3 refused */
+        free(st);
     }
     if (fails) {
         fprintf(stderr, "%d checks failed\n", fails);
