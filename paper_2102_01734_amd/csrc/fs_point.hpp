@@ -151,16 +151,17 @@ struct PointW {
     T a, b, g, ex, dlin;
 };
 
-template <typename T>
+// FULL: double-accurate moments (the default for double results); false: the
+// shorter forms that suffice for single-precision results.
+template <typename T, bool FULL = sizeof(T) == 8>
 __device__ __forceinline__ PointW<T> point_weights(double D, double Dp, bool last)
 {
-    constexpr bool FULL = sizeof(T) == 8;
     const double Dv = D < kMinStep ? kMinStep : D;  // NaN propagates
     double ex, e0, e1, e2;
     kernel_moments<FULL>(Dv, ex, e0, e1, e2);
     const double Dq = Dp < kMinStep ? Dv : Dp;   // keeps r finite on last/vacuum points; NaN propagates
     const double Ds = Dv + Dq;
-    const double r = rcp_f64(Dv * Dq * Ds);
+    const double r = rcp_f64<FULL>(Dv * Dq * Ds);
     const double bl = e1 * ((Dq * Ds) * r);      // e1 / D
     const bool lin = last || (Dp < 0.5 * D) || (Dp * e0 <= __builtin_fma(Dv, e1, -e2));
     const double bp = __builtin_fma(Ds, e1, -e2) * (Ds * r);

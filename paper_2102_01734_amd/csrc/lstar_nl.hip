@@ -126,16 +126,16 @@ __global__ void __launch_bounds__(256) lstar_stencil_kernel(StencilArgs a)
         const double D = half_sum(t_prev, t_cur);
         const double Dp = last ? 0.0 : half_sum(t_cur, t_nxt);
         double ex, wa, wb, wg;
+        // single-precision grids keep the stencil in float: the shorter
+        // moment forms of the float sweep suffice there
         if (PARA) {
-            const PointW<double> pw = point_weights<double>(D, Dp, last);  // full double series
+            const PointW<double> pw = point_weights<double, sizeof(G) == 8>(D, Dp, last);
             ex = pw.ex; wa = pw.a; wb = pw.b; wg = pw.g;
         } else {
-            // single-precision grids keep the stencil in float: the shorter
-            // moment series of the float sweep suffices there
             const double Dv = D < kMinStep ? kMinStep : D;
             double e0, e1, e2;
             kernel_moments<sizeof(G) == 8>(Dv, ex, e0, e1, e2);
-            wb = e1 * rcp_f64(Dv);
+            wb = e1 * rcp_f64<sizeof(G) == 8>(Dv);
             wa = e0 - wb;
             wg = 0.0;
         }
@@ -339,13 +339,13 @@ __global__ void __launch_bounds__(1024) lstar_stencil_rows_kernel(StencilArgs a)
             const double Dp = last ? 0.0 : half_sum(t_cur[r], t_nxt[r]);
             double ex, wa, wb, wg;
             if (PARA) {
-                const PointW<double> pw = point_weights<double>(D, Dp, last);
+                const PointW<double> pw = point_weights<double, sizeof(G) == 8>(D, Dp, last);
                 ex = pw.ex; wa = pw.a; wb = pw.b; wg = pw.g;
             } else {
                 const double Dv = D < kMinStep ? kMinStep : D;
                 double e0, e1, e2;
                 kernel_moments<sizeof(G) == 8>(Dv, ex, e0, e1, e2);
-                wb = e1 * rcp_f64(Dv);
+                wb = e1 * rcp_f64<sizeof(G) == 8>(Dv);
                 wa = e0 - wb;
                 wg = 0.0;
             }
@@ -515,13 +515,13 @@ __global__ void __launch_bounds__(256) lstar_stencil_sphere_kernel(SphereStencil
         const double Dp = last ? 0.0 : half_sum(t_cur, t_nxt);
         double ex, wa, wb, wg;
         if (PARA) {
-            const PointW<double> pw = point_weights<double>(D, Dp, last);
+            const PointW<double> pw = point_weights<double, sizeof(G) == 8>(D, Dp, last);
             ex = pw.ex; wa = pw.a; wb = pw.b; wg = pw.g;
         } else {
             const double Dv = D < kMinStep ? kMinStep : D;
             double e0m, e1, e2;
             kernel_moments<sizeof(G) == 8>(Dv, ex, e0m, e1, e2);
-            wb = e1 * rcp_f64(Dv);
+            wb = e1 * rcp_f64<sizeof(G) == 8>(Dv);
             wa = e0m - wb;
             wg = 0.0;
         }

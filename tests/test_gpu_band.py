@@ -4,7 +4,7 @@ whole-layer tile): parity with the oracle.
 With band tiles a workgroup sweeps a bundle of whole ray rows and keeps only
 the rows those rays reach within the current layer.  The visits, the point
 arithmetic and the per-voxel averaging are those of the layer-tile sweep, so
-the tolerances are the ones of test_gpu_fs: 1e-12 for double grids, 2e-5
+the tolerances are the ones of test_gpu_fs: 1e-12 for double grids, 5e-6
 relative for single grids; against the layer-tile sweep of the same grid the
 results differ only in the summation order of J.
 """
@@ -67,8 +67,8 @@ def test_band_tiles_fp32_match_oracle(orc, shape):
     J, L = gpu_fs(case, S, grid=g)
     g.close()
     Jo, Lo = _oracle_fs(orc, case, S, "linear")
-    np.testing.assert_allclose(J, Jo, rtol=2e-5, atol=1e-6 * np.abs(Jo).max())
-    np.testing.assert_allclose(L, Lo, rtol=2e-5, atol=1e-7)
+    np.testing.assert_allclose(J, Jo, rtol=5e-6, atol=1e-7 * np.abs(Jo).max())
+    np.testing.assert_allclose(L, Lo, rtol=5e-6, atol=1e-8)
 
 
 def test_band_and_layer_tiles_agree():
@@ -134,15 +134,15 @@ def test_wide_layer_uses_band_tiles_and_every_band_shape_matches_oracle(orc):
     assert g.launch_shape()["band"]
     Jo, Lo = _oracle_fs(orc, case, S, "linear")
     J, L = gpu_fs(case, S, grid=g)
-    np.testing.assert_allclose(J, Jo, rtol=2e-5, atol=1e-6 * np.abs(Jo).max())
-    np.testing.assert_allclose(L, Lo, rtol=2e-5, atol=1e-7)
+    np.testing.assert_allclose(J, Jo, rtol=5e-6, atol=1e-7 * np.abs(Jo).max())
+    np.testing.assert_allclose(L, Lo, rtol=5e-6, atol=1e-8)
     for threads, rays in BAND_TUNE:
         print(f"band shape {threads} x {rays}", flush=True)
         g.set_launch_shape(threads, rays)
         ls = g.launch_shape()
         assert (ls["threads"], ls["rays"], ls["band"]) == (threads, rays, True)
         J1, _ = gpu_fs(case, S, grid=g, want_lstar=False)
-        np.testing.assert_allclose(J1, Jo, rtol=2e-5, atol=1e-6 * np.abs(Jo).max())
+        np.testing.assert_allclose(J1, Jo, rtol=5e-6, atol=1e-7 * np.abs(Jo).max())
     with pytest.raises(rt.RtError):
         g.set_launch_shape(256, 5)    # compiled for layer tiles only
     g.close()
@@ -171,7 +171,7 @@ def test_band_shape_on_a_layer_grid(orc, prec):
     case = sy.random_box(31, 23, 9, 4, 8, seed=23, dtype=prec)
     S = sy.random_source(case.chi.shape, seed=24, dtype=prec)
     Jo, _ = _oracle_fs(orc, case, S, "linear")
-    tol = dict(rtol=1e-12) if prec == "f64" else dict(rtol=2e-5, atol=1e-6 * np.abs(Jo).max())
+    tol = dict(rtol=1e-12) if prec == "f64" else dict(rtol=5e-6, atol=1e-7 * np.abs(Jo).max())
     out = []
     for band in (False, True, True):
         g = make_grid(case)
@@ -228,6 +228,6 @@ def test_fs_257_lognormal_sampled(orc):
     vox = np.unique(np.concatenate([[0, n - 1, NxNy - 1, n - NxNy, 128 * NxNy + 128 * case.Nx + 128],
                                     rng.integers(0, n, 12)]))
     Jo, Lo = orc.fs_box_sampled(case.chi[0], S[0], case.I_bc[0, 0], case.I_bc[0, 1], case.n_mu, case.n_phi, vox)
-    np.testing.assert_allclose(J[0].ravel()[vox], Jo, rtol=2e-5, atol=1e-6 * np.abs(Jo).max())
-    np.testing.assert_allclose(L[0].ravel()[vox], Lo, rtol=2e-5, atol=1e-7)
+    np.testing.assert_allclose(J[0].ravel()[vox], Jo, rtol=5e-6, atol=1e-7 * np.abs(Jo).max())
+    np.testing.assert_allclose(L[0].ravel()[vox], Lo, rtol=5e-6, atol=1e-8)
     assert np.all(np.isfinite(J)) and np.all((L > 0) & (L <= 1))

@@ -146,8 +146,8 @@ def test_fs_full_size_lognormal_sampled(orc):
     vox = np.unique(np.concatenate([[0, n - 1, case.Nx * case.Ny - 1, n - case.Nx * case.Ny],
                                     rng.integers(0, n, 20)]))
     Jo, Lo = orc.fs_box_sampled(case.chi[0], S[0], case.I_bc[0, 0], case.I_bc[0, 1], case.n_mu, case.n_phi, vox)
-    np.testing.assert_allclose(J[0].ravel()[vox], Jo, rtol=2e-5, atol=1e-6 * np.abs(Jo).max())
-    np.testing.assert_allclose(L[0].ravel()[vox], Lo, rtol=2e-5, atol=1e-7)
+    np.testing.assert_allclose(J[0].ravel()[vox], Jo, rtol=5e-6, atol=1e-7 * np.abs(Jo).max())
+    np.testing.assert_allclose(L[0].ravel()[vox], Lo, rtol=5e-6, atol=1e-8)
     assert np.all(np.isfinite(J)) and np.all((L > 0) & (L < 1))
 
 
@@ -213,9 +213,9 @@ def test_largest_layer_tile(orc, prec):
         J, L = gpu_fs(case, S, grid=g)
         g.close()
         Jo, Lo = _oracle_fs(orc, case, S, "linear")
-        tol = 1e-12 if prec == "f64" else 2e-5
-        np.testing.assert_allclose(J, Jo, rtol=tol, atol=tol * 0.05 * np.abs(Jo).max())
-        np.testing.assert_allclose(L, Lo, rtol=tol, atol=tol * 0.005)
+        tol = 1e-12 if prec == "f64" else 5e-6
+        np.testing.assert_allclose(J, Jo, rtol=tol, atol=tol * 0.02 * np.abs(Jo).max())
+        np.testing.assert_allclose(L, Lo, rtol=tol, atol=tol * 0.002)
 
 
 def test_batched_64_wavelengths_full_size_sampled(orc):
@@ -231,8 +231,8 @@ def test_batched_64_wavelengths_full_size_sampled(orc):
     vox = np.unique(rng.integers(0, case.n_vox, 12))
     for l in (0, 37, 63):
         Jo, Lo = orc.fs_box_sampled(case.chi[l], S[l], case.I_bc[l, 0], case.I_bc[l, 1], case.n_mu, case.n_phi, vox)
-        np.testing.assert_allclose(J[l].ravel()[vox], Jo, rtol=2e-5, atol=1e-6 * np.abs(Jo).max())
-        np.testing.assert_allclose(L[l].ravel()[vox], Lo, rtol=2e-5, atol=1e-7)
+        np.testing.assert_allclose(J[l].ravel()[vox], Jo, rtol=5e-6, atol=1e-7 * np.abs(Jo).max())
+        np.testing.assert_allclose(L[l].ravel()[vox], Lo, rtol=5e-6, atol=1e-8)
 
 
 @pytest.mark.parametrize("prec,shape", [("f32", (512, 3)), ("f32", (512, 17)), ("f64", (512, 3)), ("f64", (512, 17))])
@@ -251,7 +251,8 @@ def test_ray_bundle_shapes_match_single_workgroup_sweeps(orc, prec, shape):
     tol = 1e-14 if prec == "f64" else 2e-6
     np.testing.assert_allclose(J1, J0, rtol=tol, atol=tol * np.abs(J0).max())
     Jo, _ = _oracle_fs(orc, case, S, "linear")
-    np.testing.assert_allclose(J1, Jo, rtol=1e-12 if prec == "f64" else 2e-5, atol=1e-6 * np.abs(Jo).max())
+    np.testing.assert_allclose(J1, Jo, rtol=1e-12 if prec == "f64" else 5e-6,
+                               atol=(1e-14 if prec == "f64" else 1e-7) * np.abs(Jo).max())
 
 
 # Launch shapes of the single-precision sweep that the autotuner chooses among

@@ -92,4 +92,4 @@ def test_autotune_on_a_share_with_band_tiles(orc):
             g.autotune_dirs(chi, St, np.array(bad, np.int32))
     g.close()
     Jo, _ = orc.fs_box_dirs(case.chi[0], S[0], case.I_bc[0, 0], case.I_bc[0, 1], 4, 8, dirs)
-    np.testing.assert_allclose(Jp.cpu().numpy()[0], Jo, rtol=2e-5, atol=1e-6 * np.abs(Jo).max())
+    np.testing.assert_allclose(Jp.cpu().numpy()[0], Jo, rtol=5e-6, atol=1e-7 * np.abs(Jo).max())
