@@ -172,7 +172,7 @@ def one_gpu_share(case, shape, n_gpus: int = 8, reps: int = 3):
             "full_run_shape_ms_per_fs": wall_l * 1e3, "share_tuned_band_ms_per_fs": wall_b * 1e3}
 
 
-def time_to_solution(case, net_every: int = 12, tol: float = 1e-6, shape=None):
+def time_to_solution(case, net_every: int = 12, tol: float = 1e-6, shape=None, net_path=None):
     """Wall seconds of rt_solve, both to the stopping tolerance `tol` (which lands
     below 1e-5 relative error on this workload) and to the target error 1e-5
     itself (the fewest steps whose J is within 1e-5 of the reference, found by
@@ -188,7 +188,7 @@ def time_to_solution(case, net_every: int = 12, tol: float = 1e-6, shape=None):
     import torch
 
     import paper_2102_01734_amd as rt
-    blob_path = os.path.join(ROOT, "paper_2102_01734_amd", "data", "precond_box.rtun")
+    blob_path = net_path or os.path.join(ROOT, "paper_2102_01734_amd", "data", "precond_box.rtun")
     blob = open(blob_path, "rb").read()
     import synthetic as sy
     # the double-precision legs get their own tuned sweep shape (setup, not timed)
@@ -230,7 +230,11 @@ def time_to_solution(case, net_every: int = 12, tol: float = 1e-6, shape=None):
     gpu_ref, _, rref, _ = run("f64", 1e-9, 80)
     progress(f"time to solution: GPU double-precision reference {rref.iters} steps")
     target = 1e-5
+    import struct
+    n_lev = struct.unpack_from("<I", blob, 8)[0]
     out = {"tol": tol, "target_error": target, "f64_launch_shape": list(shape64),
+           "network": {"channels": list(struct.unpack_from(f"<{n_lev}I", blob, 12)),
+                       "blob": os.path.relpath(blob_path, ROOT)},
            "protocol": "seconds = wall time of rt_solve stopped at max|dJ/J| < tol; seconds_to_target = wall time "
                        "of a fresh rt_solve limited to the fewest steps (iterations) whose J is within the target "
                        "of the reference (binary search over the step limit; error evaluation not timed)"}
@@ -521,6 +525,7 @@ def main():
     ap.add_argument("--workload", default="batched129", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-solution comparison")
+    ap.add_argument("--net", default=None, help="network blob for the learned leg (default: the shipped one)")
     ap.add_argument("--no-extra", action="store_true",
                     help="batched workload: skip the single-wavelength line, the one-GPU share and time to solution")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
@@ -579,7 +584,7 @@ def main():
         out["one_gpu_share"] = one_gpu_share(single, shape1)
         progress("one-GPU share timed")
         if not args.no_solve:
-            out["time_to_solution"] = time_to_solution(single, shape=shape1)
+            out["time_to_solution"] = time_to_solution(single, shape=shape1, net_path=args.net)
     if not args.no_cpu_baseline:
         # about 4e8 voxel-directions on all threads, 3.4e7 on one
         n_sub = max(8, min(case.n_dir, round(4.1e8 / case.n_vox)))
