@@ -485,7 +485,7 @@ rt_status rt_create_grid(const rt_grid_desc *desc, rt_grid_t *out)
     }
 
     // stencil components and LDS planes of the row-window Lambda* kernel
-    std::vector<int8_t> planes((size_t)2 * g->n_dir * kPlaneStride, (int8_t)-1);
+    std::vector<int32_t> planes((size_t)2 * g->n_dir * kPlaneStride, -1);
     g->nl_rows = true;
     for (int d = 0; d < g->n_dir; ++d) {
         const Direction &dir = g->geo.dirs[d];
@@ -507,12 +507,12 @@ rt_status rt_create_grid(const rt_grid_desc *desc, rt_grid_t *out)
             if (db != 0) step = db;
         }
         for (int skip = 0; skip < 2; ++skip) {
-            int8_t *tab = planes.data() + ((size_t)skip * g->n_dir + d) * kPlaneStride;
+            int32_t *tab = planes.data() + ((size_t)skip * g->n_dir + d) * kPlaneStride;
             int p = 0;
             for (int c = 0; c < kStencil; ++c) {
                 if (!used[c] || (skip && c == kStencilCentre)) continue;
-                tab[c] = (int8_t)p;
-                tab[32 + p] = (int8_t)c;
+                tab[c] = p;
+                tab[32 + p] = c;
                 ++p;
             }
             g->nl_np[skip] = std::max(g->nl_np[skip], p);
@@ -591,8 +591,8 @@ rt_status rt_create_grid(const rt_grid_desc *desc, rt_grid_t *out)
     HIPCHK(hipMemcpy(g->mu.p, mu.data(), g->n_dir * 8, hipMemcpyHostToDevice));
     HIPCHK(g->span.ensure(g->n_dir * 4));
     HIPCHK(hipMemcpy(g->span.p, sp.data(), g->n_dir * 4, hipMemcpyHostToDevice));
-    HIPCHK(g->nl_planes.ensure(planes.size()));
-    HIPCHK(hipMemcpy(g->nl_planes.p, planes.data(), planes.size(), hipMemcpyHostToDevice));
+    HIPCHK(g->nl_planes.ensure(planes.size() * 4));
+    HIPCHK(hipMemcpy(g->nl_planes.p, planes.data(), planes.size() * 4, hipMemcpyHostToDevice));
 
     *out = g.release();
     clear_error();

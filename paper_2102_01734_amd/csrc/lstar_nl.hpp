@@ -36,14 +36,16 @@ struct StencilArgs {
     int skip_centre;           // 1: leave the centre component (the diagonal Lambda*) out
     // row-window kernel (used when dir_plane is set): per visit the row
     // relative to the lowest template row of its layer; per direction
-    // kPlaneStride bytes: [0, 27) component -> tile plane (-1: never added,
+    // kPlaneStride entries: [0, 27) component -> tile plane (-1: never added,
     // including the centre when skip_centre), [32, 32 + planes) plane ->
-    // component; planes: the largest plane count of any direction; rows:
-    // ray rows per workgroup (set by the launcher)
+    // component (32-bit entries: the kernel reads them with scalar loads);
+    // planes: the largest plane count of any direction; rows: ray rows per
+    // workgroup (set by the launcher)
     const int32_t *brow;
-    const int8_t *dir_plane;
+    const int32_t *dir_plane;
     int planes;
     int rows;
+    int fast_fix;  // 1: fixed-point values by one FMA (needs w_d <= 1/8, see fix52)
 };
 
 constexpr int kPlaneStride = 64;
@@ -68,6 +70,7 @@ struct SphereStencilArgs {
     int n_batch;
     unsigned long long *acc;      // [lambda][27][n_vox]
     int skip_centre;
+    int fast_fix;
 };
 hipError_t lstar_stencil_sphere_accumulate(const SphereStencilArgs &a, bool grid_double, bool geom_double,
                                            bool parabolic, hipStream_t st);

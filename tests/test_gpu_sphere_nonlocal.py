@@ -125,3 +125,24 @@ def test_sphere_nonlocal_arguments():
         with pytest.raises(rt.RtError) as e:
             rt.SphereGrid(4, 4, Np, 1.0, 2.0, 2, 4, "f64", 1, nonlocal_lstar=True, host_cache=kw.get("host_cache", False))
         assert e.value.status == rt.rt3d.RT_E_INVALID
+
+
+@pytest.mark.parametrize("method", ["jacobi", "gauss-seidel"])
+def test_sphere_nonlocal_graph_replay_equals_eager_bitwise(method):
+    """Plain non-local steps replayed from captured HIP graphs (stencil built
+    in the first, eager step) give bitwise the eager iterates."""
+    torch = torch_cuda()
+    case = sy.random_sphere(7, 6, 8, 4, 8, seed=72, dtype="f32", n_lambda=2, eps_dex=(-3, -1))
+    out = []
+    for use_graph in (False, True):
+        g = _grid(case)
+        st = g.new_state(*(to_dev(a, "f32") for a in (case.chi, case.eps, case.B, case.I_bc)))
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            for _ in range(9):
+                g.ali_step(st, g.opts(tol=1e-30, max_iter=1, use_graph=use_graph, os_sweeps=3, os_method=method),
+                           stream=s)
+        s.synchronize()
+        out.append(g.state_tensors(st)["J"].cpu().numpy())
+        g.close()
+    assert np.array_equal(out[0], out[1])
