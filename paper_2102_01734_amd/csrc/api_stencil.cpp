@@ -38,7 +38,6 @@ rt_status accumulate_stencil(rt_grid *g, const void *chi, int n_lambda, int nb, 
             a.n_batch = nb;
             a.acc = g->nl_acc.as<unsigned long long>();
             a.skip_centre = skip_centre ? 1 : 0;
-            a.fast_fix = g->n_dir >= 8 ? 1 : 0;
             HIPCHK(lstar_stencil_sphere_accumulate(a, g->dbl, g->sph_gdouble, g->para, st));
         }
         return RT_OK;
@@ -57,7 +56,6 @@ rt_status accumulate_stencil(rt_grid *g, const void *chi, int n_lambda, int nb, 
     a.lambda_of = lambda_of;
     a.acc = g->nl_acc.as<unsigned long long>();
     a.skip_centre = skip_centre ? 1 : 0;
-    a.fast_fix = g->n_dir >= 8 ? 1 : 0;  // every direction weight w_d <= 1/8
     if (g->nl_rows) {
         a.brow = g->brow.as<int32_t>();
         a.dir_plane = g->nl_planes.as<int32_t>() + (size_t)(skip_centre ? 1 : 0) * g->n_dir * kPlaneStride;

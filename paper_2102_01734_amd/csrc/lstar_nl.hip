@@ -51,19 +51,8 @@
 namespace rt3d {
 
 // One contribution w G in fixed point, round(w G 2^52) as a signed 64-bit
-// integer (ties to even).  fast: cw52 G + 1.5 2^52 by one FMA lands in
-// [2^52, 2^53) while |w G 2^52| < 2^51, where the double's mantissa holds
-// the integer itself (its high word offset by that of 1.5 2^52); that holds
-// for w <= 1/8 (w = w_d |mu_d| s on the box, |mu| s <= 1, or the sphere's
-// averaging weight, <= w_d) since |G| <= 2.  Else the library conversion.
-__device__ __forceinline__ long long fix52(double cw52, double G, bool fast)
-{
-    if (fast) {
-        const double y = __builtin_fma(cw52, G, 0x1.8p52);
-        return __double_as_longlong(y) - 0x4338000000000000LL;
-    }
-    return __double2ll_rn(cw52 * G);
-}
+// integer (ties to even).
+__device__ __forceinline__ long long fix52(double cw52, double G) { return __double2ll_rn(cw52 * G); }
 
 template <typename G, bool PARA>
 __global__ void __launch_bounds__(256) lstar_stencil_kernel(StencilArgs a)
@@ -93,7 +82,6 @@ __global__ void __launch_bounds__(256) lstar_stencil_kernel(StencilArgs a)
         return (int64_t)k * NxNy + (int64_t)y * Nx + x;
     };
     // adds w |mu| s_m G_j to component c_j of voxel v (j = -1..3)
-    const bool fast = a.fast_fix != 0;
     auto add = [&](int64_t v, double cw, uint32_t comps, const double (&Gv)[5]) {
         const double cw52 = cw * 0x1p52;
 #pragma unroll
@@ -101,7 +89,7 @@ __global__ void __launch_bounds__(256) lstar_stencil_kernel(StencilArgs a)
             if (!PARA && j == 0) continue;  // no downwind weight in the linear operator
             const uint32_t c = (comps >> (6 * j)) & 63u;
             if (c == kNoComp || (a.skip_centre && c == (uint32_t)kStencilCentre)) continue;
-            const long long f = fix52(cw52, Gv[j], fast);
+            const long long f = fix52(cw52, Gv[j]);
             if (f != 0) atomicAdd(&acc[(int64_t)c * a.n_vox + v], (unsigned long long)f);
         }
     };
@@ -189,7 +177,6 @@ __global__ void __launch_bounds__(1024) lstar_stencil_rows_kernel(StencilArgs a)
     const int32_t *__restrict__ brow = a.brow + vb;
     const int32_t *__restrict__ plane_of = a.dir_plane + (int64_t)d * kPlaneStride;
     const int32_t *__restrict__ comp_of = plane_of + 32;
-    const bool fast = a.fast_fix != 0;
 
     __shared__ int64_t coff[kStencil];  // plane -> offset of its component in the sums
     for (int i = tid; i < P * W * Nx; i += nthr) tile[i] = 0;
@@ -270,7 +257,7 @@ __global__ void __launch_bounds__(1024) lstar_stencil_rows_kernel(StencilArgs a)
             unsigned long long *plane = tile + p * W * Nx;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const long long f = fix52(cw52, Gv[r][j], fast);
+                const long long f = fix52(cw52, Gv[r][j]);
                 if (act[r] && f != 0) atomicAdd(&plane[word[r]], (unsigned long long)f);
             }
         }
@@ -498,7 +485,7 @@ __global__ void __launch_bounds__(256) lstar_stencil_sphere_kernel(SphereStencil
             if (dr < -1 || dr > 1 || dt < -1 || dt > 1 || dp > 1) continue;
             const int comp = (dp + 1) * 9 + (dt + 1) * 3 + (dr + 1);
             if (a.skip_centre && comp == kStencilCentre) continue;
-            const long long f = fix52(cw * 0x1p52, Gv[j], a.fast_fix != 0);
+            const long long f = fix52(cw * 0x1p52, Gv[j]);
             if (f != 0) atomicAdd(&acc[(int64_t)comp * a.n_vox + vv[1]], (unsigned long long)f);
         }
     };

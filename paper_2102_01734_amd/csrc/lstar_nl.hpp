@@ -45,7 +45,6 @@ struct StencilArgs {
     const int32_t *dir_plane;
     int planes;
     int rows;
-    int fast_fix;  // 1: fixed-point values by one FMA (needs w_d <= 1/8, see fix52)
 };
 
 constexpr int kPlaneStride = 64;
@@ -70,7 +69,6 @@ struct SphereStencilArgs {
     int n_batch;
     unsigned long long *acc;      // [lambda][27][n_vox]
     int skip_centre;
-    int fast_fix;
 };
 hipError_t lstar_stencil_sphere_accumulate(const SphereStencilArgs &a, bool grid_double, bool geom_double,
                                            bool parabolic, hipStream_t st);
