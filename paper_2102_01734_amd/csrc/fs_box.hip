@@ -75,6 +75,24 @@ __device__ __forceinline__ Pair<double> ld_pair<double>(__amdgpu_buffer_rsrc_t r
 // ---------------------------------------------------------------------------
 // the sweep kernel
 // ---------------------------------------------------------------------------
+// Fused multiply-add in the recurrence type.
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// A value that is the same in every lane, kept in a scalar register: the
+// weight of a visit, formed by vector instructions from scalar inputs, then
+// serves every ray of the thread as a scalar operand.  Double values stay
+// as they are.
+__device__ __forceinline__ float uniform(float v)
+{
+    // by an explicit v_readfirstlane: the builtin would be moved ahead of the
+    // conversion to single precision, which is then redone per ray
+    float s;
+    asm("v_readfirstlane_b32 %0, %1" : "=s"(s) : "v"(v));
+    return s;
+}
+__device__ __forceinline__ double uniform(double v) { return v; }
+
 template <typename T, int LB, int R, bool WJ, bool WL, bool PARA, int OCC, bool BAND>
 __global__ void __launch_bounds__(LB) __attribute__((amdgpu_waves_per_eu(OCC * LB / 256 > 0 ? OCC * LB / 256 : 1)))
 fs_box_kernel(FsBoxArgs a)
@@ -293,7 +311,7 @@ fs_box_kernel(FsBoxArgs a)
             for (int j = 0; j < R; ++j) {
                 gprev[j] = T(0);
                 const Pair<T> f0 = ld_pair<T>(rf, vb[j], g_c);
-                const double t0 = seg_depth_pos((double)f0.chi, s_c);
+                const double t0 = seg_depth((double)f0.chi, s_c);
                 T ex, e0;
                 entry_weights<T>(0.5 * t0, ex, e0);
                 I[j] = WJ ? Ibc * ex + f0.S * e0 : T(0);
@@ -306,7 +324,7 @@ fs_box_kernel(FsBoxArgs a)
                     Sp[j] = f0.S;
                     Sc[j] = f1.S;
                     Xc[j] = f1.chi;
-                    Dc[j] = half_sum(t0, seg_depth_pos((double)f1.chi, s_n));
+                    Dc[j] = step_depth(t0, seg_depth((double)f1.chi, s_n));
                 }
             }
             __syncthreads();
@@ -317,7 +335,7 @@ fs_box_kernel(FsBoxArgs a)
         // has no downwind neighbour
         auto step = [&](auto last_tag) {
             constexpr bool LAST = decltype(last_tag)::value;
-            const T cw = T(wmu * s_c);
+            const T cw = uniform(T(wmu * s_c));
             const TileStep ts = tile_step(w_c, r_c);
             // software pipeline over the rays of this thread: the loads of
             // ray j+1 are in flight while ray j is computed
@@ -341,17 +359,23 @@ fs_box_kernel(FsBoxArgs a)
                     D = Dc[j];
                     S_prev = Sp[j];
                     S_cur = Sc[j];
-                    // the current depth unclamped: Dp >= kMinStep / 2 all the same
-                    if (!LAST) Dp = half_sum(seg_depth((double)Xc[j], s_c), seg_depth_pos((double)fn.chi, s_n));
+                    if (!LAST) Dp = step_depth(seg_depth((double)Xc[j], s_c), seg_depth((double)fn.chi, s_n));
                 } else {
-                    const double tc = seg_depth_pos((double)fc.chi, s_c);
-                    D = half_sum(seg_depth_pos((double)fp.chi, s_p), tc);
-                    if (!LAST) Dp = half_sum(tc, seg_depth_pos((double)fn.chi, s_n));
+                    const double tc = seg_depth((double)fc.chi, s_c);
+                    D = step_depth(seg_depth((double)fp.chi, s_p), tc);
+                    if (!LAST) Dp = step_depth(tc, seg_depth((double)fn.chi, s_n));
                     S_prev = fp.S;
                     S_cur = fc.S;
                 }
                 const PointW<T> pw = point_weights_pos<T, LAST>(D, Dp);
-                if (WJ) I[j] = I[j] * pw.ex + pw.a * S_prev + pw.b * S_cur + (LAST ? T(0) : pw.g * fn.S);
+                if (WJ) {
+                    // accumulated in place: I ex, then the three source terms
+                    T Ij = I[j] * pw.ex;
+                    Ij = fma_t(pw.a, S_prev, Ij);
+                    Ij = fma_t(pw.b, S_cur, Ij);
+                    if (!LAST) Ij = fma_t(pw.g, fn.S, Ij);
+                    I[j] = Ij;
+                }
                 const uint32_t ad = tile_addr(j, ts);
                 const T cj = ray_weight(j, cw);
                 if (WJ) tile_add(tJb, ad, cj * I[j]);

@@ -12,6 +12,17 @@
 
 namespace rt3d {
 
+// a b + c by the three-address v_fma_f64 with every operand in a vector
+// register: the compiler's two-address v_fmac form would first copy a
+// constant addend (a polynomial coefficient held in a register) into the
+// destination at every use.
+__device__ __forceinline__ double fma3(double a, double b, double c)
+{
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+
 __device__ __forceinline__ double seg_depth(double chi, double s)
 {
 #pragma clang fp contract(off)
@@ -38,45 +49,22 @@ __device__ __forceinline__ double rcp_f64(double x)
     return __builtin_fma(r, e, r);
 }
 
-// exp(-D) for 1/4 <= D, with the Cody-Waite argument reduction: x = -D =
-// n ln2 + r, |r| <= ln2/2, where n ln2 is subtracted in two parts (ln2 split
-// into a high part with trailing zero bits, so that n times it is exact, and
-// the low remainder; the split of the fdlibm exponential), exp(r) by its
-// degree-12 Taylor polynomial for double results (for single-precision ones,
-// see below), scaled by 2^n.  D is clamped at 745, where the result is
-// already below the smallest subnormal.
-template <bool FULL>
+// exp(-D) for 1/4 <= D, double results: the Cody-Waite argument reduction
+// x = -D = n ln2 + r, |r| <= ln2/2, where n ln2 is subtracted in two parts
+// (ln2 split into a high part with trailing zero bits, so that n times it is
+// exact, and the low remainder; the split of the fdlibm exponential), exp(r)
+// by its degree-12 Taylor polynomial, scaled by 2^n.  D is clamped at 745,
+// where the result is already below the smallest subnormal.
 __device__ __forceinline__ double exp_neg(double D)
 {
     const double x = -(D < 745.0 ? D : 745.0);
     const double n = __builtin_rint(x * 1.4426950408889634);
     double r = __builtin_fma(-n, 6.93147180369123816490e-01, x);
     r = __builtin_fma(-n, 1.90821492927058770002e-10, r);
-    double p;
-    if (!FULL) {
-        // single-precision results: exp(r) = exp(r/16)^16, with exp(r/16)
-        // (|r/16| <= 0.0217) from its degree-6 Taylor polynomial (truncation
-        // below 1e-14 relative after the squarings, rounding ~3e-15); fewer
-        // non-trivial constants than the degree-12 polynomial in r
-        const double s = __builtin_ldexp(r, -4);
-        p = __builtin_fma(s, 1.0 / 720.0, 1.0 / 120.0);
-        p = __builtin_fma(p, s, 1.0 / 24.0);
-        p = __builtin_fma(p, s, 1.0 / 6.0);
-        p = __builtin_fma(p, s, 0.5);
-        p = __builtin_fma(p, s, 1.0);
-        p = __builtin_fma(p, s, 1.0);
-        p = p * p;
-        p = p * p;
-        p = p * p;
-        p = p * p;
-        return __builtin_ldexp(p, (int)n);
-    }
-    {
-        p = 1.0 / 479001600.0;
-        p = __builtin_fma(p, r, 1.0 / 39916800.0);
-        p = __builtin_fma(p, r, 1.0 / 3628800.0);
-        p = __builtin_fma(p, r, 1.0 / 362880.0);
-    }
+    double p = 1.0 / 479001600.0;
+    p = __builtin_fma(p, r, 1.0 / 39916800.0);
+    p = __builtin_fma(p, r, 1.0 / 3628800.0);
+    p = __builtin_fma(p, r, 1.0 / 362880.0);
     p = __builtin_fma(p, r, 1.0 / 40320.0);
     p = __builtin_fma(p, r, 1.0 / 5040.0);
     p = __builtin_fma(p, r, 1.0 / 720.0);
@@ -89,28 +77,68 @@ __device__ __forceinline__ double exp_neg(double D)
     return __builtin_ldexp(p, (int)n);
 }
 
+// Attenuation moments for single-precision results, one polynomial for every
+// step D > 0 (see kernel_moments for the definitions).  x = -min(D, 745) =
+// n ln2 + r with n = rint(x / ln2) and |r| <= ln2/2; the reduction takes one
+// FMA with ln2 rounded to double, whose error (|n| <= 1075 times 2.3e-17)
+// stays below 3e-14.  The tail u = e^r - 1 - r = r^2 (1/2 + r P(r)), with
+// P(r) = sum_{j>=0} r^j/(j+3)! from its degree-7 Taylor polynomial (relative
+// error below 4e-11 on |r| <= ln2/2).  Where n = 0 (D below ln2/2) r is -D
+// exactly and the moments follow from u with no cancellation: e1 = u,
+// e0 = D - u, ex = 1 - e0, e2 = D^2 - 2 e1 = -2 r^3 P.  Elsewhere
+// ex = 2^n (1 + r + u) and the closed forms below, which lose at most about
+// five bits to cancellation from D = ln2/2 up.
+__device__ __forceinline__ void moments_single(double D, double &ex, double &e0, double &e1, double &e2)
+{
+    // x = max(-D, -745) by one instruction (the library minimum would first
+    // quiet signalling NaNs, which arithmetic never produces); a NaN step
+    // gives a finite x, and e1, e2 keep the NaN
+    double x;
+    asm("v_max_f64 %0, -%1, %2" : "=v"(x) : "v"(D), "s"(-745.0));
+    const double n = __builtin_rint(x * 1.4426950408889634);
+    const double r = __builtin_fma(-n, 0.6931471805599453, x);
+    double P = fma3(1.0 / 3628800.0, r, 1.0 / 362880.0);  // 1/10!, 1/9!
+    P = fma3(P, r, 1.0 / 40320.0);                        // 1/8!
+    P = fma3(P, r, 1.0 / 5040.0);                         // 1/7!
+    P = fma3(P, r, 1.0 / 720.0);                          // 1/6!
+    P = fma3(P, r, 1.0 / 120.0);                          // 1/5!
+    P = fma3(P, r, 1.0 / 24.0);                           // 1/4!
+    P = fma3(P, r, 1.0 / 6.0);                            // 1/3!
+    const double r2 = r * r;
+    const double u = r2 * __builtin_fma(r, P, 0.5);
+    if (n == 0.0) {
+        e1 = u;
+        e0 = D - u;
+        ex = 1.0 - e0;
+        e2 = (-2.0 * r2) * (r * P);
+    } else {
+        ex = __builtin_ldexp(1.0 + (r + u), (int)n);
+        e0 = 1.0 - ex;
+        e1 = D - e0;
+        e2 = __builtin_fma(D, D, -2.0 * e1);
+    }
+}
+
 // Attenuation moments over an optical step D > 0:
 //   ex = exp(-D), e0 = 1 - ex, e1 = D - e0, e2 = D^2 - 2 e1.
-// Below D = 1/4, e2 comes from its Taylor series 2 D^3 sum_j (-D)^j/(j+3)!
-// (12 terms for double results; 7 for single-precision ones, whose first
-// omitted term is below 1e-10 of e2 at D = 1/4), and e1, e0, ex follow from
-// it without cancellation; from 1/4 up the closed forms are used.  The series
-// and the exponential are separate branches (a wave whose steps straddle 1/4
-// runs both).
+// Double results (FULL): below D = 1/4, e2 comes from its 12-term Taylor
+// series 2 D^3 sum_j (-D)^j/(j+3)! and e1, e0, ex follow from it without
+// cancellation; from 1/4 up the closed forms are used (separate branches: a
+// wave whose steps straddle 1/4 runs both).  Single-precision results take
+// moments_single, one path for all D.
 template <bool FULL>
 __device__ __forceinline__ void kernel_moments(double D, double &ex, double &e0, double &e1, double &e2)
 {
-    double p;
-    if (FULL) {
-        p = 1.0 / 87178291200.0;                       // 1/14!
-        p = __builtin_fma(-D, p, 1.0 / 6227020800.0);  // 1/13!
-        p = __builtin_fma(-D, p, 1.0 / 479001600.0);   // 1/12!
-        p = __builtin_fma(-D, p, 1.0 / 39916800.0);    // 1/11!
-        p = __builtin_fma(-D, p, 1.0 / 3628800.0);     // 1/10!
-        p = __builtin_fma(-D, p, 1.0 / 362880.0);      // 1/9!
-    } else {
-        p = 1.0 / 362880.0;                            // 1/9!
+    if constexpr (!FULL) {
+        moments_single(D, ex, e0, e1, e2);
+        return;
     }
+    double p = 1.0 / 87178291200.0;                // 1/14!
+    p = __builtin_fma(-D, p, 1.0 / 6227020800.0);  // 1/13!
+    p = __builtin_fma(-D, p, 1.0 / 479001600.0);   // 1/12!
+    p = __builtin_fma(-D, p, 1.0 / 39916800.0);    // 1/11!
+    p = __builtin_fma(-D, p, 1.0 / 3628800.0);     // 1/10!
+    p = __builtin_fma(-D, p, 1.0 / 362880.0);      // 1/9!
     p = __builtin_fma(-D, p, 1.0 / 40320.0);       // 1/8!
     p = __builtin_fma(-D, p, 1.0 / 5040.0);        // 1/7!
     p = __builtin_fma(-D, p, 1.0 / 720.0);         // 1/6!
@@ -125,7 +153,7 @@ __device__ __forceinline__ void kernel_moments(double D, double &ex, double &e0,
         ex = 1.0 - e0;
         return;
     }
-    ex = exp_neg<FULL>(D);
+    ex = exp_neg(D);
     e0 = 1.0 - ex;
     e1 = D - e0;
     e2 = __builtin_fma(D, D, -2.0 * e1);
@@ -182,9 +210,9 @@ __device__ __forceinline__ PointW<T> point_weights(double D, double Dp, bool las
     return w;
 }
 
-// point_weights for optical steps that are already at least kMinStep / 2
-// (optical depths clamped at kMinStep where they are formed): no clamping
-// here.  LAST: the final point of a ray (linear weights; Dp is not read).
+// point_weights for optical steps that are already at least kMinStep (formed
+// by step_depth): no clamping here.  LAST: the final point of a ray (linear
+// weights; Dp is not read).
 template <typename T, bool LAST>
 __device__ __forceinline__ PointW<T> point_weights_pos(double D, double Dp)
 {
@@ -194,8 +222,10 @@ __device__ __forceinline__ PointW<T> point_weights_pos(double D, double Dp)
     const double Dq = LAST ? D : Dp;
     const double Ds = D + Dq;
     const double r = rcp_f64<FULL>(D * Dq * Ds);
-    const double bl = e1 * ((Dq * Ds) * r);  // e1 / D
-    const bool lin = LAST || (Dp < 0.5 * D) || (Dp * e0 <= __builtin_fma(D, e1, -e2));
+    const double q = Ds * r;                 // 1 / (D Dq)
+    const double bl = e1 * (Dq * q);         // e1 / D
+    const double h = __builtin_fma(D, e1, -e2);  // D e1 - e2
+    const bool lin = LAST || (Dp < 0.5 * D) || (Dp * e0 <= h);
     PointW<T> w;
     w.ex = T(ex);
     w.dlin = T(bl);
@@ -205,8 +235,8 @@ __device__ __forceinline__ PointW<T> point_weights_pos(double D, double Dp)
         w.a = T(e0 - bl);
         return w;
     }
-    const double bp = __builtin_fma(Ds, e1, -e2) * (Ds * r);
-    const double gp = (e2 - D * e1) * (D * r);
+    const double bp = __builtin_fma(Ds, e1, -e2) * q;
+    const double gp = h * (-D * r);
     const double b = lin ? bl : bp;
     const double g = lin ? 0.0 : gp;
     w.b = T(b);
@@ -215,13 +245,21 @@ __device__ __forceinline__ PointW<T> point_weights_pos(double D, double Dp)
     return w;
 }
 
-// Optical depth chi s of a segment, at least kMinStep: a vacuum segment
-// (Listing 1 step 4a) then contributes a step of 1e-100 instead of 0, which
-// changes the intensity by less than 1e-100 S; NaN propagates.
-__device__ __forceinline__ double seg_depth_pos(double chi, double s)
+// Optical step between two points from their optical depths: D = (ta + tb)/2
+// + kMinStep by one FMA (the half sum is exact, so the sum rounds back to it
+// for every D above 2^-276; a vacuum step, ta = tb = 0, becomes kMinStep, and
+// so the shared reciprocal of the weights stays finite).  NaN and Inf
+// propagate.  Depths ta, tb >= 0 (opacities are non-negative).
+__device__ __forceinline__ double step_depth(double ta, double tb)
 {
-    const double t = seg_depth(chi, s);
-    return t < kMinStep ? kMinStep : t;
+    double sum;
+    {
+#pragma clang fp contract(off)
+        sum = ta + tb;
+    }
+    double d;
+    asm("v_fma_f64 %0, %1, 0.5, %2" : "=v"(d) : "v"(sum), "s"(kMinStep));
+    return d;
 }
 
 // Entry half-segment: constant S from the entry point to the first point.

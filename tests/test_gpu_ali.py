@@ -184,11 +184,15 @@ def test_batched_wavelengths_converge_independently(orc):
 def test_pure_scattering_slab_reaches_fixed_point(orc, prec):
     """eps = 0 (pure scattering) on a stratified slab (tau 1e-4..1e2) lit from its
     thin top: the solve converges to the layer reduction's direct solution
-    (single precision: within 1e-5 through the double anchors)."""
+    (single precision: within 1e-5 through the double anchors).  The error of an
+    iteration stopped at relative change tol is about tol / (1 - rho), rho the
+    contraction of the accelerated iteration, close to 1 here: stopped at 1e-11
+    the double-precision error measured 1.2e-9 to 1.6e-9 (at 1e-10, 7e-9 to 1.3e-8
+    depending on where the Ng steps fall), so 1e-8 keeps a margin of six."""
     import dataclasses
     case = sy.box_stratified(N=9, Nz=33, eps=0.0, dtype=prec, tau_max=1e2)
     case = dataclasses.replace(case, I_bc=np.array([[1.0, 0.0]]))
-    r = gpu_solve(case, tol=1e-10, max_iter=4000)
+    r = gpu_solve(case, tol=1e-11, max_iter=4000)
     prob = orc.Plane1DProblem(case.chi[0, :, 0, 0], case.eps[0, :, 0, 0], 1.0, 1.0, 0.0, case.n_mu, case.n_phi)
     exact = orc.direct(prob)
     Jg = r["J"][0]
