@@ -82,8 +82,8 @@ __device__ __forceinline__ double exp_neg(double D)
 // n ln2 + r with n = rint(x / ln2) and |r| <= ln2/2; the reduction takes one
 // FMA with ln2 rounded to double, whose error (|n| <= 1075 times 2.3e-17)
 // stays below 3e-14.  The tail u = e^r - 1 - r = r^2 (1/2 + r P(r)), with
-// P(r) = sum_{j>=0} r^j/(j+3)! from its degree-7 Taylor polynomial (relative
-// error below 4e-11 on |r| <= ln2/2).  Where n = 0 (D below ln2/2) r is -D
+// P(r) = sum_{j>=0} r^j/(j+3)! from its degree-6 interpolant at the Chebyshev
+// nodes of |r| <= ln2/2 (relative error 1.6e-11 there).  Where n = 0 (D below ln2/2) r is -D
 // exactly and the moments follow from u with no cancellation: e1 = u,
 // e0 = D - u, ex = 1 - e0, e2 = D^2 - 2 e1 = -2 r^3 P.  Elsewhere
 // ex = 2^n (1 + r + u) and the closed forms below, which lose at most about
@@ -97,13 +97,13 @@ __device__ __forceinline__ void moments_single(double D, double &ex, double &e0,
     asm("v_max_f64 %0, -%1, %2" : "=v"(x) : "v"(D), "s"(-745.0));
     const double n = __builtin_rint(x * 1.4426950408889634);
     const double r = __builtin_fma(-n, 0.6931471805599453, x);
-    double P = fma3(1.0 / 3628800.0, r, 1.0 / 362880.0);  // 1/10!, 1/9!
-    P = fma3(P, r, 1.0 / 40320.0);                        // 1/8!
-    P = fma3(P, r, 1.0 / 5040.0);                         // 1/7!
-    P = fma3(P, r, 1.0 / 720.0);                          // 1/6!
-    P = fma3(P, r, 1.0 / 120.0);                          // 1/5!
-    P = fma3(P, r, 1.0 / 24.0);                           // 1/4!
-    P = fma3(P, r, 1.0 / 6.0);                            // 1/3!
+    // degree-6 Chebyshev interpolant of P on |r| <= ln2/2 (gen_moment_poly.py)
+    double P = fma3(2.761004197490652e-06, r, 2.485957814859904e-05);
+    P = fma3(P, r, 0.00019841238150245533);
+    P = fma3(P, r, 0.0013888854049701165);
+    P = fma3(P, r, 0.008333333338101687);
+    P = fma3(P, r, 0.0416666667189806);
+    P = fma3(P, r, 0.16666666666666652);
     const double r2 = r * r;
     const double u = r2 * __builtin_fma(r, P, 0.5);
     if (n == 0.0) {
