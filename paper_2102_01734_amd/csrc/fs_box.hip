@@ -85,10 +85,13 @@ __device__ __forceinline__ double fma_t(double a, double b, double c) { return _
 // as they are.
 __device__ __forceinline__ float uniform(float v)
 {
-    // by an explicit v_readfirstlane: the builtin would be moved ahead of the
-    // conversion to single precision, which is then redone per ray
+    // by an explicit v_readfirstlane (the builtin would be moved ahead of the
+    // conversion to single precision, which is then redone per ray).  A
+    // readlane of a VGPR that the previous VALU instruction wrote needs wait
+    // states in between, which the compiler inserts only around its own
+    // instructions: the s_nop gives them here.
     float s;
-    asm("v_readfirstlane_b32 %0, %1" : "=s"(s) : "v"(v));
+    asm("s_nop 1\n\tv_readfirstlane_b32 %0, %1" : "=s"(s) : "v"(v));
     return s;
 }
 __device__ __forceinline__ double uniform(double v) { return v; }

@@ -77,6 +77,30 @@ __device__ __forceinline__ double exp_neg(double D)
     return __builtin_ldexp(p, (int)n);
 }
 
+// exp(-D) for 1/4 <= D and single-precision results (the split moments
+// below): the reduction of exp_neg, then exp(r) = exp(r/16)^16 with exp(r/16)
+// (|r/16| <= 0.0217) from its degree-6 Taylor polynomial (truncation below
+// 1e-14 relative after the squarings, rounding ~3e-15).
+__device__ __forceinline__ double exp_neg_single(double D)
+{
+    const double x = -(D < 745.0 ? D : 745.0);
+    const double n = __builtin_rint(x * 1.4426950408889634);
+    double r = __builtin_fma(-n, 6.93147180369123816490e-01, x);
+    r = __builtin_fma(-n, 1.90821492927058770002e-10, r);
+    const double s = __builtin_ldexp(r, -4);
+    double p = __builtin_fma(s, 1.0 / 720.0, 1.0 / 120.0);
+    p = __builtin_fma(p, s, 1.0 / 24.0);
+    p = __builtin_fma(p, s, 1.0 / 6.0);
+    p = __builtin_fma(p, s, 0.5);
+    p = __builtin_fma(p, s, 1.0);
+    p = __builtin_fma(p, s, 1.0);
+    p = p * p;
+    p = p * p;
+    p = p * p;
+    p = p * p;
+    return __builtin_ldexp(p, (int)n);
+}
+
 // Attenuation moments for single-precision results, one polynomial for every
 // step D > 0 (see kernel_moments for the definitions).  x = -min(D, 745) =
 // n ln2 + r with n = rint(x / ln2) and |r| <= ln2/2; the reduction takes one
@@ -105,14 +129,15 @@ __device__ __forceinline__ void moments_single(double D, double &ex, double &e0,
     P = fma3(P, r, 0.0416666667189806);
     P = fma3(P, r, 0.16666666666666652);
     const double r2 = r * r;
-    const double u = r2 * __builtin_fma(r, P, 0.5);
+    const double h = __builtin_fma(r, P, 0.5);  // u = r^2 h
     if (n == 0.0) {
+        const double u = r2 * h;
         e1 = u;
         e0 = D - u;
         ex = 1.0 - e0;
         e2 = (-2.0 * r2) * (r * P);
     } else {
-        ex = __builtin_ldexp(1.0 + (r + u), (int)n);
+        ex = __builtin_ldexp(__builtin_fma(r2, h, 1.0 + r), (int)n);
         e0 = 1.0 - ex;
         e1 = D - e0;
         e2 = __builtin_fma(D, D, -2.0 * e1);
@@ -125,20 +150,28 @@ __device__ __forceinline__ void moments_single(double D, double &ex, double &e0,
 // series 2 D^3 sum_j (-D)^j/(j+3)! and e1, e0, ex follow from it without
 // cancellation; from 1/4 up the closed forms are used (separate branches: a
 // wave whose steps straddle 1/4 runs both).  Single-precision results take
-// moments_single, one path for all D.
-template <bool FULL>
+// moments_single, one path for all D, or with SPLIT the same two branches
+// with a 7-term series (first omitted term below 1e-10 of e2 at D = 1/4) and
+// exp_neg_single: fewer registers, cheaper where the steps of a wave seldom
+// straddle 1/4 (the spherical sweep).
+template <bool FULL, bool SPLIT = false>
 __device__ __forceinline__ void kernel_moments(double D, double &ex, double &e0, double &e1, double &e2)
 {
-    if constexpr (!FULL) {
+    if constexpr (!FULL && !SPLIT) {
         moments_single(D, ex, e0, e1, e2);
         return;
     }
-    double p = 1.0 / 87178291200.0;                // 1/14!
-    p = __builtin_fma(-D, p, 1.0 / 6227020800.0);  // 1/13!
-    p = __builtin_fma(-D, p, 1.0 / 479001600.0);   // 1/12!
-    p = __builtin_fma(-D, p, 1.0 / 39916800.0);    // 1/11!
-    p = __builtin_fma(-D, p, 1.0 / 3628800.0);     // 1/10!
-    p = __builtin_fma(-D, p, 1.0 / 362880.0);      // 1/9!
+    double p;
+    if constexpr (FULL) {
+        p = 1.0 / 87178291200.0;                       // 1/14!
+        p = __builtin_fma(-D, p, 1.0 / 6227020800.0);  // 1/13!
+        p = __builtin_fma(-D, p, 1.0 / 479001600.0);   // 1/12!
+        p = __builtin_fma(-D, p, 1.0 / 39916800.0);    // 1/11!
+        p = __builtin_fma(-D, p, 1.0 / 3628800.0);     // 1/10!
+        p = __builtin_fma(-D, p, 1.0 / 362880.0);      // 1/9!
+    } else {
+        p = 1.0 / 362880.0;                            // 1/9!
+    }
     p = __builtin_fma(-D, p, 1.0 / 40320.0);       // 1/8!
     p = __builtin_fma(-D, p, 1.0 / 5040.0);        // 1/7!
     p = __builtin_fma(-D, p, 1.0 / 720.0);         // 1/6!
@@ -153,7 +186,7 @@ __device__ __forceinline__ void kernel_moments(double D, double &ex, double &e0,
         ex = 1.0 - e0;
         return;
     }
-    ex = exp_neg(D);
+    ex = FULL ? exp_neg(D) : exp_neg_single(D);
     e0 = 1.0 - ex;
     e1 = D - e0;
     e2 = __builtin_fma(D, D, -2.0 * e1);
@@ -180,13 +213,14 @@ struct PointW {
 };
 
 // FULL: double-accurate moments (the default for double results); false: the
-// shorter forms that suffice for single-precision results.
-template <typename T, bool FULL = sizeof(T) == 8>
+// shorter forms that suffice for single-precision results (SPLIT: their
+// two-branch variant).
+template <typename T, bool FULL = sizeof(T) == 8, bool SPLIT = false>
 __device__ __forceinline__ PointW<T> point_weights(double D, double Dp, bool last)
 {
     const double Dv = D < kMinStep ? kMinStep : D;  // NaN propagates
     double ex, e0, e1, e2;
-    kernel_moments<FULL>(Dv, ex, e0, e1, e2);
+    kernel_moments<FULL, SPLIT>(Dv, ex, e0, e1, e2);
     const double Dq = Dp < kMinStep ? Dv : Dp;   // keeps r finite on last/vacuum points; NaN propagates
     const double Ds = Dv + Dq;
     const double r = rcp_f64<FULL>(Dv * Dq * Ds);
@@ -263,12 +297,12 @@ __device__ __forceinline__ double step_depth(double ta, double tb)
 }
 
 // Entry half-segment: constant S from the entry point to the first point.
-template <typename T>
+template <typename T, bool SPLIT = false>
 __device__ __forceinline__ void entry_weights(double D0, T &ex_t, T &e0_t)
 {
     constexpr bool FULL = sizeof(T) == 8;
     double ex, e0, e1, e2;
-    kernel_moments<FULL>(D0 < kMinStep ? kMinStep : D0, ex, e0, e1, e2);
+    kernel_moments<FULL, SPLIT>(D0 < kMinStep ? kMinStep : D0, ex, e0, e1, e2);
     ex_t = T(ex);
     e0_t = T(e0);
 }

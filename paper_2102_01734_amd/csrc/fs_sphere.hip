@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(256) fs_sphere_kernel(FsSphereArgs a)
     T I;
     {
         T ex, e0w;
-        entry_weights<T>(0.5 * tp, ex, e0w);
+        entry_weights<T, true>(0.5 * tp, ex, e0w);
         I = I0 * ex + fp.S * e0w;
         const T w0 = T(wv[e0]);
         if (WJ) oJ[e0 * nb] = w0 * I;
@@ -101,7 +101,7 @@ __global__ void __launch_bounds__(256) fs_sphere_kernel(FsSphereArgs a)
         }
         const double D = half_sum(tp, tc);
         const double Dp = last ? 0.0 : half_sum(tc, tn);
-        const PointW<T> pw = point_weights<T>(D, Dp, last);
+        const PointW<T> pw = point_weights<T, sizeof(T) == 8, true>(D, Dp, last);
         const T wk = T(wv[e]);
         if (WJ) {
             I = I * pw.ex + pw.a * fp.S + pw.b * fc.S + (last ? T(0) : pw.g * fn.S);

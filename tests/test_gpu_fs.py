@@ -318,3 +318,47 @@ def test_batched_64_wavelengths_at_the_timed_shape(orc):
         Jg = J[l].ravel()[vox]
         print(f"  wavelength {l}: max rel err J {float(np.max(np.abs(Jg - Jo) / np.abs(Jo))):.2e}")
         np.testing.assert_allclose(Jg, Jo, rtol=5e-6, atol=1e-7 * np.abs(Jo).max())
+
+
+def _compiled_shapes():
+    """(threads, rays, band) of every compiled single-output sweep shape, read from the kernel source."""
+    import os
+    import re
+    src = open(os.path.join(os.path.dirname(__file__), "..", "paper_2102_01734_amd", "csrc", "fs_box.hip")).read()
+    out = []
+    for macro, band in (("RT_FS_SHAPES_FULL", False), ("RT_FS_SHAPES_TUNE", False),
+                        ("RT_FS_SHAPES_BAND_FULL", True), ("RT_FS_SHAPES_BAND_TUNE", True)):
+        text = re.search(r"#define " + macro + r"\(X\)(.*?)(?=\n#define|\nstatic const)", src, re.S).group(1)
+        for lb, r, _ in re.findall(r"X\((\d+),\s*(\d+),\s*(\d+)\)", text):
+            out.append((int(lb), int(r), band))
+    return sorted(set(out))
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("dims", [(37, 29, 3), (97, 89, 3), (160, 158, 3)])
+def test_every_compiled_shape_matches_oracle(orc, dims):
+    """Every compiled launch shape that can hold a direction's rays on this grid
+    (single precision, J only), and the default J + Lambda* sweep, give the
+    oracle's results: each kernel instantiation is run, not only the shapes the
+    autotuner or the defaults pick."""
+    import paper_2102_01734_amd as rt
+    Nx, Ny, Nz = dims
+    case = sy.random_box(Nx, Ny, Nz, 2, 4, seed=97, dtype="f32")
+    S = sy.random_source(case.chi.shape, seed=98, dtype="f32")
+    Jo, Lo = _oracle_fs(orc, case, S, "linear")
+    g = make_grid(case)
+    J, L = gpu_fs(case, S, grid=g)
+    np.testing.assert_allclose(J, Jo, rtol=5e-6, atol=1e-7 * np.abs(Jo).max())
+    np.testing.assert_allclose(L, Lo, rtol=5e-6, atol=1e-8)
+    ran = 0
+    for threads, rays, band in _compiled_shapes():
+        try:
+            g.set_launch_shape(threads, rays, band=band)
+        except rt.RtError:
+            continue  # this grid's rays do not fit the shape (or layer tiles where bands are needed)
+        print(f"shape {threads} x {rays} {'band' if band else 'layer'}", flush=True)
+        J1, _ = gpu_fs(case, S, grid=g, want_lstar=False)
+        np.testing.assert_allclose(J1, Jo, rtol=5e-6, atol=1e-7 * np.abs(Jo).max())
+        ran += 1
+    g.close()
+    assert ran >= 4

@@ -64,14 +64,15 @@ def _moments_single(D, c):
     for k in (4, 3, 2, 1, 0):
         P = _fma(P, r, c[k])
     r2 = r * r
-    u = r2 * _fma(r, P, 0.5)
+    h = _fma(r, P, 0.5)
     if n == 0.0:
+        u = r2 * h
         e1 = u
         e0 = D - u
         ex = 1.0 - e0
         e2 = (-2.0 * r2) * (r * P)
     else:
-        ex = math.ldexp(1.0 + (r + u), int(n))
+        ex = math.ldexp(_fma(r2, h, 1.0 + r), int(n))
         e0 = 1.0 - ex
         e1 = D - e0
         e2 = _fma(D, D, -2.0 * e1)
