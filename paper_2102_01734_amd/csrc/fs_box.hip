@@ -370,7 +370,7 @@ fs_box_kernel(FsBoxArgs a)
                     S_prev = fp.S;
                     S_cur = fc.S;
                 }
-                const PointW<T> pw = point_weights_pos<T, LAST>(D, Dp);
+                const PointW<T> pw = point_weights_pos<T, LAST, WL && !PARA>(D, Dp);
                 if (WJ) {
                     // accumulated in place: I ex, then the three source terms
                     T Ij = I[j] * pw.ex;

@@ -246,40 +246,38 @@ __device__ __forceinline__ PointW<T> point_weights(double D, double Dp, bool las
 
 // point_weights for optical steps that are already at least kMinStep (formed
 // by step_depth): no clamping here.  LAST: the final point of a ray (linear
-// weights; Dp is not read).
-template <typename T, bool LAST>
+// weights; Dp is not read).  DLIN: also the linear operator's diagonal e1/D.
+// The linear weights are the parabolic ones in the limit of an infinite
+// downwind step, so a point that takes them is evaluated with Dp replaced by
+// 2^300: beta = e1/D (1 + O(D/2^300)) and gamma = -(D e1 - e2)/(2^300 (D +
+// 2^300)), far below the rounding of either for any physical step (gamma is
+// then zero in single precision), with one select in place of one per
+// weight.  D D'(D + D') stays finite for every D below 2^424.
+template <typename T, bool LAST, bool DLIN = true>
 __device__ __forceinline__ PointW<T> point_weights_pos(double D, double Dp)
 {
     constexpr bool FULL = sizeof(T) == 8;
     double ex, e0, e1, e2;
     kernel_moments<FULL>(D, ex, e0, e1, e2);
-    const double Dq = LAST ? D : Dp;
+    const double h = __builtin_fma(D, e1, -e2);  // D e1 - e2
+    const bool lin = LAST || (Dp < 0.5 * D) || (Dp * e0 <= h);
+    const double Dq = lin ? 0x1p300 : Dp;
     const double Ds = D + Dq;
     // single-precision results take the hardware estimate as it is: its relative
     // error, at most 4.6e-8 (2^-24.4) over a million random arguments, is below
     // the rounding of the weights to single precision, and a = e0 - b - g keeps
     // the three weights summing to e0 whatever the error of b and g
     const double r = FULL ? rcp_f64<true>(D * Dq * Ds) : __builtin_amdgcn_rcp(D * Dq * Ds);
-    const double q = Ds * r;                 // 1 / (D Dq)
-    const double bl = e1 * (Dq * q);         // e1 / D
-    const double h = __builtin_fma(D, e1, -e2);  // D e1 - e2
-    const bool lin = LAST || (Dp < 0.5 * D) || (Dp * e0 <= h);
+    const double q = Ds * r;  // 1 / (D Dq)
+    const double b = __builtin_fma(Ds, e1, -e2) * q;
+    const double g = h * (-D * r);
     PointW<T> w;
     w.ex = T(ex);
-    w.dlin = T(bl);
-    if (LAST) {
-        w.b = T(bl);
-        w.g = T(0);
-        w.a = T(e0 - bl);
-        return w;
-    }
-    const double bp = __builtin_fma(Ds, e1, -e2) * q;
-    const double gp = h * (-D * r);
-    const double b = lin ? bl : bp;
-    const double g = lin ? 0.0 : gp;
     w.b = T(b);
     w.g = T(g);
     w.a = T(e0 - b - g);
+    w.dlin = T(0);
+    if constexpr (DLIN) w.dlin = T(e1 * (FULL ? rcp_f64<true>(D) : __builtin_amdgcn_rcp(D)));
     return w;
 }
 
