@@ -146,6 +146,11 @@ fs_box_kernel(FsBoxArgs a)
     // first row yb for band tiles.  Only the last slot of a thread can be a
     // padding slot (padj).
     const uint32_t row_bytes = (uint32_t)(2 * Nx * ES);
+    // Single-precision band tiles are two layer rows wide, like the padded
+    // field: a ray's column x0 + dx (below 2 Nx) then needs no wrap, and the
+    // layer flush adds word x + Nx of a tile row to column x.
+    constexpr bool WIDE = BAND && sizeof(T) == 4;
+    const uint32_t tpitch = WIDE ? 2u * (uint32_t)Nx : (uint32_t)Nx;
     const int gshift = BAND ? (int)((uint32_t)yb * row_bytes) : 0;
     constexpr uint32_t kTileMask = (1u << 19) - 1u;
     int vb[R];
@@ -161,12 +166,14 @@ fs_box_kernel(FsBoxArgs a)
         const int x0 = q - y0 * Nx;
         const uint32_t yr = (uint32_t)(y0 - yb);
         vb[j] = (int)(yr * row_bytes + (uint32_t)x0 * ES);
-        tw[j] = ((uint32_t)x0 << 19) | ((yr * (uint32_t)Nx + (uint32_t)x0) * (uint32_t)sizeof(T));
+        tw[j] = ((uint32_t)x0 << 19) | ((yr * tpitch + (uint32_t)x0) * (uint32_t)sizeof(T));
         if (j == R - 1) padj = pad;
     }
     unsigned char *const tJb = reinterpret_cast<unsigned char *>(tJ);
     unsigned char *const tLb = reinterpret_cast<unsigned char *>(tL);
     const uint32_t pad_addr = (uint32_t)(TW + tid) * (uint32_t)sizeof(T);
+    const int f_row0 = tid / Nx, f_x0 = tid - f_row0 * Nx;    // flush position of this thread
+    const int f_drow = nthr / Nx, f_dx = nthr - f_drow * Nx;  // and its step
     __syncthreads();
 
     const uint32_t slice_bytes = (uint32_t)(a.pad_stride * ES);
@@ -214,6 +221,37 @@ fs_box_kernel(FsBoxArgs a)
                 if (base < 0) base += Ny;
                 const uint32_t g0 = (uint32_t)base * (uint32_t)Nx;
                 const int n = (hb + span + 1) * Nx;
+                if (WIDE) {
+                    // output word i = row Nx + x takes tile words row 2Nx + x and
+                    // row 2Nx + x + Nx; row and x advance without division
+                    int row = f_row0, x = f_x0;
+                    for (int i = tid; i < n; i += nthr) {
+                        uint32_t gi = g0 + (uint32_t)i;
+                        gi = min(gi, gi - (uint32_t)NxNy);
+                        const int t0 = i + row * Nx;
+                        if (WJ) {
+                            const T v = tJ[t0] + tJ[t0 + Nx];
+                            tJ[t0] = T(0);
+                            tJ[t0 + Nx] = T(0);
+                            pJ[lo + gi] += v;
+                        }
+                        if (WL) {
+                            const T v = tL[t0] + tL[t0 + Nx];
+                            tL[t0] = T(0);
+                            tL[t0 + Nx] = T(0);
+                            pL[lo + gi] += v;
+                        }
+                        x += f_dx;
+                        row += f_drow;
+                        if (x >= Nx) {
+                            x -= Nx;
+                            ++row;
+                        }
+                    }
+                    layer += dlayer;
+                    __syncthreads();
+                    return;
+                }
                 for (int i = tid; i < n; i += nthr) {
                     uint32_t gi = g0 + (uint32_t)i;
                     gi = min(gi, gi - (uint32_t)NxNy);
@@ -257,7 +295,7 @@ fs_box_kernel(FsBoxArgs a)
             TileStep s;
             s.thx = ((uint32_t)Nx - dx) << 19;
             if (BAND) {
-                s.off = ((uint32_t)r * (uint32_t)Nx + dx) * (uint32_t)sizeof(T);
+                s.off = ((uint32_t)r * tpitch + dx) * (uint32_t)sizeof(T);
                 s.thy = 0;
             } else {
                 const uint32_t dy = (w >> kOffBits) & kOffMask;
@@ -271,7 +309,8 @@ fs_box_kernel(FsBoxArgs a)
         // the same word in one step
         auto tile_addr = [&](int j, const TileStep &s) {
             const uint32_t base = tw[j] & kTileMask;
-            uint32_t a4 = base + s.off - (tw[j] >= s.thx ? (uint32_t)Nx * (uint32_t)sizeof(T) : 0u);
+            uint32_t a4 = base + s.off;
+            if (!WIDE) a4 -= tw[j] >= s.thx ? (uint32_t)Nx * (uint32_t)sizeof(T) : 0u;
             if (!BAND) a4 -= base >= s.thy ? (uint32_t)NxNy * (uint32_t)sizeof(T) : 0u;
             return (j == R - 1 && padj) ? pad_addr : a4;
         };
