@@ -314,6 +314,37 @@ def load_golden(case):
         return {"J": z["J"].astype(np.float64), "steps": int(z["steps"]), "residual": float(z["residual"])}
 
 
+def cpu_baseline_sphere(case, lam: int = 0):
+    """The oracle's spherical formal solution, as it stands, on wavelength `lam`
+    of the spherical workload: all voxels, a 4 x 8 direction quadrature on all
+    host threads and a 2 x 4 one on one thread (its cost grows linearly with
+    the directions, so VDU/s carry over to the full 32 x 32 set)."""
+    import numpy as np
+
+    import oracle
+    import synthetic as sy
+    g = oracle.SphereGrid(case.Nr, case.Nt, case.Np, case.r_core, case.r_out)
+    S = sy.random_source(case.chi.shape[1:], seed=7, lo=0.2, hi=1.0, dtype="f32").ravel()
+    I_out, I_core, J_sub = case.I_bc[lam]
+    bv = np.full(case.n_vox, I_core)
+    threads = oracle.default_threads()
+
+    def timed(n_mu, n_phi, th):
+        t0 = time.perf_counter()
+        oracle.fs_sphere(g, n_mu, n_phi, case.chi[lam], S, bv, I_out=I_out, dsrc=case.source_distance,
+                         B_sub=J_sub, threads=th)
+        wall = time.perf_counter() - t0
+        return case.n_vox * n_mu * n_phi / wall, wall
+
+    v, wall = timed(4, 8, threads)
+    v1, wall1 = timed(2, 4, 1)
+    return {"value": v, "unit": "VDU/s", "cores": threads, "kind": "oracle",
+            "sample": f"one FP64 formal solution of wavelength {lam} of {case.n_lambda} over all {case.n_vox} voxels "
+                      f"with a 4 x 8 direction quadrature ({wall:.1f} s wall on {threads} threads)",
+            "single_core": {"value": v1, "unit": "VDU/s", "cores": 1,
+                            "sample": f"2 x 4 directions, all voxels ({wall1:.1f} s wall)"}}
+
+
 def bench_sphere(args, w):
     """The spherical workload: one ALI step over the wavelength batch per step."""
     import torch
@@ -370,6 +401,9 @@ def bench_sphere(args, w):
     if not args.no_solve:
         out["time_to_solution"] = sphere_time_to_solution(case, g, args.host_cache)
     g.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_sphere(case)
+        progress("CPU baseline timed")
     print(json.dumps(out), flush=True)
 
 
