@@ -214,14 +214,33 @@ struct PointW {
 
 // FULL: double-accurate moments (the default for double results); false: the
 // shorter forms that suffice for single-precision results (SPLIT: their
-// two-branch variant).
-template <typename T, bool FULL = sizeof(T) == 8, bool SPLIT = false>
+// two-branch variant).  LIMIT: linear points by the parabolic formulas with
+// the downwind step replaced by 2^300, as in point_weights_pos (DLIN: also
+// the linear diagonal e1/D, else dlin is left zero).
+template <typename T, bool FULL = sizeof(T) == 8, bool SPLIT = false, bool LIMIT = false, bool DLIN = true>
 __device__ __forceinline__ PointW<T> point_weights(double D, double Dp, bool last)
 {
     const double Dv = D < kMinStep ? kMinStep : D;  // NaN propagates
     double ex, e0, e1, e2;
     kernel_moments<FULL, SPLIT>(Dv, ex, e0, e1, e2);
     const double Dq = Dp < kMinStep ? Dv : Dp;   // keeps r finite on last/vacuum points; NaN propagates
+    if constexpr (LIMIT) {
+        const double h = __builtin_fma(Dv, e1, -e2);  // D e1 - e2
+        const bool lin = last || (Dp < 0.5 * D) || (Dp * e0 <= h);
+        const double Dl = lin ? 0x1p300 : Dq;
+        const double Ds = Dv + Dl;
+        const double r = rcp_f64<FULL>(Dv * Dl * Ds);
+        const double b = __builtin_fma(Ds, e1, -e2) * (Ds * r);
+        const double g = h * (-Dv * r);
+        PointW<T> w;
+        w.ex = T(ex);
+        w.b = T(b);
+        w.g = T(g);
+        w.a = T(e0 - b - g);
+        w.dlin = T(0);
+        if constexpr (DLIN) w.dlin = T(e1 * rcp_f64<FULL>(Dv));
+        return w;
+    }
     const double Ds = Dv + Dq;
     const double r = rcp_f64<FULL>(Dv * Dq * Ds);
     const double bl = e1 * ((Dq * Ds) * r);      // e1 / D

@@ -101,7 +101,7 @@ __global__ void __launch_bounds__(256) fs_sphere_kernel(FsSphereArgs a)
         }
         const double D = half_sum(tp, tc);
         const double Dp = last ? 0.0 : half_sum(tc, tn);
-        const PointW<T> pw = point_weights<T, sizeof(T) == 8, true>(D, Dp, last);
+        const PointW<T> pw = point_weights<T, sizeof(T) == 8, true, true, WL && !PARA>(D, Dp, last);
         const T wk = T(wv[e]);
         if (WJ) {
             I = I * pw.ex + pw.a * fp.S + pw.b * fc.S + (last ? T(0) : pw.g * fn.S);
