@@ -88,9 +88,9 @@ typedef enum { RT_FP64 = 0, RT_FP32 = 1 } rt_prec;
                                      129 x 129); the flag forces it for any box
                                      grid (results differ only in the
                                      summation order).  Single-precision band
-                                     tiles are two layer rows wide (twice the
-                                     LDS per row), so that no ray's column
-                                     wraps.                                    */
+                                     tiles of J-only or Lambda*-only sweeps
+                                     are two layer rows wide (twice the LDS
+                                     per row), so that no ray's column wraps. */
 #define RT_F_LSTAR_NONLOCAL 0x4u  /* box or sphere (Nphi >= 3, geometry cache
                                      in device memory): the ALI uses the
                                      nearest-neighbour

@@ -70,8 +70,9 @@ Variant make_variant(rt_grid *g, bool dbl, bool wj, bool wl, int lb, int R, int 
             if (need > lb) continue;
             const int nthr = std::min(lb, (int)((need + 63) / 64) * 64);
             if ((int64_t)nthr * (R - 1) >= (int64_t)Hmin * Nx) continue;
-            // single-precision band tiles are two layer rows wide (no column wrap)
-            const int tw = (H + span + 1) * Nx * (dbl ? 1 : 2);
+            // single-precision band tiles of single-output sweeps are two layer
+            // rows wide (no column wrap)
+            const int tw = (H + span + 1) * Nx * (dbl || nout > 1 ? 1 : 2);
             if ((size_t)(tw + nthr) * esz * nout * (size_t)occ > g->max_lds) continue;
             v.nb = nb; v.Q = (int)Q; v.nthr = nthr; v.tile_words = tw;
             found = true;

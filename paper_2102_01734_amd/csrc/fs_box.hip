@@ -146,10 +146,12 @@ fs_box_kernel(FsBoxArgs a)
     // first row yb for band tiles.  Only the last slot of a thread can be a
     // padding slot (padj).
     const uint32_t row_bytes = (uint32_t)(2 * Nx * ES);
-    // Single-precision band tiles are two layer rows wide, like the padded
-    // field: a ray's column x0 + dx (below 2 Nx) then needs no wrap, and the
-    // layer flush adds word x + Nx of a tile row to column x.
-    constexpr bool WIDE = BAND && sizeof(T) == 4;
+    // Single-precision band tiles of single-output sweeps are two layer rows
+    // wide, like the padded field: a ray's column x0 + dx (below 2 Nx) then
+    // needs no wrap, and the layer flush adds word x + Nx of a tile row to
+    // column x.  (Two outputs at twice the width would leave room for fewer
+    // rows per band.)
+    constexpr bool WIDE = BAND && sizeof(T) == 4 && !(WJ && WL);
     const uint32_t tpitch = WIDE ? 2u * (uint32_t)Nx : (uint32_t)Nx;
     const int gshift = BAND ? (int)((uint32_t)yb * row_bytes) : 0;
     constexpr uint32_t kTileMask = (1u << 19) - 1u;
