@@ -171,7 +171,20 @@ __global__ void __launch_bounds__(256) sphere_gather_kernel(const TS *__restrict
     const int b = (int)(id - v * nb);
     double acc = 0.0;
     const int32_t e = row[v + 1];
-    for (int32_t k = row[v]; k < e; ++k) acc += (double)src[(int64_t)idx[k] * nb + b];
+    int32_t k = row[v];
+    // eight visits' loads in flight at a time; the sum keeps the order of k
+    constexpr int U = 8;
+    for (; k + U <= e; k += U) {
+        int64_t i[U];
+        TS s[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) i[u] = idx[k + u];
+#pragma unroll
+        for (int u = 0; u < U; ++u) s[u] = src[i[u] * nb + b];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += (double)s[u];
+    }
+    for (; k < e; ++k) acc += (double)src[(int64_t)idx[k] * nb + b];
     TD *d = dst + (int64_t)b * n_vox + v;
     *d = accumulate ? (TD)((double)*d + acc) : (TD)acc;
 }
