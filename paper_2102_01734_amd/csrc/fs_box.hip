@@ -225,47 +225,77 @@ fs_box_kernel(FsBoxArgs a)
                 const int n = (hb + span + 1) * Nx;
                 if (WIDE) {
                     // output word i = row Nx + x takes tile words row 2Nx + x and
-                    // row 2Nx + x + Nx; row and x advance without division
+                    // row 2Nx + x + Nx; row and x advance without division.  A
+                    // single-output sweep (one tile, one slot); eight words of a
+                    // thread at a time, their slot reads issued together
+                    T *const tile = WJ ? tJ : tL;
+                    T *__restrict__ const part = WJ ? pJ : pL;
                     int row = f_row0, x = f_x0;
-                    for (int i = tid; i < n; i += nthr) {
-                        uint32_t gi = g0 + (uint32_t)i;
+                    auto word = [&](int i, uint32_t &gi, int &t0) {
+                        gi = g0 + (uint32_t)i;
                         gi = min(gi, gi - (uint32_t)NxNy);
-                        const int t0 = i + row * Nx;
-                        if (WJ) {
-                            const T v = tJ[t0] + tJ[t0 + Nx];
-                            tJ[t0] = T(0);
-                            tJ[t0 + Nx] = T(0);
-                            pJ[lo + gi] += v;
-                        }
-                        if (WL) {
-                            const T v = tL[t0] + tL[t0 + Nx];
-                            tL[t0] = T(0);
-                            tL[t0 + Nx] = T(0);
-                            pL[lo + gi] += v;
-                        }
+                        t0 = i + row * Nx;
                         x += f_dx;
                         row += f_drow;
                         if (x >= Nx) {
                             x -= Nx;
                             ++row;
                         }
+                    };
+                    constexpr int U = 8;
+                    for (int i = tid; i < n; i += U * nthr) {
+                        uint32_t gi[U];
+                        int t0[U];
+                        T old[U];
+#pragma unroll
+                        for (int u = 0; u < U; ++u) word(i + u * nthr, gi[u], t0[u]);
+#pragma unroll
+                        for (int u = 0; u < U; ++u)
+                            if (i + u * nthr < n) old[u] = part[lo + gi[u]];
+#pragma unroll
+                        for (int u = 0; u < U; ++u)
+                            if (i + u * nthr < n) {
+                                const T v = tile[t0[u]] + tile[t0[u] + Nx];
+                                tile[t0[u]] = T(0);
+                                tile[t0[u] + Nx] = T(0);
+                                part[lo + gi[u]] = old[u] + v;
+                            }
                     }
                     layer += dlayer;
                     __syncthreads();
                     return;
                 }
-                for (int i = tid; i < n; i += nthr) {
-                    uint32_t gi = g0 + (uint32_t)i;
-                    gi = min(gi, gi - (uint32_t)NxNy);
-                    if (WJ) {
-                        const T v = tJ[i];
-                        tJ[i] = T(0);
-                        pJ[lo + gi] += v;
+                // four words of a thread at a time, their slot reads issued together
+                constexpr int U = 4;
+                for (int i = tid; i < n; i += U * nthr) {
+                    uint32_t gi[U];
+                    T oJ[U], oL[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        gi[u] = g0 + (uint32_t)(i + u * nthr);
+                        gi[u] = min(gi[u], gi[u] - (uint32_t)NxNy);
                     }
-                    if (WL) {
-                        const T v = tL[i];
-                        tL[i] = T(0);
-                        pL[lo + gi] += v;
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        if (i + u * nthr < n) {
+                            if (WJ) oJ[u] = pJ[lo + gi[u]];
+                            if (WL) oL[u] = pL[lo + gi[u]];
+                        }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int k = i + u * nthr;
+                        if (k < n) {
+                            if (WJ) {
+                                const T v = tJ[k];
+                                tJ[k] = T(0);
+                                pJ[lo + gi[u]] = oJ[u] + v;
+                            }
+                            if (WL) {
+                                const T v = tL[k];
+                                tL[k] = T(0);
+                                pL[lo + gi[u]] = oL[u] + v;
+                            }
+                        }
                     }
                 }
             } else {
