@@ -247,8 +247,10 @@ fs_box_kernel(FsBoxArgs a)
                         uint32_t gi[U];
                         int t0[U];
                         T old[U];
+                        // slots past the band end only the thread's last group
 #pragma unroll
-                        for (int u = 0; u < U; ++u) word(i + u * nthr, gi[u], t0[u]);
+                        for (int u = 0; u < U; ++u)
+                            if (i + u * nthr < n) word(i + u * nthr, gi[u], t0[u]);
 #pragma unroll
                         for (int u = 0; u < U; ++u)
                             if (i + u * nthr < n) old[u] = part[lo + gi[u]];
