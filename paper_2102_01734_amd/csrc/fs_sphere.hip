@@ -90,14 +90,30 @@ __global__ void __launch_bounds__(256) fs_sphere_kernel(FsSphereArgs a)
     SPair<T> fc = pair(e0 + 64);
     double tc = seg_depth((double)fc.chi, (double)sv[e0 + 64]);
     T gprev = T(0);
+    // software pipeline: the (chi, S) pair and path length of a point are read
+    // one visit before it is used, its voxel index two visits before
+    SPair<T> fq{T(0), T(0)};
+    TG sq = TG(0);
+    int32_t vq = 0;
+    if (len > 2) {
+        fq = pair(e0 + 128);
+        sq = sv[e0 + 128];
+    }
+    if (len > 3) vq = vx[e0 + 192];
     for (int m = 1; m < len; ++m) {
         const int64_t e = e0 + 64 * (int64_t)m;
         const bool last = m + 1 == len;
         SPair<T> fn{T(0), T(0)};
         double tn = 0.0;
         if (!last) {
-            fn = pair(e + 64);
-            tn = seg_depth((double)fn.chi, (double)sv[e + 64]);
+            fn = fq;  // point m + 1
+            const TG sn = sq;
+            if (m + 2 < len) {
+                fq = F[(int64_t)vq * ls];  // point m + 2
+                sq = sv[e + 128];
+                if (m + 3 < len) vq = vx[e + 192];  // point m + 3
+            }
+            tn = seg_depth((double)fn.chi, (double)sn);
         }
         const double D = half_sum(tp, tc);
         const double Dp = last ? 0.0 : half_sum(tc, tn);
